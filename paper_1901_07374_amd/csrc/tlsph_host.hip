@@ -1,0 +1,647 @@
+// Host runtime of libtlsph: the C ABI declared in include/tlsph.h.
+//
+// The context owns host metadata only.  Every device array lives in the
+// caller's workspace, carved here at 256-byte alignment; the library never
+// allocates device memory, so tlsph_step enqueues nothing but kernels (and,
+// with TLSPH_USE_GRAPHS, replays of a captured two-step graph).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/tlsph.h"
+#include "tlsph_internal.h"
+
+using namespace tlsph;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+int64_t next_pow2(int64_t x) {
+    int64_t p = 64;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// Offsets of every device array inside the workspace.
+struct Layout {
+    int64_t n, np, n_pow2, n_slices;
+    int32_t n_spec, n_bc, k_cap;
+    bool mixed;
+    size_t X, V0, spec, bc, perm, iperm, nnb, slice_ptr, col, Linv, Linv32, specs, bcs, t;
+    size_t u0, u1, v, F, H, sig, sig32, Q, Q32, eps_p, eps_rate, d_init, w_p, f_void, e, D0, D1,
+        force, err, spec_off, bbox, keys, vals, bc_list, bc_ptr, backup, readback;
+    size_t backup_bytes;
+    size_t total;
+};
+
+Layout make_layout(int64_t n, int32_t n_spec, int32_t n_bc, int32_t k_cap, bool mixed) {
+    Layout L{};
+    L.n = n;
+    L.np = (n + kSlice - 1) / kSlice * kSlice;
+    L.n_pow2 = next_pow2(n);
+    L.n_slices = L.np / kSlice;
+    L.n_spec = n_spec;
+    L.n_bc = n_bc;
+    L.k_cap = k_cap;
+    L.mixed = mixed;
+    size_t cur = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = align_up(cur);
+        cur = o + bytes;
+        return o;
+    };
+    const size_t np = (size_t)L.np;
+    L.X = take(3 * np * 8);
+    L.V0 = take(np * 8);
+    L.spec = take(np * 4);
+    L.bc = take(np * 4);
+    L.perm = take(np * 4);
+    L.iperm = take((size_t)n * 4);
+    L.nnb = take(np * 4);
+    L.slice_ptr = take(((size_t)L.n_slices + 1) * 8);
+    L.col = take((size_t)k_cap * np * 4);
+    L.Linv = take(9 * np * 8);
+    L.Linv32 = take(mixed ? 9 * np * 4 : 0);
+    L.specs = take((size_t)n_spec * sizeof(DevSpec));
+    L.bcs = take((size_t)(n_bc > 0 ? n_bc : 1) * sizeof(DevBC));
+    L.t = take((size_t)n_spec * 8);
+    // evolving state, contiguous from u0 to force (saved/restored by autotune)
+    const size_t state_begin = align_up(cur);
+    L.u0 = take(3 * np * 8);
+    L.u1 = take(3 * np * 8);
+    L.v = take(3 * np * 8);
+    L.F = take(mixed ? 0 : 9 * np * 8);
+    L.H = take(mixed ? 9 * np * 4 : 0);
+    L.sig = take(mixed ? 0 : 6 * np * 8);
+    L.sig32 = take(mixed ? 6 * np * 4 : 0);
+    L.Q = take(mixed ? 0 : 9 * np * 8);
+    L.Q32 = take(mixed ? 9 * np * 4 : 0);
+    L.eps_p = take(np * 8);
+    L.eps_rate = take(np * 8);
+    L.d_init = take(np * 8);
+    L.w_p = take(np * 8);
+    L.f_void = take(np * 8);
+    L.e = take(np * 8);
+    L.D0 = take(np * 8);
+    L.D1 = take(np * 8);
+    L.force = take(3 * np * 8);
+    L.backup_bytes = align_up(cur) - state_begin;
+    L.err = take(8 * 4);
+    L.spec_off = take(((size_t)n_spec + 1) * 8);
+    L.bbox = take((size_t)n_spec * 6 * 8);
+    L.keys = take((size_t)L.n_pow2 * 8);
+    L.vals = take((size_t)L.n_pow2 * 4);
+    L.bc_list = take(np * 4);
+    L.bc_ptr = take(((size_t)n_bc + 2) * 8);
+    L.readback = take(64);
+    L.backup = take(L.backup_bytes + (size_t)n_spec * 8);
+    L.total = align_up(cur);
+    return L;
+}
+
+bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
+
+}  // namespace
+
+struct tlsph_ctx {
+    Layout L;
+    uint8_t* ws = nullptr;
+    uint32_t flags = 0;
+    DevState st{};
+    std::vector<int64_t> spec_off;
+    std::vector<DevSpec> specs;
+    std::vector<DevBC> bcs;
+    int32_t n_bc_cap = 0;
+    bool built = false;
+    int parity = 0;
+    int64_t nnz = 0, slots = 0;
+    int block_a = 256, block_b = 256;
+    std::string last_error;
+    // per-kernel timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<int, size_t>> ev_marks;  // (kernel, index of start event)
+    // graphs
+    hipGraphExec_t gexec = nullptr;
+    int graph_parity = -1;
+    int graph_block_a = 0, graph_block_b = 0;
+};
+
+namespace {
+
+tlsph_status fail(tlsph_ctx* c, tlsph_status s, const std::string& msg) {
+    if (c) c->last_error = msg;
+    return s;
+}
+
+tlsph_status hip_fail(tlsph_ctx* c, hipError_t e, const char* where) {
+    std::string m = std::string(where) + ": " + hipGetErrorString(e);
+    return fail(c, TLSPH_E_HIP, m);
+}
+
+#define HIPCHK(ctx, call)                                   \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+    } while (0)
+
+template <typename T>
+T* at(tlsph_ctx* c, size_t off) {
+    return reinterpret_cast<T*>(c->ws + off);
+}
+
+void wire_state(tlsph_ctx* c) {
+    const Layout& L = c->L;
+    DevState& s = c->st;
+    s.n = L.n;
+    s.np = L.np;
+    s.n_spec = L.n_spec;
+    s.n_bc = c->n_bc_cap;
+    s.flags = c->flags;
+    s.X = at<double>(c, L.X);
+    s.V0 = at<double>(c, L.V0);
+    s.spec = at<int32_t>(c, L.spec);
+    s.bc = at<int32_t>(c, L.bc);
+    s.perm = at<int32_t>(c, L.perm);
+    s.iperm = at<int32_t>(c, L.iperm);
+    s.nnb = at<int32_t>(c, L.nnb);
+    s.slice_ptr = at<int64_t>(c, L.slice_ptr);
+    s.col = at<int32_t>(c, L.col);
+    s.col_cap = (int64_t)L.k_cap * L.np;
+    s.Linv = at<double>(c, L.Linv);
+    s.Linv32 = L.mixed ? at<float>(c, L.Linv32) : nullptr;
+    s.specs = at<DevSpec>(c, L.specs);
+    s.bcs = at<DevBC>(c, L.bcs);
+    s.t = at<double>(c, L.t);
+    s.u[0] = at<double>(c, L.u0);
+    s.u[1] = at<double>(c, L.u1);
+    s.v = at<double>(c, L.v);
+    s.F = L.mixed ? nullptr : at<double>(c, L.F);
+    s.H = L.mixed ? at<float>(c, L.H) : nullptr;
+    s.sig = L.mixed ? nullptr : at<double>(c, L.sig);
+    s.sig32 = L.mixed ? at<float>(c, L.sig32) : nullptr;
+    s.Q = L.mixed ? nullptr : at<double>(c, L.Q);
+    s.Q32 = L.mixed ? at<float>(c, L.Q32) : nullptr;
+    s.eps_p = at<double>(c, L.eps_p);
+    s.eps_rate = at<double>(c, L.eps_rate);
+    s.d_init = at<double>(c, L.d_init);
+    s.w_p = at<double>(c, L.w_p);
+    s.f_void = at<double>(c, L.f_void);
+    s.e = at<double>(c, L.e);
+    s.D[0] = at<double>(c, L.D0);
+    s.D[1] = at<double>(c, L.D1);
+    s.force = at<double>(c, L.force);
+    s.err = at<int32_t>(c, L.err);
+}
+
+DevBC to_dev(const tlsph_bc_group& g) {
+    DevBC d{};
+    d.mask = g.mask;
+    for (int k = 0; k < 3; ++k) d.v_max[k] = g.v_max[k];
+    d.tau = g.tau;
+    for (int k = 0; k < 9; ++k) d.grad[k] = g.grad[k];
+    return d;
+}
+
+hipEvent_t next_event(tlsph_ctx* c) {
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->ev_pool.push_back(e);
+    }
+    return c->ev_pool[c->ev_used++];
+}
+
+tlsph_status run_steps_eager(tlsph_ctx* c, int32_t n_steps, hipStream_t stream) {
+    const bool mixed = c->L.mixed;
+    for (int32_t k = 0; k < n_steps; ++k) {
+        for (int pass = 0; pass < 2; ++pass) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (c->timing) {
+                const size_t idx = c->ev_used;
+                e0 = next_event(c);
+                e1 = next_event(c);
+                if (!e0 || !e1) return fail(c, TLSPH_E_HIP, "hipEventCreate failed");
+                HIPCHK(c, hipEventRecord(e0, stream));
+                c->ev_marks.push_back({pass, idx});
+            }
+            hipError_t e = pass == 0 ? launch_pass_b(c->st, c->parity, c->block_b, mixed, stream)
+                                     : launch_pass_a(c->st, c->parity, c->block_a, mixed, stream);
+            if (e != hipSuccess) return hip_fail(c, e, pass == 0 ? "force pass" : "deformation pass");
+            if (c->timing) HIPCHK(c, hipEventRecord(e1, stream));
+        }
+        c->parity ^= 1;
+    }
+    return TLSPH_OK;
+}
+
+tlsph_status ensure_graph(tlsph_ctx* c, hipStream_t stream) {
+    if (c->gexec && c->graph_parity == c->parity && c->graph_block_a == c->block_a &&
+        c->graph_block_b == c->block_b)
+        return TLSPH_OK;
+    if (c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    const int p0 = c->parity;
+    HIPCHK(c, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    const bool timing = c->timing;
+    c->timing = false;
+    tlsph_status s = run_steps_eager(c, 2, stream);
+    c->timing = timing;
+    hipError_t ce = hipStreamEndCapture(stream, &g);
+    c->parity = p0;  // capture only recorded the launches
+    if (s != TLSPH_OK) return s;
+    if (ce != hipSuccess) return hip_fail(c, ce, "hipStreamEndCapture");
+    hipError_t ie = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return hip_fail(c, ie, "hipGraphInstantiate");
+    c->graph_parity = p0;
+    c->graph_block_a = c->block_a;
+    c->graph_block_b = c->block_b;
+    return TLSPH_OK;
+}
+
+int field_comps(int f, int32_t n_spec) {
+    switch (f) {
+        case TLSPH_F_X: case TLSPH_F_U: case TLSPH_F_V: case TLSPH_F_FORCE: return 3;
+        case TLSPH_F_DEFGRAD: case TLSPH_F_Q: case TLSPH_F_LINV: return 9;
+        case TLSPH_F_SIGMA: return 6;
+        case TLSPH_F_TIME: return -n_spec;
+        case TLSPH_F_EPS_P: case TLSPH_F_EPS_P_RATE: case TLSPH_F_D_INIT: case TLSPH_F_W_P:
+        case TLSPH_F_VOID: case TLSPH_F_D: case TLSPH_F_E_INT: return 1;
+        default: return 0;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tlsph_status_string(tlsph_status s) {
+    switch (s) {
+        case TLSPH_OK: return "ok";
+        case TLSPH_E_INVALID_ARG: return "invalid argument";
+        case TLSPH_E_BAD_STATE: return "bad call order";
+        case TLSPH_E_HIP: return "HIP runtime error";
+        case TLSPH_E_SINGULAR_L: return "singular correction matrix";
+        case TLSPH_E_NONFINITE: return "non-finite state";
+        case TLSPH_E_CAPACITY: return "neighbour capacity exceeded";
+        case TLSPH_E_UNSUPPORTED: return "unsupported configuration";
+    }
+    return "unknown status";
+}
+
+const char* tlsph_last_error(const tlsph_ctx* c) { return c ? c->last_error.c_str() : ""; }
+
+tlsph_status tlsph_workspace_bytes(int64_t n, int32_t n_spec, int32_t n_bc, int32_t k_cap,
+                                   tlsph_precision precision, size_t* bytes) {
+    if (!bytes || n < 1 || n > (int64_t)1 << 30 || n_spec < 1 || n_spec > (1 << 20) ||
+        n_spec > n || n_bc < 0 || k_cap < 1 || k_cap > 512 ||
+        (precision != TLSPH_FP64 && precision != TLSPH_MIXED))
+        return TLSPH_E_INVALID_ARG;
+    *bytes = make_layout(n, n_spec, n_bc, k_cap, precision == TLSPH_MIXED).total;
+    return TLSPH_OK;
+}
+
+tlsph_status tlsph_create(int64_t n, int32_t n_spec, const int64_t* spec_offsets,
+                          const tlsph_specimen* spec, int32_t n_bc, const tlsph_bc_group* bc,
+                          tlsph_precision precision, int32_t k_cap, uint32_t flags,
+                          void* workspace, size_t ws_bytes, hipStream_t stream, tlsph_ctx** out) {
+    if (!out) return TLSPH_E_INVALID_ARG;
+    *out = nullptr;
+    size_t need = 0;
+    if (tlsph_workspace_bytes(n, n_spec, n_bc, k_cap, precision, &need) != TLSPH_OK)
+        return TLSPH_E_INVALID_ARG;
+    if (!spec_offsets || !spec || (n_bc > 0 && !bc) || !workspace || ws_bytes < need ||
+        ((uintptr_t)workspace % kAlign) != 0 || (flags & ~7u) != 0)
+        return TLSPH_E_INVALID_ARG;
+    if (spec_offsets[0] != 0 || spec_offsets[n_spec] != n) return TLSPH_E_INVALID_ARG;
+    for (int32_t s = 0; s < n_spec; ++s)
+        if (spec_offsets[s + 1] <= spec_offsets[s]) return TLSPH_E_INVALID_ARG;
+    for (int32_t s = 0; s < n_spec; ++s) {
+        const tlsph_specimen& p = spec[s];
+        if (!finite_pos(p.rho0) || !finite_pos(p.E) || !finite_pos(p.c0) || !finite_pos(p.h) ||
+            !finite_pos(p.dt) || !(p.nu > -1.0 && p.nu < 0.5) || p.damage < 0 || p.damage > 3 ||
+            !finite_pos(p.eps_dot0) || !(p.A >= 0.0) || !(p.hg_alpha >= 0.0))
+            return TLSPH_E_INVALID_ARG;
+        if (p.damage == TLSPH_DMG_CL && !finite_pos(p.Wcr)) return TLSPH_E_INVALID_ARG;
+        if (p.damage == TLSPH_DMG_GTN &&
+            (!finite_pos(p.q1) || !finite_pos(p.sN) || !(p.fF > p.fc) || !(p.fc > 0.0)))
+            return TLSPH_E_INVALID_ARG;
+        if (p.has_wall) {
+            const double nn = p.wall_n[0] * p.wall_n[0] + p.wall_n[1] * p.wall_n[1] +
+                              p.wall_n[2] * p.wall_n[2];
+            if (!(fabs(nn - 1.0) < 1e-12)) return TLSPH_E_INVALID_ARG;
+        }
+    }
+    for (int32_t g = 0; g < n_bc; ++g)
+        if (bc[g].mask < 0 || bc[g].mask > 7 || !(bc[g].tau >= 0.0)) return TLSPH_E_INVALID_ARG;
+
+    tlsph_ctx* c = new tlsph_ctx();
+    c->L = make_layout(n, n_spec, n_bc, k_cap, precision == TLSPH_MIXED);
+    c->ws = static_cast<uint8_t*>(workspace);
+    c->flags = flags;
+    c->n_bc_cap = n_bc;
+    c->spec_off.assign(spec_offsets, spec_offsets + n_spec + 1);
+    c->specs.resize(n_spec);
+    for (int32_t s = 0; s < n_spec; ++s) {
+        const tlsph_specimen& p = spec[s];
+        DevSpec& d = c->specs[s];
+        d.rho0 = p.rho0; d.E = p.E; d.nu = p.nu; d.c0 = p.c0; d.S_alpha = p.S_alpha;
+        d.Gamma0 = p.Gamma0; d.A = p.A; d.B = p.B; d.n = p.n; d.C = p.C; d.eps_dot0 = p.eps_dot0;
+        d.Wcr = p.Wcr; d.D1 = p.D1; d.D2 = p.D2; d.D3 = p.D3; d.D4 = p.D4; d.D5 = p.D5;
+        d.q1 = p.q1; d.q2 = p.q2; d.q3 = p.q3; d.f0 = p.f0; d.fN = p.fN; d.eN = p.eN;
+        d.sN = p.sN; d.fc = p.fc; d.fF = p.fF; d.k_omega = p.k_omega;
+        d.h = p.h; d.dt = p.dt; d.hg_alpha = p.hg_alpha;
+        for (int k = 0; k < 3; ++k) d.wall_n[k] = p.wall_n[k];
+        d.wall_d = p.wall_d;
+        d.G = p.E / (2.0 * (1.0 + p.nu));
+        d.inv_h = 1.0 / p.h;
+        d.wnorm = 8.0 / (M_PI * p.h * p.h * p.h);
+        d.h2 = p.h * p.h;
+        d.inv_cell = 1.0 / (p.h * (1.0 + 1e-9));
+        d.damage = p.damage;
+        d.has_wall = p.has_wall;
+        d.first = spec_offsets[s];
+        d.last = spec_offsets[s + 1];
+    }
+    c->bcs.resize(n_bc > 0 ? n_bc : 1);
+    for (int32_t g = 0; g < n_bc; ++g) c->bcs[g] = to_dev(bc[g]);
+    wire_state(c);
+    const Layout& L = c->L;
+    hipError_t e = hipMemcpyAsync(c->ws + L.specs, c->specs.data(), n_spec * sizeof(DevSpec),
+                                  hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && n_bc > 0)
+        e = hipMemcpyAsync(c->ws + L.bcs, c->bcs.data(), n_bc * sizeof(DevBC),
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->ws + L.spec_off, c->spec_off.data(), (n_spec + 1) * sizeof(int64_t),
+                           hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) {
+        delete c;
+        return TLSPH_E_HIP;
+    }
+    *out = c;
+    return TLSPH_OK;
+}
+
+tlsph_status tlsph_build_neighbors(tlsph_ctx* c, const double* X, const double* V0,
+                                   const int32_t* bc_group, hipStream_t stream) {
+    if (!c || !X || !V0 || !bc_group) return fail(c, TLSPH_E_INVALID_ARG, "null argument");
+    const Layout& L = c->L;
+    c->built = false;
+    c->parity = 0;
+    if (c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+    // error words: first singular = INT_MAX, max count = 0, flags = 0, build = 0
+    const int32_t init_err[8] = {0x7fffffff, 0, 0, 0, 0, 0, 0, 0};
+    HIPCHK(c, hipMemcpyAsync(c->ws + L.err, init_err, sizeof init_err, hipMemcpyHostToDevice, stream));
+    BuildBuffers b{};
+    b.X_in = X;
+    b.V0_in = V0;
+    b.bc_in = bc_group;
+    b.spec_off = at<int64_t>(c, L.spec_off);
+    b.bbox = at<double>(c, L.bbox);
+    b.keys = at<uint64_t>(c, L.keys);
+    b.vals = at<int32_t>(c, L.vals);
+    b.n_pow2 = L.n_pow2;
+    HIPCHK(c, launch_build_count(c->st, b, stream));
+    int32_t err[8];
+    int64_t total_slots = 0;
+    HIPCHK(c, hipMemcpyAsync(err, c->ws + L.err, sizeof err, hipMemcpyDeviceToHost, stream));
+    HIPCHK(c, hipMemcpyAsync(&total_slots, c->ws + L.slice_ptr + L.n_slices * 8, 8,
+                             hipMemcpyDeviceToHost, stream));
+    HIPCHK(c, hipStreamSynchronize(stream));
+    if (err[3] & 2) return fail(c, TLSPH_E_INVALID_ARG, "bc_group entry outside [-1, n_bc)");
+    if (err[3] & 1) return fail(c, TLSPH_E_UNSUPPORTED, "more than 16384 cells along an axis");
+    if (err[1] > L.k_cap || total_slots > (int64_t)L.k_cap * L.np)
+        return fail(c, TLSPH_E_CAPACITY, "a particle has " + std::to_string(err[1]) +
+                                             " neighbours, k_cap is " + std::to_string(L.k_cap));
+    HIPCHK(c, launch_build_fill(c->st, b, stream));
+    HIPCHK(c, launch_shape_and_init(c->st, L.mixed, stream));
+    HIPCHK(c, launch_bc_lists(c->st, b.keys, b.vals, L.n_pow2, at<int32_t>(c, L.bc_list),
+                              at<int64_t>(c, L.bc_ptr), stream));
+    HIPCHK(c, hipMemcpyAsync(err, c->ws + L.err, sizeof err, hipMemcpyDeviceToHost, stream));
+    HIPCHK(c, hipStreamSynchronize(stream));
+    if (err[0] != 0x7fffffff) {
+        int32_t orig = -1;
+        HIPCHK(c, hipMemcpy(&orig, c->ws + L.perm + (size_t)err[0] * 4, 4, hipMemcpyDeviceToHost));
+        return fail(c, TLSPH_E_SINGULAR_L,
+                    "singular correction matrix at particle " + std::to_string(orig));
+    }
+    // neighbour pairs: sum of counts
+    std::vector<int32_t> cnt(L.np);
+    HIPCHK(c, hipMemcpy(cnt.data(), c->ws + L.nnb, L.np * 4, hipMemcpyDeviceToHost));
+    int64_t nnz = 0;
+    for (int64_t p = 0; p < L.n; ++p) nnz += cnt[p];
+    c->nnz = nnz;
+    c->slots = total_slots;
+    c->built = true;
+    return TLSPH_OK;
+}
+
+tlsph_status tlsph_step(tlsph_ctx* c, int32_t n_steps, hipStream_t stream) {
+    if (!c) return TLSPH_E_INVALID_ARG;
+    if (!c->built) return fail(c, TLSPH_E_BAD_STATE, "step before build");
+    if (n_steps < 0) return fail(c, TLSPH_E_INVALID_ARG, "negative step count");
+    bool graphs = (c->flags & TLSPH_USE_GRAPHS) && !c->timing && n_steps >= 2 && stream != nullptr;
+    if (graphs) {
+        // a caller that is capturing already records the plain launches
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        HIPCHK(c, hipStreamIsCapturing(stream, &cs));
+        graphs = cs == hipStreamCaptureStatusNone;
+    }
+    if (!graphs) return run_steps_eager(c, n_steps, stream);
+    int32_t left = n_steps;
+    if (c->gexec && c->graph_parity != c->parity) {
+        tlsph_status s = run_steps_eager(c, 1, stream);
+        if (s != TLSPH_OK) return s;
+        --left;
+    }
+    if (left >= 2) {
+        tlsph_status s = ensure_graph(c, stream);
+        if (s != TLSPH_OK) return s;
+        for (; left >= 2; left -= 2) HIPCHK(c, hipGraphLaunch(c->gexec, stream));
+    }
+    if (left) return run_steps_eager(c, left, stream);
+    return TLSPH_OK;
+}
+
+tlsph_status tlsph_get_state(tlsph_ctx* c, tlsph_field field, double* dst, size_t bytes,
+                             hipStream_t stream) {
+    if (!c) return TLSPH_E_INVALID_ARG;
+    if (!c->built) return fail(c, TLSPH_E_BAD_STATE, "get_state before build");
+    const int comps = field_comps(field, c->L.n_spec);
+    if (!dst || comps == 0) return fail(c, TLSPH_E_INVALID_ARG, "bad field or null dst");
+    const size_t need = comps > 0 ? (size_t)comps * c->L.n * 8 : (size_t)(-comps) * 8;
+    if (bytes != need) return fail(c, TLSPH_E_INVALID_ARG, "wrong byte count");
+    if (field == TLSPH_F_TIME) {
+        HIPCHK(c, hipMemcpyAsync(dst, c->st.t, need, hipMemcpyDeviceToDevice, stream));
+        return TLSPH_OK;
+    }
+    HIPCHK(c, launch_get_field(c->st, field, c->parity, c->L.mixed, dst, stream));
+    return TLSPH_OK;
+}
+
+tlsph_status tlsph_set_state(tlsph_ctx* c, tlsph_field field, const double* src, size_t bytes,
+                             hipStream_t stream) {
+    if (!c) return TLSPH_E_INVALID_ARG;
+    if (!c->built) return fail(c, TLSPH_E_BAD_STATE, "set_state before build");
+    const int comps = field_comps(field, c->L.n_spec);
+    if (!src || comps == 0 || field == TLSPH_F_X || field == TLSPH_F_FORCE ||
+        field == TLSPH_F_LINV)
+        return fail(c, TLSPH_E_INVALID_ARG, "bad or read-only field, or null src");
+    const size_t need = comps > 0 ? (size_t)comps * c->L.n * 8 : (size_t)(-comps) * 8;
+    if (bytes != need) return fail(c, TLSPH_E_INVALID_ARG, "wrong byte count");
+    if (field == TLSPH_F_TIME) {
+        HIPCHK(c, hipMemcpyAsync(c->st.t, src, need, hipMemcpyDeviceToDevice, stream));
+        return TLSPH_OK;
+    }
+    HIPCHK(c, launch_set_field(c->st, field, c->parity, c->L.mixed, src, stream));
+    return TLSPH_OK;
+}
+
+tlsph_status tlsph_neighbor_count(const tlsph_ctx* c, int64_t* nnz) {
+    if (!c || !nnz) return TLSPH_E_INVALID_ARG;
+    if (!c->built) return TLSPH_E_BAD_STATE;
+    *nnz = c->nnz;
+    return TLSPH_OK;
+}
+
+tlsph_status tlsph_get_neighbors(tlsph_ctx* c, int64_t* row_ptr, int32_t* col, hipStream_t stream) {
+    if (!c || !row_ptr || !col) return fail(c, TLSPH_E_INVALID_ARG, "null argument");
+    if (!c->built) return fail(c, TLSPH_E_BAD_STATE, "get_neighbors before build");
+    HIPCHK(c, launch_export_neighbors(c->st, row_ptr, col, nullptr, stream));
+    return TLSPH_OK;
+}
+
+tlsph_status tlsph_get_diagnostics(tlsph_ctx* c, double* spec_diag, double* bc_diag,
+                                   hipStream_t stream) {
+    if (!c || !spec_diag) return fail(c, TLSPH_E_INVALID_ARG, "null argument");
+    if (!c->built) return fail(c, TLSPH_E_BAD_STATE, "diagnostics before build");
+    HIPCHK(c, launch_diagnostics(c->st, c->parity, at<int32_t>(c, c->L.bc_list),
+                                 at<int64_t>(c, c->L.bc_ptr), spec_diag, bc_diag, stream));
+    return TLSPH_OK;
+}
+
+tlsph_status tlsph_set_bc_groups(tlsph_ctx* c, int32_t n_bc, const tlsph_bc_group* bc,
+                                 hipStream_t stream) {
+    if (!c || n_bc < 0 || n_bc > c->n_bc_cap || (n_bc > 0 && !bc))
+        return fail(c, TLSPH_E_INVALID_ARG, "bad group table");
+    for (int32_t g = 0; g < n_bc; ++g) {
+        if (bc[g].mask < 0 || bc[g].mask > 7 || !(bc[g].tau >= 0.0))
+            return fail(c, TLSPH_E_INVALID_ARG, "bad group");
+        c->bcs[g] = to_dev(bc[g]);
+    }
+    if (n_bc > 0)
+        HIPCHK(c, hipMemcpyAsync(c->ws + c->L.bcs, c->bcs.data(), n_bc * sizeof(DevBC),
+                                 hipMemcpyHostToDevice, stream));
+    return TLSPH_OK;
+}
+
+tlsph_status tlsph_enable_kernel_timing(tlsph_ctx* c, int32_t enable) {
+    if (!c) return TLSPH_E_INVALID_ARG;
+    c->timing = enable != 0;
+    return TLSPH_OK;
+}
+
+tlsph_status tlsph_kernel_times(tlsph_ctx* c, double ms[2], int64_t launches[2]) {
+    if (!c || !ms || !launches) return TLSPH_E_INVALID_ARG;
+    ms[0] = ms[1] = 0.0;
+    launches[0] = launches[1] = 0;
+    if (c->ev_used > 0) HIPCHK(c, hipEventSynchronize(c->ev_pool[c->ev_used - 1]));
+    for (auto& m : c->ev_marks) {
+        float t = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&t, c->ev_pool[m.second], c->ev_pool[m.second + 1]));
+        ms[m.first] += t;
+        launches[m.first] += 1;
+    }
+    c->ev_marks.clear();
+    c->ev_used = 0;
+    return TLSPH_OK;
+}
+
+tlsph_status tlsph_autotune(tlsph_ctx* c, hipStream_t stream) {
+    if (!c) return TLSPH_E_INVALID_ARG;
+    if (!c->built) return fail(c, TLSPH_E_BAD_STATE, "autotune before build");
+    const Layout& L = c->L;
+    uint8_t* state = c->ws + L.u0;
+    uint8_t* backup = c->ws + L.backup;
+    HIPCHK(c, hipMemcpyAsync(backup, state, L.backup_bytes, hipMemcpyDeviceToDevice, stream));
+    HIPCHK(c, hipMemcpyAsync(backup + L.backup_bytes, c->st.t, L.n_spec * 8,
+                             hipMemcpyDeviceToDevice, stream));
+    const int cand[3] = {64, 128, 256};  // the step kernels are built for <= 256 threads
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    const int reps = 5;
+    for (int pass = 0; pass < 2; ++pass) {
+        float best = 1e30f;
+        int best_b = 256;
+        for (int b : cand) {
+            // every candidate starts from the saved state
+            HIPCHK(c, hipMemcpyAsync(state, backup, L.backup_bytes, hipMemcpyDeviceToDevice,
+                                     stream));
+            hipError_t e = hipSuccess;
+            for (int r = 0; r < reps + 1 && e == hipSuccess; ++r) {
+                if (r == 1) HIPCHK(c, hipEventRecord(e0, stream));
+                e = pass == 0 ? launch_pass_b(c->st, c->parity, b, L.mixed, stream)
+                              : launch_pass_a(c->st, c->parity, b, L.mixed, stream);
+            }
+            if (e != hipSuccess) return hip_fail(c, e, "autotune launch");
+            HIPCHK(c, hipEventRecord(e1, stream));
+            HIPCHK(c, hipEventSynchronize(e1));
+            float t = 0.0f;
+            HIPCHK(c, hipEventElapsedTime(&t, e0, e1));
+            if (t < best) {
+                best = t;
+                best_b = b;
+            }
+        }
+        if (pass == 0) c->block_b = best_b; else c->block_a = best_b;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(c, hipMemcpyAsync(state, backup, L.backup_bytes, hipMemcpyDeviceToDevice, stream));
+    HIPCHK(c, hipMemcpyAsync(c->st.t, backup + L.backup_bytes, L.n_spec * 8,
+                             hipMemcpyDeviceToDevice, stream));
+    HIPCHK(c, hipStreamSynchronize(stream));
+    return TLSPH_OK;
+}
+
+tlsph_status tlsph_info(tlsph_ctx* c, int64_t out[6]) {
+    if (!c || !out) return TLSPH_E_INVALID_ARG;
+    out[0] = c->block_b;
+    out[1] = c->block_a;
+    out[2] = c->nnz;
+    out[3] = c->slots;
+    out[4] = c->L.n;
+    out[5] = 0;
+    if (c->built) {
+        int32_t fl = 0;
+        HIPCHK(c, hipMemcpy(&fl, c->ws + c->L.err + 8, 4, hipMemcpyDeviceToHost));
+        out[5] = fl;
+    }
+    return TLSPH_OK;
+}
+
+void tlsph_destroy(tlsph_ctx* c) {
+    if (!c) return;
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+}  // extern "C"

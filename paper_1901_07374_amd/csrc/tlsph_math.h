@@ -1,0 +1,397 @@
+// Device-side small-tensor helpers and the constitutive update of one
+// particle (Secs. 4-5 of de Vaucorbeil & Hutchinson, arXiv:1901.07374).
+// Tensors are row-major 3x3 (A_ab at 3a+b); symmetric ones in Voigt order
+// (xx, yy, zz, yz, xz, xy).  R is the working precision of the bulk
+// arithmetic (double for the FP64 form, float for the mixed form); the GTN
+// return mapping and every accumulator are always double.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "tlsph_internal.h"
+
+namespace tlsph {
+
+template <typename R>
+__host__ __device__ __forceinline__ R det33(const R a[9]) {
+    return a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+           a[2] * (a[3] * a[7] - a[4] * a[6]);
+}
+
+// adjugate / determinant
+template <typename R>
+__host__ __device__ __forceinline__ void inv33(const R a[9], R o[9]) {
+    const R c0 = a[4] * a[8] - a[5] * a[7];
+    const R c1 = a[5] * a[6] - a[3] * a[8];
+    const R c2 = a[3] * a[7] - a[4] * a[6];
+    const R inv = R(1) / (a[0] * c0 + a[1] * c1 + a[2] * c2);
+    o[0] = c0 * inv;
+    o[1] = (a[2] * a[7] - a[1] * a[8]) * inv;
+    o[2] = (a[1] * a[5] - a[2] * a[4]) * inv;
+    o[3] = c1 * inv;
+    o[4] = (a[0] * a[8] - a[2] * a[6]) * inv;
+    o[5] = (a[2] * a[3] - a[0] * a[5]) * inv;
+    o[6] = c2 * inv;
+    o[7] = (a[1] * a[6] - a[0] * a[7]) * inv;
+    o[8] = (a[0] * a[4] - a[1] * a[3]) * inv;
+}
+
+template <typename R>
+__host__ __device__ __forceinline__ void mm33(const R a[9], const R b[9], R o[9]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            o[3 * i + j] = a[3 * i] * b[j] + a[3 * i + 1] * b[3 + j] + a[3 * i + 2] * b[6 + j];
+}
+
+// o = a b^T
+template <typename R>
+__host__ __device__ __forceinline__ void mmT33(const R a[9], const R b[9], R o[9]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            o[3 * i + j] =
+                a[3 * i] * b[3 * j] + a[3 * i + 1] * b[3 * j + 1] + a[3 * i + 2] * b[3 * j + 2];
+}
+
+template <typename R>
+__host__ __device__ __forceinline__ void sym_from_voigt(const R s[6], R a[9]) {
+    a[0] = s[0]; a[4] = s[1]; a[8] = s[2];
+    a[5] = a[7] = s[3];
+    a[2] = a[6] = s[4];
+    a[1] = a[3] = s[5];
+}
+
+template <typename R>
+__host__ __device__ __forceinline__ void voigt_from_sym(const R a[9], R s[6]) {
+    s[0] = a[0]; s[1] = a[4]; s[2] = a[8];
+    s[3] = R(0.5) * (a[5] + a[7]);
+    s[4] = R(0.5) * (a[2] + a[6]);
+    s[5] = R(0.5) * (a[1] + a[3]);
+}
+
+// sqrt(3/2 s:s) of a deviator held in Voigt form
+template <typename R>
+__host__ __device__ __forceinline__ R mises_voigt(const R s[6]) {
+    return sqrt(R(1.5) * (s[0] * s[0] + s[1] * s[1] + s[2] * s[2] +
+                          R(2) * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5])));
+}
+
+// Cubic spline with compact support h (q = r/h < 1 for every listed pair):
+// W = c (1 - 6q^2 + 6q^3) for q < 1/2, 2c (1-q)^3 beyond; c = 8 / (pi h^3).
+template <typename R>
+__host__ __device__ __forceinline__ void spline(R r, R inv_h, R wnorm, R& W, R& dW) {
+    const R q = r * inv_h;
+    const R a = R(1) - q;
+    if (q < R(0.5)) {
+        W = wnorm * (R(1) + q * q * (R(6) * q - R(6)));
+        dW = wnorm * inv_h * (q * (R(18) * q - R(12)));
+    } else {
+        W = wnorm * R(2) * a * a * a;
+        dW = wnorm * inv_h * (R(-6) * a * a);
+    }
+}
+
+// det(I + H) - 1 without forming I + H (keeps J - 1 accurate in float)
+template <typename R>
+__host__ __device__ __forceinline__ R det_ipH_m1(const R h[9]) {
+    const R tr = h[0] + h[4] + h[8];
+    const R m2 = h[0] * h[4] - h[1] * h[3] + h[0] * h[8] - h[2] * h[6] + h[4] * h[8] - h[5] * h[7];
+    return tr + m2 + det33(h);
+}
+
+// Mie-Grueneisen (Sec. 4, eq. pH) as the pressure p (compression positive)
+// written in mu = eta - 1; the mean stress is -p.
+template <typename R>
+__host__ __device__ __forceinline__ R mg_pressure(R pref, R c0, R S, R G0, R mu) {
+    const R eta = R(1) + mu;
+    const R den = eta - S * mu;
+    return pref * c0 * c0 * mu * (eta - R(0.5) * G0 * mu) / (den * den);
+}
+
+// Mean stress from Jm1 = J - 1 (eta = 1/J).  Tension with damage uses
+// rho0 (1 - D) and eta = (1 - D)/J (decided on the undamaged value) unless
+// switched off.
+template <typename R>
+__host__ __device__ __forceinline__ R mean_stress(const DevSpec& P, R Jm1, R D, R e, bool damaged_branch) {
+    const R rho0 = R(P.rho0), c0 = R(P.c0), S = R(P.S_alpha), G0 = R(P.Gamma0);
+    const R J = R(1) + Jm1;
+    const R eterm = G0 * rho0 * e;
+    R p = mg_pressure(rho0, c0, S, G0, -Jm1 / J) + eterm;
+    if (damaged_branch && p < R(0))
+        p = mg_pressure(rho0 * (R(1) - D), c0, S, G0, -(D + Jm1) / J) + eterm;
+    return -p;
+}
+
+// Johnson-Cook flow stress, undamaged, isothermal; ln of the normalised rate
+// floored at 0.
+__host__ __device__ __forceinline__ double jc_rate_factor(const DevSpec& P, double rate) {
+    const double rs = rate / P.eps_dot0;
+    return 1.0 + P.C * log(rs > 1.0 ? rs : 1.0);
+}
+
+// Largest eigenvalue of a symmetric tensor (closed form of the cubic's roots).
+template <typename R>
+__host__ __device__ __forceinline__ R max_principal(const R s[6]) {
+    const R m = (s[0] + s[1] + s[2]) / R(3);
+    const R b0 = s[0] - m, b1 = s[1] - m, b2 = s[2] - m;
+    const R off = s[3] * s[3] + s[4] * s[4] + s[5] * s[5];
+    const R p = (b0 * b0 + b1 * b1 + b2 * b2 + R(2) * off) / R(6);
+    if (!(p > R(0))) return m;
+    const R detB = b0 * (b1 * b2 - s[3] * s[3]) - s[5] * (s[5] * b2 - s[3] * s[4]) +
+                   s[4] * (s[5] * s[3] - b1 * s[4]);
+    R rq = detB / (R(2) * p * sqrt(p));
+    rq = rq < R(-1) ? R(-1) : (rq > R(1) ? R(1) : rq);
+    const R phi = acos(rq) / R(3);
+    return m + R(2) * sqrt(p) * cos(phi);
+}
+
+__host__ __device__ __forceinline__ double gtn_fstar(const DevSpec& P, double f) {
+    if (f <= P.fc) return f;
+    if (f < P.fF) return P.fc + (1.0 / P.q1 - P.fc) / (P.fF - P.fc) * (f - P.fc);
+    return 1.0 / P.q1;
+}
+
+__host__ __device__ __forceinline__ double gtn_D(const DevSpec& P, double f) {
+    if (f >= P.fF) return 1.0;
+    const double d = P.q1 * gtn_fstar(P, f);
+    return d < 1.0 ? d : 1.0;
+}
+
+// GTN return mapping (Algorithm 2), double precision.  In: trial deviator
+// (Voigt) and trial mean stress, state (eps_M, its last rate, f), damage D.
+// Out: returned deviator and mean stress, updated eps_M, rate, f.
+__host__ __device__ inline void gtn_return(const DevSpec& P, double D, double dt, const double sdt[6],
+                                  double smt, double& epsM, double& rate, double& f,
+                                  double sd[6], double& sm, int32_t& flags) {
+    const double seq = mises_voigt(sdt);
+    const double rf = jc_rate_factor(P, rate);
+    const double sM0 = (P.A + P.B * pow(epsM, P.n)) * rf;
+    const double fs = gtn_fstar(P, f);
+    const double q1 = P.q1, q2 = P.q2, q3 = P.q3;
+    bool plastic = false;
+    double ss = 0.0;
+    if (seq >= 1e-12 * sM0) {
+        ss = smt / seq;
+        const double r = seq / sM0;
+        const double phi = r * r + 2.0 * q1 * fs * cosh(1.5 * q2 * ss * r) - (1.0 + q3 * fs * fs);
+        plastic = !(phi < 0.0);
+    }
+    if (!plastic) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) sd[k] = sdt[k];
+        sm = smt;
+        rate = 0.0;
+        return;
+    }
+    // yield ratio x = sigma_y / sigma_M: Newton from above on the convex,
+    // increasing yield function
+    double x = seq / sM0 < 1.0 ? seq / sM0 : 1.0;
+    const double kx = 1.5 * q2 * ss;
+    const double cst = 1.0 + q3 * fs * fs;
+    int it = 0;
+    for (; it < 50; ++it) {
+        const double ch = cosh(kx * x), sh = sinh(kx * x);
+        const double dx = -(x * x + 2.0 * q1 * fs * ch - cst) / (2.0 * x + 3.0 * q1 * q2 * fs * ss * sh);
+        x += dx;
+        if (fabs(dx) <= 1e-14) break;
+    }
+    if (it == 50) flags |= kErrNewton;
+    // matrix plastic strain increment: d = c (seq - x sigma_f(eps_M + d))
+    const double shx = sinh(kx * x);
+    const double c = (x + 1.5 * q1 * q2 * f * ss * shx) / (3.0 * P.G * (1.0 - D) * (1.0 - f));
+    double dem = c * (seq - x * sM0);
+    for (it = 0; it < 50; ++it) {
+        const double e1 = epsM + dem;
+        const double hard = (e1 > 0.0) ? P.B * P.n * pow(e1, P.n - 1.0) * rf : 0.0;
+        const double sf = (P.A + P.B * pow(e1, P.n)) * rf;
+        const double g = dem - c * (seq - x * sf);
+        double nx = dem - g / (1.0 + c * x * hard);
+        if (nx < 0.0) nx = 0.5 * dem;
+        const double stp = nx - dem;
+        dem = nx;
+        if (fabs(stp) <= 1e-14 * (dem > 1e-12 ? dem : 1e-12)) break;
+    }
+    if (it == 50) flags |= kErrNewton;
+    epsM += dem;
+    const double sM = (P.A + P.B * pow(epsM, P.n)) * rf;
+    const double sy = x * sM;
+    const double scale = sy / seq;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sd[k] = scale * sdt[k];
+    // mean stress returned at constant triaxiality
+    sm = smt - ss * (seq - sy);
+    const double alpha = 1.5 * (sM / sy) * q1 * q2 * f * shx;
+    // omega of the returned stress: 1 - (27 det(s_d) / (2 s_eq^3))^2
+    const double detd = sd[0] * (sd[1] * sd[2] - sd[3] * sd[3]) -
+                        sd[5] * (sd[5] * sd[2] - sd[3] * sd[4]) +
+                        sd[4] * (sd[5] * sd[3] - sd[1] * sd[4]);
+    double om = 0.0;
+    if (sy > 0.0) {
+        const double xi = 27.0 * detd / (2.0 * sy * sy * sy);
+        om = 1.0 - xi * xi;
+        om = om < 0.0 ? 0.0 : (om > 1.0 ? 1.0 : om);
+    }
+    const double z = (epsM - P.eN) / P.sN;
+    const double AN = P.fN / (P.sN * 2.5066282746310002) * exp(-0.5 * z * z);
+    f = f + AN * dem +
+        (1.0 - f) / (alpha * ss + 1.0) * (sM / sy) * (alpha * (1.0 - f) + f * P.k_omega * om) * dem;
+    rate = dem / dt;
+}
+
+// Result of the constitutive update of one particle.
+template <typename R>
+struct PointOut {
+    R H[9];      // F^{n+1} - I
+    R sig[6];    // Cauchy stress (Voigt)
+    R P[9];      // first Piola-Kirchhoff stress
+    double D;    // D^{n+1}
+};
+
+// Constitutive and damage update of one particle over one step (Secs. 4-5).
+// In: Hn = F^n - I, Fd = dF/dt, sn = sigma^n (Voigt).  Kinematics from dF/dt
+// and the midpoint F, Hughes-Winget rotation of the deviator, Mie-Grueneisen
+// mean stress, Johnson-Cook radial return (Algorithm 1) or GTN (Algorithm 2),
+// Cockcroft-Latham / Johnson-Cook initiation and evolution (Secs. 5.1-5.3),
+// failed particles stress free, energy by the trapezoid rule on P,
+// P = J sigma F^-T.
+template <typename R>
+__host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R Hn[9], const R Fd[9],
+                                             const R sn[6], double& eps, double& rate,
+                                             double& dinit, double& wp, double& fv, double& e,
+                                             double D, PointOut<R>& o, int32_t& flags) {
+    const R dt = R(P.dt);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) o.H[k] = Hn[k] + dt * Fd[k];
+    if (D >= 1.0) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) o.sig[k] = R(0);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) o.P[k] = R(0);
+        o.D = 1.0;
+        return;
+    }
+    R Fb[9], Fbi[9], l[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Fb[k] = R(0.5) * (Hn[k] + o.H[k]);
+    Fb[0] += R(1); Fb[4] += R(1); Fb[8] += R(1);
+    inv33(Fb, Fbi);
+    mm33(Fd, Fbi, l);
+    const R Jm1 = det_ipH_m1(o.H);
+    const R J = R(1) + Jm1;
+    // rate of deformation (Voigt) and spin
+    R d6[6] = {l[0], l[4], l[8], R(0.5) * (l[5] + l[7]), R(0.5) * (l[2] + l[6]),
+               R(0.5) * (l[1] + l[3])};
+    const R w01 = R(0.5) * (l[1] - l[3]), w02 = R(0.5) * (l[2] - l[6]), w12 = R(0.5) * (l[5] - l[7]);
+    // stored deviator, rotated by R = (I - dt/2 w)^-1 (I + dt/2 w)
+    const R smn = (sn[0] + sn[1] + sn[2]) / R(3);
+    R Sd[9];
+    {
+        R s6[6] = {sn[0] - smn, sn[1] - smn, sn[2] - smn, sn[3], sn[4], sn[5]};
+        sym_from_voigt(s6, Sd);
+    }
+    {
+        const R hd = R(0.5) * dt;
+        R Am[9] = {R(1), -hd * w01, -hd * w02, hd * w01, R(1), -hd * w12, hd * w02, hd * w12, R(1)};
+        R Bm[9] = {R(1), hd * w01, hd * w02, -hd * w01, R(1), hd * w12, -hd * w02, -hd * w12, R(1)};
+        R Ai[9], Rm[9], T[9], Sr[9];
+        inv33(Am, Ai);
+        mm33(Ai, Bm, Rm);
+        mm33(Rm, Sd, T);
+        mmT33(T, Rm, Sr);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Sd[k] = Sr[k];
+    }
+    // deviatoric strain increment
+    const R trd = (d6[0] + d6[1] + d6[2]) / R(3);
+    const R de[6] = {(d6[0] - trd) * dt, (d6[1] - trd) * dt, (d6[2] - trd) * dt,
+                     d6[3] * dt, d6[4] * dt, d6[5] * dt};
+    R sdr[6];
+    voigt_from_sym(Sd, sdr);
+    const R G = R(P.G);
+    const R omD = R(1.0 - D);
+    R sd[6], sm;
+    double Dn = D;
+    if (P.damage == 3) {
+        double sdt[6], sdo[6], smo;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) sdt[k] = double(sdr[k] + R(2) * G * omD * de[k]);
+        const double smt = double(mean_stress<R>(P, Jm1, R(D), R(e), false));
+        gtn_return(P, D, P.dt, sdt, smt, eps, rate, fv, sdo, smo, flags);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) sd[k] = R(sdo[k]);
+        sm = R(smo);
+        Dn = gtn_D(P, fv);
+    } else {
+        sm = mean_stress<R>(P, Jm1, R(D), R(e), true);
+        R st[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) st[k] = sdr[k] + R(2) * G * omD * de[k];
+        const R seq = mises_voigt(st);
+        const R sf = R((P.A + P.B * pow(eps, P.n)) * jc_rate_factor(P, rate)) * omD;
+        R dep = R(0);
+        if (seq < sf) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) sd[k] = st[k];
+        } else {
+            dep = (seq - sf) / (R(3) * G * omD);
+            const R sc = sf / seq;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) sd[k] = sc * st[k];
+        }
+        eps += double(dep);
+        rate = double(dep) / P.dt;
+        if (dep > R(0) && (P.damage == 1 || P.damage == 2)) {
+            if (P.damage == 2) {
+                const R sstar = sm / mises_voigt(sd);
+                const double ef = (P.D1 + P.D2 * exp(P.D3 * double(sstar))) *
+                                  pow(1.0 + rate / P.eps_dot0, P.D4);
+                dinit += double(dep) / ef;
+            } else {
+                R full6[6] = {sd[0] + sm, sd[1] + sm, sd[2] + sm, sd[3], sd[4], sd[5]};
+                const R s1 = max_principal(full6);
+                wp += double(s1 > R(0) ? s1 : R(0)) * double(dep);
+                dinit = wp / P.Wcr;
+            }
+            double dn = 10.0 * (dinit - 1.0);
+            Dn = dn < 0.0 ? 0.0 : (dn > 1.0 ? 1.0 : dn);
+        }
+    }
+    o.D = Dn;
+    if (Dn >= 1.0) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) o.sig[k] = R(0);
+    } else {
+        o.sig[0] = sd[0] + sm; o.sig[1] = sd[1] + sm; o.sig[2] = sd[2] + sm;
+        o.sig[3] = sd[3]; o.sig[4] = sd[4]; o.sig[5] = sd[5];
+    }
+    // P^{n+1} = J sigma F^{-T}
+    R S1[9], F1[9], Fi[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) F1[k] = o.H[k];
+    F1[0] += R(1); F1[4] += R(1); F1[8] += R(1);
+    sym_from_voigt(o.sig, S1);
+    inv33(F1, Fi);
+    mmT33(S1, Fi, o.P);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) o.P[k] *= J;
+    // energy per unit mass: dF/dt : (P^n + P^{n+1}) / 2 / rho0
+    R S0[9], F0[9], F0i[9], P0[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) F0[k] = Hn[k];
+    F0[0] += R(1); F0[4] += R(1); F0[8] += R(1);
+    sym_from_voigt(sn, S0);
+    inv33(F0, F0i);
+    mmT33(S0, F0i, P0);
+    const R J0 = R(1) + det_ipH_m1(Hn);
+    R work = R(0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) work += Fd[k] * (J0 * P0[k] + o.P[k]);
+    e += double(P.dt) * double(R(0.5) * work) / P.rho0;
+}
+
+}  // namespace tlsph

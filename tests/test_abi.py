@@ -1,0 +1,108 @@
+"""The C-ABI library loads, exports every entry point include/tlsph.h
+declares, and rejects bad arguments before any HIP call (host only)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1901_07374_amd import inputs as I
+from paper_1901_07374_amd import tlsph
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tlsph.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tlsph_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(tlsph.LIB_PATH):
+        pytest.skip("libtlsph.so not built")
+    return tlsph.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared()
+    assert len(names) >= 16
+    out = subprocess.run(["nm", "-D", "--defined-only", tlsph.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (tlsph_\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert hasattr(L, n)
+
+
+def test_library_targets_gfx950():
+    # the library built here embeds a code object for gfx950 only
+    data = open(tlsph.LIB_PATH, "rb").read()
+    assert b"amdgcn-amd-amdhsa--gfx950" in data
+    assert b"gfx942" not in data and b"gfx90a" not in data
+
+
+def test_status_strings(L):
+    assert L.tlsph_status_string(0) == b"ok"
+    assert L.tlsph_status_string(6) == b"neighbour capacity exceeded"
+
+
+def test_workspace_bytes_validation(L):
+    b = C.c_size_t()
+    assert L.tlsph_workspace_bytes(1000, 1, 2, 32, 0, C.byref(b)) == 0 and b.value > 1000 * 500
+    fp64 = b.value
+    assert L.tlsph_workspace_bytes(1000, 1, 2, 32, 1, C.byref(b)) == 0 and b.value < fp64
+    for args in [(0, 1, 0, 32, 0), (10, 0, 0, 32, 0), (10, 1, -1, 32, 0), (10, 1, 0, 0, 0),
+                 (10, 1, 0, 513, 0), (10, 1, 0, 32, 7), (10, 11, 0, 32, 0)]:
+        assert L.tlsph_workspace_bytes(*args, C.byref(b)) == 1, args
+    assert L.tlsph_workspace_bytes(10, 1, 0, 32, 0, None) == 1
+
+
+def _create(L, prob, ws=256 * 1024, nbytes=None, offs=None, mats=None, flags=0, k_cap=32):
+    specs = (tlsph.Specimen * prob.n_spec)(*[tlsph.specimen_struct(m) for m in (mats or prob.materials)])
+    nb = max(len(prob.bc_groups), 1)
+    bcs = (tlsph.BCGroup * nb)(*[tlsph.bc_struct(g) for g in prob.bc_groups])
+    o = np.ascontiguousarray(prob.spec_offsets if offs is None else offs, np.int64)
+    need = tlsph.workspace_bytes(prob.n, prob.n_spec, len(prob.bc_groups), k_cap, 0)
+    ctx = C.c_void_p()
+    st = L.tlsph_create(prob.n, prob.n_spec, o.ctypes.data, specs, len(prob.bc_groups), bcs, 0,
+                        k_cap, flags, ws, need if nbytes is None else nbytes, None, C.byref(ctx))
+    return st, ctx
+
+
+def test_create_rejects_bad_arguments_without_hip(L):
+    p = I.cube(nside=4)
+    # workspace pointer: never dereferenced on these paths
+    assert _create(L, p, ws=None)[0] == 1
+    assert _create(L, p, ws=256 * 1024 + 8)[0] == 1                 # misaligned
+    assert _create(L, p, nbytes=1024)[0] == 1                         # too small
+    assert _create(L, p, offs=[0, p.n - 1])[0] == 1                   # offsets do not cover n
+    assert _create(L, p, flags=64)[0] == 1
+    bad = dict(p.materials[0])
+    for k, v in [("rho0", 0.0), ("E", -1.0), ("nu", 0.5), ("h", 0.0), ("dt", float("nan")),
+                 ("damage", 9), ("eps_dot0", 0.0)]:
+        m = dict(bad, **{k: v})
+        assert _create(L, p, mats=[m])[0] == 1, k
+    cl = dict(bad, damage=I.DMG_CL, Wcr=0.0)
+    assert _create(L, p, mats=[cl])[0] == 1
+    wall = dict(bad, has_wall=1, wall_n=(0.0, 0.0, 2.0))
+    assert _create(L, p, mats=[wall])[0] == 1
+    q = I.Problem(p.name, p.X, p.V0, p.spec_offsets, p.materials, p.bc_group,
+                  [I.bc_group(9)], p.v_init)
+    assert _create(L, q)[0] == 1
+
+
+def test_null_context_calls(L):
+    assert L.tlsph_step(None, 1, None) == 1
+    assert L.tlsph_get_state(None, 1, None, 0, None) == 1
+    assert L.tlsph_set_state(None, 1, None, 0, None) == 1
+    assert L.tlsph_build_neighbors(None, None, None, None, None) == 1
+    assert L.tlsph_autotune(None, None) == 1
+    assert L.tlsph_info(None, None) == 1
+    L.tlsph_destroy(None)
+    assert L.tlsph_last_error(None) == b""
