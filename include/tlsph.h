@@ -216,12 +216,13 @@ tlsph_status tlsph_set_bc_groups(tlsph_ctx *ctx, int32_t n_bc, const tlsph_bc_gr
  * Synchronises.  Errors: BAD_STATE, HIP. */
 tlsph_status tlsph_autotune(tlsph_ctx *ctx, hipStream_t stream);
 
-/* Per-kernel timing with HIP events recorded on the stream around every
- * launch of the two step kernels while enabled (not with TLSPH_USE_GRAPHS).
- * tlsph_kernel_times synchronises on the last event and returns the summed
- * milliseconds and launch counts of the force pass (index 0) and the
- * deformation/constitutive pass (index 1), then clears them. */
-tlsph_status tlsph_enable_kernel_timing(tlsph_ctx *ctx, int32_t enable);
+/* Per-kernel timing with HIP events recorded on the stream around both step
+ * kernels of every stride-th step (stride 0 switches timing off; steps then
+ * run without graphs).  tlsph_kernel_times synchronises on the last event
+ * and returns the summed milliseconds and launch counts of the force pass
+ * (index 0) and the deformation/constitutive pass (index 1), then clears
+ * them.  Errors: INVALID_ARG (stride < 0), HIP. */
+tlsph_status tlsph_enable_kernel_timing(tlsph_ctx *ctx, int32_t stride);
 tlsph_status tlsph_kernel_times(tlsph_ctx *ctx, double ms[2], int64_t launches[2]);
 
 /* Launch shape and layout facts: [0] threads per block of the force pass,

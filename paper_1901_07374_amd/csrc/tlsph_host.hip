@@ -34,10 +34,10 @@ struct Layout {
     int64_t n, np, n_pow2, n_slices;
     int32_t n_spec, n_bc, k_cap;
     bool mixed;
-    size_t X, V0, spec, bc, perm, iperm, nnb, slice_ptr, col, Linv, Linv32, specs, bcs, t;
-    size_t u0, u1, v, F, H, sig, sig32, Q, Q32, eps_p, eps_rate, d_init, w_p, f_void, e, D0, D1,
-        force, err, spec_off, bbox, keys, vals, bc_list, bc_ptr, backup, readback;
-    size_t backup_bytes;
+    size_t XV, spec, bc, perm, iperm, nnb, slice_ptr, col, Linv, Linv32, specs, bcs, t;
+    size_t GB, U0, U1, VW, sig, eps_p, eps_rate, d_init, w_p, f_void, e, D, force, err,
+        spec_off, bbox, keys, vals, bc_list, bc_ptr, backup;
+    size_t state_begin, backup_bytes;
     size_t total;
 };
 
@@ -58,8 +58,7 @@ Layout make_layout(int64_t n, int32_t n_spec, int32_t n_bc, int32_t k_cap, bool 
         return o;
     };
     const size_t np = (size_t)L.np;
-    L.X = take(3 * np * 8);
-    L.V0 = take(np * 8);
+    L.XV = take(np * sizeof(D4));
     L.spec = take(np * 4);
     L.bc = take(np * 4);
     L.perm = take(np * 4);
@@ -72,27 +71,22 @@ Layout make_layout(int64_t n, int32_t n_spec, int32_t n_bc, int32_t k_cap, bool 
     L.specs = take((size_t)n_spec * sizeof(DevSpec));
     L.bcs = take((size_t)(n_bc > 0 ? n_bc : 1) * sizeof(DevBC));
     L.t = take((size_t)n_spec * 8);
-    // evolving state, contiguous from u0 to force (saved/restored by autotune)
-    const size_t state_begin = align_up(cur);
-    L.u0 = take(3 * np * 8);
-    L.u1 = take(3 * np * 8);
-    L.v = take(3 * np * 8);
-    L.F = take(mixed ? 0 : 9 * np * 8);
-    L.H = take(mixed ? 9 * np * 4 : 0);
-    L.sig = take(mixed ? 0 : 6 * np * 8);
-    L.sig32 = take(mixed ? 6 * np * 4 : 0);
-    L.Q = take(mixed ? 0 : 9 * np * 8);
-    L.Q32 = take(mixed ? 9 * np * 4 : 0);
+    // evolving state, contiguous (saved and restored by the autotuner)
+    L.state_begin = align_up(cur);
+    L.GB = take(np * (mixed ? sizeof(GBRec<float>) : sizeof(GBRec<double>)));
+    L.U0 = take(np * sizeof(D4));
+    L.U1 = take(np * sizeof(D4));
+    L.VW = take(np * sizeof(D4));
+    L.sig = take(6 * np * (mixed ? 4 : 8));
     L.eps_p = take(np * 8);
     L.eps_rate = take(np * 8);
     L.d_init = take(np * 8);
     L.w_p = take(np * 8);
     L.f_void = take(np * 8);
     L.e = take(np * 8);
-    L.D0 = take(np * 8);
-    L.D1 = take(np * 8);
+    L.D = take(np * 8);
     L.force = take(3 * np * 8);
-    L.backup_bytes = align_up(cur) - state_begin;
+    L.backup_bytes = align_up(cur) - L.state_begin;
     L.err = take(8 * 4);
     L.spec_off = take(((size_t)n_spec + 1) * 8);
     L.bbox = take((size_t)n_spec * 6 * 8);
@@ -100,7 +94,6 @@ Layout make_layout(int64_t n, int32_t n_spec, int32_t n_bc, int32_t k_cap, bool 
     L.vals = take((size_t)L.n_pow2 * 4);
     L.bc_list = take(np * 4);
     L.bc_ptr = take(((size_t)n_bc + 2) * 8);
-    L.readback = take(64);
     L.backup = take(L.backup_bytes + (size_t)n_spec * 8);
     L.total = align_up(cur);
     return L;
@@ -124,8 +117,10 @@ struct tlsph_ctx {
     int64_t nnz = 0, slots = 0;
     int block_a = 256, block_b = 256;
     std::string last_error;
-    // per-kernel timing
+    // per-kernel timing (every timing_stride-th step while enabled)
     bool timing = false;
+    int32_t timing_stride = 1;
+    int64_t step_count = 0;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<std::pair<int, size_t>> ev_marks;  // (kernel, index of start event)
@@ -166,8 +161,7 @@ void wire_state(tlsph_ctx* c) {
     s.n_spec = L.n_spec;
     s.n_bc = c->n_bc_cap;
     s.flags = c->flags;
-    s.X = at<double>(c, L.X);
-    s.V0 = at<double>(c, L.V0);
+    s.XV = at<D4>(c, L.XV);
     s.spec = at<int32_t>(c, L.spec);
     s.bc = at<int32_t>(c, L.bc);
     s.perm = at<int32_t>(c, L.perm);
@@ -181,23 +175,20 @@ void wire_state(tlsph_ctx* c) {
     s.specs = at<DevSpec>(c, L.specs);
     s.bcs = at<DevBC>(c, L.bcs);
     s.t = at<double>(c, L.t);
-    s.u[0] = at<double>(c, L.u0);
-    s.u[1] = at<double>(c, L.u1);
-    s.v = at<double>(c, L.v);
-    s.F = L.mixed ? nullptr : at<double>(c, L.F);
-    s.H = L.mixed ? at<float>(c, L.H) : nullptr;
+    s.GB = L.mixed ? nullptr : at<GBRec<double>>(c, L.GB);
+    s.GB32 = L.mixed ? at<GBRec<float>>(c, L.GB) : nullptr;
+    s.U[0] = at<D4>(c, L.U0);
+    s.U[1] = at<D4>(c, L.U1);
+    s.VW = at<D4>(c, L.VW);
     s.sig = L.mixed ? nullptr : at<double>(c, L.sig);
-    s.sig32 = L.mixed ? at<float>(c, L.sig32) : nullptr;
-    s.Q = L.mixed ? nullptr : at<double>(c, L.Q);
-    s.Q32 = L.mixed ? at<float>(c, L.Q32) : nullptr;
+    s.sig32 = L.mixed ? at<float>(c, L.sig) : nullptr;
     s.eps_p = at<double>(c, L.eps_p);
     s.eps_rate = at<double>(c, L.eps_rate);
     s.d_init = at<double>(c, L.d_init);
     s.w_p = at<double>(c, L.w_p);
     s.f_void = at<double>(c, L.f_void);
     s.e = at<double>(c, L.e);
-    s.D[0] = at<double>(c, L.D0);
-    s.D[1] = at<double>(c, L.D1);
+    s.D = at<double>(c, L.D);
     s.force = at<double>(c, L.force);
     s.err = at<int32_t>(c, L.err);
 }
@@ -223,9 +214,10 @@ hipEvent_t next_event(tlsph_ctx* c) {
 tlsph_status run_steps_eager(tlsph_ctx* c, int32_t n_steps, hipStream_t stream) {
     const bool mixed = c->L.mixed;
     for (int32_t k = 0; k < n_steps; ++k) {
+        const bool timed = c->timing && (c->step_count++ % c->timing_stride) == 0;
         for (int pass = 0; pass < 2; ++pass) {
             hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (c->timing) {
+            if (timed) {
                 const size_t idx = c->ev_used;
                 e0 = next_event(c);
                 e1 = next_event(c);
@@ -236,7 +228,7 @@ tlsph_status run_steps_eager(tlsph_ctx* c, int32_t n_steps, hipStream_t stream) 
             hipError_t e = pass == 0 ? launch_pass_b(c->st, c->parity, c->block_b, mixed, stream)
                                      : launch_pass_a(c->st, c->parity, c->block_a, mixed, stream);
             if (e != hipSuccess) return hip_fail(c, e, pass == 0 ? "force pass" : "deformation pass");
-            if (c->timing) HIPCHK(c, hipEventRecord(e1, stream));
+            if (timed) HIPCHK(c, hipEventRecord(e1, stream));
         }
         c->parity ^= 1;
     }
@@ -551,9 +543,11 @@ tlsph_status tlsph_set_bc_groups(tlsph_ctx* c, int32_t n_bc, const tlsph_bc_grou
     return TLSPH_OK;
 }
 
-tlsph_status tlsph_enable_kernel_timing(tlsph_ctx* c, int32_t enable) {
-    if (!c) return TLSPH_E_INVALID_ARG;
-    c->timing = enable != 0;
+tlsph_status tlsph_enable_kernel_timing(tlsph_ctx* c, int32_t stride) {
+    if (!c || stride < 0) return TLSPH_E_INVALID_ARG;
+    c->timing = stride > 0;
+    c->timing_stride = stride > 0 ? stride : 1;
+    c->step_count = 0;
     return TLSPH_OK;
 }
 
@@ -577,7 +571,7 @@ tlsph_status tlsph_autotune(tlsph_ctx* c, hipStream_t stream) {
     if (!c) return TLSPH_E_INVALID_ARG;
     if (!c->built) return fail(c, TLSPH_E_BAD_STATE, "autotune before build");
     const Layout& L = c->L;
-    uint8_t* state = c->ws + L.u0;
+    uint8_t* state = c->ws + L.state_begin;
     uint8_t* backup = c->ws + L.backup;
     HIPCHK(c, hipMemcpyAsync(backup, state, L.backup_bytes, hipMemcpyDeviceToDevice, stream));
     HIPCHK(c, hipMemcpyAsync(backup + L.backup_bytes, c->st.t, L.n_spec * 8,

@@ -39,15 +39,32 @@ struct DevBC {
     double grad[9];
 };
 
-// Device pointers of one context (all per-particle arrays in Morton order with
-// stride np, a multiple of kSlice; component c of a field at [c * np + i]).
+// Records read through neighbour gathers (array-of-structures, 16-byte
+// aligned so a record arrives in a few 128-bit loads).
+struct alignas(16) D4 {
+    double x, y, z, w;
+};
+
+// What the force pass gathers from a neighbour besides geometry: Q = P L^-T,
+// H = F - I and 1 - D.  R is the storage precision (double, or float in the
+// mixed form).
+template <typename R>
+struct alignas(16) GBRec {
+    R q[9];
+    R h[9];
+    R omd;
+    R pad;
+};
+
+// Device pointers of one context.  Per-particle data is in Morton order;
+// SoA fields have stride np (a multiple of kSlice), component c of particle
+// i at [c * np + i]; AoS records are indexed by particle.
 struct DevState {
     int64_t n, np;
     int32_t n_spec, n_bc;
     uint32_t flags;
     int32_t pad_;
-    const double* X;
-    const double* V0;
+    const D4* XV;            // reference position and volume (x, y, z, V0)
     const int32_t* spec;
     const int32_t* bc;
     const int32_t* perm;     // sorted -> caller
@@ -56,27 +73,25 @@ struct DevState {
     const int64_t* slice_ptr;
     const int32_t* col;
     int64_t col_cap;         // entries of col (k_cap * np)
-    const double* Linv;
-    const float* Linv32;
+    const double* Linv;      // SoA [9][np]
+    const float* Linv32;     // mixed form copy
     const DevSpec* specs;
     const DevBC* bcs;
     double* t;
-    double* u[2];
-    double* v;
-    double* F;       // FP64 form
-    float* H;        // mixed form: F - I
-    double* sig;     // FP64 form, Voigt
-    float* sig32;    // mixed form
-    double* Q;       // FP64 form
-    float* Q32;      // mixed form
+    D4* U[2];                // displacement (x, y, z, 0), two buffers
+    D4* VW;                  // half-step velocity and V0 (1 - D) (x, y, z, w)
+    GBRec<double>* GB;       // FP64 form
+    GBRec<float>* GB32;      // mixed form
+    double* sig;             // FP64 form, SoA Voigt
+    float* sig32;            // mixed form
     double* eps_p;
     double* eps_rate;
     double* d_init;
     double* w_p;
     double* f_void;
     double* e;
-    double* D[2];
-    double* force;
+    double* D;
+    double* force;           // SoA [3][np]
     int32_t* err;    // [0] first singular (sorted), [1] max count, [2] sticky flags,
                      // [3] build status
 };

@@ -116,18 +116,17 @@ __global__ void k_bitonic(uint64_t* __restrict__ keys, int32_t* __restrict__ val
 __global__ void k_apply_perm(DevState s, const double* __restrict__ X_in,
                              const double* __restrict__ V0_in, const int32_t* __restrict__ bc_in,
                              const uint64_t* __restrict__ keys, const int32_t* __restrict__ vals,
-                             double* __restrict__ Xs, double* __restrict__ V0s,
-                             int32_t* __restrict__ specs_out, int32_t* __restrict__ bcs,
-                             int32_t* __restrict__ perm, int32_t* __restrict__ iperm) {
+                             D4* __restrict__ XV, int32_t* __restrict__ specs_out,
+                             int32_t* __restrict__ bcs, int32_t* __restrict__ perm,
+                             int32_t* __restrict__ iperm) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= s.np) return;
-    const int64_t n = s.n, np = s.np;
+    const int64_t n = s.n;
     if (p < n) {
         const int32_t o = vals[p];
         perm[p] = o;
         iperm[o] = (int32_t)p;
-        for (int c = 0; c < 3; ++c) Xs[c * np + p] = X_in[c * n + o];
-        V0s[p] = V0_in[o];
+        XV[p] = D4{X_in[o], X_in[n + o], X_in[2 * n + o], V0_in[o]};
         int32_t g = bc_in[o];
         if (g < -1 || g >= s.n_bc) {  // reported as an argument error by the host
             atomicOr(&s.err[3], 2);
@@ -137,8 +136,7 @@ __global__ void k_apply_perm(DevState s, const double* __restrict__ X_in,
         specs_out[p] = (int32_t)(keys[p] >> kSpecShift);
     } else {
         perm[p] = -1;
-        for (int c = 0; c < 3; ++c) Xs[c * np + p] = 0.0;
-        V0s[p] = 0.0;
+        XV[p] = D4{0.0, 0.0, 0.0, 0.0};
         bcs[p] = -1;
         specs_out[p] = 0;
     }
@@ -171,8 +169,8 @@ __device__ __forceinline__ int for_neighbours(const DevState& s, const uint64_t*
 #pragma clang fp contract(off)
     const int sp = s.spec[p];
     const DevSpec& P = s.specs[sp];
-    const int64_t np = s.np;
-    const double xi = s.X[p], yi = s.X[np + p], zi = s.X[2 * np + p];
+    const D4 xp = s.XV[p];
+    const double xi = xp.x, yi = xp.y, zi = xp.z;
     int32_t c[3];
     cell_of(P, bbox + 6 * sp, xi, yi, zi, c);
     int count = 0;
@@ -191,9 +189,10 @@ __device__ __forceinline__ int for_neighbours(const DevState& s, const uint64_t*
                 }
                 for (int64_t q = lo; q < P.last && keys[q] == key; ++q) {
                     if (q == p) continue;
-                    const double d0 = s.X[q] - xi;
-                    const double d1 = s.X[np + q] - yi;
-                    const double d2 = s.X[2 * np + q] - zi;
+                    const D4 xq = s.XV[q];
+                    const double d0 = xq.x - xi;
+                    const double d1 = xq.y - yi;
+                    const double d2 = xq.z - zi;
                     const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
                     if (r2 < P.h2) visit(count++, (int32_t)q);
                 }
@@ -275,17 +274,18 @@ __global__ void k_shape(DevState s, double* __restrict__ Linv, float* __restrict
     }
     if (s.slice_ptr[np / kSlice] > s.col_cap) return;  // list did not fit: never read col
     const DevSpec& P = s.specs[s.spec[p]];
-    const double xi = s.X[p], yi = s.X[np + p], zi = s.X[2 * np + p];
+    const D4 xp = s.XV[p];
     double L[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int cnt = s.nnb[p];
     const int32_t* cp = s.col + s.slice_ptr[p / kSlice] + (p % kSlice);
     for (int k = 0; k < cnt; ++k) {
         const int32_t j = cp[(int64_t)k * kSlice];
-        const double d[3] = {s.X[j] - xi, s.X[np + j] - yi, s.X[2 * np + j] - zi};
+        const D4 xj = s.XV[j];
+        const double d[3] = {xj.x - xp.x, xj.y - xp.y, xj.z - xp.z};
         const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         double W, dW;
         spline(r, P.inv_h, P.wnorm, W, dW);
-        const double g = s.V0[j] * dW / r;
+        const double g = xj.w * dW / r;
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) L[3 * a + b] += d[a] * g * d[b];
     }
@@ -314,17 +314,23 @@ __global__ void k_init(DevState s) {
     if (p >= s.np) return;
     const int64_t np = s.np;
     const DevSpec& P = s.specs[s.spec[p]];
-    for (int c = 0; c < 3; ++c) {
-        s.u[0][c * np + p] = 0.0;
-        s.u[1][c * np + p] = 0.0;
-        s.v[c * np + p] = 0.0;
-        s.force[c * np + p] = 0.0;
-    }
-    for (int k = 0; k < 9; ++k) {
-        if (s.F) s.F[k * np + p] = (k % 4 == 0) ? 1.0 : 0.0;
-        if (s.H) s.H[k * np + p] = 0.0f;
-        if (s.Q) s.Q[k * np + p] = 0.0;
-        if (s.Q32) s.Q32[k * np + p] = 0.0f;
+    const double D0 = (P.damage == 3) ? gtn_D(P, P.f0) : 0.0;
+    s.U[0][p] = D4{0.0, 0.0, 0.0, 0.0};
+    s.U[1][p] = D4{0.0, 0.0, 0.0, 0.0};
+    s.VW[p] = D4{0.0, 0.0, 0.0, s.XV[p].w * (1.0 - D0)};
+    for (int c = 0; c < 3; ++c) s.force[c * np + p] = 0.0;
+    if (s.GB) {
+        GBRec<double> g;
+        for (int k = 0; k < 9; ++k) { g.q[k] = 0.0; g.h[k] = 0.0; }
+        g.omd = 1.0 - D0;
+        g.pad = 0.0;
+        s.GB[p] = g;
+    } else {
+        GBRec<float> g;
+        for (int k = 0; k < 9; ++k) { g.q[k] = 0.0f; g.h[k] = 0.0f; }
+        g.omd = (float)(1.0 - D0);
+        g.pad = 0.0f;
+        s.GB32[p] = g;
     }
     for (int k = 0; k < 6; ++k) {
         if (s.sig) s.sig[k * np + p] = 0.0;
@@ -336,9 +342,7 @@ __global__ void k_init(DevState s) {
     s.w_p[p] = 0.0;
     s.e[p] = 0.0;
     s.f_void[p] = P.f0;
-    const double D0 = (P.damage == 3) ? gtn_D(P, P.f0) : 0.0;
-    s.D[0][p] = D0;
-    s.D[1][p] = D0;
+    s.D[p] = D0;
 }
 
 hipError_t launch_build_count(DevState& s, const BuildBuffers& b, hipStream_t st) {
@@ -353,9 +357,9 @@ hipError_t launch_build_count(DevState& s, const BuildBuffers& b, hipStream_t st
                                                                         j, k);
     const unsigned gp = (unsigned)((s.np + T - 1) / T);
     k_apply_perm<<<gp, T, 0, st>>>(s, b.X_in, b.V0_in, b.bc_in, b.keys, b.vals,
-                                   const_cast<double*>(s.X), const_cast<double*>(s.V0),
-                                   const_cast<int32_t*>(s.spec), const_cast<int32_t*>(s.bc),
-                                   const_cast<int32_t*>(s.perm), const_cast<int32_t*>(s.iperm));
+                                   const_cast<D4*>(s.XV), const_cast<int32_t*>(s.spec),
+                                   const_cast<int32_t*>(s.bc), const_cast<int32_t*>(s.perm),
+                                   const_cast<int32_t*>(s.iperm));
     k_spec_ranges<<<(s.n_spec + 63) / 64, 64, 0, st>>>(const_cast<DevSpec*>(s.specs), s.n_spec,
                                                       b.keys, s.n);
     k_count<<<gp, T, 0, st>>>(s, b.keys, b.bbox, const_cast<int32_t*>(s.nnb));
@@ -385,30 +389,22 @@ hipError_t launch_shape_and_init(const DevState& s, bool mixed, hipStream_t st) 
 // the step
 // ===========================================================================
 
-template <typename R>
-__device__ __forceinline__ void load_tensor9(const DevState& s, int64_t i, R out[9]) {
-    const int64_t np = s.np;
-    if constexpr (std::is_same<R, float>::value) {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) out[k] = s.H[k * np + i];
-    } else {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) out[k] = s.F[k * np + i];
-        out[0] -= 1.0; out[4] -= 1.0; out[8] -= 1.0;
-    }
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Give XCD x a contiguous run of tiles instead, so the neighbour halos
+// of Morton-adjacent tiles are shared through one L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nblk) {
+    constexpr int64_t kXcd = 8;
+    const int64_t q = nblk / kXcd, r = nblk % kXcd;
+    const int64_t x = b % kXcd, k = b / kXcd;
+    return x * q + (x < r ? x : r) + k;
 }
 
 template <typename R>
-__device__ __forceinline__ void load_Q(const DevState& s, int64_t i, R out[9]) {
-    const int64_t np = s.np;
-    if constexpr (std::is_same<R, float>::value) {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) out[k] = s.Q32[k * np + i];
-    } else {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) out[k] = s.Q[k * np + i];
-    }
-}
+__device__ __forceinline__ const GBRec<R>* gb_of(const DevState& s);
+template <>
+__device__ __forceinline__ const GBRec<double>* gb_of<double>(const DevState& s) { return s.GB; }
+template <>
+__device__ __forceinline__ const GBRec<float>* gb_of<float>(const DevState& s) { return s.GB32; }
 
 // Pass B (forces at t^n, kick, drift).  Nodal force of Sec. 3.1,
 //   f_i = V_i sum_j V_j [(1 - D_j) Q_i + (1 - D_i) Q_j] gradW_ij,
@@ -418,69 +414,69 @@ __device__ __forceinline__ void load_Q(const DevState& s, int64_t i, R out[9]) {
 //   f_i^HG = -alpha E (1 - D_i) V_i sum_j (1 - D_j) V_j W_ij delta / |X_ij|^2
 //            x_ij / |x_ij|.
 // Then v += dt f / m, prescribed velocities at t^{n+1/2}, D = 1 at rest,
-// u^{n+1} = u^n + dt v (into the other displacement buffer), rigid wall.
+// u^{n+1} = u^n + dt v (into the other displacement buffer), rigid wall, and
+// the record (v, V0 (1 - D)) the deformation pass gathers.
 template <typename R>
 __global__ void __launch_bounds__(256) k_pass_b(DevState s, int par) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= s.n) return;
     const int64_t np = s.np;
     const int sp = s.spec[i];
     const DevSpec& P = s.specs[sp];
-    const double* __restrict__ X = s.X;
-    const double* __restrict__ V0 = s.V0;
-    const double* __restrict__ Dc = s.D[par];
-    const double* __restrict__ uc = s.u[par];
-    const double xi = X[i], yi = X[np + i], zi = X[2 * np + i];
-    const double ui0 = uc[i], ui1 = uc[np + i], ui2 = uc[2 * np + i];
-    const double Di = Dc[i];
-    const double Vi = V0[i];
-    R Hi[9];
-    load_tensor9<R>(s, i, Hi);
+    const D4* __restrict__ XV = s.XV;
+    const D4* __restrict__ Uc = s.U[par];
+    const GBRec<R>* __restrict__ GB = gb_of<R>(s);
+    const D4 xi = XV[i];
+    const D4 ui = Uc[i];
+    const GBRec<R> gi = GB[i];
+    const double Di = s.D[i];
     const R inv_h = R(P.inv_h), wnorm = R(P.wnorm);
     R a0 = 0, a1 = 0, a2 = 0, b0 = 0, b1 = 0, b2 = 0, g0 = 0, g1 = 0, g2 = 0;
     const int cnt = s.nnb[i];
     const int32_t* __restrict__ cp = s.col + s.slice_ptr[i / kSlice] + (i % kSlice);
     for (int k = 0; k < cnt; ++k) {
         const int32_t j = cp[(int64_t)k * kSlice];
-        const R dx = R(X[j] - xi), dy = R(X[np + j] - yi), dz = R(X[2 * np + j] - zi);
+        const D4 xj = XV[j];
+        const GBRec<R> gj = GB[j];
+        const D4 uj = Uc[j];
+        const R dx = R(xj.x - xi.x), dy = R(xj.y - xi.y), dz = R(xj.z - xi.z);
         const R r = sqrt(dx * dx + dy * dy + dz * dz);
         const R ir = R(1) / r;
         R W, dW;
         spline(r, inv_h, wnorm, W, dW);
         const R gs = dW * ir;
         const R gx = gs * dx, gy = gs * dy, gz = gs * dz;
-        const R Vj = R(V0[j]);
-        const R wj = Vj * R(1.0 - Dc[j]);
+        const R Vj = R(xj.w);
+        const R wj = Vj * gj.omd;
         a0 += wj * gx; a1 += wj * gy; a2 += wj * gz;
-        R Qj[9];
-        load_Q<R>(s, j, Qj);
-        b0 += Vj * (Qj[0] * gx + Qj[1] * gy + Qj[2] * gz);
-        b1 += Vj * (Qj[3] * gx + Qj[4] * gy + Qj[5] * gz);
-        b2 += Vj * (Qj[6] * gx + Qj[7] * gy + Qj[8] * gz);
+        b0 += Vj * (gj.q[0] * gx + gj.q[1] * gy + gj.q[2] * gz);
+        b1 += Vj * (gj.q[3] * gx + gj.q[4] * gy + gj.q[5] * gz);
+        b2 += Vj * (gj.q[6] * gx + gj.q[7] * gy + gj.q[8] * gz);
         // hourglass
-        const R du0 = R(uc[j] - ui0), du1 = R(uc[np + j] - ui1), du2 = R(uc[2 * np + j] - ui2);
+        const R du0 = R(uj.x - ui.x), du1 = R(uj.y - ui.y), du2 = R(uj.z - ui.z);
         const R x0 = dx + du0, x1 = dy + du1, x2 = dz + du2;
         const R irc = R(1) / sqrt(x0 * x0 + x1 * x1 + x2 * x2);
-        R Hj[9];
-        load_tensor9<R>(s, j, Hj);
-        const R e0 = R(0.5) * ((Hi[0] + Hj[0]) * dx + (Hi[1] + Hj[1]) * dy + (Hi[2] + Hj[2]) * dz) - du0;
-        const R e1 = R(0.5) * ((Hi[3] + Hj[3]) * dx + (Hi[4] + Hj[4]) * dy + (Hi[5] + Hj[5]) * dz) - du1;
-        const R e2 = R(0.5) * ((Hi[6] + Hj[6]) * dx + (Hi[7] + Hj[7]) * dy + (Hi[8] + Hj[8]) * dz) - du2;
+        const R e0 = R(0.5) * ((gi.h[0] + gj.h[0]) * dx + (gi.h[1] + gj.h[1]) * dy +
+                               (gi.h[2] + gj.h[2]) * dz) - du0;
+        const R e1 = R(0.5) * ((gi.h[3] + gj.h[3]) * dx + (gi.h[4] + gj.h[4]) * dy +
+                               (gi.h[5] + gj.h[5]) * dz) - du1;
+        const R e2 = R(0.5) * ((gi.h[6] + gj.h[6]) * dx + (gi.h[7] + gj.h[7]) * dy +
+                               (gi.h[8] + gj.h[8]) * dz) - du2;
         const R delta = (e0 * x0 + e1 * x1 + e2 * x2) * irc;
         const R c = wj * W * delta * ir * ir * irc;
         g0 += c * x0; g1 += c * x1; g2 += c * x2;
     }
-    R Qi[9];
-    load_Q<R>(s, i, Qi);
     const R omDi = R(1.0 - Di);
     const R hgk = R(-P.hg_alpha * P.E) * omDi;
-    const double f0 = Vi * double(Qi[0] * a0 + Qi[1] * a1 + Qi[2] * a2 + omDi * b0 + hgk * g0);
-    const double f1 = Vi * double(Qi[3] * a0 + Qi[4] * a1 + Qi[5] * a2 + omDi * b1 + hgk * g1);
-    const double f2 = Vi * double(Qi[6] * a0 + Qi[7] * a1 + Qi[8] * a2 + omDi * b2 + hgk * g2);
+    const double Vi = xi.w;
+    const double f0 = Vi * double(gi.q[0] * a0 + gi.q[1] * a1 + gi.q[2] * a2 + omDi * b0 + hgk * g0);
+    const double f1 = Vi * double(gi.q[3] * a0 + gi.q[4] * a1 + gi.q[5] * a2 + omDi * b1 + hgk * g1);
+    const double f2 = Vi * double(gi.q[6] * a0 + gi.q[7] * a1 + gi.q[8] * a2 + omDi * b2 + hgk * g2);
     // kick
     const double dt = P.dt;
     const double m = P.rho0 * Vi;
-    double v[3] = {s.v[i], s.v[np + i], s.v[2 * np + i]};
+    const D4 vo = s.VW[i];
+    double v[3] = {vo.x, vo.y, vo.z};
     v[0] += dt * f0 / m;
     v[1] += dt * f1 / m;
     v[2] += dt * f2 / m;
@@ -492,18 +488,18 @@ __global__ void __launch_bounds__(256) k_pass_b(DevState s, int par) {
 #pragma unroll
         for (int c = 0; c < 3; ++c)
             if (B.mask & (1 << c))
-                v[c] = B.v_max[c] * ramp + (B.grad[3 * c] * xi + B.grad[3 * c + 1] * yi +
-                                            B.grad[3 * c + 2] * zi);
+                v[c] = B.v_max[c] * ramp + (B.grad[3 * c] * xi.x + B.grad[3 * c + 1] * xi.y +
+                                            B.grad[3 * c + 2] * xi.z);
     }
     if (Di >= 1.0) v[0] = v[1] = v[2] = 0.0;
-    double un[3] = {ui0 + dt * v[0], ui1 + dt * v[1], ui2 + dt * v[2]};
+    double un[3] = {ui.x + dt * v[0], ui.y + dt * v[1], ui.z + dt * v[2]};
     if (P.has_wall) {
-        const double xw[3] = {xi + un[0], yi + un[1], zi + un[2]};
+        const double xw[3] = {xi.x + un[0], xi.y + un[1], xi.z + un[2]};
         const double dn = xw[0] * P.wall_n[0] + xw[1] * P.wall_n[1] + xw[2] * P.wall_n[2] - P.wall_d;
         if (dn < 0.0) {
-            un[0] = (xw[0] - dn * P.wall_n[0]) - xi;
-            un[1] = (xw[1] - dn * P.wall_n[1]) - yi;
-            un[2] = (xw[2] - dn * P.wall_n[2]) - zi;
+            un[0] = (xw[0] - dn * P.wall_n[0]) - xi.x;
+            un[1] = (xw[1] - dn * P.wall_n[1]) - xi.y;
+            un[2] = (xw[2] - dn * P.wall_n[2]) - xi.z;
             const double vn = v[0] * P.wall_n[0] + v[1] * P.wall_n[1] + v[2] * P.wall_n[2];
             if (vn < 0.0) {
                 v[0] -= vn * P.wall_n[0];
@@ -512,9 +508,8 @@ __global__ void __launch_bounds__(256) k_pass_b(DevState s, int par) {
             }
         }
     }
-    s.v[i] = v[0]; s.v[np + i] = v[1]; s.v[2 * np + i] = v[2];
-    double* __restrict__ un_out = s.u[par ^ 1];
-    un_out[i] = un[0]; un_out[np + i] = un[1]; un_out[2 * np + i] = un[2];
+    s.VW[i] = D4{v[0], v[1], v[2], Vi * (1.0 - Di)};
+    s.U[par ^ 1][i] = D4{un[0], un[1], un[2], 0.0};
     if ((s.flags & kFlagStoreForce) || g >= 0) {
         s.force[i] = f0; s.force[np + i] = f1; s.force[2 * np + i] = f2;
     }
@@ -527,32 +522,31 @@ __global__ void __launch_bounds__(256) k_pass_b(DevState s, int par) {
 // the constitutive update and Q_i = P_i L_i^-T (0 for failed particles).
 template <typename R>
 __global__ void __launch_bounds__(256) k_pass_a(DevState s, int par) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= s.n) return;
     const int64_t np = s.np;
     const int sp = s.spec[i];
     const DevSpec& P = s.specs[sp];
-    const double* __restrict__ X = s.X;
-    const double* __restrict__ V0 = s.V0;
-    const double* __restrict__ Dc = s.D[par];
-    const double* __restrict__ vv = s.v;
-    const double xi = X[i], yi = X[np + i], zi = X[2 * np + i];
-    const double vi0 = vv[i], vi1 = vv[np + i], vi2 = vv[2 * np + i];
+    const D4* __restrict__ XV = s.XV;
+    const D4* __restrict__ VW = s.VW;
+    const D4 xi = XV[i];
+    const D4 vi = VW[i];
     const R inv_h = R(P.inv_h), wnorm = R(P.wnorm);
     R M[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int cnt = s.nnb[i];
     const int32_t* __restrict__ cp = s.col + s.slice_ptr[i / kSlice] + (i % kSlice);
     for (int k = 0; k < cnt; ++k) {
         const int32_t j = cp[(int64_t)k * kSlice];
-        const R dx = R(X[j] - xi), dy = R(X[np + j] - yi), dz = R(X[2 * np + j] - zi);
+        const D4 xj = XV[j];
+        const D4 vj = VW[j];
+        const R dx = R(xj.x - xi.x), dy = R(xj.y - xi.y), dz = R(xj.z - xi.z);
         const R r = sqrt(dx * dx + dy * dy + dz * dz);
         R W, dW;
         spline(r, inv_h, wnorm, W, dW);
         const R gs = dW / r;
         const R gx = gs * dx, gy = gs * dy, gz = gs * dz;
-        const R wj = R(V0[j]) * R(1.0 - Dc[j]);
-        const R t0 = wj * R(vv[j] - vi0), t1 = wj * R(vv[np + j] - vi1),
-                t2 = wj * R(vv[2 * np + j] - vi2);
+        const R wj = R(vj.w);
+        const R t0 = wj * R(vj.x - vi.x), t1 = wj * R(vj.y - vi.y), t2 = wj * R(vj.z - vi.z);
         M[0] += t0 * gx; M[1] += t0 * gy; M[2] += t0 * gz;
         M[3] += t1 * gx; M[4] += t1 * gy; M[5] += t1 * gz;
         M[6] += t2 * gx; M[7] += t2 * gy; M[8] += t2 * gz;
@@ -567,8 +561,13 @@ __global__ void __launch_bounds__(256) k_pass_a(DevState s, int par) {
     }
     R Fd[9];
     mm33(M, Li, Fd);
+    GBRec<R>* __restrict__ GB = const_cast<GBRec<R>*>(gb_of<R>(s));
     R Hn[9], sn[6];
-    load_tensor9<R>(s, i, Hn);
+    {
+        const GBRec<R> gi = GB[i];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Hn[k] = gi.h[k];
+    }
     if constexpr (std::is_same<R, float>::value) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) sn[k] = s.sig32[k * np + i];
@@ -582,38 +581,32 @@ __global__ void __launch_bounds__(256) k_pass_a(DevState s, int par) {
     if (model == 1 || model == 2) dinit = s.d_init[i];
     if (model == 1) wp = s.w_p[i];
     if (model == 3) fv = s.f_void[i];
-    const double Di = Dc[i];
+    const double Di = s.D[i];
     PointOut<R> o;
     int32_t flags = 0;
     point_update<R>(P, Hn, Fd, sn, eps, rate, dinit, wp, fv, e, Di, o, flags);
     // stores
     if constexpr (std::is_same<R, float>::value) {
 #pragma unroll
-        for (int k = 0; k < 9; ++k) s.H[k * np + i] = o.H[k];
-#pragma unroll
         for (int k = 0; k < 6; ++k) s.sig32[k * np + i] = o.sig[k];
     } else {
 #pragma unroll
-        for (int k = 0; k < 9; ++k) s.F[k * np + i] = o.H[k] + ((k % 4 == 0) ? 1.0 : 0.0);
-#pragma unroll
         for (int k = 0; k < 6; ++k) s.sig[k * np + i] = o.sig[k];
     }
-    R Qo[9];
+    GBRec<R> go;
     const bool failed = o.D >= 1.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b)
-            Qo[3 * a + b] = failed ? R(0)
-                                   : o.P[3 * a] * Li[3 * b] + o.P[3 * a + 1] * Li[3 * b + 1] +
-                                         o.P[3 * a + 2] * Li[3 * b + 2];
-    if constexpr (std::is_same<R, float>::value) {
+            go.q[3 * a + b] = failed ? R(0)
+                                     : o.P[3 * a] * Li[3 * b] + o.P[3 * a + 1] * Li[3 * b + 1] +
+                                           o.P[3 * a + 2] * Li[3 * b + 2];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) s.Q32[k * np + i] = Qo[k];
-    } else {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) s.Q[k * np + i] = Qo[k];
-    }
+    for (int k = 0; k < 9; ++k) go.h[k] = o.H[k];
+    go.omd = R(1.0 - o.D);
+    go.pad = R(0);
+    GB[i] = go;
     if (Di < 1.0) {
         s.eps_p[i] = eps;
         s.eps_rate[i] = rate;
@@ -622,7 +615,7 @@ __global__ void __launch_bounds__(256) k_pass_a(DevState s, int par) {
         if (model == 1) s.w_p[i] = wp;
         if (model == 3) s.f_void[i] = fv;
     }
-    s.D[par ^ 1][i] = o.D;
+    s.D[i] = o.D;
     if (i == P.first) s.t[sp] += P.dt;
     if (flags || (s.flags & kFlagCheckFinite)) {
         int32_t fl = flags;
@@ -667,27 +660,34 @@ struct FieldRef {
     const double* d;   // double storage, or
     const float* f;    // float storage
     int comps;
-    int kind;          // 0 plain, 1 deformation gradient stored as F - I in float
+    int kind;          // 0 plain, 1 deformation gradient stored as F - I, 2 damage
+    int64_t cs, ps;    // element (particle p, component c) at [c * cs + p * ps]
 };
 
 __device__ __forceinline__ FieldRef field_ref(const DevState& s, int field, int par) {
+    const int64_t np = s.np;
     switch (field) {
-        case F_X: return {s.X, nullptr, 3, 0};
-        case F_U: return {s.u[par], nullptr, 3, 0};
-        case F_V: return {s.v, nullptr, 3, 0};
-        case F_DEFGRAD: return s.F ? FieldRef{s.F, nullptr, 9, 0} : FieldRef{nullptr, s.H, 9, 1};
-        case F_SIGMA: return s.sig ? FieldRef{s.sig, nullptr, 6, 0} : FieldRef{nullptr, s.sig32, 6, 0};
-        case F_EPS_P: return {s.eps_p, nullptr, 1, 0};
-        case F_EPS_P_RATE: return {s.eps_rate, nullptr, 1, 0};
-        case F_D_INIT: return {s.d_init, nullptr, 1, 0};
-        case F_W_P: return {s.w_p, nullptr, 1, 0};
-        case F_VOID: return {s.f_void, nullptr, 1, 0};
-        case F_D: return {s.D[par], nullptr, 1, 0};
-        case F_E_INT: return {s.e, nullptr, 1, 0};
-        case F_FORCE: return {s.force, nullptr, 3, 0};
-        case F_Q: return s.Q ? FieldRef{s.Q, nullptr, 9, 0} : FieldRef{nullptr, s.Q32, 9, 0};
-        case F_LINV: return {s.Linv, nullptr, 9, 0};
-        default: return {nullptr, nullptr, 0, 0};
+        case F_X: return {reinterpret_cast<const double*>(s.XV), nullptr, 3, 0, 1, 4};
+        case F_U: return {reinterpret_cast<const double*>(s.U[par]), nullptr, 3, 0, 1, 4};
+        case F_V: return {reinterpret_cast<const double*>(s.VW), nullptr, 3, 0, 1, 4};
+        case F_DEFGRAD:
+            return s.GB ? FieldRef{reinterpret_cast<const double*>(s.GB) + 9, nullptr, 9, 1, 1, 20}
+                        : FieldRef{nullptr, reinterpret_cast<const float*>(s.GB32) + 9, 9, 1, 1, 20};
+        case F_Q:
+            return s.GB ? FieldRef{reinterpret_cast<const double*>(s.GB), nullptr, 9, 0, 1, 20}
+                        : FieldRef{nullptr, reinterpret_cast<const float*>(s.GB32), 9, 0, 1, 20};
+        case F_SIGMA:
+            return s.sig ? FieldRef{s.sig, nullptr, 6, 0, np, 1} : FieldRef{nullptr, s.sig32, 6, 0, np, 1};
+        case F_EPS_P: return {s.eps_p, nullptr, 1, 0, np, 1};
+        case F_EPS_P_RATE: return {s.eps_rate, nullptr, 1, 0, np, 1};
+        case F_D_INIT: return {s.d_init, nullptr, 1, 0, np, 1};
+        case F_W_P: return {s.w_p, nullptr, 1, 0, np, 1};
+        case F_VOID: return {s.f_void, nullptr, 1, 0, np, 1};
+        case F_D: return {s.D, nullptr, 1, 2, np, 1};
+        case F_E_INT: return {s.e, nullptr, 1, 0, np, 1};
+        case F_FORCE: return {s.force, nullptr, 3, 0, np, 1};
+        case F_LINV: return {s.Linv, nullptr, 9, 0, np, 1};
+        default: return {nullptr, nullptr, 0, 0, 0, 0};
     }
 }
 
@@ -697,12 +697,15 @@ __global__ void k_get(DevState s, int field, int par, double* __restrict__ dst) 
     const FieldRef r = field_ref(s, field, par);
     const int64_t p = s.iperm[i];
     for (int c = 0; c < r.comps; ++c) {
-        double x = r.d ? r.d[c * s.np + p] : (double)r.f[c * s.np + p];
+        const int64_t at = c * r.cs + p * r.ps;
+        double x = r.d ? r.d[at] : (double)r.f[at];
         if (r.kind == 1 && (c % 4 == 0)) x += 1.0;
         dst[c * s.n + i] = x;
     }
 }
 
+// Writes keep the gathered copies consistent: damage also sets 1 - D in the
+// force-pass record and V0 (1 - D) in the velocity record.
 __global__ void k_set(DevState s, int field, int par, const double* __restrict__ src) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= s.n) return;
@@ -711,10 +714,16 @@ __global__ void k_set(DevState s, int field, int par, const double* __restrict__
     for (int c = 0; c < r.comps; ++c) {
         double x = src[c * s.n + i];
         if (r.kind == 1 && (c % 4 == 0)) x -= 1.0;
+        const int64_t at = c * r.cs + p * r.ps;
         if (r.d)
-            const_cast<double*>(r.d)[c * s.np + p] = x;
+            const_cast<double*>(r.d)[at] = x;
         else
-            const_cast<float*>(r.f)[c * s.np + p] = (float)x;
+            const_cast<float*>(r.f)[at] = (float)x;
+    }
+    if (r.kind == 2) {
+        const double D = src[i];
+        if (s.GB) s.GB[p].omd = 1.0 - D; else s.GB32[p].omd = (float)(1.0 - D);
+        s.VW[p].w = s.XV[p].w * (1.0 - D);
     }
 }
 
@@ -861,11 +870,11 @@ __global__ void __launch_bounds__(256) k_spec_diag(DevState s, int par, double* 
     const int64_t np = s.np;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t p = P.first + threadIdx.x; p < P.last; p += 256) {
-        const double m = P.rho0 * s.V0[p];
-        const double a = s.v[p], b = s.v[np + p], c = s.v[2 * np + p];
-        v[0] += 0.5 * m * (a * a + b * b + c * c);
+        const double m = P.rho0 * s.XV[p].w;
+        const D4 vv = s.VW[p];
+        v[0] += 0.5 * m * (vv.x * vv.x + vv.y * vv.y + vv.z * vv.z);
         v[1] += m * s.e[p];
-        const double D = s.D[par][p];
+        const double D = s.D[p];
         v[2] += D >= 1.0 ? 1.0 : 0.0;
         v[3] = fmax(v[3], D);
     }
@@ -884,14 +893,13 @@ __global__ void __launch_bounds__(256) k_bc_diag(DevState s, int par, const int3
     __shared__ double red[7][256];
     const int g = blockIdx.x;
     const int64_t np = s.np;
-    const double* uc = s.u[par];
+    const D4* uc = s.U[par];
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int64_t q = ptr[g] + threadIdx.x; q < ptr[g + 1]; q += 256) {
         const int64_t p = list[q];
-        for (int c = 0; c < 3; ++c) {
-            v[c] += s.force[c * np + p];
-            v[3 + c] += uc[c * np + p];
-        }
+        for (int c = 0; c < 3; ++c) v[c] += s.force[c * np + p];
+        const D4 up = uc[p];
+        v[3] += up.x; v[4] += up.y; v[5] += up.z;
         v[6] += 1.0;
     }
     const bool mx[7] = {false, false, false, false, false, false, false};

@@ -263,8 +263,9 @@ class Sim:
     def autotune(self):
         self._check(lib().tlsph_autotune(self.ctx, self._sp()), "tlsph_autotune")
 
-    def enable_kernel_timing(self, on: bool = True):
-        self._check(lib().tlsph_enable_kernel_timing(self.ctx, int(on)), "enable_kernel_timing")
+    def enable_kernel_timing(self, stride: int = 1):
+        """Time both step kernels of every stride-th step (0: off)."""
+        self._check(lib().tlsph_enable_kernel_timing(self.ctx, int(stride)), "enable_kernel_timing")
 
     def kernel_times(self):
         ms = (C.c_double * 2)()
