@@ -96,8 +96,8 @@ def failure_displacement(sep, reaction):
     return None
 
 
-def run_form(prob, precision, steps, warmup, torch, T):
-    sim = T.Sim(prob, precision=precision)
+def run_form(prob, precision, steps, warmup, torch, T, flags=0, autotune=True):
+    sim = T.Sim(prob, precision=precision, flags=flags)
     n_rec = (warmup + steps) // DIAG_EVERY + 1
     sd = torch.zeros((n_rec, prob.n_spec, 8), dtype=torch.float64, device="cuda")
     bd = torch.zeros((n_rec, len(prob.bc_groups), 8), dtype=torch.float64, device="cuda")
@@ -119,6 +119,8 @@ def run_form(prob, precision, steps, warmup, torch, T):
                 rec += 1
 
     advance(warmup)
+    if autotune:
+        sim.autotune()     # picks launch shapes on the current state; results unchanged
     torch.cuda.synchronize()
     sim.enable_kernel_timing(TIMING_STRIDE)
     t0 = time.perf_counter()
@@ -162,6 +164,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--unstaged", action="store_true",
+                    help="force pass gathers from global memory instead of LDS tiles")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -182,7 +187,8 @@ def main():
     damage = prob.materials[0]["damage"]
     workload = "notched_bar_200k"
 
-    fp = run_form(prob, T.FP64, args.steps, args.warmup, torch, T)
+    flags = T.NO_STAGING if args.unstaged else 0
+    fp = run_form(prob, T.FP64, args.steps, args.warmup, torch, T, flags, not args.no_autotune)
     nnz = fp["info"]["nnz"]
     value = prob.n * args.steps / fp["seconds"]
     ms_step = fp["seconds"] / args.steps * 1e3
@@ -210,6 +216,10 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": workload, "particles": prob.n, "neighbour_pairs": nnz,
                    "damage": "johnson-cook", "precision": "fp64",
+                   "force_pass_variant": ("LDS-staged tiles" if fp["info"]["staged"] else
+                                          "global gathers"),
+                   "launch_shape": {"force_pass": fp["info"]["block_force"],
+                                    "deformation_pass": fp["info"]["block_deformation"]},
                    "steps_from_rest": args.warmup + args.steps,
                    "dt_s": prob.materials[0]["dt"]},
         "step_algorithmic_GBs": round(step_bytes * args.steps / fp["seconds"] / 1e9, 1),
@@ -222,7 +232,7 @@ def main():
     del fp["sim"]
 
     if not args.no_mixed:
-        mx = run_form(prob, T.MIXED, args.steps, args.warmup, torch, T)
+        mx = run_form(prob, T.MIXED, args.steps, args.warmup, torch, T, flags, not args.no_autotune)
         fdm = failure_displacement(mx["sep"], mx["reaction"])
         r64, rmx = fp["reaction"], mx["reaction"]
         ipk = int(np.argmax(r64))

@@ -77,6 +77,8 @@ typedef enum {
                                    of particles in a prescribed-velocity group) */
 #define TLSPH_USE_GRAPHS    2u  /* tlsph_step replays a captured two-step hipGraph */
 #define TLSPH_CHECK_FINITE  4u  /* latch TLSPH_E_NONFINITE if a stress turns non-finite */
+#define TLSPH_NO_STAGING    8u  /* gather neighbours from global memory instead of staging
+                                   each tile and its halo in LDS (same results, bitwise) */
 
 /* One specimen: material (Sec. 4 and Tables 1-3) and run parameters. */
 typedef struct {
@@ -225,7 +227,8 @@ tlsph_status tlsph_autotune(tlsph_ctx *ctx, hipStream_t stream);
 tlsph_status tlsph_enable_kernel_timing(tlsph_ctx *ctx, int32_t stride);
 tlsph_status tlsph_kernel_times(tlsph_ctx *ctx, double ms[2], int64_t launches[2]);
 
-/* Launch shape and layout facts: [0] threads per block of the force pass,
+/* Launch shape and layout facts: [0] threads per block of the force pass
+ * (negative when the LDS-staged variant is in use),
  * [1] of the deformation pass, [2] neighbour pairs, [3] padded slots of the
  * sliced neighbour layout, [4] particles, [5] sticky device error flags
  * (bit 0 non-finite, bit 1 GTN Newton not converged). */

@@ -13,6 +13,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # no implicit multiply-add fusion: the hot loops spell out their fma()
+    # calls, so every kernel variant rounds the same arithmetic the same way
+    "-ffp-contract=off",
     # packed FP32 instructions stay off in all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",

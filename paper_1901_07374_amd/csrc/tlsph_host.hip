@@ -34,7 +34,10 @@ struct Layout {
     int64_t n, np, n_pow2, n_slices;
     int32_t n_spec, n_bc, k_cap;
     bool mixed;
-    size_t XV, spec, bc, perm, iperm, nnb, slice_ptr, col, Linv, Linv32, specs, bcs, t;
+    size_t XV, spec, bc, perm, iperm, nnb, slice_ptr, col, lcol, halo, halo_cnt, Linv, Linv32,
+        specs, bcs, t;
+    int64_t n_tiles;
+    int32_t halo_cap;
     size_t GB, U0, U1, VW, sig, eps_p, eps_rate, d_init, w_p, f_void, e, D, force, err,
         spec_off, bbox, keys, vals, bc_list, bc_ptr, backup;
     size_t state_begin, backup_bytes;
@@ -66,6 +69,11 @@ Layout make_layout(int64_t n, int32_t n_spec, int32_t n_bc, int32_t k_cap, bool 
     L.nnb = take(np * 4);
     L.slice_ptr = take(((size_t)L.n_slices + 1) * 8);
     L.col = take((size_t)k_cap * np * 4);
+    L.lcol = take((size_t)k_cap * np * 2);
+    L.n_tiles = (n + kTile - 1) / kTile;
+    L.halo_cap = kTile * k_cap;
+    L.halo = take((size_t)L.n_tiles * L.halo_cap * 4);
+    L.halo_cnt = take((size_t)L.n_tiles * 4);
     L.Linv = take(9 * np * 8);
     L.Linv32 = take(mixed ? 9 * np * 4 : 0);
     L.specs = take((size_t)n_spec * sizeof(DevSpec));
@@ -116,6 +124,8 @@ struct tlsph_ctx {
     int parity = 0;
     int64_t nnz = 0, slots = 0;
     int block_a = 256, block_b = 256;
+    bool staged_ok = false;     // the staged force pass fits this device's LDS
+    size_t lds_b = 0;           // its dynamic LDS bytes
     std::string last_error;
     // per-kernel timing (every timing_stride-th step while enabled)
     bool timing = false;
@@ -170,6 +180,12 @@ void wire_state(tlsph_ctx* c) {
     s.slice_ptr = at<int64_t>(c, L.slice_ptr);
     s.col = at<int32_t>(c, L.col);
     s.col_cap = (int64_t)L.k_cap * L.np;
+    s.lcol = at<uint16_t>(c, L.lcol);
+    s.halo = at<int32_t>(c, L.halo);
+    s.halo_cnt = at<int32_t>(c, L.halo_cnt);
+    s.halo_cap = L.halo_cap;
+    s.staged = 0;
+    s.lds_slots = 0;
     s.Linv = at<double>(c, L.Linv);
     s.Linv32 = L.mixed ? at<float>(c, L.Linv32) : nullptr;
     s.specs = at<DevSpec>(c, L.specs);
@@ -225,8 +241,9 @@ tlsph_status run_steps_eager(tlsph_ctx* c, int32_t n_steps, hipStream_t stream) 
                 HIPCHK(c, hipEventRecord(e0, stream));
                 c->ev_marks.push_back({pass, idx});
             }
-            hipError_t e = pass == 0 ? launch_pass_b(c->st, c->parity, c->block_b, mixed, stream)
-                                     : launch_pass_a(c->st, c->parity, c->block_a, mixed, stream);
+            hipError_t e = pass == 0
+                               ? launch_pass_b(c->st, c->parity, c->block_b, mixed, stream, c->lds_b)
+                               : launch_pass_a(c->st, c->parity, c->block_a, mixed, stream);
             if (e != hipSuccess) return hip_fail(c, e, pass == 0 ? "force pass" : "deformation pass");
             if (timed) HIPCHK(c, hipEventRecord(e1, stream));
         }
@@ -237,7 +254,7 @@ tlsph_status run_steps_eager(tlsph_ctx* c, int32_t n_steps, hipStream_t stream) 
 
 tlsph_status ensure_graph(tlsph_ctx* c, hipStream_t stream) {
     if (c->gexec && c->graph_parity == c->parity && c->graph_block_a == c->block_a &&
-        c->graph_block_b == c->block_b)
+        c->graph_block_b == (c->st.staged ? -c->block_b : c->block_b))
         return TLSPH_OK;
     if (c->gexec) {
         (void)hipGraphExecDestroy(c->gexec);
@@ -259,7 +276,7 @@ tlsph_status ensure_graph(tlsph_ctx* c, hipStream_t stream) {
     if (ie != hipSuccess) return hip_fail(c, ie, "hipGraphInstantiate");
     c->graph_parity = p0;
     c->graph_block_a = c->block_a;
-    c->graph_block_b = c->block_b;
+    c->graph_block_b = c->st.staged ? -c->block_b : c->block_b;
     return TLSPH_OK;
 }
 
@@ -315,7 +332,7 @@ tlsph_status tlsph_create(int64_t n, int32_t n_spec, const int64_t* spec_offsets
     if (tlsph_workspace_bytes(n, n_spec, n_bc, k_cap, precision, &need) != TLSPH_OK)
         return TLSPH_E_INVALID_ARG;
     if (!spec_offsets || !spec || (n_bc > 0 && !bc) || !workspace || ws_bytes < need ||
-        ((uintptr_t)workspace % kAlign) != 0 || (flags & ~7u) != 0)
+        ((uintptr_t)workspace % kAlign) != 0 || (flags & ~15u) != 0)
         return TLSPH_E_INVALID_ARG;
     if (spec_offsets[0] != 0 || spec_offsets[n_spec] != n) return TLSPH_E_INVALID_ARG;
     for (int32_t s = 0; s < n_spec; ++s)
@@ -422,6 +439,17 @@ tlsph_status tlsph_build_neighbors(tlsph_ctx* c, const double* X, const double* 
         return fail(c, TLSPH_E_CAPACITY, "a particle has " + std::to_string(err[1]) +
                                              " neighbours, k_cap is " + std::to_string(L.k_cap));
     HIPCHK(c, launch_build_fill(c->st, b, stream));
+    // LDS staging of the force pass: per-tile halo lists when they fit
+    c->st.staged = 0;
+    c->staged_ok = false;
+    c->lds_b = 0;
+    int dev = 0, max_lds = 0;
+    HIPCHK(c, hipGetDevice(&dev));
+    HIPCHK(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    int E = 256;
+    while (E < kTile * L.k_cap) E <<= 1;
+    const bool halo_fits = (2 * (size_t)E + 257) * 4 <= (size_t)max_lds && !(c->flags & TLSPH_NO_STAGING);
+    if (halo_fits) HIPCHK(c, launch_halo(c->st, L.k_cap, stream));
     HIPCHK(c, launch_shape_and_init(c->st, L.mixed, stream));
     HIPCHK(c, launch_bc_lists(c->st, b.keys, b.vals, L.n_pow2, at<int32_t>(c, L.bc_list),
                               at<int64_t>(c, L.bc_ptr), stream));
@@ -432,6 +460,16 @@ tlsph_status tlsph_build_neighbors(tlsph_ctx* c, const double* X, const double* 
         HIPCHK(c, hipMemcpy(&orig, c->ws + L.perm + (size_t)err[0] * 4, 4, hipMemcpyDeviceToHost));
         return fail(c, TLSPH_E_SINGULAR_L,
                     "singular correction matrix at particle " + std::to_string(orig));
+    }
+    if (halo_fits) {
+        const size_t lds = (size_t)(kTile + err[4]) * staged_record_bytes(L.mixed);
+        if (lds <= (size_t)max_lds && kTile + err[4] <= 65536) {
+            HIPCHK(c, prepare_staged(lds));
+            c->staged_ok = true;
+            c->lds_b = lds;
+            c->st.lds_slots = kTile + err[4];
+            c->st.staged = 1;
+        }
     }
     // neighbour pairs: sum of counts
     std::vector<int32_t> cnt(L.np);
@@ -576,7 +614,7 @@ tlsph_status tlsph_autotune(tlsph_ctx* c, hipStream_t stream) {
     HIPCHK(c, hipMemcpyAsync(backup, state, L.backup_bytes, hipMemcpyDeviceToDevice, stream));
     HIPCHK(c, hipMemcpyAsync(backup + L.backup_bytes, c->st.t, L.n_spec * 8,
                              hipMemcpyDeviceToDevice, stream));
-    const int cand[3] = {64, 128, 256};  // the step kernels are built for <= 256 threads
+    const int cand[4] = {64, 128, 256, 0};  // 0: LDS-staged force pass (256 threads)
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
@@ -585,13 +623,16 @@ tlsph_status tlsph_autotune(tlsph_ctx* c, hipStream_t stream) {
         float best = 1e30f;
         int best_b = 256;
         for (int b : cand) {
+            if (b == 0 && (pass == 1 || !c->staged_ok)) continue;
+            if (pass == 0) c->st.staged = (b == 0) ? 1 : 0;
             // every candidate starts from the saved state
             HIPCHK(c, hipMemcpyAsync(state, backup, L.backup_bytes, hipMemcpyDeviceToDevice,
                                      stream));
             hipError_t e = hipSuccess;
             for (int r = 0; r < reps + 1 && e == hipSuccess; ++r) {
                 if (r == 1) HIPCHK(c, hipEventRecord(e0, stream));
-                e = pass == 0 ? launch_pass_b(c->st, c->parity, b, L.mixed, stream)
+                e = pass == 0 ? launch_pass_b(c->st, c->parity, b == 0 ? 256 : b, L.mixed, stream,
+                                              c->lds_b)
                               : launch_pass_a(c->st, c->parity, b, L.mixed, stream);
             }
             if (e != hipSuccess) return hip_fail(c, e, "autotune launch");
@@ -604,7 +645,12 @@ tlsph_status tlsph_autotune(tlsph_ctx* c, hipStream_t stream) {
                 best_b = b;
             }
         }
-        if (pass == 0) c->block_b = best_b; else c->block_a = best_b;
+        if (pass == 0) {
+            c->st.staged = best_b == 0 ? 1 : 0;
+            c->block_b = best_b == 0 ? 256 : best_b;
+        } else {
+            c->block_a = best_b;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -617,7 +663,7 @@ tlsph_status tlsph_autotune(tlsph_ctx* c, hipStream_t stream) {
 
 tlsph_status tlsph_info(tlsph_ctx* c, int64_t out[6]) {
     if (!c || !out) return TLSPH_E_INVALID_ARG;
-    out[0] = c->block_b;
+    out[0] = c->st.staged ? -c->block_b : c->block_b;
     out[1] = c->block_a;
     out[2] = c->nnz;
     out[3] = c->slots;

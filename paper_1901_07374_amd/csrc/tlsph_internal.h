@@ -10,6 +10,8 @@ constexpr int kSlice = 64;          // particles per slice of the sliced neighbo
 constexpr int kMortonBits = 14;     // cells per axis < 2^14
 constexpr int kSpecShift = 3 * kMortonBits;
 constexpr int kNDiag = 8;          // doubles per diagnostics record
+constexpr int kTile = 256;         // particles per workgroup tile of the LDS-staged passes
+constexpr int kHaloSortMax = 8192; // tile entries sorted in LDS at build (kTile * k_cap)
 
 // Per-specimen parameters as the kernels read them (raw + derived).
 struct DevSpec {
@@ -93,14 +95,26 @@ struct DevState {
     double* D;
     double* force;           // SoA [3][np]
     int32_t* err;    // [0] first singular (sorted), [1] max count, [2] sticky flags,
-                     // [3] build status
+                     // [3] build status, [4] largest tile halo
+    // LDS staging: per tile of kTile particles, the sorted outside neighbours
+    // (halo) and every neighbour as a local slot (tile member j - start, or
+    // kTile + position in the halo), in the sliced layout of col
+    const int32_t* halo;      // [n_tiles][halo_cap]
+    const int32_t* halo_cnt;  // [n_tiles]
+    const uint16_t* lcol;
+    int32_t halo_cap;
+    int32_t staged;           // 1 when the staged force pass is in use
+    int32_t lds_slots;        // slots per field array of the staged kernel's LDS image
+    int32_t pad2_;
 };
 
-enum : uint32_t { kFlagStoreForce = 1u, kFlagGraphs = 2u, kFlagCheckFinite = 4u };
+enum : uint32_t { kFlagStoreForce = 1u, kFlagGraphs = 2u, kFlagCheckFinite = 4u,
+                  kFlagNoStaging = 8u };
 enum : int32_t { kErrNonFinite = 1, kErrNewton = 2 };
 
 // launch helpers implemented in tlsph_kernels.hip
-hipError_t launch_pass_b(const DevState& s, int parity, int block, bool mixed, hipStream_t st);
+hipError_t launch_pass_b(const DevState& s, int parity, int block, bool mixed, hipStream_t st,
+                         size_t lds_bytes = 0);
 hipError_t launch_pass_a(const DevState& s, int parity, int block, bool mixed, hipStream_t st);
 
 struct BuildBuffers {
@@ -116,6 +130,9 @@ struct BuildBuffers {
 
 hipError_t launch_build_count(DevState& s, const BuildBuffers& b, hipStream_t st);
 hipError_t launch_build_fill(DevState& s, const BuildBuffers& b, hipStream_t st);
+hipError_t launch_halo(const DevState& s, int k_cap, hipStream_t st);
+hipError_t prepare_staged(size_t lds_bytes_b);
+size_t staged_record_bytes(bool mixed);
 hipError_t launch_shape_and_init(const DevState& s, bool mixed, hipStream_t st);
 hipError_t launch_get_field(const DevState& s, int field, int parity, bool mixed, double* dst,
                             hipStream_t st);

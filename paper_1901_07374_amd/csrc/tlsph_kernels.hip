@@ -253,10 +253,19 @@ __global__ void k_fill(DevState s, const uint64_t* __restrict__ keys,
                        const double* __restrict__ bbox, int32_t* __restrict__ col,
                        int64_t cap_slots) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= s.n) return;
+    if (p >= s.np) return;
     if (s.slice_ptr[s.np / kSlice] > cap_slots) return;  // capacity error reported by the host
-    int32_t* base = col + s.slice_ptr[p / kSlice] + (p % kSlice);
-    for_neighbours(s, keys, bbox, p, [&](int k, int32_t q) { base[(int64_t)k * kSlice] = q; });
+    const int64_t sl = p / kSlice;
+    const int w = (int)((s.slice_ptr[sl + 1] - s.slice_ptr[sl]) / kSlice);
+    int32_t* base = col + s.slice_ptr[sl] + (p % kSlice);
+    int cnt = 0;
+    if (p < s.n)
+        cnt = for_neighbours(s, keys, bbox, p,
+                             [&](int k, int32_t q) { base[(int64_t)k * kSlice] = q; });
+    // the rest of the slice's width points at the particle itself (a valid
+    // address for loops that run to the slice width and mask the excess)
+    const int32_t self = p < s.n ? (int32_t)p : 0;
+    for (int k = cnt; k < w; ++k) base[(int64_t)k * kSlice] = self;
 }
 
 // Correction matrix L_i = sum_j V_j (X_j - X_i) (x) gradW_ij (eq.
@@ -367,6 +376,119 @@ hipError_t launch_build_count(DevState& s, const BuildBuffers& b, hipStream_t st
     return hipGetLastError();
 }
 
+// One workgroup per tile of kTile particles: sort the tile's neighbour
+// entries that lie outside the tile (bitonic, in LDS), keep each index once
+// (the halo, ascending), then give every neighbour entry its local slot:
+// j - start inside the tile, kTile + position in the halo outside.
+__global__ void __launch_bounds__(256) k_halo(DevState s, int k_cap, int E,
+                                              int32_t* __restrict__ halo,
+                                              int32_t* __restrict__ halo_cnt,
+                                              uint16_t* __restrict__ lcol) {
+    extern __shared__ int32_t sh[];
+    int32_t* srt = sh;            // [E]
+    int32_t* hl = sh + E;         // [E]
+    int32_t* part = sh + 2 * E;   // [257]
+    const int tid = threadIdx.x;
+    const int64_t t = blockIdx.x;
+    const int64_t start = t * kTile;
+    const int64_t end = start + kTile < s.n ? start + kTile : s.n;
+    for (int e = tid; e < E; e += 256) srt[e] = 0x7fffffff;
+    __syncthreads();
+    const int64_t p = start + tid;
+    int cnt = 0;
+    const int32_t* cp = nullptr;
+    if (p < s.n) {
+        cnt = s.nnb[p];
+        cp = s.col + s.slice_ptr[p / kSlice] + (p % kSlice);
+        for (int k = 0; k < cnt; ++k) {
+            const int32_t j = cp[(int64_t)k * kSlice];
+            if (j < start || j >= end) srt[tid * k_cap + k] = j;
+        }
+    }
+    __syncthreads();
+    for (int k = 2; k <= E; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int e = tid; e < E; e += 256) {
+                const int l = e ^ j;
+                if (l > e) {
+                    const int32_t a = srt[e], b = srt[l];
+                    if ((a > b) == ((e & k) == 0)) {
+                        srt[e] = b;
+                        srt[l] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    const int per = E / 256;
+    int c = 0;
+    for (int e = tid * per; e < (tid + 1) * per; ++e) {
+        const int32_t v = srt[e];
+        if (v != 0x7fffffff && (e == 0 || srt[e - 1] != v)) ++c;
+    }
+    part[tid] = c;
+    __syncthreads();
+    if (tid == 0) {
+        int run = 0;
+        for (int q = 0; q < 256; ++q) {
+            const int v = part[q];
+            part[q] = run;
+            run += v;
+        }
+        part[256] = run;
+    }
+    __syncthreads();
+    int pos = part[tid];
+    for (int e = tid * per; e < (tid + 1) * per; ++e) {
+        const int32_t v = srt[e];
+        if (v != 0x7fffffff && (e == 0 || srt[e - 1] != v)) hl[pos++] = v;
+    }
+    __syncthreads();
+    const int H = part[256];
+    for (int h = tid; h < H; h += 256) halo[t * s.halo_cap + h] = hl[h];
+    if (tid == 0) {
+        halo_cnt[t] = H;
+        atomicMax(&s.err[4], H);
+    }
+    if (p < s.np) {
+        const int64_t sl = p / kSlice;
+        const int w = (int)((s.slice_ptr[sl + 1] - s.slice_ptr[sl]) / kSlice);
+        uint16_t* lp = lcol + s.slice_ptr[sl] + (p % kSlice);
+        for (int k = cnt; k < w; ++k) lp[(int64_t)k * kSlice] = (uint16_t)tid;
+    }
+    if (p < s.n) {
+        uint16_t* lp = lcol + s.slice_ptr[p / kSlice] + (p % kSlice);
+        for (int k = 0; k < cnt; ++k) {
+            const int32_t j = cp[(int64_t)k * kSlice];
+            int loc;
+            if (j >= start && j < end) {
+                loc = (int)(j - start);
+            } else {
+                int lo = 0, hi = H;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (hl[mid] < j) lo = mid + 1; else hi = mid;
+                }
+                loc = kTile + lo;
+            }
+            lp[(int64_t)k * kSlice] = (uint16_t)loc;
+        }
+    }
+}
+
+hipError_t launch_halo(const DevState& s, int k_cap, hipStream_t st) {
+    int E = 256;
+    while (E < kTile * k_cap) E <<= 1;
+    const size_t lds = (2 * (size_t)E + 257) * sizeof(int32_t);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_halo),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const unsigned tiles = (unsigned)((s.n + kTile - 1) / kTile);
+    k_halo<<<tiles, 256, lds, st>>>(s, k_cap, E, const_cast<int32_t*>(s.halo),
+                                    const_cast<int32_t*>(s.halo_cnt), const_cast<uint16_t*>(s.lcol));
+    return hipGetLastError();
+}
+
 // Only after the host has checked that the sliced list fits col.
 hipError_t launch_build_fill(DevState& s, const BuildBuffers& b, hipStream_t st) {
     const int T = 256;
@@ -406,73 +528,87 @@ __device__ __forceinline__ const GBRec<double>* gb_of<double>(const DevState& s)
 template <>
 __device__ __forceinline__ const GBRec<float>* gb_of<float>(const DevState& s) { return s.GB32; }
 
-// Pass B (forces at t^n, kick, drift).  Nodal force of Sec. 3.1,
-//   f_i = V_i sum_j V_j [(1 - D_j) Q_i + (1 - D_i) Q_j] gradW_ij,
-// evaluated as V_i [Q_i a + (1 - D_i) b] with a = sum_j V_j (1 - D_j) gradW_ij
-// and b = sum_j V_j Q_j gradW_ij, plus hourglass control: with the error
-// vector e_ij = (F_i + F_j)/2 X_ij - x_ij and delta = e_ij . x_ij / |x_ij|,
-//   f_i^HG = -alpha E (1 - D_i) V_i sum_j (1 - D_j) V_j W_ij delta / |X_ij|^2
-//            x_ij / |x_ij|.
-// Then v += dt f / m, prescribed velocities at t^{n+1/2}, D = 1 at rest,
-// u^{n+1} = u^n + dt v (into the other displacement buffer), rigid wall, and
-// the record (v, V0 (1 - D)) the deformation pass gathers.
+// Everything the force pass needs of a neighbour (and of the particle
+// itself): reference position and volume, displacement, 1 - D, Q = P L^-T
+// and H = F - I.  Also the LDS record of the staged kernel.
 template <typename R>
-__global__ void __launch_bounds__(256) k_pass_b(DevState s, int par) {
-    const int64_t i = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (i >= s.n) return;
-    const int64_t np = s.np;
-    const int sp = s.spec[i];
-    const DevSpec& P = s.specs[sp];
-    const D4* __restrict__ XV = s.XV;
-    const D4* __restrict__ Uc = s.U[par];
-    const GBRec<R>* __restrict__ GB = gb_of<R>(s);
-    const D4 xi = XV[i];
-    const D4 ui = Uc[i];
-    const GBRec<R> gi = GB[i];
-    const double Di = s.D[i];
-    const R inv_h = R(P.inv_h), wnorm = R(P.wnorm);
+struct LRecB;
+template <>
+struct alignas(16) LRecB<double> {
+    double x, y, z, V0, ux, uy, uz, omd;
+    double q[9], h[9];
+};
+template <>
+struct alignas(16) LRecB<float> {
+    double x, y, z, ux, uy, uz;   // positions and displacements stay double
+    float V0, omd;
+    float q[9], h[9];
+};
+
+template <typename R>
+__device__ __forceinline__ LRecB<R> make_recb(const D4& xv, const GBRec<R>& g, const D4& u) {
+    LRecB<R> r;
+    r.x = xv.x; r.y = xv.y; r.z = xv.z; r.V0 = R(xv.w);
+    r.ux = u.x; r.uy = u.y; r.uz = u.z; r.omd = g.omd;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) { r.q[k] = g.q[k]; r.h[k] = g.h[k]; }
+    return r;
+}
+
+template <typename R>
+struct ForceAcc {
     R a0 = 0, a1 = 0, a2 = 0, b0 = 0, b1 = 0, b2 = 0, g0 = 0, g1 = 0, g2 = 0;
-    const int cnt = s.nnb[i];
-    const int32_t* __restrict__ cp = s.col + s.slice_ptr[i / kSlice] + (i % kSlice);
-    for (int k = 0; k < cnt; ++k) {
-        const int32_t j = cp[(int64_t)k * kSlice];
-        const D4 xj = XV[j];
-        const GBRec<R> gj = GB[j];
-        const D4 uj = Uc[j];
-        const R dx = R(xj.x - xi.x), dy = R(xj.y - xi.y), dz = R(xj.z - xi.z);
-        const R r = sqrt(dx * dx + dy * dy + dz * dz);
-        const R ir = R(1) / r;
-        R W, dW;
-        spline(r, inv_h, wnorm, W, dW);
-        const R gs = dW * ir;
-        const R gx = gs * dx, gy = gs * dy, gz = gs * dz;
-        const R Vj = R(xj.w);
-        const R wj = Vj * gj.omd;
-        a0 += wj * gx; a1 += wj * gy; a2 += wj * gz;
-        b0 += Vj * (gj.q[0] * gx + gj.q[1] * gy + gj.q[2] * gz);
-        b1 += Vj * (gj.q[3] * gx + gj.q[4] * gy + gj.q[5] * gz);
-        b2 += Vj * (gj.q[6] * gx + gj.q[7] * gy + gj.q[8] * gz);
-        // hourglass
-        const R du0 = R(uj.x - ui.x), du1 = R(uj.y - ui.y), du2 = R(uj.z - ui.z);
-        const R x0 = dx + du0, x1 = dy + du1, x2 = dz + du2;
-        const R irc = R(1) / sqrt(x0 * x0 + x1 * x1 + x2 * x2);
-        const R e0 = R(0.5) * ((gi.h[0] + gj.h[0]) * dx + (gi.h[1] + gj.h[1]) * dy +
-                               (gi.h[2] + gj.h[2]) * dz) - du0;
-        const R e1 = R(0.5) * ((gi.h[3] + gj.h[3]) * dx + (gi.h[4] + gj.h[4]) * dy +
-                               (gi.h[5] + gj.h[5]) * dz) - du1;
-        const R e2 = R(0.5) * ((gi.h[6] + gj.h[6]) * dx + (gi.h[7] + gj.h[7]) * dy +
-                               (gi.h[8] + gj.h[8]) * dz) - du2;
-        const R delta = (e0 * x0 + e1 * x1 + e2 * x2) * irc;
-        const R c = wj * W * delta * ir * ir * irc;
-        g0 += c * x0; g1 += c * x1; g2 += c * x2;
-    }
+};
+
+// One pair of the force pass: a += V_j (1 - D_j) gradW, b += V_j Q_j gradW,
+// and the hourglass sum (1 - D_j) V_j W delta / |X_ij|^2 x_ij / |x_ij|.
+template <typename R>
+__device__ __forceinline__ void force_pair(const LRecB<R>& ni, const LRecB<R>& nj, R inv_h,
+                                           R wnorm, ForceAcc<R>& A, bool live = true) {
+    const R dx = R(nj.x - ni.x), dy = R(nj.y - ni.y), dz = R(nj.z - ni.z);
+    const R r = sqrt(fma(dx, dx, fma(dy, dy, dz * dz)));
+    const R ir = R(1) / r;
+    R W, dW;
+    spline(r, inv_h, wnorm, W, dW);
+    const R gs = dW * ir;
+    const R gx = gs * dx, gy = gs * dy, gz = gs * dz;
+    const R Vj = nj.V0;
+    const R wj = Vj * nj.omd;
+    const R na0 = fma(wj, gx, A.a0), na1 = fma(wj, gy, A.a1), na2 = fma(wj, gz, A.a2);
+    const R nb0 = fma(Vj, fma(nj.q[0], gx, fma(nj.q[1], gy, nj.q[2] * gz)), A.b0);
+    const R nb1 = fma(Vj, fma(nj.q[3], gx, fma(nj.q[4], gy, nj.q[5] * gz)), A.b1);
+    const R nb2 = fma(Vj, fma(nj.q[6], gx, fma(nj.q[7], gy, nj.q[8] * gz)), A.b2);
+    const R du0 = R(nj.ux - ni.ux), du1 = R(nj.uy - ni.uy), du2 = R(nj.uz - ni.uz);
+    const R x0 = dx + du0, x1 = dy + du1, x2 = dz + du2;
+    const R irc = R(1) / sqrt(fma(x0, x0, fma(x1, x1, x2 * x2)));
+    const R e0 = R(0.5) * fma(ni.h[0] + nj.h[0], dx, fma(ni.h[1] + nj.h[1], dy,
+                                                       (ni.h[2] + nj.h[2]) * dz)) - du0;
+    const R e1 = R(0.5) * fma(ni.h[3] + nj.h[3], dx, fma(ni.h[4] + nj.h[4], dy,
+                                                       (ni.h[5] + nj.h[5]) * dz)) - du1;
+    const R e2 = R(0.5) * fma(ni.h[6] + nj.h[6], dx, fma(ni.h[7] + nj.h[7], dy,
+                                                       (ni.h[8] + nj.h[8]) * dz)) - du2;
+    const R delta = fma(e0, x0, fma(e1, x1, e2 * x2)) * irc;
+    const R c = wj * W * delta * ir * ir * irc;
+    const R ng0 = fma(c, x0, A.g0), ng1 = fma(c, x1, A.g1), ng2 = fma(c, x2, A.g2);
+    // padding slots (live = false) leave the sums untouched
+    A.a0 = live ? na0 : A.a0; A.a1 = live ? na1 : A.a1; A.a2 = live ? na2 : A.a2;
+    A.b0 = live ? nb0 : A.b0; A.b1 = live ? nb1 : A.b1; A.b2 = live ? nb2 : A.b2;
+    A.g0 = live ? ng0 : A.g0; A.g1 = live ? ng1 : A.g1; A.g2 = live ? ng2 : A.g2;
+}
+
+// Nodal force, kick, prescribed velocities, failed particles at rest, drift,
+// rigid wall; stores v, V0 (1 - D), u^{n+1} and (for groups) the force.
+template <typename R>
+__device__ __forceinline__ void force_finish(const DevState& s, int64_t i, int par, const DevSpec& P,
+                                             int sp, const LRecB<R>& ni, const ForceAcc<R>& A) {
+    const int64_t np = s.np;
+    const double Di = s.D[i];
     const R omDi = R(1.0 - Di);
     const R hgk = R(-P.hg_alpha * P.E) * omDi;
-    const double Vi = xi.w;
-    const double f0 = Vi * double(gi.q[0] * a0 + gi.q[1] * a1 + gi.q[2] * a2 + omDi * b0 + hgk * g0);
-    const double f1 = Vi * double(gi.q[3] * a0 + gi.q[4] * a1 + gi.q[5] * a2 + omDi * b1 + hgk * g1);
-    const double f2 = Vi * double(gi.q[6] * a0 + gi.q[7] * a1 + gi.q[8] * a2 + omDi * b2 + hgk * g2);
-    // kick
+    const double Vi = s.XV[i].w;
+    const double f0 = Vi * double(ni.q[0] * A.a0 + ni.q[1] * A.a1 + ni.q[2] * A.a2 + omDi * A.b0 + hgk * A.g0);
+    const double f1 = Vi * double(ni.q[3] * A.a0 + ni.q[4] * A.a1 + ni.q[5] * A.a2 + omDi * A.b1 + hgk * A.g1);
+    const double f2 = Vi * double(ni.q[6] * A.a0 + ni.q[7] * A.a1 + ni.q[8] * A.a2 + omDi * A.b2 + hgk * A.g2);
     const double dt = P.dt;
     const double m = P.rho0 * Vi;
     const D4 vo = s.VW[i];
@@ -480,6 +616,7 @@ __global__ void __launch_bounds__(256) k_pass_b(DevState s, int par) {
     v[0] += dt * f0 / m;
     v[1] += dt * f1 / m;
     v[2] += dt * f2 / m;
+    const double xi = ni.x, yi = ni.y, zi = ni.z;
     const int g = s.bc[i];
     if (g >= 0) {
         const DevBC& B = s.bcs[g];
@@ -488,18 +625,18 @@ __global__ void __launch_bounds__(256) k_pass_b(DevState s, int par) {
 #pragma unroll
         for (int c = 0; c < 3; ++c)
             if (B.mask & (1 << c))
-                v[c] = B.v_max[c] * ramp + (B.grad[3 * c] * xi.x + B.grad[3 * c + 1] * xi.y +
-                                            B.grad[3 * c + 2] * xi.z);
+                v[c] = B.v_max[c] * ramp + (B.grad[3 * c] * xi + B.grad[3 * c + 1] * yi +
+                                            B.grad[3 * c + 2] * zi);
     }
     if (Di >= 1.0) v[0] = v[1] = v[2] = 0.0;
-    double un[3] = {ui.x + dt * v[0], ui.y + dt * v[1], ui.z + dt * v[2]};
+    double un[3] = {ni.ux + dt * v[0], ni.uy + dt * v[1], ni.uz + dt * v[2]};
     if (P.has_wall) {
-        const double xw[3] = {xi.x + un[0], xi.y + un[1], xi.z + un[2]};
+        const double xw[3] = {xi + un[0], yi + un[1], zi + un[2]};
         const double dn = xw[0] * P.wall_n[0] + xw[1] * P.wall_n[1] + xw[2] * P.wall_n[2] - P.wall_d;
         if (dn < 0.0) {
-            un[0] = (xw[0] - dn * P.wall_n[0]) - xi.x;
-            un[1] = (xw[1] - dn * P.wall_n[1]) - xi.y;
-            un[2] = (xw[2] - dn * P.wall_n[2]) - xi.z;
+            un[0] = (xw[0] - dn * P.wall_n[0]) - xi;
+            un[1] = (xw[1] - dn * P.wall_n[1]) - yi;
+            un[2] = (xw[2] - dn * P.wall_n[2]) - zi;
             const double vn = v[0] * P.wall_n[0] + v[1] * P.wall_n[1] + v[2] * P.wall_n[2];
             if (vn < 0.0) {
                 v[0] -= vn * P.wall_n[0];
@@ -513,6 +650,150 @@ __global__ void __launch_bounds__(256) k_pass_b(DevState s, int par) {
     if ((s.flags & kFlagStoreForce) || g >= 0) {
         s.force[i] = f0; s.force[np + i] = f1; s.force[2 * np + i] = f2;
     }
+}
+
+// Pass B (forces at t^n, kick, drift).  Nodal force of Sec. 3.1,
+//   f_i = V_i sum_j V_j [(1 - D_j) Q_i + (1 - D_i) Q_j] gradW_ij,
+// evaluated as V_i [Q_i a + (1 - D_i) b] with a = sum_j V_j (1 - D_j) gradW_ij
+// and b = sum_j V_j Q_j gradW_ij, plus hourglass control: with the error
+// vector e_ij = (F_i + F_j)/2 X_ij - x_ij and delta = e_ij . x_ij / |x_ij|,
+//   f_i^HG = -alpha E (1 - D_i) V_i sum_j (1 - D_j) V_j W_ij delta / |X_ij|^2
+//            x_ij / |x_ij|.
+// Then v += dt f / m, prescribed velocities at t^{n+1/2}, D = 1 at rest,
+// u^{n+1} = u^n + dt v (into the other displacement buffer), rigid wall, and
+// the record (v, V0 (1 - D)) the deformation pass gathers.  This variant
+// gathers neighbours straight from global memory.
+template <typename R>
+__global__ void __launch_bounds__(256) k_pass_b(DevState s, int par) {
+    const int64_t i = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (i >= s.n) return;
+    const int sp = s.spec[i];
+    const DevSpec& P = s.specs[sp];
+    const D4* __restrict__ XV = s.XV;
+    const D4* __restrict__ Uc = s.U[par];
+    const GBRec<R>* __restrict__ GB = gb_of<R>(s);
+    const LRecB<R> ni = make_recb<R>(XV[i], GB[i], Uc[i]);
+    const R inv_h = R(P.inv_h), wnorm = R(P.wnorm);
+    ForceAcc<R> A;
+    const int cnt = s.nnb[i];
+    const int32_t* __restrict__ cp = s.col + s.slice_ptr[i / kSlice] + (i % kSlice);
+    for (int k = 0; k < cnt; ++k) {
+        const int32_t j = cp[(int64_t)k * kSlice];
+        force_pair<R>(ni, make_recb<R>(XV[j], GB[j], Uc[j]), inv_h, wnorm, A);
+    }
+    force_finish<R>(s, i, par, P, sp, ni, A);
+}
+
+// LDS image of the force-pass records of one tile and its halo, stored
+// field-pair-major (array f of 16-byte elements holds one pair of fields for
+// every slot), so 64 lanes reading near-consecutive slots touch each bank at
+// most four times per 128-bit read.
+template <typename R>
+struct LdsB;
+template <>
+struct LdsB<double> {
+    static constexpr int kPairs = 13;   // 26 doubles
+    __device__ static void put(double2* L, int M, int m, const LRecB<double>& r) {
+        L[0 * M + m] = double2{r.x, r.y};
+        L[1 * M + m] = double2{r.z, r.V0};
+        L[2 * M + m] = double2{r.ux, r.uy};
+        L[3 * M + m] = double2{r.uz, r.omd};
+        L[4 * M + m] = double2{r.q[0], r.q[1]};
+        L[5 * M + m] = double2{r.q[2], r.q[3]};
+        L[6 * M + m] = double2{r.q[4], r.q[5]};
+        L[7 * M + m] = double2{r.q[6], r.q[7]};
+        L[8 * M + m] = double2{r.q[8], r.h[0]};
+        L[9 * M + m] = double2{r.h[1], r.h[2]};
+        L[10 * M + m] = double2{r.h[3], r.h[4]};
+        L[11 * M + m] = double2{r.h[5], r.h[6]};
+        L[12 * M + m] = double2{r.h[7], r.h[8]};
+    }
+    __device__ static LRecB<double> get(const double2* L, int M, int m) {
+        LRecB<double> r;
+        double2 t;
+        t = L[0 * M + m]; r.x = t.x; r.y = t.y;
+        t = L[1 * M + m]; r.z = t.x; r.V0 = t.y;
+        t = L[2 * M + m]; r.ux = t.x; r.uy = t.y;
+        t = L[3 * M + m]; r.uz = t.x; r.omd = t.y;
+        t = L[4 * M + m]; r.q[0] = t.x; r.q[1] = t.y;
+        t = L[5 * M + m]; r.q[2] = t.x; r.q[3] = t.y;
+        t = L[6 * M + m]; r.q[4] = t.x; r.q[5] = t.y;
+        t = L[7 * M + m]; r.q[6] = t.x; r.q[7] = t.y;
+        t = L[8 * M + m]; r.q[8] = t.x; r.h[0] = t.y;
+        t = L[9 * M + m]; r.h[1] = t.x; r.h[2] = t.y;
+        t = L[10 * M + m]; r.h[3] = t.x; r.h[4] = t.y;
+        t = L[11 * M + m]; r.h[5] = t.x; r.h[6] = t.y;
+        t = L[12 * M + m]; r.h[7] = t.x; r.h[8] = t.y;
+        return r;
+    }
+};
+template <>
+struct LdsB<float> {
+    static constexpr int kPairs = 8;    // 6 doubles + 20 floats = 8 x 16 bytes
+    __device__ static void put(double2* L, int M, int m, const LRecB<float>& r) {
+        L[0 * M + m] = double2{r.x, r.y};
+        L[1 * M + m] = double2{r.z, r.ux};
+        L[2 * M + m] = double2{r.uy, r.uz};
+        float4* F = reinterpret_cast<float4*>(L + 3 * M);
+        F[0 * M + m] = float4{r.V0, r.omd, r.q[0], r.q[1]};
+        F[1 * M + m] = float4{r.q[2], r.q[3], r.q[4], r.q[5]};
+        F[2 * M + m] = float4{r.q[6], r.q[7], r.q[8], r.h[0]};
+        F[3 * M + m] = float4{r.h[1], r.h[2], r.h[3], r.h[4]};
+        F[4 * M + m] = float4{r.h[5], r.h[6], r.h[7], r.h[8]};
+    }
+    __device__ static LRecB<float> get(const double2* L, int M, int m) {
+        LRecB<float> r;
+        double2 t;
+        t = L[0 * M + m]; r.x = t.x; r.y = t.y;
+        t = L[1 * M + m]; r.z = t.x; r.ux = t.y;
+        t = L[2 * M + m]; r.uy = t.x; r.uz = t.y;
+        const float4* F = reinterpret_cast<const float4*>(L + 3 * M);
+        float4 f;
+        f = F[0 * M + m]; r.V0 = f.x; r.omd = f.y; r.q[0] = f.z; r.q[1] = f.w;
+        f = F[1 * M + m]; r.q[2] = f.x; r.q[3] = f.y; r.q[4] = f.z; r.q[5] = f.w;
+        f = F[2 * M + m]; r.q[6] = f.x; r.q[7] = f.y; r.q[8] = f.z; r.h[0] = f.w;
+        f = F[3 * M + m]; r.h[1] = f.x; r.h[2] = f.y; r.h[3] = f.z; r.h[4] = f.w;
+        f = F[4 * M + m]; r.h[5] = f.x; r.h[6] = f.y; r.h[7] = f.z; r.h[8] = f.w;
+        return r;
+    }
+};
+
+// The same pass with the tile's particles and its halo staged in LDS: the
+// workgroup loads every record it needs once, then each lane runs its pair
+// sum from LDS through the 16-bit local neighbour slots.  Same arithmetic in
+// the same order as the unstaged kernel, so results are bitwise identical.
+// Occupancy is bounded by LDS, so the register budget is left to the
+// scheduler (one wave per SIMD).
+template <typename R>
+__global__ void __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_pass_b_staged(DevState s, int par) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    double2* __restrict__ L = reinterpret_cast<double2*>(lds_raw);
+    const int M = s.lds_slots;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t start = tile * kTile;
+    const int nh = s.halo_cnt[tile];
+    const int32_t* __restrict__ hl = s.halo + tile * (int64_t)s.halo_cap;
+    const D4* __restrict__ XV = s.XV;
+    const D4* __restrict__ Uc = s.U[par];
+    const GBRec<R>* __restrict__ GB = gb_of<R>(s);
+    for (int m = threadIdx.x; m < kTile + nh; m += kTile) {
+        const int64_t g = m < kTile ? start + m : (int64_t)hl[m - kTile];
+        if (g < s.n) LdsB<R>::put(L, M, m, make_recb<R>(XV[g], GB[g], Uc[g]));
+    }
+    __syncthreads();
+    const int64_t i = start + threadIdx.x;
+    if (i >= s.n) return;
+    const int sp = s.spec[i];
+    const DevSpec& P = s.specs[sp];
+    const LRecB<R> ni = LdsB<R>::get(L, M, threadIdx.x);
+    const R inv_h = R(P.inv_h), wnorm = R(P.wnorm);
+    ForceAcc<R> A;
+    const int cnt = s.nnb[i];
+    const uint16_t* __restrict__ lp = s.lcol + s.slice_ptr[i / kSlice] + (i % kSlice);
+    for (int k = 0; k < cnt; ++k)
+        force_pair<R>(ni, LdsB<R>::get(L, M, lp[(int64_t)k * kSlice]), inv_h, wnorm, A);
+    force_finish<R>(s, i, par, P, sp, ni, A);
 }
 
 // Pass A (deformation and constitutive update to t^{n+1}).
@@ -540,16 +821,16 @@ __global__ void __launch_bounds__(256) k_pass_a(DevState s, int par) {
         const D4 xj = XV[j];
         const D4 vj = VW[j];
         const R dx = R(xj.x - xi.x), dy = R(xj.y - xi.y), dz = R(xj.z - xi.z);
-        const R r = sqrt(dx * dx + dy * dy + dz * dz);
+        const R r = sqrt(fma(dx, dx, fma(dy, dy, dz * dz)));
         R W, dW;
         spline(r, inv_h, wnorm, W, dW);
         const R gs = dW / r;
         const R gx = gs * dx, gy = gs * dy, gz = gs * dz;
         const R wj = R(vj.w);
         const R t0 = wj * R(vj.x - vi.x), t1 = wj * R(vj.y - vi.y), t2 = wj * R(vj.z - vi.z);
-        M[0] += t0 * gx; M[1] += t0 * gy; M[2] += t0 * gz;
-        M[3] += t1 * gx; M[4] += t1 * gy; M[5] += t1 * gz;
-        M[6] += t2 * gx; M[7] += t2 * gy; M[8] += t2 * gz;
+        M[0] = fma(t0, gx, M[0]); M[1] = fma(t0, gy, M[1]); M[2] = fma(t0, gz, M[2]);
+        M[3] = fma(t1, gx, M[3]); M[4] = fma(t1, gy, M[4]); M[5] = fma(t1, gz, M[5]);
+        M[6] = fma(t2, gx, M[6]); M[7] = fma(t2, gy, M[7]); M[8] = fma(t2, gz, M[8]);
     }
     R Li[9];
     if constexpr (std::is_same<R, float>::value) {
@@ -629,13 +910,38 @@ __global__ void __launch_bounds__(256) k_pass_a(DevState s, int par) {
     }
 }
 
-hipError_t launch_pass_b(const DevState& s, int parity, int block, bool mixed, hipStream_t st) {
+hipError_t launch_pass_b(const DevState& s, int parity, int block, bool mixed, hipStream_t st,
+                         size_t lds_bytes) {
+    if (s.staged) {
+        const unsigned grid = (unsigned)((s.n + kTile - 1) / kTile);
+        if (mixed)
+            k_pass_b_staged<float><<<grid, kTile, lds_bytes, st>>>(s, parity);
+        else
+            k_pass_b_staged<double><<<grid, kTile, lds_bytes, st>>>(s, parity);
+        return hipGetLastError();
+    }
     const unsigned grid = (unsigned)((s.n + block - 1) / block);
     if (mixed)
         k_pass_b<float><<<grid, block, 0, st>>>(s, parity);
     else
         k_pass_b<double><<<grid, block, 0, st>>>(s, parity);
     return hipGetLastError();
+}
+
+size_t staged_record_bytes(bool mixed) {
+    return 16 * (size_t)(mixed ? LdsB<float>::kPairs : LdsB<double>::kPairs);
+}
+
+// Dynamic LDS above the default limit must be allowed per kernel.
+hipError_t prepare_staged(size_t lds_bytes_b) {
+    const void* fns[2] = {reinterpret_cast<const void*>(&k_pass_b_staged<double>),
+                          reinterpret_cast<const void*>(&k_pass_b_staged<float>)};
+    for (const void* f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds_bytes_b);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_pass_a(const DevState& s, int parity, int block, bool mixed, hipStream_t st) {

@@ -88,8 +88,8 @@ __host__ __device__ __forceinline__ void spline(R r, R inv_h, R wnorm, R& W, R& 
     const R q = r * inv_h;
     const R a = R(1) - q;
     if (q < R(0.5)) {
-        W = wnorm * (R(1) + q * q * (R(6) * q - R(6)));
-        dW = wnorm * inv_h * (q * (R(18) * q - R(12)));
+        W = wnorm * fma(q * q, fma(R(6), q, R(-6)), R(1));
+        dW = wnorm * inv_h * (q * fma(R(18), q, R(-12)));
     } else {
         W = wnorm * R(2) * a * a * a;
         dW = wnorm * inv_h * (R(-6) * a * a);

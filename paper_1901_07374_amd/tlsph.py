@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtlsph.so")
 
 FP64, MIXED = 0, 1
-STORE_FORCE, USE_GRAPHS, CHECK_FINITE = 1, 2, 4
+STORE_FORCE, USE_GRAPHS, CHECK_FINITE, NO_STAGING = 1, 2, 4, 8
 
 FIELDS = {"X": (0, 3), "u": (1, 3), "v": (2, 3), "F": (3, 9), "sig": (4, 6), "eps_p": (5, 1),
           "eps_p_rate": (6, 1), "d_init": (7, 1), "w_p": (8, 1), "f_void": (9, 1), "D": (10, 1),
@@ -276,5 +276,5 @@ class Sim:
     def info(self) -> Dict[str, int]:
         out = (C.c_int64 * 6)()
         self._check(lib().tlsph_info(self.ctx, out), "tlsph_info")
-        return dict(block_force=out[0], block_deformation=out[1], nnz=out[2], slots=out[3],
-                    n=out[4], flags=out[5])
+        return dict(block_force=abs(out[0]), staged=out[0] < 0, block_deformation=out[1],
+                    nnz=out[2], slots=out[3], n=out[4], flags=out[5])
