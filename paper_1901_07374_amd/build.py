@@ -36,3 +36,14 @@ def build(verbose: bool = False) -> str:
 if __name__ == "__main__":
     build(verbose="-v" in sys.argv)
     print(LIB)
+
+
+def source_hash() -> str:
+    """Short digest of the device sources: counter summaries taken on other
+    sources are recognised as stale."""
+    import hashlib
+    h = hashlib.sha1()
+    for f in ("tlsph_kernels.hip", "tlsph_math.h", "tlsph_internal.h"):
+        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
