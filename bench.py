@@ -17,7 +17,6 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -30,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle-steps/s + achieved HBM GB/s; mixed FP32 vs FP64 at stated error"
 HBM_PEAK_GBS = 8000.0
-DIAG_EVERY = 250
+DIAG_EVERY = 20
 TIMING_STRIDE = 10
 
 # Algorithmic HBM bytes per particle of each step kernel: every per-particle
@@ -55,17 +54,19 @@ def algorithmic_bytes(kernel: str, mixed: bool, damage: int, n: int, nnz: int) -
     return per * n + 4 * nnz
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha1()
-    for f in ("tlsph_kernels.hip", "tlsph_math.h", "tlsph_internal.h"):
-        with open(os.path.join(ROOT, "paper_1901_07374_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+def kernel_symbol(kernel: str, info: dict, mixed: bool) -> str:
+    r = "float" if mixed else "double"
+    if kernel == "force_pass":
+        name = "k_pass_b_staged" if info["staged"] else "k_pass_b"
+        return f"{name}<{r}, {info['lanes_per_particle']}>"
+    return f"k_pass_a<{r}>"
 
 
-def counter_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary,
-    if it was taken on the kernels as they are now (else None)."""
+def counter_traffic(symbol: str, workload: str):
+    """HBM bytes per launch of one kernel from the committed rocprofv3
+    counter summary, if it was taken on the kernels as they are now (else
+    None)."""
+    from paper_1901_07374_amd.build import source_hash
     path = os.path.join(ROOT, "profiles", f"pmc_{workload}.txt")
     if not os.path.exists(path):
         return None
@@ -75,24 +76,31 @@ def counter_traffic(kernel: str, workload: str):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_hash") != kernel_source_hash():
+    if vals.get("kernel_source_hash") != source_hash():
         return None
-    key = f"{kernel}_hbm_bytes_per_launch"
+    key = f"{symbol}_hbm_bytes_per_launch"
     return float(vals[key]) if key in vals else None
 
 
 def failure_displacement(sep, reaction):
     """Grip separation where the reaction first drops below 10 % of its running
-    maximum after the peak (None if it never does)."""
+    maximum after the peak, interpolated linearly between samples (None if it
+    never does)."""
     run_max = 0.0
     peak_seen = False
+    prev = None
     for s, r in zip(sep, reaction):
         if r > run_max:
             run_max = r
         elif run_max > 0 and r < 0.98 * run_max:
             peak_seen = True
         if peak_seen and r < 0.1 * run_max:
-            return float(s)
+            if prev is None or prev[1] <= r:
+                return float(s)
+            s0, r0 = prev
+            lvl = 0.1 * run_max
+            return float(s0 + (s - s0) * (r0 - lvl) / (r0 - r))
+        prev = (s, r)
     return None
 
 
@@ -198,10 +206,11 @@ def main():
     dom = max(kts, key=kts.get)
     bytes_launch = algorithmic_bytes(dom, False, damage, prob.n, nnz)
     achieved = bytes_launch / (kts[dom] * 1e-3) / 1e9
-    traffic = counter_traffic(dom, workload)
+    symbol = kernel_symbol(dom, fp["info"], False)
+    traffic = counter_traffic(symbol, workload)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": dom,
+                "traffic": traffic, "kernel": dom, "symbol": symbol,
                 "avg_launch_us": round(kts[dom] * 1e3, 2),
                 "algorithmic_bytes_per_launch": bytes_launch}
     step_bytes = sum(algorithmic_bytes(k, False, damage, prob.n, nnz) for k in kts)
@@ -219,6 +228,7 @@ def main():
                    "force_pass_variant": ("LDS-staged tiles" if fp["info"]["staged"] else
                                           "global gathers"),
                    "launch_shape": {"force_pass": fp["info"]["block_force"],
+                                    "force_lanes_per_particle": fp["info"]["lanes_per_particle"],
                                     "deformation_pass": fp["info"]["block_deformation"]},
                    "steps_from_rest": args.warmup + args.steps,
                    "dt_s": prob.materials[0]["dt"]},

@@ -228,11 +228,22 @@ tlsph_status tlsph_enable_kernel_timing(tlsph_ctx *ctx, int32_t stride);
 tlsph_status tlsph_kernel_times(tlsph_ctx *ctx, double ms[2], int64_t launches[2]);
 
 /* Launch shape and layout facts: [0] threads per block of the force pass
- * (negative when the LDS-staged variant is in use),
- * [1] of the deformation pass, [2] neighbour pairs, [3] padded slots of the
- * sliced neighbour layout, [4] particles, [5] sticky device error flags
- * (bit 0 non-finite, bit 1 GTN Newton not converged). */
-tlsph_status tlsph_info(tlsph_ctx *ctx, int64_t out[6]);
+ * (negative when the LDS-staged variant is in use), [1] of the deformation
+ * pass, [2] neighbour pairs, [3] padded slots of the sliced neighbour layout,
+ * [4] particles, [5] sticky device error flags (bit 0 non-finite, bit 1 GTN
+ * Newton not converged), [6] lanes per particle of the force pass, [7] LDS
+ * bytes per workgroup of the staged force pass (0 when unstaged). */
+tlsph_status tlsph_info(tlsph_ctx *ctx, int64_t out[8]);
+
+/* Pin the launch shape (host int32[4]): [0] 1 = LDS-staged force pass, 0 =
+ * gathers from global memory; [1] lanes per particle of the force pass (1,
+ * 2 or 4); [2] threads per block of the unstaged force pass (64, 128, 192 or
+ * 256; ignored when staged, which runs 256 particles per block); [3] threads
+ * per block of the deformation pass (64 to 256, multiple of 64).  Every shape
+ * gives bitwise identical results: the neighbour sums keep one canonical
+ * order.  Errors: INVALID_ARG, BAD_STATE (before build), UNSUPPORTED (staged
+ * requested where the tile and halo records do not fit in LDS). */
+tlsph_status tlsph_set_launch_shape(tlsph_ctx *ctx, const int32_t shape[4]);
 
 /* Free the host-side context (not the workspace).  Null is accepted. */
 void tlsph_destroy(tlsph_ctx *ctx);

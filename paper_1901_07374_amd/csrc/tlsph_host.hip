@@ -39,7 +39,8 @@ struct Layout {
     int64_t n_tiles;
     int32_t halo_cap;
     size_t GB, U0, U1, VW, sig, eps_p, eps_rate, d_init, w_p, f_void, e, D, force, err,
-        spec_off, bbox, keys, vals, bc_list, bc_ptr, backup;
+        spec_off, bbox, keys, vals, bc_list, bc_ptr, diag_seg, diag_part, backup;
+    int64_t diag_chunk_cap;
     size_t state_begin, backup_bytes;
     size_t total;
 };
@@ -102,6 +103,11 @@ Layout make_layout(int64_t n, int32_t n_spec, int32_t n_bc, int32_t k_cap, bool 
     L.vals = take((size_t)L.n_pow2 * 4);
     L.bc_list = take(np * 4);
     L.bc_ptr = take(((size_t)n_bc + 2) * 8);
+    // diagnostics partials: sum over segments of ceil(size / chunk), at most
+    // 2 n / chunk + one per segment
+    L.diag_chunk_cap = 2 * (n / kDiagChunk) + n_spec + n_bc + 2;
+    L.diag_seg = take(((size_t)n_spec + n_bc + 1) * 8);
+    L.diag_part = take((size_t)L.diag_chunk_cap * kNDiag * 8);
     L.backup = take(L.backup_bytes + (size_t)n_spec * 8);
     L.total = align_up(cur);
     return L;
@@ -123,7 +129,8 @@ struct tlsph_ctx {
     bool built = false;
     int parity = 0;
     int64_t nnz = 0, slots = 0;
-    int block_a = 256, block_b = 256;
+    int64_t diag_chunks_spec = 0, diag_chunks_all = 0;
+    int block_a = 256, block_b = 256, sub_b = 4;
     bool staged_ok = false;     // the staged force pass fits this device's LDS
     size_t lds_b = 0;           // its dynamic LDS bytes
     std::string last_error;
@@ -137,7 +144,7 @@ struct tlsph_ctx {
     // graphs
     hipGraphExec_t gexec = nullptr;
     int graph_parity = -1;
-    int graph_block_a = 0, graph_block_b = 0;
+    int graph_block_a = 0, graph_block_b = 0, graph_sub_b = 0;
 };
 
 namespace {
@@ -242,7 +249,8 @@ tlsph_status run_steps_eager(tlsph_ctx* c, int32_t n_steps, hipStream_t stream) 
                 c->ev_marks.push_back({pass, idx});
             }
             hipError_t e = pass == 0
-                               ? launch_pass_b(c->st, c->parity, c->block_b, mixed, stream, c->lds_b)
+                               ? launch_pass_b(c->st, c->parity, c->block_b, c->sub_b, mixed,
+                                               stream, c->lds_b)
                                : launch_pass_a(c->st, c->parity, c->block_a, mixed, stream);
             if (e != hipSuccess) return hip_fail(c, e, pass == 0 ? "force pass" : "deformation pass");
             if (timed) HIPCHK(c, hipEventRecord(e1, stream));
@@ -254,7 +262,8 @@ tlsph_status run_steps_eager(tlsph_ctx* c, int32_t n_steps, hipStream_t stream) 
 
 tlsph_status ensure_graph(tlsph_ctx* c, hipStream_t stream) {
     if (c->gexec && c->graph_parity == c->parity && c->graph_block_a == c->block_a &&
-        c->graph_block_b == (c->st.staged ? -c->block_b : c->block_b))
+        c->graph_block_b == (c->st.staged ? -c->block_b : c->block_b) &&
+        c->graph_sub_b == c->sub_b)
         return TLSPH_OK;
     if (c->gexec) {
         (void)hipGraphExecDestroy(c->gexec);
@@ -277,6 +286,7 @@ tlsph_status ensure_graph(tlsph_ctx* c, hipStream_t stream) {
     c->graph_parity = p0;
     c->graph_block_a = c->block_a;
     c->graph_block_b = c->st.staged ? -c->block_b : c->block_b;
+    c->graph_sub_b = c->sub_b;
     return TLSPH_OK;
 }
 
@@ -387,6 +397,9 @@ tlsph_status tlsph_create(int64_t n, int32_t n_spec, const int64_t* spec_offsets
     c->bcs.resize(n_bc > 0 ? n_bc : 1);
     for (int32_t g = 0; g < n_bc; ++g) c->bcs[g] = to_dev(bc[g]);
     wire_state(c);
+    c->st.model = spec[0].damage;
+    for (int32_t q = 1; q < n_spec; ++q)
+        if (spec[q].damage != spec[0].damage) c->st.model = -1;
     const Layout& L = c->L;
     hipError_t e = hipMemcpyAsync(c->ws + L.specs, c->specs.data(), n_spec * sizeof(DevSpec),
                                   hipMemcpyHostToDevice, stream);
@@ -443,6 +456,8 @@ tlsph_status tlsph_build_neighbors(tlsph_ctx* c, const double* X, const double* 
     c->st.staged = 0;
     c->staged_ok = false;
     c->lds_b = 0;
+    c->block_b = 256;
+    c->sub_b = 4;
     int dev = 0, max_lds = 0;
     HIPCHK(c, hipGetDevice(&dev));
     HIPCHK(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -469,7 +484,26 @@ tlsph_status tlsph_build_neighbors(tlsph_ctx* c, const double* X, const double* 
             c->lds_b = lds;
             c->st.lds_slots = kTile + err[4];
             c->st.staged = 1;
+            c->block_b = kTile * c->sub_b;
         }
+    }
+    // diagnostics segments: chunks of each specimen, then of each group
+    {
+        std::vector<int64_t> bptr((size_t)L.n_bc + 1, 0);
+        if (L.n_bc > 0)
+            HIPCHK(c, hipMemcpy(bptr.data(), c->ws + L.bc_ptr, bptr.size() * 8,
+                                hipMemcpyDeviceToHost));
+        std::vector<int64_t> seg((size_t)L.n_spec + L.n_bc + 1, 0);
+        auto chunks = [](int64_t m) { return m > 0 ? (m + kDiagChunk - 1) / kDiagChunk : 1; };
+        for (int32_t q = 0; q < L.n_spec; ++q)
+            seg[q + 1] = seg[q] + chunks(c->spec_off[q + 1] - c->spec_off[q]);
+        for (int32_t g = 0; g < L.n_bc; ++g)
+            seg[L.n_spec + g + 1] = seg[L.n_spec + g] + chunks(bptr[g + 1] - bptr[g]);
+        if (seg.back() > L.diag_chunk_cap)
+            return fail(c, TLSPH_E_HIP, "diagnostics chunk table exceeds its capacity");
+        HIPCHK(c, hipMemcpy(c->ws + L.diag_seg, seg.data(), seg.size() * 8, hipMemcpyHostToDevice));
+        c->diag_chunks_spec = seg[L.n_spec];
+        c->diag_chunks_all = seg.back();
     }
     // neighbour pairs: sum of counts
     std::vector<int32_t> cnt(L.np);
@@ -561,8 +595,12 @@ tlsph_status tlsph_get_diagnostics(tlsph_ctx* c, double* spec_diag, double* bc_d
                                    hipStream_t stream) {
     if (!c || !spec_diag) return fail(c, TLSPH_E_INVALID_ARG, "null argument");
     if (!c->built) return fail(c, TLSPH_E_BAD_STATE, "diagnostics before build");
+    const bool groups = bc_diag != nullptr && c->L.n_bc > 0;
     HIPCHK(c, launch_diagnostics(c->st, c->parity, at<int32_t>(c, c->L.bc_list),
-                                 at<int64_t>(c, c->L.bc_ptr), spec_diag, bc_diag, stream));
+                                 at<int64_t>(c, c->L.bc_ptr), at<int64_t>(c, c->L.diag_seg),
+                                 groups ? c->L.n_spec + c->L.n_bc : c->L.n_spec,
+                                 groups ? c->diag_chunks_all : c->diag_chunks_spec,
+                                 at<double>(c, c->L.diag_part), spec_diag, bc_diag, stream));
     return TLSPH_OK;
 }
 
@@ -614,43 +652,65 @@ tlsph_status tlsph_autotune(tlsph_ctx* c, hipStream_t stream) {
     HIPCHK(c, hipMemcpyAsync(backup, state, L.backup_bytes, hipMemcpyDeviceToDevice, stream));
     HIPCHK(c, hipMemcpyAsync(backup + L.backup_bytes, c->st.t, L.n_spec * 8,
                              hipMemcpyDeviceToDevice, stream));
-    const int cand[4] = {64, 128, 256, 0};  // 0: LDS-staged force pass (256 threads)
+    // force pass: (staged, lanes per particle, block); deformation pass: block
+    struct Cand { int staged, sub, block; };
+    const Cand cand_b[] = {{1, 4, 0}, {1, 2, 0}, {1, 1, 0}, {0, 4, 256}, {0, 4, 128},
+                           {0, 2, 128}, {0, 1, 64}, {0, 1, 128}, {0, 1, 256}};
+    const int cand_a[] = {64, 128, 256};
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
     const int reps = 5;
-    for (int pass = 0; pass < 2; ++pass) {
+    auto timed = [&](auto&& launch, float* ms) -> tlsph_status {
+        // every candidate starts from the saved state
+        HIPCHK(c, hipMemcpyAsync(state, backup, L.backup_bytes, hipMemcpyDeviceToDevice, stream));
+        hipError_t e = hipSuccess;
+        for (int r = 0; r < reps + 1 && e == hipSuccess; ++r) {
+            if (r == 1) HIPCHK(c, hipEventRecord(e0, stream));
+            e = launch();
+        }
+        if (e != hipSuccess) return hip_fail(c, e, "autotune launch");
+        HIPCHK(c, hipEventRecord(e1, stream));
+        HIPCHK(c, hipEventSynchronize(e1));
+        HIPCHK(c, hipEventElapsedTime(ms, e0, e1));
+        return TLSPH_OK;
+    };
+    {
         float best = 1e30f;
-        int best_b = 256;
-        for (int b : cand) {
-            if (b == 0 && (pass == 1 || !c->staged_ok)) continue;
-            if (pass == 0) c->st.staged = (b == 0) ? 1 : 0;
-            // every candidate starts from the saved state
-            HIPCHK(c, hipMemcpyAsync(state, backup, L.backup_bytes, hipMemcpyDeviceToDevice,
-                                     stream));
-            hipError_t e = hipSuccess;
-            for (int r = 0; r < reps + 1 && e == hipSuccess; ++r) {
-                if (r == 1) HIPCHK(c, hipEventRecord(e0, stream));
-                e = pass == 0 ? launch_pass_b(c->st, c->parity, b == 0 ? 256 : b, L.mixed, stream,
-                                              c->lds_b)
-                              : launch_pass_a(c->st, c->parity, b, L.mixed, stream);
-            }
-            if (e != hipSuccess) return hip_fail(c, e, "autotune launch");
-            HIPCHK(c, hipEventRecord(e1, stream));
-            HIPCHK(c, hipEventSynchronize(e1));
+        Cand pick{0, c->sub_b, c->block_b};
+        for (const Cand& k : cand_b) {
+            if (k.staged && !c->staged_ok) continue;
+            c->st.staged = k.staged;
+            const int blk = k.staged ? kTile * k.sub : k.block;
             float t = 0.0f;
-            HIPCHK(c, hipEventElapsedTime(&t, e0, e1));
+            tlsph_status st = timed([&] {
+                return launch_pass_b(c->st, c->parity, blk, k.sub, L.mixed, stream, c->lds_b);
+            }, &t);
+            if (st != TLSPH_OK) return st;
             if (t < best) {
                 best = t;
-                best_b = b;
+                pick = Cand{k.staged, k.sub, blk};
             }
         }
-        if (pass == 0) {
-            c->st.staged = best_b == 0 ? 1 : 0;
-            c->block_b = best_b == 0 ? 256 : best_b;
-        } else {
-            c->block_a = best_b;
+        c->st.staged = pick.staged;
+        c->sub_b = pick.sub;
+        c->block_b = pick.block;
+    }
+    {
+        float best = 1e30f;
+        int pick = c->block_a;
+        for (int b : cand_a) {
+            float t = 0.0f;
+            tlsph_status st = timed([&] {
+                return launch_pass_a(c->st, c->parity, b, L.mixed, stream);
+            }, &t);
+            if (st != TLSPH_OK) return st;
+            if (t < best) {
+                best = t;
+                pick = b;
+            }
         }
+        c->block_a = pick;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -661,7 +721,7 @@ tlsph_status tlsph_autotune(tlsph_ctx* c, hipStream_t stream) {
     return TLSPH_OK;
 }
 
-tlsph_status tlsph_info(tlsph_ctx* c, int64_t out[6]) {
+tlsph_status tlsph_info(tlsph_ctx* c, int64_t out[8]) {
     if (!c || !out) return TLSPH_E_INVALID_ARG;
     out[0] = c->st.staged ? -c->block_b : c->block_b;
     out[1] = c->block_a;
@@ -669,11 +729,32 @@ tlsph_status tlsph_info(tlsph_ctx* c, int64_t out[6]) {
     out[3] = c->slots;
     out[4] = c->L.n;
     out[5] = 0;
+    out[6] = c->sub_b;
+    out[7] = c->st.staged ? (int64_t)c->lds_b : 0;
     if (c->built) {
         int32_t fl = 0;
         HIPCHK(c, hipMemcpy(&fl, c->ws + c->L.err + 8, 4, hipMemcpyDeviceToHost));
         out[5] = fl;
     }
+    return TLSPH_OK;
+}
+
+tlsph_status tlsph_set_launch_shape(tlsph_ctx* c, const int32_t shape[4]) {
+    if (!c || !shape) return TLSPH_E_INVALID_ARG;
+    if (!c->built) return fail(c, TLSPH_E_BAD_STATE, "launch shape before build");
+    const int32_t staged = shape[0], sub = shape[1], blk_b = shape[2], blk_a = shape[3];
+    if (staged != 0 && staged != 1) return fail(c, TLSPH_E_INVALID_ARG, "staged must be 0 or 1");
+    if (staged && !c->staged_ok)
+        return fail(c, TLSPH_E_UNSUPPORTED, "the LDS-staged force pass does not fit this input");
+    if (sub != 1 && sub != 2 && sub != 4) return fail(c, TLSPH_E_INVALID_ARG, "lanes per particle");
+    if (!staged && (blk_b < 64 || blk_b > 256 || blk_b % 64 != 0))
+        return fail(c, TLSPH_E_INVALID_ARG, "force-pass block must be 64, 128, 192 or 256");
+    if (blk_a < 64 || blk_a > 256 || blk_a % 64 != 0)
+        return fail(c, TLSPH_E_INVALID_ARG, "deformation-pass block must be 64, 128, 192 or 256");
+    c->st.staged = staged;
+    c->sub_b = sub;
+    c->block_b = staged ? kTile * sub : blk_b;
+    c->block_a = blk_a;
     return TLSPH_OK;
 }
 

@@ -9,7 +9,9 @@ namespace tlsph {
 constexpr int kSlice = 64;          // particles per slice of the sliced neighbour layout
 constexpr int kMortonBits = 14;     // cells per axis < 2^14
 constexpr int kSpecShift = 3 * kMortonBits;
+constexpr int kSub = 4;            // partial sums per particle in the force pass (canonical order)
 constexpr int kNDiag = 8;          // doubles per diagnostics record
+constexpr int kDiagChunk = 2048;   // particles per partial sum of the diagnostics
 constexpr int kTile = 256;         // particles per workgroup tile of the LDS-staged passes
 constexpr int kHaloSortMax = 8192; // tile entries sorted in LDS at build (kTile * k_cap)
 
@@ -105,7 +107,7 @@ struct DevState {
     int32_t halo_cap;
     int32_t staged;           // 1 when the staged force pass is in use
     int32_t lds_slots;        // slots per field array of the staged kernel's LDS image
-    int32_t pad2_;
+    int32_t model;            // damage model shared by every specimen, -1 if they differ
 };
 
 enum : uint32_t { kFlagStoreForce = 1u, kFlagGraphs = 2u, kFlagCheckFinite = 4u,
@@ -113,8 +115,10 @@ enum : uint32_t { kFlagStoreForce = 1u, kFlagGraphs = 2u, kFlagCheckFinite = 4u,
 enum : int32_t { kErrNonFinite = 1, kErrNewton = 2 };
 
 // launch helpers implemented in tlsph_kernels.hip
-hipError_t launch_pass_b(const DevState& s, int parity, int block, bool mixed, hipStream_t st,
-                         size_t lds_bytes = 0);
+// Force pass: `sub` lanes per particle (1, 2 or 4); the unstaged variant runs
+// `block` threads per workgroup, the LDS-staged one kTile * sub.
+hipError_t launch_pass_b(const DevState& s, int parity, int block, int sub, bool mixed,
+                         hipStream_t st, size_t lds_bytes = 0);
 hipError_t launch_pass_a(const DevState& s, int parity, int block, bool mixed, hipStream_t st);
 
 struct BuildBuffers {
@@ -140,8 +144,12 @@ hipError_t launch_set_field(const DevState& s, int field, int parity, bool mixed
                             const double* src, hipStream_t st);
 hipError_t launch_export_neighbors(const DevState& s, int64_t* row_ptr, int32_t* col,
                                    int64_t* scratch, hipStream_t st);
+// Two-level fixed-order reductions: chunk partials (seg[q] .. seg[q+1] are the
+// chunks of segment q: specimens first, then boundary groups), then one block
+// per segment.
 hipError_t launch_diagnostics(const DevState& s, int parity, const int32_t* bc_list,
-                              const int64_t* bc_ptr, double* spec_diag, double* bc_diag,
+                              const int64_t* bc_ptr, const int64_t* seg, int32_t n_seg,
+                              int64_t n_chunks, double* part, double* spec_diag, double* bc_diag,
                               hipStream_t st);
 hipError_t launch_bc_lists(const DevState& s, uint64_t* keys, int32_t* vals, int64_t n_pow2,
                            int32_t* bc_list, int64_t* bc_ptr, hipStream_t st);

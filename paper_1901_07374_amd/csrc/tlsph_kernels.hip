@@ -596,6 +596,69 @@ __device__ __forceinline__ void force_pair(const LRecB<R>& ni, const LRecB<R>& n
     A.g0 = live ? ng0 : A.g0; A.g1 = live ? ng1 : A.g1; A.g2 = live ? ng2 : A.g2;
 }
 
+template <typename R>
+__device__ __forceinline__ ForceAcc<R> acc_sum(const ForceAcc<R>& x, const ForceAcc<R>& y) {
+    ForceAcc<R> r;
+    r.a0 = x.a0 + y.a0; r.a1 = x.a1 + y.a1; r.a2 = x.a2 + y.a2;
+    r.b0 = x.b0 + y.b0; r.b1 = x.b1 + y.b1; r.b2 = x.b2 + y.b2;
+    r.g0 = x.g0 + y.g0; r.g1 = x.g1 + y.g1; r.g2 = x.g2 + y.g2;
+    return r;
+}
+
+template <typename R>
+__device__ __forceinline__ ForceAcc<R> acc_xor(const ForceAcc<R>& x, int m) {
+    ForceAcc<R> r;
+    r.a0 = __shfl_xor(x.a0, m); r.a1 = __shfl_xor(x.a1, m); r.a2 = __shfl_xor(x.a2, m);
+    r.b0 = __shfl_xor(x.b0, m); r.b1 = __shfl_xor(x.b1, m); r.b2 = __shfl_xor(x.b2, m);
+    r.g0 = __shfl_xor(x.g0, m); r.g1 = __shfl_xor(x.g1, m); r.g2 = __shfl_xor(x.g2, m);
+    return r;
+}
+
+// Pair sums of one particle in the canonical order of the force pass:
+// neighbour k feeds partial sum k mod kSub (each partial in increasing k) and
+// the partials combine as (p0 + p1) + (p2 + p3).  S adjacent lanes share a
+// particle (S = 1, 2 or 4), lane `sub` holding partials sub, sub + S, ...;
+// every S rounds identically.  All lanes of the wave must call this (the
+// partials are exchanged across lanes); lanes without a particle pass cnt = 0.
+template <typename R, int S, typename IdxOf, typename RecOf>
+__device__ __forceinline__ ForceAcc<R> pair_sums(const LRecB<R>& ni, int cnt, int sub, R inv_h,
+                                                 R wnorm, IdxOf idx, RecOf rec) {
+    static_assert(kSub == 4 && (S == 1 || S == 2 || S == 4), "canonical order has 4 partials");
+    constexpr int NP = kSub / S;
+    ForceAcc<R> A[NP];
+    // neighbour indices run one group of kSub ahead of the arithmetic
+    int nxt[NP];
+#pragma unroll
+    for (int t = 0; t < NP; ++t) {
+        const int k = sub + S * t;
+        nxt[t] = idx(k < cnt ? k : 0);
+    }
+    for (int k0 = 0; k0 < cnt; k0 += kSub) {
+        int cur[NP];
+#pragma unroll
+        for (int t = 0; t < NP; ++t) {
+            cur[t] = nxt[t];
+            const int kn = k0 + kSub + sub + S * t;
+            nxt[t] = idx(kn < cnt ? kn : 0);
+        }
+#pragma unroll
+        for (int t = 0; t < NP; ++t) {
+            const int k = k0 + sub + S * t;
+            force_pair<R>(ni, rec(cur[t]), inv_h, wnorm, A[t], k < cnt);
+        }
+    }
+    if constexpr (S == 1) {
+        return acc_sum(acc_sum(A[0], A[1]), acc_sum(A[2], A[3]));
+    } else if constexpr (S == 2) {
+        const ForceAcc<R> x = acc_sum(A[0], acc_xor(A[0], 1));   // p0 + p1
+        const ForceAcc<R> y = acc_sum(A[1], acc_xor(A[1], 1));   // p2 + p3
+        return acc_sum(x, y);
+    } else {
+        const ForceAcc<R> x = acc_sum(A[0], acc_xor(A[0], 1));   // p0 + p1 | p2 + p3
+        return acc_sum(x, acc_xor(x, 2));
+    }
+}
+
 // Nodal force, kick, prescribed velocities, failed particles at rest, drift,
 // rigid wall; stores v, V0 (1 - D), u^{n+1} and (for groups) the force.
 template <typename R>
@@ -663,25 +726,30 @@ __device__ __forceinline__ void force_finish(const DevState& s, int64_t i, int p
 // u^{n+1} = u^n + dt v (into the other displacement buffer), rigid wall, and
 // the record (v, V0 (1 - D)) the deformation pass gathers.  This variant
 // gathers neighbours straight from global memory.
-template <typename R>
-__global__ void __launch_bounds__(256) k_pass_b(DevState s, int par) {
-    const int64_t i = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (i >= s.n) return;
-    const int sp = s.spec[i];
+template <typename R, int S>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S, 8)))
+k_pass_b(DevState s, int par) {
+    const int64_t t = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int64_t i = t / S;
+    const int sub = (int)(t % S);
+    const bool in = i < s.n;
+    const int64_t ii = in ? i : 0;
+    const int sp = s.spec[ii];
     const DevSpec& P = s.specs[sp];
     const D4* __restrict__ XV = s.XV;
     const D4* __restrict__ Uc = s.U[par];
     const GBRec<R>* __restrict__ GB = gb_of<R>(s);
-    const LRecB<R> ni = make_recb<R>(XV[i], GB[i], Uc[i]);
+    const LRecB<R> ni = make_recb<R>(XV[ii], GB[ii], Uc[ii]);
     const R inv_h = R(P.inv_h), wnorm = R(P.wnorm);
-    ForceAcc<R> A;
-    const int cnt = s.nnb[i];
-    const int32_t* __restrict__ cp = s.col + s.slice_ptr[i / kSlice] + (i % kSlice);
-    for (int k = 0; k < cnt; ++k) {
-        const int32_t j = cp[(int64_t)k * kSlice];
-        force_pair<R>(ni, make_recb<R>(XV[j], GB[j], Uc[j]), inv_h, wnorm, A);
-    }
-    force_finish<R>(s, i, par, P, sp, ni, A);
+    const int cnt = in ? s.nnb[i] : 0;
+    const int32_t* __restrict__ cp = s.col + s.slice_ptr[ii / kSlice] + (ii % kSlice);
+    const ForceAcc<R> A = pair_sums<R, S>(
+        ni, cnt, sub, inv_h, wnorm, [&](int k) { return (int)cp[(int64_t)k * kSlice]; },
+        [&](int j) { return make_recb<R>(XV[j], GB[j], Uc[j]); });
+    // the particle's own Q is needed only now: reread it (the compiler barrier
+    // keeps the load here) rather than keep it in registers through the loop
+    asm volatile("" ::: "memory");
+    if (in && sub == 0) force_finish<R>(s, i, par, P, sp, make_recb<R>(XV[i], GB[i], Uc[i]), A);
 }
 
 // LDS image of the force-pass records of one tile and its halo, stored
@@ -759,14 +827,13 @@ struct LdsB<float> {
 };
 
 // The same pass with the tile's particles and its halo staged in LDS: the
-// workgroup loads every record it needs once, then each lane runs its pair
-// sum from LDS through the 16-bit local neighbour slots.  Same arithmetic in
-// the same order as the unstaged kernel, so results are bitwise identical.
-// Occupancy is bounded by LDS, so the register budget is left to the
-// scheduler (one wave per SIMD).
-template <typename R>
-__global__ void __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(1, 1)))
-k_pass_b_staged(DevState s, int par) {
+// workgroup loads every record it needs once, then S lanes per particle run
+// the pair sums from LDS through the 16-bit local neighbour slots.  Same
+// arithmetic in the same order as the unstaged kernel, so results are bitwise
+// identical.  Occupancy is bounded by LDS (one tile per CU); S lanes per
+// particle give the SIMDs several waves to switch between.
+template <typename R, int S>
+__global__ void __launch_bounds__(kTile * S) k_pass_b_staged(DevState s, int par) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     double2* __restrict__ L = reinterpret_cast<double2*>(lds_raw);
     const int M = s.lds_slots;
@@ -777,23 +844,29 @@ k_pass_b_staged(DevState s, int par) {
     const D4* __restrict__ XV = s.XV;
     const D4* __restrict__ Uc = s.U[par];
     const GBRec<R>* __restrict__ GB = gb_of<R>(s);
-    for (int m = threadIdx.x; m < kTile + nh; m += kTile) {
+    for (int m = threadIdx.x; m < kTile + nh; m += kTile * S) {
         const int64_t g = m < kTile ? start + m : (int64_t)hl[m - kTile];
         if (g < s.n) LdsB<R>::put(L, M, m, make_recb<R>(XV[g], GB[g], Uc[g]));
     }
     __syncthreads();
-    const int64_t i = start + threadIdx.x;
-    if (i >= s.n) return;
-    const int sp = s.spec[i];
+    const int pl = threadIdx.x / S;
+    const int sub = threadIdx.x % S;
+    const int64_t i = start + pl;
+    const bool in = i < s.n;
+    const int64_t ii = in ? i : start;
+    const int sp = s.spec[ii];
     const DevSpec& P = s.specs[sp];
-    const LRecB<R> ni = LdsB<R>::get(L, M, threadIdx.x);
+    const LRecB<R> ni = LdsB<R>::get(L, M, in ? pl : 0);
     const R inv_h = R(P.inv_h), wnorm = R(P.wnorm);
-    ForceAcc<R> A;
-    const int cnt = s.nnb[i];
-    const uint16_t* __restrict__ lp = s.lcol + s.slice_ptr[i / kSlice] + (i % kSlice);
-    for (int k = 0; k < cnt; ++k)
-        force_pair<R>(ni, LdsB<R>::get(L, M, lp[(int64_t)k * kSlice]), inv_h, wnorm, A);
-    force_finish<R>(s, i, par, P, sp, ni, A);
+    const int cnt = in ? s.nnb[i] : 0;
+    const uint16_t* __restrict__ lp = s.lcol + s.slice_ptr[ii / kSlice] + (ii % kSlice);
+    const ForceAcc<R> A = pair_sums<R, S>(
+        ni, cnt, sub, inv_h, wnorm, [&](int k) { return (int)lp[(int64_t)k * kSlice]; },
+        [&](int m) { return LdsB<R>::get(L, M, m); });
+    // the particle's own Q is needed only now: reread it rather than keep it
+    // in registers through the pair loop
+    __syncthreads();
+    if (in && sub == 0) force_finish<R>(s, i, par, P, sp, LdsB<R>::get(L, M, pl), A);
 }
 
 // Pass A (deformation and constitutive update to t^{n+1}).
@@ -801,7 +874,7 @@ k_pass_b_staged(DevState s, int par) {
 // (eq. Crack_approx_Fdot, D at level n), accumulated as
 // M = sum_j V_j (1 - D_j)(v_j - v_i) (x) gradW_ij and dF/dt = M L_i^-1; then
 // the constitutive update and Q_i = P_i L_i^-T (0 for failed particles).
-template <typename R>
+template <typename R, int DM>
 __global__ void __launch_bounds__(256) k_pass_a(DevState s, int par) {
     const int64_t i = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= s.n) return;
@@ -816,21 +889,37 @@ __global__ void __launch_bounds__(256) k_pass_a(DevState s, int par) {
     R M[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int cnt = s.nnb[i];
     const int32_t* __restrict__ cp = s.col + s.slice_ptr[i / kSlice] + (i % kSlice);
-    for (int k = 0; k < cnt; ++k) {
-        const int32_t j = cp[(int64_t)k * kSlice];
-        const D4 xj = XV[j];
-        const D4 vj = VW[j];
-        const R dx = R(xj.x - xi.x), dy = R(xj.y - xi.y), dz = R(xj.z - xi.z);
-        const R r = sqrt(fma(dx, dx, fma(dy, dy, dz * dz)));
-        R W, dW;
-        spline(r, inv_h, wnorm, W, dW);
-        const R gs = dW / r;
-        const R gx = gs * dx, gy = gs * dy, gz = gs * dz;
-        const R wj = R(vj.w);
-        const R t0 = wj * R(vj.x - vi.x), t1 = wj * R(vj.y - vi.y), t2 = wj * R(vj.z - vi.z);
-        M[0] = fma(t0, gx, M[0]); M[1] = fma(t0, gy, M[1]); M[2] = fma(t0, gz, M[2]);
-        M[3] = fma(t1, gx, M[3]); M[4] = fma(t1, gy, M[4]); M[5] = fma(t1, gz, M[5]);
-        M[6] = fma(t2, gx, M[6]); M[7] = fma(t2, gy, M[7]); M[8] = fma(t2, gz, M[8]);
+    // neighbours in groups of kGatherA: every index and record load of a
+    // group is issued before its arithmetic (the sum keeps increasing k)
+    constexpr int kGatherA = 4;
+    for (int k0 = 0; k0 < cnt; k0 += kGatherA) {
+        int32_t j[kGatherA];
+        D4 xj[kGatherA], vj[kGatherA];
+#pragma unroll
+        for (int t = 0; t < kGatherA; ++t) j[t] = cp[(int64_t)(k0 + t < cnt ? k0 + t : 0) * kSlice];
+#pragma unroll
+        for (int t = 0; t < kGatherA; ++t) {
+            xj[t] = XV[j[t]];
+            vj[t] = VW[j[t]];
+        }
+#pragma unroll
+        for (int t = 0; t < kGatherA; ++t) {
+            const bool live = k0 + t < cnt;
+            const R dx = R(xj[t].x - xi.x), dy = R(xj[t].y - xi.y), dz = R(xj[t].z - xi.z);
+            const R r = sqrt(fma(dx, dx, fma(dy, dy, dz * dz)));
+            R W, dW;
+            spline(r, inv_h, wnorm, W, dW);
+            const R gs = dW / r;
+            const R gx = gs * dx, gy = gs * dy, gz = gs * dz;
+            const R wj = R(vj[t].w);
+            const R t0 = wj * R(vj[t].x - vi.x), t1 = wj * R(vj[t].y - vi.y),
+                    t2 = wj * R(vj[t].z - vi.z);
+            const R m[9] = {fma(t0, gx, M[0]), fma(t0, gy, M[1]), fma(t0, gz, M[2]),
+                            fma(t1, gx, M[3]), fma(t1, gy, M[4]), fma(t1, gz, M[5]),
+                            fma(t2, gx, M[6]), fma(t2, gy, M[7]), fma(t2, gz, M[8])};
+#pragma unroll
+            for (int q = 0; q < 9; ++q) M[q] = live ? m[q] : M[q];
+        }
     }
     R Li[9];
     if constexpr (std::is_same<R, float>::value) {
@@ -858,14 +947,14 @@ __global__ void __launch_bounds__(256) k_pass_a(DevState s, int par) {
     }
     double eps = s.eps_p[i], rate = s.eps_rate[i], e = s.e[i];
     double dinit = 0.0, wp = 0.0, fv = 0.0;
-    const int model = P.damage;
+    const int model = DM >= 0 ? DM : P.damage;
     if (model == 1 || model == 2) dinit = s.d_init[i];
     if (model == 1) wp = s.w_p[i];
     if (model == 3) fv = s.f_void[i];
     const double Di = s.D[i];
     PointOut<R> o;
     int32_t flags = 0;
-    point_update<R>(P, Hn, Fd, sn, eps, rate, dinit, wp, fv, e, Di, o, flags);
+    point_update<R, DM>(P, Hn, Fd, sn, eps, rate, dinit, wp, fv, e, Di, o, flags);
     // stores
     if constexpr (std::is_same<R, float>::value) {
 #pragma unroll
@@ -910,22 +999,34 @@ __global__ void __launch_bounds__(256) k_pass_a(DevState s, int par) {
     }
 }
 
-hipError_t launch_pass_b(const DevState& s, int parity, int block, bool mixed, hipStream_t st,
-                         size_t lds_bytes) {
+template <int S>
+static hipError_t launch_b(const DevState& s, int parity, int block, bool mixed, hipStream_t st,
+                           size_t lds_bytes) {
     if (s.staged) {
         const unsigned grid = (unsigned)((s.n + kTile - 1) / kTile);
         if (mixed)
-            k_pass_b_staged<float><<<grid, kTile, lds_bytes, st>>>(s, parity);
+            k_pass_b_staged<float, S><<<grid, kTile * S, lds_bytes, st>>>(s, parity);
         else
-            k_pass_b_staged<double><<<grid, kTile, lds_bytes, st>>>(s, parity);
+            k_pass_b_staged<double, S><<<grid, kTile * S, lds_bytes, st>>>(s, parity);
         return hipGetLastError();
     }
-    const unsigned grid = (unsigned)((s.n + block - 1) / block);
+    const unsigned grid = (unsigned)((s.n * S + block - 1) / block);
     if (mixed)
-        k_pass_b<float><<<grid, block, 0, st>>>(s, parity);
+        k_pass_b<float, S><<<grid, block, 0, st>>>(s, parity);
     else
-        k_pass_b<double><<<grid, block, 0, st>>>(s, parity);
+        k_pass_b<double, S><<<grid, block, 0, st>>>(s, parity);
     return hipGetLastError();
+}
+
+hipError_t launch_pass_b(const DevState& s, int parity, int block, int sub, bool mixed,
+                         hipStream_t st, size_t lds_bytes) {
+    if (!s.staged && (block <= 0 || block > 256 || block % sub != 0)) return hipErrorInvalidValue;
+    switch (sub) {
+        case 1: return launch_b<1>(s, parity, block, mixed, st, lds_bytes);
+        case 2: return launch_b<2>(s, parity, block, mixed, st, lds_bytes);
+        case 4: return launch_b<4>(s, parity, block, mixed, st, lds_bytes);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 size_t staged_record_bytes(bool mixed) {
@@ -934,8 +1035,12 @@ size_t staged_record_bytes(bool mixed) {
 
 // Dynamic LDS above the default limit must be allowed per kernel.
 hipError_t prepare_staged(size_t lds_bytes_b) {
-    const void* fns[2] = {reinterpret_cast<const void*>(&k_pass_b_staged<double>),
-                          reinterpret_cast<const void*>(&k_pass_b_staged<float>)};
+    const void* fns[6] = {reinterpret_cast<const void*>(&k_pass_b_staged<double, 1>),
+                          reinterpret_cast<const void*>(&k_pass_b_staged<float, 1>),
+                          reinterpret_cast<const void*>(&k_pass_b_staged<double, 2>),
+                          reinterpret_cast<const void*>(&k_pass_b_staged<float, 2>),
+                          reinterpret_cast<const void*>(&k_pass_b_staged<double, 4>),
+                          reinterpret_cast<const void*>(&k_pass_b_staged<float, 4>)};
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds_bytes_b);
@@ -944,12 +1049,24 @@ hipError_t prepare_staged(size_t lds_bytes_b) {
     return hipSuccess;
 }
 
+template <int DM>
+static void launch_a(const DevState& s, int parity, unsigned grid, int block, bool mixed,
+                     hipStream_t st) {
+    if (mixed)
+        k_pass_a<float, DM><<<grid, block, 0, st>>>(s, parity);
+    else
+        k_pass_a<double, DM><<<grid, block, 0, st>>>(s, parity);
+}
+
 hipError_t launch_pass_a(const DevState& s, int parity, int block, bool mixed, hipStream_t st) {
     const unsigned grid = (unsigned)((s.n + block - 1) / block);
-    if (mixed)
-        k_pass_a<float><<<grid, block, 0, st>>>(s, parity);
-    else
-        k_pass_a<double><<<grid, block, 0, st>>>(s, parity);
+    switch (s.model) {
+        case 0: launch_a<0>(s, parity, grid, block, mixed, st); break;
+        case 1: launch_a<1>(s, parity, grid, block, mixed, st); break;
+        case 2: launch_a<2>(s, parity, grid, block, mixed, st); break;
+        case 3: launch_a<3>(s, parity, grid, block, mixed, st); break;
+        default: launch_a<-1>(s, parity, grid, block, mixed, st); break;
+    }
     return hipGetLastError();
 }
 
@@ -1169,49 +1286,87 @@ __device__ __forceinline__ void block_reduce(double (*red)[256], double v[NV], c
     }
 }
 
-__global__ void __launch_bounds__(256) k_spec_diag(DevState s, int par, double* __restrict__ out) {
-    __shared__ double red[4][256];
-    const int sp = blockIdx.x;
-    const DevSpec& P = s.specs[sp];
-    const int64_t np = s.np;
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t p = P.first + threadIdx.x; p < P.last; p += 256) {
-        const double m = P.rho0 * s.XV[p].w;
-        const D4 vv = s.VW[p];
-        v[0] += 0.5 * m * (vv.x * vv.x + vv.y * vv.y + vv.z * vv.z);
-        v[1] += m * s.e[p];
-        const double D = s.D[p];
-        v[2] += D >= 1.0 ? 1.0 : 0.0;
-        v[3] = fmax(v[3], D);
+__device__ __forceinline__ int find_segment(const int64_t* seg, int n_seg, int64_t b) {
+    int lo = 0, hi = n_seg;   // seg[lo] <= b < seg[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (seg[mid] <= b) lo = mid; else hi = mid;
     }
-    const bool mx[4] = {false, false, false, true};
-    block_reduce<4>(red, v, mx);
-    if (threadIdx.x == 0) {
-        double* o = out + kNDiag * sp;
-        o[0] = red[0][0]; o[1] = red[1][0]; o[2] = red[2][0]; o[3] = red[3][0];
-        o[4] = s.t[sp]; o[5] = 0.0; o[6] = 0.0; o[7] = 0.0;
+    return lo;
+}
+
+// One block per chunk of kDiagChunk particles of one segment.  Specimen
+// partials: kinetic energy, internal energy, failed count, max D; group
+// partials: force sum, displacement sum, count.
+__global__ void __launch_bounds__(256) k_diag_part(DevState s, int par, const int32_t* __restrict__ list,
+                                                   const int64_t* __restrict__ bc_ptr,
+                                                   const int64_t* __restrict__ seg, int n_seg,
+                                                   double* __restrict__ part) {
+    __shared__ double red[7][256];
+    const int64_t b = blockIdx.x;
+    const int q = find_segment(seg, n_seg, b);
+    const int64_t c = b - seg[q];
+    const int64_t np = s.np;
+    double* o = part + kNDiag * b;
+    if (q < s.n_spec) {
+        const DevSpec& P = s.specs[q];
+        const int64_t beg = P.first + c * kDiagChunk;
+        const int64_t end = beg + kDiagChunk < P.last ? beg + kDiagChunk : P.last;
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t p = beg + threadIdx.x; p < end; p += 256) {
+            const double m = P.rho0 * s.XV[p].w;
+            const D4 vv = s.VW[p];
+            v[0] += 0.5 * m * (vv.x * vv.x + vv.y * vv.y + vv.z * vv.z);
+            v[1] += m * s.e[p];
+            const double D = s.D[p];
+            v[2] += D >= 1.0 ? 1.0 : 0.0;
+            v[3] = fmax(v[3], D);
+        }
+        const bool mx[4] = {false, false, false, true};
+        block_reduce<4>(red, v, mx);
+        if (threadIdx.x < kNDiag) o[threadIdx.x] = threadIdx.x < 4 ? red[threadIdx.x][0] : 0.0;
+    } else {
+        const int g = q - s.n_spec;
+        const int64_t beg = bc_ptr[g] + c * kDiagChunk;
+        const int64_t end = beg + kDiagChunk < bc_ptr[g + 1] ? beg + kDiagChunk : bc_ptr[g + 1];
+        const D4* uc = s.U[par];
+        double v[7] = {0, 0, 0, 0, 0, 0, 0};
+        for (int64_t k = beg + threadIdx.x; k < end; k += 256) {
+            const int64_t p = list[k];
+            for (int cc = 0; cc < 3; ++cc) v[cc] += s.force[cc * np + p];
+            const D4 up = uc[p];
+            v[3] += up.x; v[4] += up.y; v[5] += up.z;
+            v[6] += 1.0;
+        }
+        const bool mx[7] = {false, false, false, false, false, false, false};
+        block_reduce<7>(red, v, mx);
+        if (threadIdx.x < kNDiag) o[threadIdx.x] = threadIdx.x < 7 ? red[threadIdx.x][0] : 0.0;
     }
 }
 
-__global__ void __launch_bounds__(256) k_bc_diag(DevState s, int par, const int32_t* __restrict__ list,
-                                                 const int64_t* __restrict__ ptr,
-                                                 double* __restrict__ out) {
+// One block per segment: the chunk partials in a fixed order.
+__global__ void __launch_bounds__(256) k_diag_final(DevState s, const int64_t* __restrict__ seg,
+                                                    const double* __restrict__ part,
+                                                    double* __restrict__ spec_out,
+                                                    double* __restrict__ bc_out) {
     __shared__ double red[7][256];
-    const int g = blockIdx.x;
-    const int64_t np = s.np;
-    const D4* uc = s.U[par];
+    const int q = blockIdx.x;
+    const bool spec = q < s.n_spec;
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
-    for (int64_t q = ptr[g] + threadIdx.x; q < ptr[g + 1]; q += 256) {
-        const int64_t p = list[q];
-        for (int c = 0; c < 3; ++c) v[c] += s.force[c * np + p];
-        const D4 up = uc[p];
-        v[3] += up.x; v[4] += up.y; v[5] += up.z;
-        v[6] += 1.0;
+    for (int64_t b = seg[q] + threadIdx.x; b < seg[q + 1]; b += 256) {
+        const double* pp = part + kNDiag * b;
+        for (int k = 0; k < 7; ++k) v[k] = (spec && k == 3) ? fmax(v[k], pp[k]) : v[k] + pp[k];
     }
-    const bool mx[7] = {false, false, false, false, false, false, false};
-    block_reduce<7>(red, v, mx);
-    if (threadIdx.x == 0) {
-        double* o = out + kNDiag * g;
+    const bool mx_spec[7] = {false, false, false, true, false, false, false};
+    const bool mx_bc[7] = {false, false, false, false, false, false, false};
+    block_reduce<7>(red, v, spec ? mx_spec : mx_bc);
+    if (threadIdx.x != 0) return;
+    if (spec) {
+        double* o = spec_out + kNDiag * q;
+        o[0] = red[0][0]; o[1] = red[1][0]; o[2] = red[2][0]; o[3] = red[3][0];
+        o[4] = s.t[q]; o[5] = 0.0; o[6] = 0.0; o[7] = 0.0;
+    } else {
+        double* o = bc_out + kNDiag * (q - s.n_spec);
         const double cnt = red[6][0];
         for (int c = 0; c < 3; ++c) {
             o[c] = red[c][0];
@@ -1223,10 +1378,12 @@ __global__ void __launch_bounds__(256) k_bc_diag(DevState s, int par, const int3
 }
 
 hipError_t launch_diagnostics(const DevState& s, int parity, const int32_t* bc_list,
-                              const int64_t* bc_ptr, double* spec_diag, double* bc_diag,
+                              const int64_t* bc_ptr, const int64_t* seg, int32_t n_seg,
+                              int64_t n_chunks, double* part, double* spec_diag, double* bc_diag,
                               hipStream_t st) {
-    k_spec_diag<<<s.n_spec, 256, 0, st>>>(s, parity, spec_diag);
-    if (bc_diag && s.n_bc > 0) k_bc_diag<<<s.n_bc, 256, 0, st>>>(s, parity, bc_list, bc_ptr, bc_diag);
+    if (n_chunks <= 0 || n_seg <= 0) return hipErrorInvalidValue;
+    k_diag_part<<<(unsigned)n_chunks, 256, 0, st>>>(s, parity, bc_list, bc_ptr, seg, n_seg, part);
+    k_diag_final<<<(unsigned)n_seg, 256, 0, st>>>(s, seg, part, spec_diag, bc_diag);
     return hipGetLastError();
 }
 

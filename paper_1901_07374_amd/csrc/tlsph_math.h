@@ -259,11 +259,14 @@ struct PointOut {
 // Cockcroft-Latham / Johnson-Cook initiation and evolution (Secs. 5.1-5.3),
 // failed particles stress free, energy by the trapezoid rule on P,
 // P = J sigma F^-T.
-template <typename R>
+// DM >= 0 fixes the damage model at compile time (the other models' code is
+// dropped); DM = -1 reads it from the specimen.
+template <typename R, int DM = -1>
 __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R Hn[9], const R Fd[9],
                                              const R sn[6], double& eps, double& rate,
                                              double& dinit, double& wp, double& fv, double& e,
                                              double D, PointOut<R>& o, int32_t& flags) {
+    const int model = DM >= 0 ? DM : P.damage;
     const R dt = R(P.dt);
 #pragma unroll
     for (int k = 0; k < 9; ++k) o.H[k] = Hn[k] + dt * Fd[k];
@@ -316,7 +319,7 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
     const R omD = R(1.0 - D);
     R sd[6], sm;
     double Dn = D;
-    if (P.damage == 3) {
+    if (model == 3) {
         double sdt[6], sdo[6], smo;
 #pragma unroll
         for (int k = 0; k < 6; ++k) sdt[k] = double(sdr[k] + R(2) * G * omD * de[k]);
@@ -345,8 +348,8 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
         }
         eps += double(dep);
         rate = double(dep) / P.dt;
-        if (dep > R(0) && (P.damage == 1 || P.damage == 2)) {
-            if (P.damage == 2) {
+        if (dep > R(0) && (model == 1 || model == 2)) {
+            if (model == 2) {
                 const R sstar = sm / mises_voigt(sd);
                 const double ef = (P.D1 + P.D2 * exp(P.D3 * double(sstar))) *
                                   pow(1.0 + rate / P.eps_dot0, P.D4);

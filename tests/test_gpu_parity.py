@@ -172,6 +172,7 @@ def test_bitwise_determinism_graphs_and_autotune(tl):
         flags = {"graphs": tl.USE_GRAPHS, "unstaged": tl.NO_STAGING}.get(mode, 0)
         g = tl.Sim(p, flags=flags, stream=side if mode == "graphs" else None)
         assert g.info()["staged"] == (mode != "unstaged")
+        assert g.info()["lanes_per_particle"] == 4
         g.set_state(st)
         if mode == "autotuned":
             g.autotune()
@@ -182,42 +183,62 @@ def test_bitwise_determinism_graphs_and_autotune(tl):
             assert np.array_equal(o[k], outs[0][k]), k
 
 
+SHAPES = [  # (staged, lanes per particle, force block, deformation block)
+    (1, 4, 256, 256), (1, 2, 256, 128), (1, 1, 256, 64), (0, 4, 256, 256), (0, 4, 64, 192),
+    (0, 2, 128, 128), (0, 1, 64, 64), (0, 1, 256, 256)]
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_staged_force_pass_is_bitwise_unstaged(tl, orc, precision):
-    """LDS staging changes where neighbour records come from, not the
-    arithmetic or its order: results are bitwise equal, on several tiles with
-    a ragged last tile, after steps that leave particles damaged."""
+def test_every_launch_shape_is_bitwise_identical(tl, orc, precision):
+    """LDS staging, lanes per particle and block sizes change where records
+    come from and which lane sums what, not the arithmetic or its order (one
+    canonical order of the neighbour sums): results are bitwise equal, on
+    several tiles with a ragged last tile, after steps that leave particles
+    damaged."""
     p = CASES["batch3"]()
     prec = tl.FP64 if precision == "fp64" else tl.MIXED
     st = injected_state(orc, p, 31)
     outs = []
-    for flags in (0, tl.NO_STAGING):
-        g = tl.Sim(p, precision=prec, flags=flags | tl.STORE_FORCE)
+    for shape in SHAPES:
+        g = tl.Sim(p, precision=prec, flags=tl.STORE_FORCE)
+        g.set_launch_shape(*shape)
+        inf = g.info()
+        assert inf["staged"] == bool(shape[0]) and inf["lanes_per_particle"] == shape[1]
         g.set_state(st)
         g.step(3)
         outs.append({k: g.get(k) for k in ("force", "v", "u", "F", "Q", "sig", "D")})
-    for o in outs[1:]:
+    for o, shape in zip(outs[1:], SHAPES[1:]):
         for k in outs[0]:
-            assert np.array_equal(outs[0][k], o[k]), k
+            assert np.array_equal(outs[0][k], o[k]), (shape, k)
 
 
-def test_diagnostics_match_fields(tl):
-    p = I.notched_bar(dx=0.7e-3)
+@pytest.mark.parametrize("case", ["bar", "batch3", "bar_large"])
+def test_diagnostics_match_fields(tl, case):
+    """Two-level reductions (chunks of 2048 particles, then per specimen or
+    group) against sums of the exported fields, with one or many chunks per
+    specimen and group."""
+    p = {"bar": lambda: I.notched_bar(dx=0.7e-3), "batch3": CASES["batch3"],
+         "bar_large": lambda: I.notched_bar(dx=0.4e-3)}[case]()
     g = tl.Sim(p, flags=tl.STORE_FORCE)
     g.step(30)
     sd, bd = g.diagnostics()
     v, e, D = g.get("v"), g.get("e"), g.get("D")
-    m = p.materials[0]["rho0"] * p.V0
-    assert sd[0, 0] == pytest.approx(0.5 * np.sum(m[:, None] * v * v), rel=1e-12)
-    assert sd[0, 1] == pytest.approx(np.sum(m * e), rel=1e-10, abs=1e-300)
-    assert sd[0, 2] == np.sum(D >= 1.0) and sd[0, 3] == D.max()
-    assert sd[0, 4] == pytest.approx(30 * p.materials[0]["dt"], rel=1e-14)
     f, u = g.get("force"), g.get("u")
-    for grp in range(2):
+    for s in range(p.n_spec):
+        a, b = p.spec_offsets[s], p.spec_offsets[s + 1]
+        m = p.materials[s]["rho0"] * p.V0[a:b]
+        assert sd[s, 0] == pytest.approx(0.5 * np.sum(m[:, None] * v[a:b] * v[a:b]), rel=1e-12)
+        assert sd[s, 1] == pytest.approx(np.sum(m * e[a:b]), rel=1e-10, abs=1e-300)
+        assert sd[s, 2] == np.sum(D[a:b] >= 1.0) and sd[s, 3] == D[a:b].max()
+        assert sd[s, 4] == pytest.approx(30 * p.materials[s]["dt"], rel=1e-14)
+    for grp in range(len(p.bc_groups)):
         sel = p.bc_group == grp
         assert bd[grp, 6] == sel.sum()
         assert np.allclose(bd[grp, :3], f[sel].sum(0), rtol=1e-12, atol=1e-9)
         assert np.allclose(bd[grp, 3:6], u[sel].mean(0), rtol=1e-12, atol=1e-18)
+    # fixed order: a repeat gives the same bits
+    sd2, bd2 = g.diagnostics()
+    assert np.array_equal(sd, sd2) and np.array_equal(bd, bd2)
 
 
 def test_error_paths(tl):
@@ -236,3 +257,13 @@ def test_error_paths(tl):
     with pytest.raises(tl.TLSPHError) as ei:
         g.step(1)
     assert ei.value.status == 2
+    g = tl.Sim(p)
+    for bad in ((2, 4, 256, 256), (0, 3, 256, 256), (0, 4, 96, 256), (0, 4, 256, 32),
+                (0, 4, 512, 256)):
+        with pytest.raises(tl.TLSPHError) as ei:
+            g.set_launch_shape(*bad)
+        assert ei.value.status == 1, bad
+    g2 = tl.Sim(p, flags=tl.NO_STAGING)
+    with pytest.raises(tl.TLSPHError) as ei:
+        g2.set_launch_shape(1, 4)
+    assert ei.value.status == 7
