@@ -1,18 +1,24 @@
-"""Benchmark: damaged TLSPH steps of the notched round bar on one MI355X.
+"""Benchmark: damaged TLSPH steps on one MI355X.
 
-Workload: the notched round bar in tension (radius 5 mm, length 40 mm,
-90-degree V-notch 1 mm deep, 0.25 mm lattice, 200 216 particles, seeded 3 %
-jitter), Johnson-Cook plasticity and Johnson-Cook damage, grips driven at
-+-10 m/s (1 - exp(-t / 1 ms)).  A step is one pass of the whole path: nodal
-forces with hourglass control, leapfrog update, damaged dF/dt, EOS, radial
-return, damage, PK1.  The default run goes from rest to past failure.
-
+Default workload (the headline): the notched round bar in tension (radius
+5 mm, length 40 mm, 90-degree V-notch 1 mm deep, 0.25 mm lattice, 200 216
+particles, seeded 3 % jitter), Johnson-Cook plasticity and Johnson-Cook
+damage, grips driven at +-10 m/s (1 - exp(-t / 1 ms)), from rest to past
+failure.  A step is one pass of the whole path: nodal forces with hourglass
+control, leapfrog update, damaged dF/dt, EOS, radial return, damage, PK1.
 The headline value is the FP64 form; the mixed FP32/FP64 form runs the same
-steps and is reported beside it with its deviation from FP64 (reaction-
-force curve and failure displacement).  Inputs and state are resident in HBM
-before the timed region starts.  Prints one JSON line.
+steps and is reported beside it with its deviation from FP64 (reaction-force
+curve and failure displacement).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Other workloads (--workload): the Taylor bar (996 314 particles, CL, rigid
+wall, 5000 steps), the GTN holed plate (4.08 M particles), and a batch of 256
+notched bars of 2k-60k particles (8.55 M in all) stepped in one captured launch
+per pass in the mixed form, against 256 separate FP64 contexts.
+
+Inputs and state are resident in HBM before the timed region starts.
+Prints one JSON line.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
 from __future__ import annotations
 
@@ -54,12 +60,13 @@ def algorithmic_bytes(kernel: str, mixed: bool, damage: int, n: int, nnz: int) -
     return per * n + 4 * nnz
 
 
-def kernel_symbol(kernel: str, info: dict, mixed: bool) -> str:
+def kernel_symbol(kernel: str, info: dict, mixed: bool, damage: int) -> str:
+    """Kernel name as rocprofv3 reports it (template arguments included)."""
     r = "float" if mixed else "double"
     if kernel == "force_pass":
         name = "k_pass_b_staged" if info["staged"] else "k_pass_b"
         return f"{name}<{r}, {info['lanes_per_particle']}>"
-    return f"k_pass_a<{r}>"
+    return f"k_pass_a<{r}, {damage}>"
 
 
 def counter_traffic(symbol: str, workload: str):
@@ -104,24 +111,37 @@ def failure_displacement(sep, reaction):
     return None
 
 
-def run_form(prob, precision, steps, warmup, torch, T, flags=0, autotune=True):
-    sim = T.Sim(prob, precision=precision, flags=flags)
-    n_rec = (warmup + steps) // DIAG_EVERY + 1
-    sd = torch.zeros((n_rec, prob.n_spec, 8), dtype=torch.float64, device="cuda")
-    bd = torch.zeros((n_rec, len(prob.bc_groups), 8), dtype=torch.float64, device="cuda")
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def run_form(prob, precision, steps, warmup, torch, T, flags=0, autotune=True, stream=None,
+             diag=True):
+    """Warm up, autotune, then time `steps` steps; diagnostics every
+    DIAG_EVERY steps (inside the timed region)."""
+    log(f"{prob.name}: {prob.n} particles, precision {precision}, flags {flags}")
+    sim = T.Sim(prob, precision=precision, flags=flags, stream=stream)
+    n_rec = (warmup + steps) // DIAG_EVERY + 1 if diag else 0
+    n_bc = max(len(prob.bc_groups), 1)
+    sd = torch.zeros((max(n_rec, 1), prob.n_spec, 8), dtype=torch.float64, device="cuda")
+    bd = torch.zeros((max(n_rec, 1), n_bc, 8), dtype=torch.float64, device="cuda")
     L = T.lib()
     rec = 0
 
     def advance(k):
         nonlocal rec
+        if not diag:
+            sim.step(k)
+            return
         done = 0
         while done < k:
             chunk = min(DIAG_EVERY, k - done)
             sim.step(chunk)
             done += chunk
             if chunk == DIAG_EVERY and rec < n_rec:
-                st = L.tlsph_get_diagnostics(sim.ctx, sd[rec].data_ptr(), bd[rec].data_ptr(),
-                                             sim._sp())
+                st = L.tlsph_get_diagnostics(
+                    sim.ctx, sd[rec].data_ptr(),
+                    bd[rec].data_ptr() if prob.bc_groups else None, sim._sp())
                 if st:
                     raise RuntimeError("diagnostics failed")
                 rec += 1
@@ -129,47 +149,258 @@ def run_form(prob, precision, steps, warmup, torch, T, flags=0, autotune=True):
     advance(warmup)
     if autotune:
         sim.autotune()     # picks launch shapes on the current state; results unchanged
+    use_timing = not (flags & T.USE_GRAPHS)
     torch.cuda.synchronize()
-    sim.enable_kernel_timing(TIMING_STRIDE)
+    if use_timing:
+        sim.enable_kernel_timing(TIMING_STRIDE)
     t0 = time.perf_counter()
     advance(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kt = sim.kernel_times()
+    kt = sim.kernel_times() if use_timing else None
     sim.enable_kernel_timing(0)
-    bdh = bd[:rec].cpu().numpy()
-    sdh = sd[:rec].cpu().numpy()
-    # reaction on the top grip (group 1) and grip separation
-    reaction = -bdh[:, 1, 2]
-    sep = bdh[:, 1, 5] - bdh[:, 0, 5]
-    return dict(seconds=t1 - t0, kernel_times=kt, info=sim.info(), reaction=reaction, sep=sep,
-                failed=sdh[:, 0, 2], sim=sim)
+    log(f"  {steps} steps in {t1 - t0:.3f} s")
+    return dict(seconds=t1 - t0, kernel_times=kt, info=sim.info(), sim=sim,
+                sd=sd[:rec].cpu().numpy(), bd=bd[:rec].cpu().numpy())
 
 
-def cpu_baseline(prob, target_seconds=15.0):
+def kernel_table(kt, mixed, damage, n, nnz):
+    kts = {k: v[0] / max(v[1], 1) for k, v in kt.items()}
+    return kts, {k: {"avg_launch_us": round(v * 1e3, 2),
+                     "algorithmic_GBs": round(algorithmic_bytes(k, mixed, damage, n, nnz)
+                                              / (v * 1e-3) / 1e9, 1)} for k, v in kts.items()}
+
+
+def roofline_of(run, damage, n, workload, mixed=False):
+    nnz = run["info"]["nnz"]
+    kts, _ = kernel_table(run["kernel_times"], mixed, damage, n, nnz)
+    dom = max(kts, key=kts.get)
+    bytes_launch = algorithmic_bytes(dom, mixed, damage, n, nnz)
+    achieved = bytes_launch / (kts[dom] * 1e-3) / 1e9
+    symbol = kernel_symbol(dom, run["info"], mixed, damage)
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": counter_traffic(symbol, workload), "kernel": dom, "symbol": symbol,
+            "avg_launch_us": round(kts[dom] * 1e3, 2),
+            "algorithmic_bytes_per_launch": bytes_launch}
+
+
+def cpu_baseline(prob, label, target_seconds=15.0, max_steps=400):
     """The FP64 oracle on the host cores over a bounded sample of the same
-    workload (the full notched bar, a few steps from rest)."""
+    workload (the same particles, a few steps from the start)."""
     import oracle
+    log(f"cpu baseline: {label}")
     o = oracle.Sim(prob)
     threads = oracle.get_threads()
     t0 = time.perf_counter()
     o.step(1)
     one = time.perf_counter() - t0
-    k = int(max(2, min(400, target_seconds / max(one, 1e-6))))
+    k = int(max(2, min(max_steps, target_seconds / max(one, 1e-6))))
     t0 = time.perf_counter()
     o.step(k)
     dt = time.perf_counter() - t0
     return {"value": prob.n * k / dt, "unit": "particle-steps/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"notched bar {prob.n} particles, JC damage, FP64 oracle, {k} steps from "
-                      f"rest after 1 untimed step, {threads} OpenMP threads"}
+            "sample": f"{label}, {prob.n} particles, FP64 oracle, {k} steps after 1 untimed "
+                      f"step, {threads} OpenMP threads"}
+
+
+def base_line(args, workload, value, ms_step, dtype, config):
+    return {"metric": METRIC, "value": round(value, 1), "unit": "particle-steps/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+            "config": dict({"workload": workload}, **config)}
+
+
+def shape_of(info):
+    return {"force_pass_variant": "LDS-staged tiles" if info["staged"] else "global gathers",
+            "force_pass_block": info["block_force"],
+            "force_lanes_per_particle": info["lanes_per_particle"],
+            "deformation_pass_block": info["block_deformation"]}
+
+
+# --------------------------------------------------------------------------
+# workloads
+# --------------------------------------------------------------------------
+def bench_notched_bar(args, torch, I, T):
+    prob = I.notched_bar()
+    damage = prob.materials[0]["damage"]
+    workload = "notched_bar_200k"
+    flags = T.NO_STAGING if args.unstaged else 0
+    tune = not args.no_autotune
+
+    def curve(r):
+        # reaction on the top grip (group 1) and grip separation
+        bd = r["bd"]
+        return -bd[:, 1, 2], bd[:, 1, 5] - bd[:, 0, 5]
+
+    fp = run_form(prob, T.FP64, args.steps, args.warmup, torch, T, flags, tune)
+    nnz = fp["info"]["nnz"]
+    _, ktab = kernel_table(fp["kernel_times"], False, damage, prob.n, nnz)
+    out = base_line(args, workload, prob.n * args.steps / fp["seconds"],
+                    fp["seconds"] / args.steps * 1e3, "f64",
+                    dict({"particles": prob.n, "neighbour_pairs": nnz, "damage": "johnson-cook",
+                          "precision": "fp64", "steps_from_rest": args.warmup + args.steps,
+                          "dt_s": prob.materials[0]["dt"]}, **shape_of(fp["info"])))
+    step_bytes = sum(algorithmic_bytes(k, False, damage, prob.n, nnz) for k in ktab)
+    out["step_algorithmic_GBs"] = round(step_bytes * args.steps / fp["seconds"] / 1e9, 1)
+    out["kernels"] = ktab
+    out["roofline"] = roofline_of(fp, damage, prob.n, workload)
+    r64, s64 = curve(fp)
+    fd64 = failure_displacement(s64, r64)
+    out["fp64_failure_displacement_mm"] = None if fd64 is None else round(fd64 * 1e3, 4)
+    out["fp64_peak_reaction_kN"] = round(float(r64.max()) / 1e3, 3) if len(r64) else None
+    del fp["sim"]
+
+    if not args.no_mixed:
+        mx = run_form(prob, T.MIXED, args.steps, args.warmup, torch, T, flags, tune)
+        rmx, smx = curve(mx)
+        fdm = failure_displacement(smx, rmx)
+        ipk = int(np.argmax(r64))
+        dev = float(np.max(np.abs(rmx[: ipk + 1] - r64[: ipk + 1])) / max(r64.max(), 1e-30))
+        _, mtab = kernel_table(mx["kernel_times"], True, damage, prob.n, nnz)
+        out["mixed"] = {
+            "value": round(prob.n * args.steps / mx["seconds"], 1), "unit": "particle-steps/s",
+            "ms_per_step": round(mx["seconds"] / args.steps * 1e3, 5), "dtype": "f32/f64",
+            "launch": shape_of(mx["info"]), "kernels": mtab,
+            "reaction_curve_max_rel_dev_to_peak_vs_fp64": round(dev, 6),
+            "failure_displacement_mm": None if fdm is None else round(fdm * 1e3, 4),
+            "failure_displacement_rel_diff_vs_fp64": (None if (fdm is None or fd64 is None)
+                                                      else round(abs(fdm - fd64) / fd64, 5)),
+        }
+        del mx["sim"]
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prob, "notched bar from rest, JC damage")
+    return out
+
+
+def final_shape(sim, prob):
+    """Taylor bar after impact: length, radius of the impact face, max plastic
+    strain, failed particles."""
+    X = prob.X
+    x = X + sim.get("u")
+    eps = sim.get("eps_p")
+    D = sim.get("D")
+    foot = X[:, 2] < 2.0 * float(prob.dx[0])
+    rad = np.sqrt(x[foot, 0] ** 2 + x[foot, 1] ** 2).max()
+    return {"length_mm": float(x[:, 2].max() - x[:, 2].min()) * 1e3,
+            "foot_radius_mm": float(rad) * 1e3, "max_eps_p": float(eps.max()),
+            "failed": int(np.sum(D >= 1.0))}
+
+
+def bench_single(args, torch, I, T, workload, prob, label, damage_name, result):
+    """One large specimen: FP64, then mixed, each with its end-state summary."""
+    damage = prob.materials[0]["damage"]
+    tune = not args.no_autotune
+    fp = run_form(prob, T.FP64, args.steps, args.warmup, torch, T, 0, tune)
+    nnz = fp["info"]["nnz"]
+    _, ktab = kernel_table(fp["kernel_times"], False, damage, prob.n, nnz)
+    out = base_line(args, workload, prob.n * args.steps / fp["seconds"],
+                    fp["seconds"] / args.steps * 1e3, "f64",
+                    dict({"particles": prob.n, "neighbour_pairs": nnz, "damage": damage_name,
+                          "precision": "fp64", "steps_total": args.warmup + args.steps,
+                          "dt_s": prob.materials[0]["dt"]}, **shape_of(fp["info"])))
+    out["kernels"] = ktab
+    out["roofline"] = roofline_of(fp, damage, prob.n, workload)
+    res64 = result(fp)
+    out["fp64_result"] = res64
+    del fp["sim"]
+    if not args.no_mixed:
+        mx = run_form(prob, T.MIXED, args.steps, args.warmup, torch, T, 0, tune)
+        _, mtab = kernel_table(mx["kernel_times"], True, damage, prob.n, nnz)
+        resm = result(mx)
+        out["mixed"] = {
+            "value": round(prob.n * args.steps / mx["seconds"], 1), "unit": "particle-steps/s",
+            "ms_per_step": round(mx["seconds"] / args.steps * 1e3, 5), "dtype": "f32/f64",
+            "launch": shape_of(mx["info"]), "kernels": mtab, "result": resm,
+            "rel_diff_vs_fp64": {k: (round(abs(resm[k] - res64[k]) / abs(res64[k]), 6)
+                                     if res64[k] else None) for k in res64}}
+        del mx["sim"]
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prob, label, max_steps=50)
+    return out
+
+
+def bench_taylor(args, torch, I, T):
+    prob = I.taylor_bar()
+    return bench_single(args, torch, I, T, "taylor_bar_1m", prob,
+                        "Taylor bar on a rigid wall, CL damage", "cockcroft-latham",
+                        lambda r: final_shape(r["sim"], prob))
+
+
+def bench_plate(args, torch, I, T):
+    prob = I.holed_plate()
+
+    def result(r):
+        bd, sd = r["bd"], r["sd"]
+        f = r["sim"].get("f_void")
+        return {"reaction_kN": float(-bd[-1, 1, 0]) / 1e3,
+                "grip_separation_mm": float(bd[-1, 1, 3] - bd[-1, 0, 3]) * 1e3,
+                "max_void_fraction": float(f.max()), "max_D": float(sd[-1, 0, 3])}
+    return bench_single(args, torch, I, T, "gtn_plate_4m", prob,
+                        "GTN holed plate in tension", "gtn", result)
+
+
+def bench_batch(args, torch, I, T):
+    """256 specimens: mixed form, one context, graph replays (two launches
+    per step for the whole batch), against 256 separate FP64 contexts stepped
+    one after the other (two launches per specimen per step); the batched
+    FP64 form is reported too."""
+    prob = I.bar_batch()
+    workload = "batch_256_bars"
+    damage = I.DMG_JC
+    side = torch.cuda.Stream()
+    mx = run_form(prob, T.MIXED, args.steps, args.warmup, torch, T, T.USE_GRAPHS,
+                  not args.no_autotune, stream=side, diag=False)
+    nnz = mx["info"]["nnz"]
+    out = base_line(args, workload, prob.n * args.steps / mx["seconds"],
+                    mx["seconds"] / args.steps * 1e3, "f32/f64",
+                    dict({"particles": prob.n, "specimens": prob.n_spec, "neighbour_pairs": nnz,
+                          "damage": "johnson-cook", "precision": "mixed", "graphs": True},
+                         **shape_of(mx["info"])))
+    del mx["sim"]
+    fb = run_form(prob, T.FP64, args.steps, args.warmup, torch, T, 0, not args.no_autotune,
+                  diag=False)
+    _, ktab = kernel_table(fb["kernel_times"], False, damage, prob.n, nnz)
+    out["fp64_batched"] = {"value": round(prob.n * args.steps / fb["seconds"], 1),
+                           "ms_per_step": round(fb["seconds"] / args.steps * 1e3, 5),
+                           "kernels": ktab, "launch": shape_of(fb["info"])}
+    out["roofline"] = roofline_of(fb, damage, prob.n, workload)
+    out["roofline"]["form"] = "fp64 batched"
+    del fb["sim"]
+    # 256 separate FP64 contexts, default launch shapes, eager launches
+    log("256 separate FP64 contexts")
+    sims = [T.Sim(I.subset(prob, [s]), precision=T.FP64) for s in range(prob.n_spec)]
+    for s in sims:
+        s.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in sims:
+        s.step(args.steps)
+    torch.cuda.synchronize()
+    sep = time.perf_counter() - t0
+    out["fp64_separate_256"] = {"value": round(prob.n * args.steps / sep, 1),
+                                "ms_per_step": round(sep / args.steps * 1e3, 5)}
+    out["speedup_batched_mixed_vs_separate_fp64"] = round(sep / mx["seconds"], 3)
+    del sims
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prob, "256 notched bars, JC damage", max_steps=20)
+    return out
+
+
+WORKLOADS = {"notched_bar_200k": (bench_notched_bar, 42000, 1000),
+             "taylor_bar_1m": (bench_taylor, 4900, 100),
+             "gtn_plate_4m": (bench_plate, 1900, 100),
+             "batch_256_bars": (bench_batch, 400, 50)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=42000)
-    ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--workload", default="notched_bar_200k", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
@@ -182,6 +413,9 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
+    fn, steps, warmup = WORKLOADS[args.workload]
+    args.steps = steps if args.steps is None else args.steps
+    args.warmup = warmup if args.warmup is None else args.warmup
 
     import torch
     from paper_1901_07374_amd import inputs as I
@@ -191,76 +425,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
-    prob = I.notched_bar()
-    damage = prob.materials[0]["damage"]
-    workload = "notched_bar_200k"
-
-    flags = T.NO_STAGING if args.unstaged else 0
-    fp = run_form(prob, T.FP64, args.steps, args.warmup, torch, T, flags, not args.no_autotune)
-    nnz = fp["info"]["nnz"]
-    value = prob.n * args.steps / fp["seconds"]
-    ms_step = fp["seconds"] / args.steps * 1e3
-
-    # roofline of the dominant kernel
-    kts = {k: v[0] / max(v[1], 1) for k, v in fp["kernel_times"].items()}
-    dom = max(kts, key=kts.get)
-    bytes_launch = algorithmic_bytes(dom, False, damage, prob.n, nnz)
-    achieved = bytes_launch / (kts[dom] * 1e-3) / 1e9
-    symbol = kernel_symbol(dom, fp["info"], False)
-    traffic = counter_traffic(symbol, workload)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": dom, "symbol": symbol,
-                "avg_launch_us": round(kts[dom] * 1e3, 2),
-                "algorithmic_bytes_per_launch": bytes_launch}
-    step_bytes = sum(algorithmic_bytes(k, False, damage, prob.n, nnz) for k in kts)
-    kernels = {k: {"avg_launch_us": round(v * 1e3, 2),
-                   "algorithmic_GBs": round(algorithmic_bytes(k, False, damage, prob.n, nnz)
-                                            / (v * 1e-3) / 1e9, 1)} for k, v in kts.items()}
-
-    out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "particle-steps/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": workload, "particles": prob.n, "neighbour_pairs": nnz,
-                   "damage": "johnson-cook", "precision": "fp64",
-                   "force_pass_variant": ("LDS-staged tiles" if fp["info"]["staged"] else
-                                          "global gathers"),
-                   "launch_shape": {"force_pass": fp["info"]["block_force"],
-                                    "force_lanes_per_particle": fp["info"]["lanes_per_particle"],
-                                    "deformation_pass": fp["info"]["block_deformation"]},
-                   "steps_from_rest": args.warmup + args.steps,
-                   "dt_s": prob.materials[0]["dt"]},
-        "step_algorithmic_GBs": round(step_bytes * args.steps / fp["seconds"] / 1e9, 1),
-        "kernels": kernels,
-        "roofline": roofline,
-    }
-    fd64 = failure_displacement(fp["sep"], fp["reaction"])
-    out["fp64_failure_displacement_mm"] = None if fd64 is None else round(fd64 * 1e3, 4)
-    out["fp64_peak_reaction_kN"] = round(float(fp["reaction"].max()) / 1e3, 3)
-    del fp["sim"]
-
-    if not args.no_mixed:
-        mx = run_form(prob, T.MIXED, args.steps, args.warmup, torch, T, flags, not args.no_autotune)
-        fdm = failure_displacement(mx["sep"], mx["reaction"])
-        r64, rmx = fp["reaction"], mx["reaction"]
-        ipk = int(np.argmax(r64))
-        dev = float(np.max(np.abs(rmx[: ipk + 1] - r64[: ipk + 1])) / max(r64.max(), 1e-30))
-        mkts = {k: v[0] / max(v[1], 1) for k, v in mx["kernel_times"].items()}
-        out["mixed"] = {
-            "value": round(prob.n * args.steps / mx["seconds"], 1), "unit": "particle-steps/s",
-            "ms_per_step": round(mx["seconds"] / args.steps * 1e3, 5), "dtype": "f32/f64",
-            "kernels": {k: {"avg_launch_us": round(v * 1e3, 2),
-                            "algorithmic_GBs": round(algorithmic_bytes(k, True, damage, prob.n, nnz)
-                                                     / (v * 1e-3) / 1e9, 1)}
-                        for k, v in mkts.items()},
-            "reaction_curve_max_rel_dev_to_peak_vs_fp64": round(dev, 6),
-            "failure_displacement_mm": None if fdm is None else round(fdm * 1e3, 4),
-            "failure_displacement_rel_diff_vs_fp64": (None if (fdm is None or fd64 is None)
-                                                      else round(abs(fdm - fd64) / fd64, 5)),
-        }
-        del mx["sim"]
+    out = fn(args, torch, I, T)
 
     if args.copy_probe_mib > 0:
         nb = args.copy_probe_mib * 1024 * 1024
@@ -271,9 +436,6 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = nb
-
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)
 
 

@@ -511,6 +511,24 @@ hipError_t launch_shape_and_init(const DevState& s, bool mixed, hipStream_t st) 
 // the step
 // ===========================================================================
 
+// 1/sqrt(x) for x > 0: the hardware estimate refined by Newton-Raphson steps
+// y <- y + y (1 - x y^2) / 2, two for double and one for float (each step
+// doubles the number of correct bits).  Not correctly rounded: a few ulp.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-x * y, y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+__device__ __forceinline__ float rsqrt_nr(float x) {
+    float y = __builtin_amdgcn_rsqf(x);
+    const float e = fmaf(-x * y, y, 1.0f);
+    return fmaf(0.5f * y, e, y);
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2).  Give XCD x a contiguous run of tiles instead, so the neighbour halos
 // of Morton-adjacent tiles are shared through one L2.
@@ -565,22 +583,25 @@ struct ForceAcc {
 template <typename R>
 __device__ __forceinline__ void force_pair(const LRecB<R>& ni, const LRecB<R>& nj, R inv_h,
                                            R wnorm, ForceAcc<R>& A, bool live = true) {
+    // a padding slot (live = false) gets 1/r = 1/|x| = 0: every term it
+    // adds is an exact zero
     const R dx = R(nj.x - ni.x), dy = R(nj.y - ni.y), dz = R(nj.z - ni.z);
-    const R r = sqrt(fma(dx, dx, fma(dy, dy, dz * dz)));
-    const R ir = R(1) / r;
+    const R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const R ir = live ? rsqrt_nr(r2) : R(0);
+    const R r = r2 * ir;
     R W, dW;
     spline(r, inv_h, wnorm, W, dW);
     const R gs = dW * ir;
     const R gx = gs * dx, gy = gs * dy, gz = gs * dz;
     const R Vj = nj.V0;
     const R wj = Vj * nj.omd;
-    const R na0 = fma(wj, gx, A.a0), na1 = fma(wj, gy, A.a1), na2 = fma(wj, gz, A.a2);
-    const R nb0 = fma(Vj, fma(nj.q[0], gx, fma(nj.q[1], gy, nj.q[2] * gz)), A.b0);
-    const R nb1 = fma(Vj, fma(nj.q[3], gx, fma(nj.q[4], gy, nj.q[5] * gz)), A.b1);
-    const R nb2 = fma(Vj, fma(nj.q[6], gx, fma(nj.q[7], gy, nj.q[8] * gz)), A.b2);
+    A.a0 = fma(wj, gx, A.a0); A.a1 = fma(wj, gy, A.a1); A.a2 = fma(wj, gz, A.a2);
+    A.b0 = fma(Vj, fma(nj.q[0], gx, fma(nj.q[1], gy, nj.q[2] * gz)), A.b0);
+    A.b1 = fma(Vj, fma(nj.q[3], gx, fma(nj.q[4], gy, nj.q[5] * gz)), A.b1);
+    A.b2 = fma(Vj, fma(nj.q[6], gx, fma(nj.q[7], gy, nj.q[8] * gz)), A.b2);
     const R du0 = R(nj.ux - ni.ux), du1 = R(nj.uy - ni.uy), du2 = R(nj.uz - ni.uz);
     const R x0 = dx + du0, x1 = dy + du1, x2 = dz + du2;
-    const R irc = R(1) / sqrt(fma(x0, x0, fma(x1, x1, x2 * x2)));
+    const R irc = live ? rsqrt_nr(fma(x0, x0, fma(x1, x1, x2 * x2))) : R(0);
     const R e0 = R(0.5) * fma(ni.h[0] + nj.h[0], dx, fma(ni.h[1] + nj.h[1], dy,
                                                        (ni.h[2] + nj.h[2]) * dz)) - du0;
     const R e1 = R(0.5) * fma(ni.h[3] + nj.h[3], dx, fma(ni.h[4] + nj.h[4], dy,
@@ -589,11 +610,7 @@ __device__ __forceinline__ void force_pair(const LRecB<R>& ni, const LRecB<R>& n
                                                        (ni.h[8] + nj.h[8]) * dz)) - du2;
     const R delta = fma(e0, x0, fma(e1, x1, e2 * x2)) * irc;
     const R c = wj * W * delta * ir * ir * irc;
-    const R ng0 = fma(c, x0, A.g0), ng1 = fma(c, x1, A.g1), ng2 = fma(c, x2, A.g2);
-    // padding slots (live = false) leave the sums untouched
-    A.a0 = live ? na0 : A.a0; A.a1 = live ? na1 : A.a1; A.a2 = live ? na2 : A.a2;
-    A.b0 = live ? nb0 : A.b0; A.b1 = live ? nb1 : A.b1; A.b2 = live ? nb2 : A.b2;
-    A.g0 = live ? ng0 : A.g0; A.g1 = live ? ng1 : A.g1; A.g2 = live ? ng2 : A.g2;
+    A.g0 = fma(c, x0, A.g0); A.g1 = fma(c, x1, A.g1); A.g2 = fma(c, x2, A.g2);
 }
 
 template <typename R>
@@ -904,21 +921,21 @@ __global__ void __launch_bounds__(256) k_pass_a(DevState s, int par) {
         }
 #pragma unroll
         for (int t = 0; t < kGatherA; ++t) {
+            // past the last neighbour 1/r = 0 makes every term an exact zero
             const bool live = k0 + t < cnt;
             const R dx = R(xj[t].x - xi.x), dy = R(xj[t].y - xi.y), dz = R(xj[t].z - xi.z);
-            const R r = sqrt(fma(dx, dx, fma(dy, dy, dz * dz)));
+            const R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+            const R ir = live ? rsqrt_nr(r2) : R(0);
             R W, dW;
-            spline(r, inv_h, wnorm, W, dW);
-            const R gs = dW / r;
+            spline(r2 * ir, inv_h, wnorm, W, dW);
+            const R gs = dW * ir;
             const R gx = gs * dx, gy = gs * dy, gz = gs * dz;
             const R wj = R(vj[t].w);
             const R t0 = wj * R(vj[t].x - vi.x), t1 = wj * R(vj[t].y - vi.y),
                     t2 = wj * R(vj[t].z - vi.z);
-            const R m[9] = {fma(t0, gx, M[0]), fma(t0, gy, M[1]), fma(t0, gz, M[2]),
-                            fma(t1, gx, M[3]), fma(t1, gy, M[4]), fma(t1, gz, M[5]),
-                            fma(t2, gx, M[6]), fma(t2, gy, M[7]), fma(t2, gz, M[8])};
-#pragma unroll
-            for (int q = 0; q < 9; ++q) M[q] = live ? m[q] : M[q];
+            M[0] = fma(t0, gx, M[0]); M[1] = fma(t0, gy, M[1]); M[2] = fma(t0, gz, M[2]);
+            M[3] = fma(t1, gx, M[3]); M[4] = fma(t1, gy, M[4]); M[5] = fma(t1, gz, M[5]);
+            M[6] = fma(t2, gx, M[6]); M[7] = fma(t2, gy, M[7]); M[8] = fma(t2, gz, M[8]);
         }
     }
     R Li[9];
