@@ -89,10 +89,10 @@ def counter_traffic(symbol: str, workload: str):
     return float(vals[key]) if key in vals else None
 
 
-def failure_displacement(sep, reaction):
-    """Grip separation where the reaction first drops below 10 % of its running
-    maximum after the peak, interpolated linearly between samples (None if it
-    never does)."""
+def failure_displacement(sep, reaction, level=0.1):
+    """Grip separation where the reaction first drops below `level` times its
+    running maximum after the peak, interpolated linearly between samples
+    (None if it never does)."""
     run_max = 0.0
     peak_seen = False
     prev = None
@@ -101,14 +101,34 @@ def failure_displacement(sep, reaction):
             run_max = r
         elif run_max > 0 and r < 0.98 * run_max:
             peak_seen = True
-        if peak_seen and r < 0.1 * run_max:
+        if peak_seen and r < level * run_max:
             if prev is None or prev[1] <= r:
                 return float(s)
             s0, r0 = prev
-            lvl = 0.1 * run_max
+            lvl = level * run_max
             return float(s0 + (s - s0) * (r0 - lvl) / (r0 - r))
         prev = (s, r)
     return None
+
+
+FD_LEVELS = (0.1, 0.5)
+
+
+def fd_mm(sep, reaction):
+    out = {}
+    for lvl in FD_LEVELS:
+        v = failure_displacement(sep, reaction, lvl)
+        out[f"{int(lvl * 100)}%"] = None if v is None else round(v * 1e3, 4)
+    return out
+
+
+def perturbed(I, p, seed, amp=1e-12):
+    """The same problem with initial velocities perturbed by +-amp m/s: a
+    rounding-level change that shows how far the failure point moves on its
+    own."""
+    rng = np.random.default_rng(seed)
+    return I.Problem(p.name, p.X, p.V0, p.spec_offsets, p.materials, p.bc_group, p.bc_groups,
+                     p.v_init + rng.uniform(-amp, amp, p.v_init.shape), p.steps, p.dx)
 
 
 def log(*a):
@@ -248,28 +268,54 @@ def bench_notched_bar(args, torch, I, T):
     out["kernels"] = ktab
     out["roofline"] = roofline_of(fp, damage, prob.n, workload)
     r64, s64 = curve(fp)
-    fd64 = failure_displacement(s64, r64)
-    out["fp64_failure_displacement_mm"] = None if fd64 is None else round(fd64 * 1e3, 4)
+    fd64 = fd_mm(s64, r64)
+    out["fp64_failure_displacement_mm"] = fd64
     out["fp64_peak_reaction_kN"] = round(float(r64.max()) / 1e3, 3) if len(r64) else None
+    shape64 = fp["info"]
     del fp["sim"]
+
+    # FP64 runs from rounding-level perturbed starts (untimed): the spread
+    # of the failure point that FP64 itself shows
+    ens = []
+    for seed in range(1, args.ensemble + 1):
+        e = run_form(perturbed(I, prob, seed), T.FP64, args.steps, args.warmup, torch, T, flags,
+                     False)
+        re_, se_ = curve(e)
+        ens.append(fd_mm(se_, re_))
+        del e["sim"]
+    if ens:
+        allfd = [fd64] + ens
+        out["fp64_ensemble"] = {
+            "perturbation": "initial velocities +-1e-12 m/s, seeds 1..%d" % args.ensemble,
+            "failure_displacement_mm": ens,
+            "spread_rel": {k: (round((max(d[k] for d in allfd) - min(d[k] for d in allfd))
+                                     / np.mean([d[k] for d in allfd]), 5)
+                               if all(d[k] for d in allfd) else None) for k in fd64}}
 
     if not args.no_mixed:
         mx = run_form(prob, T.MIXED, args.steps, args.warmup, torch, T, flags, tune)
         rmx, smx = curve(mx)
-        fdm = failure_displacement(smx, rmx)
+        fdm = fd_mm(smx, rmx)
         ipk = int(np.argmax(r64))
         dev = float(np.max(np.abs(rmx[: ipk + 1] - r64[: ipk + 1])) / max(r64.max(), 1e-30))
         _, mtab = kernel_table(mx["kernel_times"], True, damage, prob.n, nnz)
-        out["mixed"] = {
+        mixed = {
             "value": round(prob.n * args.steps / mx["seconds"], 1), "unit": "particle-steps/s",
             "ms_per_step": round(mx["seconds"] / args.steps * 1e3, 5), "dtype": "f32/f64",
             "launch": shape_of(mx["info"]), "kernels": mtab,
             "reaction_curve_max_rel_dev_to_peak_vs_fp64": round(dev, 6),
-            "failure_displacement_mm": None if fdm is None else round(fdm * 1e3, 4),
-            "failure_displacement_rel_diff_vs_fp64": (None if (fdm is None or fd64 is None)
-                                                      else round(abs(fdm - fd64) / fd64, 5)),
-        }
+            "failure_displacement_mm": fdm,
+            "failure_displacement_rel_diff_vs_fp64": {
+                k: (round(abs(fdm[k] - fd64[k]) / fd64[k], 5) if fdm[k] and fd64[k] else None)
+                for k in fd64}}
+        if ens:
+            mean = {k: float(np.mean([d[k] for d in [fd64] + ens])) for k in fd64
+                    if all(d[k] for d in [fd64] + ens)}
+            mixed["failure_displacement_rel_diff_vs_fp64_ensemble_mean"] = {
+                k: (round(abs(fdm[k] - mean[k]) / mean[k], 5) if fdm[k] else None) for k in mean}
+        out["mixed"] = mixed
         del mx["sim"]
+    assert shape64 is not None
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, "notched bar from rest, JC damage")
     return out
@@ -404,6 +450,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--ensemble", type=int, default=2,
+                    help="extra untimed FP64 runs from perturbed starts (notched bar)")
     ap.add_argument("--unstaged", action="store_true",
                     help="force pass gathers from global memory instead of LDS tiles")
     ap.add_argument("--copy-probe-mib", type=int, default=0,

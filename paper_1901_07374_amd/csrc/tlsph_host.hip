@@ -37,7 +37,6 @@ struct Layout {
     size_t XV, spec, bc, perm, iperm, nnb, slice_ptr, col, lcol, halo, halo_cnt, Linv, Linv32,
         specs, bcs, t;
     int64_t n_tiles;
-    int32_t halo_cap;
     size_t GB, U0, U1, VW, sig, eps_p, eps_rate, d_init, w_p, f_void, e, D, force, err,
         spec_off, bbox, keys, vals, bc_list, bc_ptr, diag_seg, diag_part, backup;
     int64_t diag_chunk_cap;
@@ -71,9 +70,10 @@ Layout make_layout(int64_t n, int32_t n_spec, int32_t n_bc, int32_t k_cap, bool 
     L.slice_ptr = take(((size_t)L.n_slices + 1) * 8);
     L.col = take((size_t)k_cap * np * 4);
     L.lcol = take((size_t)k_cap * np * 2);
-    L.n_tiles = (n + kTile - 1) / kTile;
-    L.halo_cap = kTile * k_cap;
-    L.halo = take((size_t)L.n_tiles * L.halo_cap * 4);
+    // staged-pass tiles hold 64..kTile particles (chosen at build): room for
+    // ceil(n / T) tiles of T * k_cap halo entries at any such T
+    L.n_tiles = (n + 63) / 64;
+    L.halo = take(((size_t)n + kTile) * k_cap * 4);
     L.halo_cnt = take((size_t)L.n_tiles * 4);
     L.Linv = take(9 * np * 8);
     L.Linv32 = take(mixed ? 9 * np * 4 : 0);
@@ -190,7 +190,8 @@ void wire_state(tlsph_ctx* c) {
     s.lcol = at<uint16_t>(c, L.lcol);
     s.halo = at<int32_t>(c, L.halo);
     s.halo_cnt = at<int32_t>(c, L.halo_cnt);
-    s.halo_cap = L.halo_cap;
+    s.halo_cap = 0;
+    s.tile = kTile;
     s.staged = 0;
     s.lds_slots = 0;
     s.Linv = at<double>(c, L.Linv);
@@ -461,8 +462,21 @@ tlsph_status tlsph_build_neighbors(tlsph_ctx* c, const double* X, const double* 
     int dev = 0, max_lds = 0;
     HIPCHK(c, hipGetDevice(&dev));
     HIPCHK(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    // Tile size of the staged force pass: whole rounds of tiles over the
+    // compute units (one tile per CU at a time), at most kTile particles.
+    int n_cu = 0;
+    HIPCHK(c, hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    if (n_cu < 1) n_cu = 1;
+    {
+        const int64_t per_round = (int64_t)kTile * n_cu;
+        const int64_t rounds = (L.n + per_round - 1) / per_round;
+        int64_t T = (L.n + rounds * n_cu - 1) / (rounds * n_cu);
+        T = T < 64 ? 64 : (T > kTile ? kTile : T);
+        c->st.tile = (int32_t)T;
+        c->st.halo_cap = (int32_t)T * L.k_cap;
+    }
     int E = 256;
-    while (E < kTile * L.k_cap) E <<= 1;
+    while (E < c->st.tile * L.k_cap) E <<= 1;
     const bool halo_fits = (2 * (size_t)E + 257) * 4 <= (size_t)max_lds && !(c->flags & TLSPH_NO_STAGING);
     if (halo_fits) HIPCHK(c, launch_halo(c->st, L.k_cap, stream));
     HIPCHK(c, launch_shape_and_init(c->st, L.mixed, stream));
@@ -477,14 +491,15 @@ tlsph_status tlsph_build_neighbors(tlsph_ctx* c, const double* X, const double* 
                     "singular correction matrix at particle " + std::to_string(orig));
     }
     if (halo_fits) {
-        const size_t lds = (size_t)(kTile + err[4]) * staged_record_bytes(L.mixed);
-        if (lds <= (size_t)max_lds && kTile + err[4] <= 65536) {
+        const int T = c->st.tile;
+        const size_t lds = (size_t)(T + err[4]) * staged_record_bytes(L.mixed);
+        if (lds <= (size_t)max_lds && T + err[4] <= 65536) {
             HIPCHK(c, prepare_staged(lds));
             c->staged_ok = true;
             c->lds_b = lds;
-            c->st.lds_slots = kTile + err[4];
+            c->st.lds_slots = T + err[4];
             c->st.staged = 1;
-            c->block_b = kTile * c->sub_b;
+            c->block_b = T * c->sub_b;
         }
     }
     // diagnostics segments: chunks of each specimen, then of each group
@@ -681,7 +696,7 @@ tlsph_status tlsph_autotune(tlsph_ctx* c, hipStream_t stream) {
         for (const Cand& k : cand_b) {
             if (k.staged && !c->staged_ok) continue;
             c->st.staged = k.staged;
-            const int blk = k.staged ? kTile * k.sub : k.block;
+            const int blk = k.staged ? c->st.tile * k.sub : k.block;
             float t = 0.0f;
             tlsph_status st = timed([&] {
                 return launch_pass_b(c->st, c->parity, blk, k.sub, L.mixed, stream, c->lds_b);
@@ -753,7 +768,7 @@ tlsph_status tlsph_set_launch_shape(tlsph_ctx* c, const int32_t shape[4]) {
         return fail(c, TLSPH_E_INVALID_ARG, "deformation-pass block must be 64, 128, 192 or 256");
     c->st.staged = staged;
     c->sub_b = sub;
-    c->block_b = staged ? kTile * sub : blk_b;
+    c->block_b = staged ? c->st.tile * sub : blk_b;
     c->block_a = blk_a;
     return TLSPH_OK;
 }

@@ -12,7 +12,7 @@ constexpr int kSpecShift = 3 * kMortonBits;
 constexpr int kSub = 4;            // partial sums per particle in the force pass (canonical order)
 constexpr int kNDiag = 8;          // doubles per diagnostics record
 constexpr int kDiagChunk = 2048;   // particles per partial sum of the diagnostics
-constexpr int kTile = 256;         // particles per workgroup tile of the LDS-staged passes
+constexpr int kTile = 256;         // most particles per workgroup tile of the LDS-staged pass
 constexpr int kHaloSortMax = 8192; // tile entries sorted in LDS at build (kTile * k_cap)
 
 // Per-specimen parameters as the kernels read them (raw + derived).
@@ -98,9 +98,9 @@ struct DevState {
     double* force;           // SoA [3][np]
     int32_t* err;    // [0] first singular (sorted), [1] max count, [2] sticky flags,
                      // [3] build status, [4] largest tile halo
-    // LDS staging: per tile of kTile particles, the sorted outside neighbours
+    // LDS staging: per tile of `tile` particles, the sorted outside neighbours
     // (halo) and every neighbour as a local slot (tile member j - start, or
-    // kTile + position in the halo), in the sliced layout of col
+    // tile + position in the halo), in the sliced layout of col
     const int32_t* halo;      // [n_tiles][halo_cap]
     const int32_t* halo_cnt;  // [n_tiles]
     const uint16_t* lcol;
@@ -108,6 +108,8 @@ struct DevState {
     int32_t staged;           // 1 when the staged force pass is in use
     int32_t lds_slots;        // slots per field array of the staged kernel's LDS image
     int32_t model;            // damage model shared by every specimen, -1 if they differ
+    int32_t tile;             // particles per tile of the staged force pass (<= kTile)
+    int32_t pad3_;
 };
 
 enum : uint32_t { kFlagStoreForce = 1u, kFlagGraphs = 2u, kFlagCheckFinite = 4u,
@@ -116,7 +118,7 @@ enum : int32_t { kErrNonFinite = 1, kErrNewton = 2 };
 
 // launch helpers implemented in tlsph_kernels.hip
 // Force pass: `sub` lanes per particle (1, 2 or 4); the unstaged variant runs
-// `block` threads per workgroup, the LDS-staged one kTile * sub.
+// `block` threads per workgroup, the LDS-staged one tile * sub.
 hipError_t launch_pass_b(const DevState& s, int parity, int block, int sub, bool mixed,
                          hipStream_t st, size_t lds_bytes = 0);
 hipError_t launch_pass_a(const DevState& s, int parity, int block, bool mixed, hipStream_t st);

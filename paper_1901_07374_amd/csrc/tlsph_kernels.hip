@@ -379,7 +379,7 @@ hipError_t launch_build_count(DevState& s, const BuildBuffers& b, hipStream_t st
 // One workgroup per tile of kTile particles: sort the tile's neighbour
 // entries that lie outside the tile (bitonic, in LDS), keep each index once
 // (the halo, ascending), then give every neighbour entry its local slot:
-// j - start inside the tile, kTile + position in the halo outside.
+// j - start inside the tile, T + position in the halo outside.
 __global__ void __launch_bounds__(256) k_halo(DevState s, int k_cap, int E,
                                               int32_t* __restrict__ halo,
                                               int32_t* __restrict__ halo_cnt,
@@ -389,15 +389,17 @@ __global__ void __launch_bounds__(256) k_halo(DevState s, int k_cap, int E,
     int32_t* hl = sh + E;         // [E]
     int32_t* part = sh + 2 * E;   // [257]
     const int tid = threadIdx.x;
+    const int T = s.tile;                  // particles per tile (<= 256 threads)
     const int64_t t = blockIdx.x;
-    const int64_t start = t * kTile;
-    const int64_t end = start + kTile < s.n ? start + kTile : s.n;
+    const int64_t start = t * T;
+    const int64_t end = start + T < s.n ? start + T : s.n;
     for (int e = tid; e < E; e += 256) srt[e] = 0x7fffffff;
     __syncthreads();
     const int64_t p = start + tid;
+    const bool mine = tid < T;             // thread tid holds particle start + tid
     int cnt = 0;
     const int32_t* cp = nullptr;
-    if (p < s.n) {
+    if (mine && p < s.n) {
         cnt = s.nnb[p];
         cp = s.col + s.slice_ptr[p / kSlice] + (p % kSlice);
         for (int k = 0; k < cnt; ++k) {
@@ -450,13 +452,13 @@ __global__ void __launch_bounds__(256) k_halo(DevState s, int k_cap, int E,
         halo_cnt[t] = H;
         atomicMax(&s.err[4], H);
     }
-    if (p < s.np) {
+    if (mine && p < s.np) {
         const int64_t sl = p / kSlice;
         const int w = (int)((s.slice_ptr[sl + 1] - s.slice_ptr[sl]) / kSlice);
         uint16_t* lp = lcol + s.slice_ptr[sl] + (p % kSlice);
         for (int k = cnt; k < w; ++k) lp[(int64_t)k * kSlice] = (uint16_t)tid;
     }
-    if (p < s.n) {
+    if (mine && p < s.n) {
         uint16_t* lp = lcol + s.slice_ptr[p / kSlice] + (p % kSlice);
         for (int k = 0; k < cnt; ++k) {
             const int32_t j = cp[(int64_t)k * kSlice];
@@ -469,7 +471,7 @@ __global__ void __launch_bounds__(256) k_halo(DevState s, int k_cap, int E,
                     const int mid = (lo + hi) >> 1;
                     if (hl[mid] < j) lo = mid + 1; else hi = mid;
                 }
-                loc = kTile + lo;
+                loc = T + lo;
             }
             lp[(int64_t)k * kSlice] = (uint16_t)loc;
         }
@@ -477,13 +479,14 @@ __global__ void __launch_bounds__(256) k_halo(DevState s, int k_cap, int E,
 }
 
 hipError_t launch_halo(const DevState& s, int k_cap, hipStream_t st) {
+    if (s.tile < 1 || s.tile > kTile) return hipErrorInvalidValue;
     int E = 256;
-    while (E < kTile * k_cap) E <<= 1;
+    while (E < s.tile * k_cap) E <<= 1;
     const size_t lds = (2 * (size_t)E + 257) * sizeof(int32_t);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_halo),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    const unsigned tiles = (unsigned)((s.n + kTile - 1) / kTile);
+    const unsigned tiles = (unsigned)((s.n + s.tile - 1) / s.tile);
     k_halo<<<tiles, 256, lds, st>>>(s, k_cap, E, const_cast<int32_t*>(s.halo),
                                     const_cast<int32_t*>(s.halo_cnt), const_cast<uint16_t*>(s.lcol));
     return hipGetLastError();
@@ -854,15 +857,16 @@ __global__ void __launch_bounds__(kTile * S) k_pass_b_staged(DevState s, int par
     extern __shared__ __align__(16) unsigned char lds_raw[];
     double2* __restrict__ L = reinterpret_cast<double2*>(lds_raw);
     const int M = s.lds_slots;
+    const int T = s.tile;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int64_t start = tile * kTile;
+    const int64_t start = tile * T;
     const int nh = s.halo_cnt[tile];
     const int32_t* __restrict__ hl = s.halo + tile * (int64_t)s.halo_cap;
     const D4* __restrict__ XV = s.XV;
     const D4* __restrict__ Uc = s.U[par];
     const GBRec<R>* __restrict__ GB = gb_of<R>(s);
-    for (int m = threadIdx.x; m < kTile + nh; m += kTile * S) {
-        const int64_t g = m < kTile ? start + m : (int64_t)hl[m - kTile];
+    for (int m = threadIdx.x; m < T + nh; m += T * S) {
+        const int64_t g = m < T ? start + m : (int64_t)hl[m - T];
         if (g < s.n) LdsB<R>::put(L, M, m, make_recb<R>(XV[g], GB[g], Uc[g]));
     }
     __syncthreads();
@@ -1020,11 +1024,11 @@ template <int S>
 static hipError_t launch_b(const DevState& s, int parity, int block, bool mixed, hipStream_t st,
                            size_t lds_bytes) {
     if (s.staged) {
-        const unsigned grid = (unsigned)((s.n + kTile - 1) / kTile);
+        const unsigned grid = (unsigned)((s.n + s.tile - 1) / s.tile);
         if (mixed)
-            k_pass_b_staged<float, S><<<grid, kTile * S, lds_bytes, st>>>(s, parity);
+            k_pass_b_staged<float, S><<<grid, s.tile * S, lds_bytes, st>>>(s, parity);
         else
-            k_pass_b_staged<double, S><<<grid, kTile * S, lds_bytes, st>>>(s, parity);
+            k_pass_b_staged<double, S><<<grid, s.tile * S, lds_bytes, st>>>(s, parity);
         return hipGetLastError();
     }
     const unsigned grid = (unsigned)((s.n * S + block - 1) / block);
