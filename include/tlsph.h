@@ -232,18 +232,23 @@ tlsph_status tlsph_kernel_times(tlsph_ctx *ctx, double ms[2], int64_t launches[2
  * pass, [2] neighbour pairs, [3] padded slots of the sliced neighbour layout,
  * [4] particles, [5] sticky device error flags (bit 0 non-finite, bit 1 GTN
  * Newton not converged), [6] lanes per particle of the force pass, [7] LDS
- * bytes per workgroup of the staged force pass (0 when unstaged). */
-tlsph_status tlsph_info(tlsph_ctx *ctx, int64_t out[8]);
+ * bytes per workgroup of the staged force pass (0 when unstaged), [8]
+ * particles per tile of the staged force pass (0 when unstaged). */
+tlsph_status tlsph_info(tlsph_ctx *ctx, int64_t out[9]);
 
-/* Pin the launch shape (host int32[4]): [0] 1 = LDS-staged force pass, 0 =
+/* Pin the launch shape (host int32[5]): [0] 1 = LDS-staged force pass, 0 =
  * gathers from global memory; [1] lanes per particle of the force pass (1,
  * 2 or 4); [2] threads per block of the unstaged force pass (64, 128, 192 or
- * 256; ignored when staged, which runs 256 particles per block); [3] threads
- * per block of the deformation pass (64 to 256, multiple of 64).  Every shape
- * gives bitwise identical results: the neighbour sums keep one canonical
- * order.  Errors: INVALID_ARG, BAD_STATE (before build), UNSUPPORTED (staged
- * requested where the tile and halo records do not fit in LDS). */
-tlsph_status tlsph_set_launch_shape(tlsph_ctx *ctx, const int32_t shape[4]);
+ * 256; ignored when staged, which runs tile * lanes threads per block);
+ * [3] threads per block of the deformation pass (64 to 256, multiple of 64);
+ * [4] particles per tile of the staged pass (64 to 256; 0 = the size chosen
+ * at build, which fills whole rounds of compute units).  A new tile size
+ * rebuilds the per-tile halo lists on the stream and synchronises.  Every
+ * shape gives bitwise identical results: the neighbour sums keep one
+ * canonical order.  Errors: INVALID_ARG, BAD_STATE (before build),
+ * UNSUPPORTED (staged requested where a tile and its halo do not fit in
+ * LDS), HIP. */
+tlsph_status tlsph_set_launch_shape(tlsph_ctx *ctx, const int32_t shape[5], hipStream_t stream);
 
 /* Free the host-side context (not the workspace).  Null is accepted. */
 void tlsph_destroy(tlsph_ctx *ctx);

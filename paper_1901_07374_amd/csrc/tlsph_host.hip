@@ -130,9 +130,11 @@ struct tlsph_ctx {
     int parity = 0;
     int64_t nnz = 0, slots = 0;
     int64_t diag_chunks_spec = 0, diag_chunks_all = 0;
-    int block_a = 256, block_b = 256, sub_b = 4;
+    int block_a = 256, block_b = 256, sub_b = 2;
     bool staged_ok = false;     // the staged force pass fits this device's LDS
     size_t lds_b = 0;           // its dynamic LDS bytes
+    int max_lds = 0;            // LDS bytes a workgroup may use on this device
+    int tile_auto = kTile;      // tile size chosen at build
     std::string last_error;
     // per-kernel timing (every timing_stride-th step while enabled)
     bool timing = false;
@@ -144,7 +146,7 @@ struct tlsph_ctx {
     // graphs
     hipGraphExec_t gexec = nullptr;
     int graph_parity = -1;
-    int graph_block_a = 0, graph_block_b = 0, graph_sub_b = 0;
+    int graph_block_a = 0, graph_block_b = 0, graph_sub_b = 0, graph_tile = 0;
 };
 
 namespace {
@@ -264,7 +266,7 @@ tlsph_status run_steps_eager(tlsph_ctx* c, int32_t n_steps, hipStream_t stream) 
 tlsph_status ensure_graph(tlsph_ctx* c, hipStream_t stream) {
     if (c->gexec && c->graph_parity == c->parity && c->graph_block_a == c->block_a &&
         c->graph_block_b == (c->st.staged ? -c->block_b : c->block_b) &&
-        c->graph_sub_b == c->sub_b)
+        c->graph_sub_b == c->sub_b && c->graph_tile == c->st.tile)
         return TLSPH_OK;
     if (c->gexec) {
         (void)hipGraphExecDestroy(c->gexec);
@@ -288,6 +290,38 @@ tlsph_status ensure_graph(tlsph_ctx* c, hipStream_t stream) {
     c->graph_block_a = c->block_a;
     c->graph_block_b = c->st.staged ? -c->block_b : c->block_b;
     c->graph_sub_b = c->sub_b;
+    c->graph_tile = c->st.tile;
+    return TLSPH_OK;
+}
+
+// Per-tile halo lists and local neighbour slots for tiles of T particles,
+// and the LDS image size they need; the staged force pass is usable when the
+// largest tile plus its halo fits one workgroup's LDS.  Synchronises.
+tlsph_status set_tile(tlsph_ctx* c, int T, hipStream_t stream) {
+    const Layout& L = c->L;
+    c->staged_ok = false;
+    c->st.staged = 0;
+    c->lds_b = 0;
+    if (T < 64 || T > kTile) return fail(c, TLSPH_E_INVALID_ARG, "tile size outside [64, 256]");
+    c->st.tile = T;
+    c->st.halo_cap = T * L.k_cap;
+    int E = 256;
+    while (E < T * L.k_cap) E <<= 1;
+    if ((2 * (size_t)E + 257) * 4 > (size_t)c->max_lds || (c->flags & TLSPH_NO_STAGING))
+        return TLSPH_OK;
+    const int32_t zero = 0;
+    HIPCHK(c, hipMemcpyAsync(c->ws + L.err + 16, &zero, 4, hipMemcpyHostToDevice, stream));
+    HIPCHK(c, launch_halo(c->st, L.k_cap, stream));
+    int32_t largest = 0;
+    HIPCHK(c, hipMemcpyAsync(&largest, c->ws + L.err + 16, 4, hipMemcpyDeviceToHost, stream));
+    HIPCHK(c, hipStreamSynchronize(stream));
+    const size_t lds = (size_t)(T + largest) * staged_record_bytes(L.mixed);
+    if (lds <= (size_t)c->max_lds && T + largest <= 65536) {
+        HIPCHK(c, prepare_staged(lds));
+        c->staged_ok = true;
+        c->lds_b = lds;
+        c->st.lds_slots = T + largest;
+    }
     return TLSPH_OK;
 }
 
@@ -390,6 +424,9 @@ tlsph_status tlsph_create(int64_t n, int32_t n_spec, const int64_t* spec_offsets
         d.wnorm = 8.0 / (M_PI * p.h * p.h * p.h);
         d.h2 = p.h * p.h;
         d.inv_cell = 1.0 / (p.h * (1.0 + 1e-9));
+        d.inv_dt = 1.0 / p.dt;
+        d.inv_rho0 = 1.0 / p.rho0;
+        d.inv_eps_dot0 = 1.0 / p.eps_dot0;
         d.damage = p.damage;
         d.has_wall = p.has_wall;
         d.first = spec_offsets[s];
@@ -453,15 +490,14 @@ tlsph_status tlsph_build_neighbors(tlsph_ctx* c, const double* X, const double* 
         return fail(c, TLSPH_E_CAPACITY, "a particle has " + std::to_string(err[1]) +
                                              " neighbours, k_cap is " + std::to_string(L.k_cap));
     HIPCHK(c, launch_build_fill(c->st, b, stream));
-    // LDS staging of the force pass: per-tile halo lists when they fit
     c->st.staged = 0;
     c->staged_ok = false;
     c->lds_b = 0;
     c->block_b = 256;
-    c->sub_b = 4;
-    int dev = 0, max_lds = 0;
+    c->sub_b = 2;
+    int dev = 0;
     HIPCHK(c, hipGetDevice(&dev));
-    HIPCHK(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    HIPCHK(c, hipDeviceGetAttribute(&c->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     // Tile size of the staged force pass: whole rounds of tiles over the
     // compute units (one tile per CU at a time), at most kTile particles.
     int n_cu = 0;
@@ -471,14 +507,8 @@ tlsph_status tlsph_build_neighbors(tlsph_ctx* c, const double* X, const double* 
         const int64_t per_round = (int64_t)kTile * n_cu;
         const int64_t rounds = (L.n + per_round - 1) / per_round;
         int64_t T = (L.n + rounds * n_cu - 1) / (rounds * n_cu);
-        T = T < 64 ? 64 : (T > kTile ? kTile : T);
-        c->st.tile = (int32_t)T;
-        c->st.halo_cap = (int32_t)T * L.k_cap;
+        c->tile_auto = (int)(T < 64 ? 64 : (T > kTile ? kTile : T));
     }
-    int E = 256;
-    while (E < c->st.tile * L.k_cap) E <<= 1;
-    const bool halo_fits = (2 * (size_t)E + 257) * 4 <= (size_t)max_lds && !(c->flags & TLSPH_NO_STAGING);
-    if (halo_fits) HIPCHK(c, launch_halo(c->st, L.k_cap, stream));
     HIPCHK(c, launch_shape_and_init(c->st, L.mixed, stream));
     HIPCHK(c, launch_bc_lists(c->st, b.keys, b.vals, L.n_pow2, at<int32_t>(c, L.bc_list),
                               at<int64_t>(c, L.bc_ptr), stream));
@@ -490,16 +520,13 @@ tlsph_status tlsph_build_neighbors(tlsph_ctx* c, const double* X, const double* 
         return fail(c, TLSPH_E_SINGULAR_L,
                     "singular correction matrix at particle " + std::to_string(orig));
     }
-    if (halo_fits) {
-        const int T = c->st.tile;
-        const size_t lds = (size_t)(T + err[4]) * staged_record_bytes(L.mixed);
-        if (lds <= (size_t)max_lds && T + err[4] <= 65536) {
-            HIPCHK(c, prepare_staged(lds));
-            c->staged_ok = true;
-            c->lds_b = lds;
-            c->st.lds_slots = T + err[4];
+    // LDS staging of the force pass: per-tile halo lists when they fit
+    {
+        tlsph_status ts = set_tile(c, c->tile_auto, stream);
+        if (ts != TLSPH_OK) return ts;
+        if (c->staged_ok) {
             c->st.staged = 1;
-            c->block_b = T * c->sub_b;
+            c->block_b = c->st.tile * c->sub_b;
         }
     }
     // diagnostics segments: chunks of each specimen, then of each group
@@ -667,10 +694,11 @@ tlsph_status tlsph_autotune(tlsph_ctx* c, hipStream_t stream) {
     HIPCHK(c, hipMemcpyAsync(backup, state, L.backup_bytes, hipMemcpyDeviceToDevice, stream));
     HIPCHK(c, hipMemcpyAsync(backup + L.backup_bytes, c->st.t, L.n_spec * 8,
                              hipMemcpyDeviceToDevice, stream));
-    // force pass: (staged, lanes per particle, block); deformation pass: block
-    struct Cand { int staged, sub, block; };
-    const Cand cand_b[] = {{1, 4, 0}, {1, 2, 0}, {1, 1, 0}, {0, 4, 256}, {0, 4, 128},
-                           {0, 2, 128}, {0, 1, 64}, {0, 1, 128}, {0, 1, 256}};
+    // force pass: unstaged (lanes per particle, block) and staged (tile
+    // size, lanes per particle); deformation pass: block
+    struct Cand { int staged, sub, block, tile; };
+    const Cand cand_u[] = {{0, 4, 256, 0}, {0, 4, 128, 0}, {0, 2, 128, 0}, {0, 1, 64, 0},
+                           {0, 1, 128, 0}, {0, 1, 256, 0}};
     const int cand_a[] = {64, 128, 256};
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
@@ -692,24 +720,65 @@ tlsph_status tlsph_autotune(tlsph_ctx* c, hipStream_t stream) {
     };
     {
         float best = 1e30f;
-        Cand pick{0, c->sub_b, c->block_b};
-        for (const Cand& k : cand_b) {
-            if (k.staged && !c->staged_ok) continue;
-            c->st.staged = k.staged;
+        Cand pick{c->st.staged, c->sub_b, c->block_b, c->st.tile};
+        auto consider = [&](const Cand& k) -> tlsph_status {
             const int blk = k.staged ? c->st.tile * k.sub : k.block;
+            c->st.staged = k.staged;
             float t = 0.0f;
             tlsph_status st = timed([&] {
                 return launch_pass_b(c->st, c->parity, blk, k.sub, L.mixed, stream, c->lds_b);
             }, &t);
-            if (st != TLSPH_OK) return st;
-            if (t < best) {
+            if (st == TLSPH_OK && t < best) {
                 best = t;
-                pick = Cand{k.staged, k.sub, blk};
+                pick = Cand{k.staged, k.sub, blk, c->st.tile};
+            }
+            return st;
+        };
+        for (const Cand& k : cand_u) {
+            tlsph_status st = consider(k);
+            if (st != TLSPH_OK) return st;
+        }
+        if (!(c->flags & TLSPH_NO_STAGING)) {
+            // Tile sizes: the build's, three fixed ones, and for each of those
+            // the size that fills whole rounds at the number of workgroups
+            // per CU its LDS image allows.
+            int dev = 0, lds_cu = 0, n_cu = 0;
+            HIPCHK(c, hipGetDevice(&dev));
+            HIPCHK(c, hipDeviceGetAttribute(&lds_cu,
+                                            hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev));
+            HIPCHK(c, hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+            if (lds_cu < c->max_lds) lds_cu = c->max_lds;
+            if (n_cu < 1) n_cu = 1;
+            std::vector<int> tiles = {c->tile_auto, 128, 96, 64};
+            for (size_t q = 0; q < tiles.size(); ++q) {
+                bool seen = false;
+                for (size_t r = 0; r < q; ++r) seen = seen || tiles[r] == tiles[q];
+                if (seen) continue;
+                tlsph_status ts = set_tile(c, tiles[q], stream);
+                if (ts != TLSPH_OK) return ts;
+                if (!c->staged_ok) continue;
+                for (int sub : {4, 2, 1}) {
+                    if (tiles[q] > staged_tile_max(sub)) continue;
+                    tlsph_status st = consider(Cand{1, sub, 0, tiles[q]});
+                    if (st != TLSPH_OK) return st;
+                }
+                const int64_t w = (int64_t)lds_cu / (int64_t)c->lds_b;
+                if (w >= 1 && q < 4) {
+                    const int64_t slots = w * n_cu;
+                    const int64_t rounds = (L.n + (int64_t)tiles[q] * slots - 1) /
+                                           ((int64_t)tiles[q] * slots);
+                    const int64_t T1 = (L.n + rounds * slots - 1) / (rounds * slots);
+                    if (T1 >= 64 && T1 < tiles[q]) tiles.push_back((int)T1);
+                }
             }
         }
-        c->st.staged = pick.staged;
+        // leave the halo lists of the chosen tile size (or of the build's)
+        tlsph_status ts = set_tile(c, pick.staged ? pick.tile : c->tile_auto, stream);
+        if (ts != TLSPH_OK) return ts;
+        c->st.staged = pick.staged && c->staged_ok;
         c->sub_b = pick.sub;
-        c->block_b = pick.block;
+        c->block_b = c->st.staged ? c->st.tile * pick.sub : (pick.staged ? 256 : pick.block);
+        if (!c->st.staged && pick.staged) c->sub_b = 2;
     }
     {
         float best = 1e30f;
@@ -736,7 +805,7 @@ tlsph_status tlsph_autotune(tlsph_ctx* c, hipStream_t stream) {
     return TLSPH_OK;
 }
 
-tlsph_status tlsph_info(tlsph_ctx* c, int64_t out[8]) {
+tlsph_status tlsph_info(tlsph_ctx* c, int64_t out[9]) {
     if (!c || !out) return TLSPH_E_INVALID_ARG;
     out[0] = c->st.staged ? -c->block_b : c->block_b;
     out[1] = c->block_a;
@@ -746,6 +815,7 @@ tlsph_status tlsph_info(tlsph_ctx* c, int64_t out[8]) {
     out[5] = 0;
     out[6] = c->sub_b;
     out[7] = c->st.staged ? (int64_t)c->lds_b : 0;
+    out[8] = c->st.staged ? c->st.tile : 0;
     if (c->built) {
         int32_t fl = 0;
         HIPCHK(c, hipMemcpy(&fl, c->ws + c->L.err + 8, 4, hipMemcpyDeviceToHost));
@@ -754,18 +824,30 @@ tlsph_status tlsph_info(tlsph_ctx* c, int64_t out[8]) {
     return TLSPH_OK;
 }
 
-tlsph_status tlsph_set_launch_shape(tlsph_ctx* c, const int32_t shape[4]) {
+tlsph_status tlsph_set_launch_shape(tlsph_ctx* c, const int32_t shape[5], hipStream_t stream) {
     if (!c || !shape) return TLSPH_E_INVALID_ARG;
     if (!c->built) return fail(c, TLSPH_E_BAD_STATE, "launch shape before build");
     const int32_t staged = shape[0], sub = shape[1], blk_b = shape[2], blk_a = shape[3];
+    const int32_t tile = shape[4] == 0 ? c->tile_auto : shape[4];
     if (staged != 0 && staged != 1) return fail(c, TLSPH_E_INVALID_ARG, "staged must be 0 or 1");
-    if (staged && !c->staged_ok)
-        return fail(c, TLSPH_E_UNSUPPORTED, "the LDS-staged force pass does not fit this input");
     if (sub != 1 && sub != 2 && sub != 4) return fail(c, TLSPH_E_INVALID_ARG, "lanes per particle");
     if (!staged && (blk_b < 64 || blk_b > 256 || blk_b % 64 != 0))
         return fail(c, TLSPH_E_INVALID_ARG, "force-pass block must be 64, 128, 192 or 256");
     if (blk_a < 64 || blk_a > 256 || blk_a % 64 != 0)
         return fail(c, TLSPH_E_INVALID_ARG, "deformation-pass block must be 64, 128, 192 or 256");
+    if (staged && (tile < 64 || tile > kTile))
+        return fail(c, TLSPH_E_INVALID_ARG, "tile must hold 64 to 256 particles");
+    if (staged && tile > staged_tile_max(sub))
+        return fail(c, TLSPH_E_UNSUPPORTED, "four lanes per particle run tiles of at most 128");
+    if (staged) {
+        if (tile != c->st.tile || !c->staged_ok) {
+            tlsph_status ts = set_tile(c, tile, stream);
+            if (ts != TLSPH_OK) return ts;
+        }
+        if (!c->staged_ok)
+            return fail(c, TLSPH_E_UNSUPPORTED,
+                        "the LDS-staged force pass does not fit this input at this tile size");
+    }
     c->st.staged = staged;
     c->sub_b = sub;
     c->block_b = staged ? c->st.tile * sub : blk_b;

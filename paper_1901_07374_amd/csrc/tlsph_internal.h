@@ -30,6 +30,7 @@ struct DevSpec {
     double h2;         // h * h (neighbour test, same rounding as a plain product)
     double inv_cell;   // 1 / cell edge, the edge a hair above h so that pairs closer
                        // than h never sit two cells apart after rounding
+    double inv_dt, inv_rho0, inv_eps_dot0;
     int32_t damage;
     int32_t has_wall;
     int64_t first, last;   // sorted-order particle range [first, last)
@@ -138,6 +139,8 @@ hipError_t launch_build_count(DevState& s, const BuildBuffers& b, hipStream_t st
 hipError_t launch_build_fill(DevState& s, const BuildBuffers& b, hipStream_t st);
 hipError_t launch_halo(const DevState& s, int k_cap, hipStream_t st);
 hipError_t prepare_staged(size_t lds_bytes_b);
+// Largest tile the staged force pass runs with `sub` lanes per particle.
+int staged_tile_max(int sub);
 size_t staged_record_bytes(bool mixed);
 hipError_t launch_shape_and_init(const DevState& s, bool mixed, hipStream_t st);
 hipError_t launch_get_field(const DevState& s, int field, int parity, bool mixed, double* dst,

@@ -514,22 +514,25 @@ hipError_t launch_shape_and_init(const DevState& s, bool mixed, hipStream_t st) 
 // the step
 // ===========================================================================
 
-// 1/sqrt(x) for x > 0: the hardware estimate refined by Newton-Raphson steps
+// 1/sqrt(x): the hardware estimate refined by Newton-Raphson steps
 // y <- y + y (1 - x y^2) / 2, two for double and one for float (each step
 // doubles the number of correct bits).  Not correctly rounded: a few ulp.
+// An estimate of 0 or infinity (x infinite or 0) is returned as it is.
 __device__ __forceinline__ double rsqrt_nr(double x) {
-    double y = __builtin_amdgcn_rsq(x);
+    const double y0 = __builtin_amdgcn_rsq(x);
+    double y = y0;
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
         const double e = fma(-x * y, y, 1.0);
         y = fma(0.5 * y, e, y);
     }
-    return y;
+    return (y0 == 0.0 || __builtin_isinf(y0)) ? y0 : y;
 }
 __device__ __forceinline__ float rsqrt_nr(float x) {
-    float y = __builtin_amdgcn_rsqf(x);
-    const float e = fmaf(-x * y, y, 1.0f);
-    return fmaf(0.5f * y, e, y);
+    const float y0 = __builtin_amdgcn_rsqf(x);
+    const float e = fmaf(-x * y0, y0, 1.0f);
+    const float y = fmaf(0.5f * y0, e, y0);
+    return (y0 == 0.0f || __builtin_isinf(y0)) ? y0 : y;
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
@@ -747,7 +750,7 @@ __device__ __forceinline__ void force_finish(const DevState& s, int64_t i, int p
 // the record (v, V0 (1 - D)) the deformation pass gathers.  This variant
 // gathers neighbours straight from global memory.
 template <typename R, int S>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S, 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S < 2 ? S : 2, 8)))
 k_pass_b(DevState s, int par) {
     const int64_t t = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int64_t i = t / S;
@@ -771,6 +774,11 @@ k_pass_b(DevState s, int par) {
     asm volatile("" ::: "memory");
     if (in && sub == 0) force_finish<R>(s, i, par, P, sp, make_recb<R>(XV[i], GB[i], Uc[i]), A);
 }
+
+// Largest workgroup of the staged force pass with S lanes per particle: four
+// lanes run tiles of at most 128 particles, so that the register budget
+// stays at two waves per SIMD.
+__host__ __device__ constexpr int staged_block_max(int S) { return S == 4 ? 512 : kTile * S; }
 
 // LDS image of the force-pass records of one tile and its halo, stored
 // field-pair-major (array f of 16-byte elements holds one pair of fields for
@@ -853,7 +861,7 @@ struct LdsB<float> {
 // identical.  Occupancy is bounded by LDS (one tile per CU); S lanes per
 // particle give the SIMDs several waves to switch between.
 template <typename R, int S>
-__global__ void __launch_bounds__(kTile * S) k_pass_b_staged(DevState s, int par) {
+__global__ void __launch_bounds__(staged_block_max(S)) k_pass_b_staged(DevState s, int par) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     double2* __restrict__ L = reinterpret_cast<double2*>(lds_raw);
     const int M = s.lds_slots;
@@ -896,11 +904,8 @@ __global__ void __launch_bounds__(kTile * S) k_pass_b_staged(DevState s, int par
 // M = sum_j V_j (1 - D_j)(v_j - v_i) (x) gradW_ij and dF/dt = M L_i^-1; then
 // the constitutive update and Q_i = P_i L_i^-T (0 for failed particles).
 template <typename R, int DM>
-__global__ void __launch_bounds__(256) k_pass_a(DevState s, int par) {
-    const int64_t i = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (i >= s.n) return;
+__device__ __forceinline__ void pass_a_particle(const DevState& s, int64_t i, int sp) {
     const int64_t np = s.np;
-    const int sp = s.spec[i];
     const DevSpec& P = s.specs[sp];
     const D4* __restrict__ XV = s.XV;
     const D4* __restrict__ VW = s.VW;
@@ -1020,6 +1025,22 @@ __global__ void __launch_bounds__(256) k_pass_a(DevState s, int par) {
     }
 }
 
+// Specimen parameters are read with scalar loads: the lanes of a wave take
+// turns by specimen, one turn unless the wave straddles two specimens.
+template <typename R, int DM>
+__global__ void __launch_bounds__(256) k_pass_a(DevState s, int par) {
+    const int64_t i = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (i >= s.n) return;
+    const int sp_lane = s.spec[i];
+    for (;;) {
+        const int sp = __builtin_amdgcn_readfirstlane(sp_lane);
+        if (sp == sp_lane) {
+            pass_a_particle<R, DM>(s, i, sp);
+            break;
+        }
+    }
+}
+
 template <int S>
 static hipError_t launch_b(const DevState& s, int parity, int block, bool mixed, hipStream_t st,
                            size_t lds_bytes) {
@@ -1049,6 +1070,8 @@ hipError_t launch_pass_b(const DevState& s, int parity, int block, int sub, bool
         default: return hipErrorInvalidValue;
     }
 }
+
+int staged_tile_max(int sub) { return staged_block_max(sub) / sub; }
 
 size_t staged_record_bytes(bool mixed) {
     return 16 * (size_t)(mixed ? LdsB<float>::kPairs : LdsB<double>::kPairs);

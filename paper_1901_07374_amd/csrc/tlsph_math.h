@@ -14,6 +14,39 @@
 
 namespace tlsph {
 
+// Reciprocal for the constitutive update: on the device the hardware
+// estimate refined by Newton-Raphson steps r <- r + r (1 - x r) (two for
+// double, one for float), a few ulp from 1/x instead of the correctly
+// rounded division sequence; on the host the plain division.  Where the
+// estimate is 0 or infinite (x infinite or 0) it is already exact and the
+// refinement (which would give NaN) is skipped.
+__host__ __device__ __forceinline__ double rcp_nr(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const double r0 = __builtin_amdgcn_rcp(x);
+    double r = fma(r0, fma(-x, r0, 1.0), r0);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return (r0 == 0.0 || __builtin_isinf(r0)) ? r0 : r;
+#else
+    return 1.0 / x;
+#endif
+}
+__host__ __device__ __forceinline__ float rcp_nr(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const float r0 = __builtin_amdgcn_rcpf(x);
+    const float r = fmaf(r0, fmaf(-x, r0, 1.0f), r0);
+    return (r0 == 0.0f || __builtin_isinf(r0)) ? r0 : r;
+#else
+    return 1.0f / x;
+#endif
+}
+
+// x^y for x >= 0, y > 0 as exp(y log x): within a few ulp of pow for the
+// exponents of the flow and failure laws (|y log x| of order 1), at a
+// fraction of its cost.
+__host__ __device__ __forceinline__ double pow_el(double x, double y) {
+    return exp(y * log(x));
+}
+
 template <typename R>
 __host__ __device__ __forceinline__ R det33(const R a[9]) {
     return a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
@@ -26,7 +59,7 @@ __host__ __device__ __forceinline__ void inv33(const R a[9], R o[9]) {
     const R c0 = a[4] * a[8] - a[5] * a[7];
     const R c1 = a[5] * a[6] - a[3] * a[8];
     const R c2 = a[3] * a[7] - a[4] * a[6];
-    const R inv = R(1) / (a[0] * c0 + a[1] * c1 + a[2] * c2);
+    const R inv = rcp_nr(a[0] * c0 + a[1] * c1 + a[2] * c2);
     o[0] = c0 * inv;
     o[1] = (a[2] * a[7] - a[1] * a[8]) * inv;
     o[2] = (a[1] * a[5] - a[2] * a[4]) * inv;
@@ -110,7 +143,7 @@ template <typename R>
 __host__ __device__ __forceinline__ R mg_pressure(R pref, R c0, R S, R G0, R mu) {
     const R eta = R(1) + mu;
     const R den = eta - S * mu;
-    return pref * c0 * c0 * mu * (eta - R(0.5) * G0 * mu) / (den * den);
+    return pref * c0 * c0 * mu * (eta - R(0.5) * G0 * mu) * rcp_nr(den * den);
 }
 
 // Mean stress from Jm1 = J - 1 (eta = 1/J).  Tension with damage uses
@@ -121,16 +154,17 @@ __host__ __device__ __forceinline__ R mean_stress(const DevSpec& P, R Jm1, R D, 
     const R rho0 = R(P.rho0), c0 = R(P.c0), S = R(P.S_alpha), G0 = R(P.Gamma0);
     const R J = R(1) + Jm1;
     const R eterm = G0 * rho0 * e;
-    R p = mg_pressure(rho0, c0, S, G0, -Jm1 / J) + eterm;
+    const R iJ = rcp_nr(J);
+    R p = mg_pressure(rho0, c0, S, G0, -Jm1 * iJ) + eterm;
     if (damaged_branch && p < R(0))
-        p = mg_pressure(rho0 * (R(1) - D), c0, S, G0, -(D + Jm1) / J) + eterm;
+        p = mg_pressure(rho0 * (R(1) - D), c0, S, G0, -(D + Jm1) * iJ) + eterm;
     return -p;
 }
 
 // Johnson-Cook flow stress, undamaged, isothermal; ln of the normalised rate
 // floored at 0.
 __host__ __device__ __forceinline__ double jc_rate_factor(const DevSpec& P, double rate) {
-    const double rs = rate / P.eps_dot0;
+    const double rs = rate * P.inv_eps_dot0;
     return 1.0 + P.C * log(rs > 1.0 ? rs : 1.0);
 }
 
@@ -278,6 +312,21 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
         o.D = 1.0;
         return;
     }
+    // energy per unit mass by the trapezoid rule, dF/dt : (P^n + P^{n+1}) / 2 / rho0:
+    // the P^n half now, so F^n and sigma^n need not stay live to the end
+    R work0 = R(0);
+    {
+        R S0[9], F0[9], F0i[9], P0[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) F0[k] = Hn[k];
+        F0[0] += R(1); F0[4] += R(1); F0[8] += R(1);
+        sym_from_voigt(sn, S0);
+        inv33(F0, F0i);
+        mmT33(S0, F0i, P0);
+        const R J0 = R(1) + det_ipH_m1(Hn);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) work0 += Fd[k] * (J0 * P0[k]);
+    }
     R Fb[9], Fbi[9], l[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) Fb[k] = R(0.5) * (Hn[k] + o.H[k]);
@@ -291,7 +340,8 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
                R(0.5) * (l[1] + l[3])};
     const R w01 = R(0.5) * (l[1] - l[3]), w02 = R(0.5) * (l[2] - l[6]), w12 = R(0.5) * (l[5] - l[7]);
     // stored deviator, rotated by R = (I - dt/2 w)^-1 (I + dt/2 w)
-    const R smn = (sn[0] + sn[1] + sn[2]) / R(3);
+    const R third = R(1.0 / 3.0);
+    const R smn = (sn[0] + sn[1] + sn[2]) * third;
     R Sd[9];
     {
         R s6[6] = {sn[0] - smn, sn[1] - smn, sn[2] - smn, sn[3], sn[4], sn[5]};
@@ -310,7 +360,7 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
         for (int k = 0; k < 9; ++k) Sd[k] = Sr[k];
     }
     // deviatoric strain increment
-    const R trd = (d6[0] + d6[1] + d6[2]) / R(3);
+    const R trd = (d6[0] + d6[1] + d6[2]) * third;
     const R de[6] = {(d6[0] - trd) * dt, (d6[1] - trd) * dt, (d6[2] - trd) * dt,
                      d6[3] * dt, d6[4] * dt, d6[5] * dt};
     R sdr[6];
@@ -335,25 +385,25 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
 #pragma unroll
         for (int k = 0; k < 6; ++k) st[k] = sdr[k] + R(2) * G * omD * de[k];
         const R seq = mises_voigt(st);
-        const R sf = R((P.A + P.B * pow(eps, P.n)) * jc_rate_factor(P, rate)) * omD;
+        const R sf = R((P.A + P.B * pow_el(eps, P.n)) * jc_rate_factor(P, rate)) * omD;
         R dep = R(0);
         if (seq < sf) {
 #pragma unroll
             for (int k = 0; k < 6; ++k) sd[k] = st[k];
         } else {
-            dep = (seq - sf) / (R(3) * G * omD);
-            const R sc = sf / seq;
+            dep = (seq - sf) * rcp_nr(R(3) * G * omD);
+            const R sc = sf * rcp_nr(seq);
 #pragma unroll
             for (int k = 0; k < 6; ++k) sd[k] = sc * st[k];
         }
         eps += double(dep);
-        rate = double(dep) / P.dt;
+        rate = double(dep) * P.inv_dt;
         if (dep > R(0) && (model == 1 || model == 2)) {
             if (model == 2) {
-                const R sstar = sm / mises_voigt(sd);
+                const R sstar = sm * rcp_nr(mises_voigt(sd));
                 const double ef = (P.D1 + P.D2 * exp(P.D3 * double(sstar))) *
-                                  pow(1.0 + rate / P.eps_dot0, P.D4);
-                dinit += double(dep) / ef;
+                                  pow_el(1.0 + rate * P.inv_eps_dot0, P.D4);
+                dinit += double(dep) * rcp_nr(ef);
             } else {
                 R full6[6] = {sd[0] + sm, sd[1] + sm, sd[2] + sm, sd[3], sd[4], sd[5]};
                 const R s1 = max_principal(full6);
@@ -382,19 +432,11 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
     mmT33(S1, Fi, o.P);
 #pragma unroll
     for (int k = 0; k < 9; ++k) o.P[k] *= J;
-    // energy per unit mass: dF/dt : (P^n + P^{n+1}) / 2 / rho0
-    R S0[9], F0[9], F0i[9], P0[9];
+    // the P^{n+1} half of the energy update
+    R work1 = R(0);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) F0[k] = Hn[k];
-    F0[0] += R(1); F0[4] += R(1); F0[8] += R(1);
-    sym_from_voigt(sn, S0);
-    inv33(F0, F0i);
-    mmT33(S0, F0i, P0);
-    const R J0 = R(1) + det_ipH_m1(Hn);
-    R work = R(0);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) work += Fd[k] * (J0 * P0[k] + o.P[k]);
-    e += double(P.dt) * double(R(0.5) * work) / P.rho0;
+    for (int k = 0; k < 9; ++k) work1 += Fd[k] * o.P[k];
+    e += double(P.dt) * double(R(0.5) * (work0 + work1)) * P.inv_rho0;
 }
 
 }  // namespace tlsph

@@ -84,7 +84,7 @@ def lib():
         L.tlsph_enable_kernel_timing.argtypes = [_vp, C.c_int32]
         L.tlsph_kernel_times.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.tlsph_info.argtypes = [_vp, C.POINTER(C.c_int64)]
-        L.tlsph_set_launch_shape.argtypes = [_vp, C.POINTER(C.c_int32)]
+        L.tlsph_set_launch_shape.argtypes = [_vp, C.POINTER(C.c_int32), _vp]
         L.tlsph_destroy.argtypes = [_vp]
         L.tlsph_destroy.restype = None
         L.tlsph_status_string.argtypes = [C.c_int]
@@ -275,14 +275,15 @@ class Sim:
         return {"force_pass": (ms[0], cnt[0]), "deformation_pass": (ms[1], cnt[1])}
 
     def info(self) -> Dict[str, int]:
-        out = (C.c_int64 * 8)()
+        out = (C.c_int64 * 9)()
         self._check(lib().tlsph_info(self.ctx, out), "tlsph_info")
         return dict(block_force=abs(out[0]), staged=out[0] < 0, block_deformation=out[1],
                     nnz=out[2], slots=out[3], n=out[4], flags=out[5],
-                    lanes_per_particle=out[6], lds_bytes=out[7])
+                    lanes_per_particle=out[6], lds_bytes=out[7], tile=out[8])
 
     def set_launch_shape(self, staged: bool, lanes: int, block_force: int = 256,
-                         block_deformation: int = 256):
-        shape = (C.c_int32 * 4)(int(staged), int(lanes), int(block_force),
-                                int(block_deformation))
-        self._check(lib().tlsph_set_launch_shape(self.ctx, shape), "tlsph_set_launch_shape")
+                         block_deformation: int = 256, tile: int = 0):
+        shape = (C.c_int32 * 5)(int(staged), int(lanes), int(block_force),
+                                int(block_deformation), int(tile))
+        self._check(lib().tlsph_set_launch_shape(self.ctx, shape, self._sp()),
+                    "tlsph_set_launch_shape")

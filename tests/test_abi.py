@@ -104,6 +104,6 @@ def test_null_context_calls(L):
     assert L.tlsph_build_neighbors(None, None, None, None, None) == 1
     assert L.tlsph_autotune(None, None) == 1
     assert L.tlsph_info(None, None) == 1
-    assert L.tlsph_set_launch_shape(None, None) == 1
+    assert L.tlsph_set_launch_shape(None, None, None) == 1
     L.tlsph_destroy(None)
     assert L.tlsph_last_error(None) == b""

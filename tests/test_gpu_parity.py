@@ -172,7 +172,7 @@ def test_bitwise_determinism_graphs_and_autotune(tl):
         flags = {"graphs": tl.USE_GRAPHS, "unstaged": tl.NO_STAGING}.get(mode, 0)
         g = tl.Sim(p, flags=flags, stream=side if mode == "graphs" else None)
         assert g.info()["staged"] == (mode != "unstaged")
-        assert g.info()["lanes_per_particle"] == 4
+        assert g.info()["lanes_per_particle"] == 2
         g.set_state(st)
         if mode == "autotuned":
             g.autotune()
@@ -183,9 +183,10 @@ def test_bitwise_determinism_graphs_and_autotune(tl):
             assert np.array_equal(o[k], outs[0][k]), k
 
 
-SHAPES = [  # (staged, lanes per particle, force block, deformation block)
-    (1, 4, 256, 256), (1, 2, 256, 128), (1, 1, 256, 64), (0, 4, 256, 256), (0, 4, 64, 192),
-    (0, 2, 128, 128), (0, 1, 64, 64), (0, 1, 256, 256)]
+SHAPES = [  # (staged, lanes per particle, force block, deformation block, tile)
+    (1, 4, 256, 256, 0), (1, 2, 256, 128, 0), (1, 1, 256, 64, 0), (1, 2, 256, 64, 64),
+    (1, 4, 256, 64, 96), (1, 1, 256, 128, 256), (0, 4, 256, 256, 0), (0, 4, 64, 192, 0),
+    (0, 2, 128, 128, 0), (0, 1, 64, 64, 0), (0, 1, 256, 256, 0)]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -204,6 +205,7 @@ def test_every_launch_shape_is_bitwise_identical(tl, orc, precision):
         g.set_launch_shape(*shape)
         inf = g.info()
         assert inf["staged"] == bool(shape[0]) and inf["lanes_per_particle"] == shape[1]
+        assert inf["tile"] == (shape[4] or inf["tile"]) if shape[0] else inf["tile"] == 0
         g.set_state(st)
         g.step(3)
         outs.append({k: g.get(k) for k in ("force", "v", "u", "F", "Q", "sig", "D")})
@@ -259,7 +261,7 @@ def test_error_paths(tl):
     assert ei.value.status == 2
     g = tl.Sim(p)
     for bad in ((2, 4, 256, 256), (0, 3, 256, 256), (0, 4, 96, 256), (0, 4, 256, 32),
-                (0, 4, 512, 256)):
+                (0, 4, 512, 256), (1, 4, 256, 256, 32), (1, 4, 256, 256, 512)):
         with pytest.raises(tl.TLSPHError) as ei:
             g.set_launch_shape(*bad)
         assert ei.value.status == 1, bad
