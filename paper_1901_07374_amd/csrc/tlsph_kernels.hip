@@ -649,20 +649,26 @@ __device__ __forceinline__ ForceAcc<R> pair_sums(const LRecB<R>& ni, int cnt, in
     static_assert(kSub == 4 && (S == 1 || S == 2 || S == 4), "canonical order has 4 partials");
     constexpr int NP = kSub / S;
     ForceAcc<R> A[NP];
-    // neighbour indices run one group of kSub ahead of the arithmetic
-    int nxt[NP];
+    // neighbour indices run kAhead groups of kSub ahead of the arithmetic
+    // (fetching further ahead measured no faster)
+    constexpr int kAhead = 1;
+    int q[kAhead][NP];
 #pragma unroll
-    for (int t = 0; t < NP; ++t) {
-        const int k = sub + S * t;
-        nxt[t] = idx(k < cnt ? k : 0);
-    }
+    for (int d = 0; d < kAhead; ++d)
+#pragma unroll
+        for (int t = 0; t < NP; ++t) {
+            const int k = d * kSub + sub + S * t;
+            q[d][t] = idx(k < cnt ? k : 0);
+        }
     for (int k0 = 0; k0 < cnt; k0 += kSub) {
         int cur[NP];
 #pragma unroll
         for (int t = 0; t < NP; ++t) {
-            cur[t] = nxt[t];
-            const int kn = k0 + kSub + sub + S * t;
-            nxt[t] = idx(kn < cnt ? kn : 0);
+            cur[t] = q[0][t];
+#pragma unroll
+            for (int d = 0; d + 1 < kAhead; ++d) q[d][t] = q[d + 1][t];
+            const int kn = k0 + kAhead * kSub + sub + S * t;
+            q[kAhead - 1][t] = idx(kn < cnt ? kn : 0);
         }
 #pragma unroll
         for (int t = 0; t < NP; ++t) {
