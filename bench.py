@@ -136,11 +136,13 @@ def log(*a):
 
 
 def run_form(prob, precision, steps, warmup, torch, T, flags=0, autotune=True, stream=None,
-             diag=True):
-    """Warm up, autotune, then time `steps` steps; diagnostics every
-    DIAG_EVERY steps (inside the timed region)."""
+             diag=True, shape=None):
+    """Warm up, autotune (or apply a given launch shape), then time `steps`
+    steps; diagnostics every DIAG_EVERY steps (inside the timed region)."""
     log(f"{prob.name}: {prob.n} particles, precision {precision}, flags {flags}")
     sim = T.Sim(prob, precision=precision, flags=flags, stream=stream)
+    if shape is not None:
+        sim.set_launch_shape(*shape)
     n_rec = (warmup + steps) // DIAG_EVERY + 1 if diag else 0
     n_bc = max(len(prob.bc_groups), 1)
     sd = torch.zeros((max(n_rec, 1), prob.n_spec, 8), dtype=torch.float64, device="cuda")
@@ -167,7 +169,7 @@ def run_form(prob, precision, steps, warmup, torch, T, flags=0, autotune=True, s
                 rec += 1
 
     advance(warmup)
-    if autotune:
+    if autotune and shape is None:
         sim.autotune()     # picks launch shapes on the current state; results unchanged
     use_timing = not (flags & T.USE_GRAPHS)
     torch.cuda.synchronize()
@@ -233,6 +235,13 @@ def base_line(args, workload, value, ms_step, dtype, config):
             "config": dict({"workload": workload}, **config)}
 
 
+def launch_shape(info):
+    """(staged, lanes, force block, deformation block, tile) of a run."""
+    return (int(info["staged"]), info["lanes_per_particle"],
+            info["block_force"] if not info["staged"] else 256, info["block_deformation"],
+            info["tile"] if info["staged"] else 0)
+
+
 def shape_of(info):
     return {"force_pass_variant": "LDS-staged tiles" if info["staged"] else "global gathers",
             "force_pass_block": info["block_force"],
@@ -279,7 +288,7 @@ def bench_notched_bar(args, torch, I, T):
     ens = []
     for seed in range(1, args.ensemble + 1):
         e = run_form(perturbed(I, prob, seed), T.FP64, args.steps, args.warmup, torch, T, flags,
-                     False)
+                     False, shape=launch_shape(shape64))
         re_, se_ = curve(e)
         ens.append(fd_mm(se_, re_))
         del e["sim"]
