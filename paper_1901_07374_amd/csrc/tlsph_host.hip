@@ -301,6 +301,8 @@ tlsph_status set_tile(tlsph_ctx* c, int T, hipStream_t stream) {
     const Layout& L = c->L;
     c->staged_ok = false;
     c->st.staged = 0;
+    c->st.staged_lds_a = 0;
+    if (c->block_a == 0) c->block_a = 256;
     c->lds_b = 0;
     if (T < 64 || T > kTile) return fail(c, TLSPH_E_INVALID_ARG, "tile size outside [64, 256]");
     c->st.tile = T;
@@ -321,6 +323,8 @@ tlsph_status set_tile(tlsph_ctx* c, int T, hipStream_t stream) {
         c->staged_ok = true;
         c->lds_b = lds;
         c->st.lds_slots = T + largest;
+        // the deformation pass's records (56 bytes) within the default LDS limit
+        c->st.staged_lds_a = (size_t)(T + largest) * 56 <= 65536 ? 1 : 0;
     }
     return TLSPH_OK;
 }
@@ -699,7 +703,7 @@ tlsph_status tlsph_autotune(tlsph_ctx* c, hipStream_t stream) {
     struct Cand { int staged, sub, block, tile; };
     const Cand cand_u[] = {{0, 4, 256, 0}, {0, 4, 128, 0}, {0, 2, 128, 0}, {0, 1, 64, 0},
                            {0, 1, 128, 0}, {0, 1, 256, 0}};
-    const int cand_a[] = {64, 128, 256};
+    const int cand_a[] = {64, 128, 256, 0};   // 0: staged over the force pass's tiles
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
@@ -718,83 +722,94 @@ tlsph_status tlsph_autotune(tlsph_ctx* c, hipStream_t stream) {
         HIPCHK(c, hipEventElapsedTime(ms, e0, e1));
         return TLSPH_OK;
     };
-    {
-        float best = 1e30f;
-        Cand pick{c->st.staged, c->sub_b, c->block_b, c->st.tile};
-        auto consider = [&](const Cand& k) -> tlsph_status {
-            const int blk = k.staged ? c->st.tile * k.sub : k.block;
-            c->st.staged = k.staged;
-            float t = 0.0f;
-            tlsph_status st = timed([&] {
-                return launch_pass_b(c->st, c->parity, blk, k.sub, L.mixed, stream, c->lds_b);
-            }, &t);
-            if (st == TLSPH_OK && t < best) {
-                best = t;
-                pick = Cand{k.staged, k.sub, blk, c->st.tile};
-            }
-            return st;
-        };
-        for (const Cand& k : cand_u) {
-            tlsph_status st = consider(k);
-            if (st != TLSPH_OK) return st;
-        }
-        if (!(c->flags & TLSPH_NO_STAGING)) {
-            // Tile sizes: the build's, three fixed ones, and for each of those
-            // the size that fills whole rounds at the number of workgroups
-            // per CU its LDS image allows.
-            int dev = 0, lds_cu = 0, n_cu = 0;
-            HIPCHK(c, hipGetDevice(&dev));
-            HIPCHK(c, hipDeviceGetAttribute(&lds_cu,
-                                            hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev));
-            HIPCHK(c, hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-            if (lds_cu < c->max_lds) lds_cu = c->max_lds;
-            if (n_cu < 1) n_cu = 1;
-            std::vector<int> tiles = {c->tile_auto, 128, 96, 64};
-            for (size_t q = 0; q < tiles.size(); ++q) {
-                bool seen = false;
-                for (size_t r = 0; r < q; ++r) seen = seen || tiles[r] == tiles[q];
-                if (seen) continue;
-                tlsph_status ts = set_tile(c, tiles[q], stream);
-                if (ts != TLSPH_OK) return ts;
-                if (!c->staged_ok) continue;
-                for (int sub : {4, 2, 1}) {
-                    if (tiles[q] > staged_tile_max(sub)) continue;
-                    tlsph_status st = consider(Cand{1, sub, 0, tiles[q]});
-                    if (st != TLSPH_OK) return st;
-                }
-                const int64_t w = (int64_t)lds_cu / (int64_t)c->lds_b;
-                if (w >= 1 && q < 4) {
-                    const int64_t slots = w * n_cu;
-                    const int64_t rounds = (L.n + (int64_t)tiles[q] * slots - 1) /
-                                           ((int64_t)tiles[q] * slots);
-                    const int64_t T1 = (L.n + rounds * slots - 1) / (rounds * slots);
-                    if (T1 >= 64 && T1 < tiles[q]) tiles.push_back((int)T1);
-                }
-            }
-        }
-        // leave the halo lists of the chosen tile size (or of the build's)
-        tlsph_status ts = set_tile(c, pick.staged ? pick.tile : c->tile_auto, stream);
-        if (ts != TLSPH_OK) return ts;
-        c->st.staged = pick.staged && c->staged_ok;
-        c->sub_b = pick.sub;
-        c->block_b = c->st.staged ? c->st.tile * pick.sub : (pick.staged ? 256 : pick.block);
-        if (!c->st.staged && pick.staged) c->sub_b = 2;
+    // The two passes are timed separately and the step's shape chosen for
+    // the least sum: unstaged candidates do not depend on the tile size,
+    // staged ones (force pass and deformation pass) are timed per tile size.
+    auto time_b = [&](int staged, int sub, int block, float* ms) -> tlsph_status {
+        c->st.staged = staged;
+        const int blk = staged ? c->st.tile * sub : block;
+        return timed([&] {
+            return launch_pass_b(c->st, c->parity, blk, sub, L.mixed, stream, c->lds_b);
+        }, ms);
+    };
+    auto time_a = [&](int block, float* ms) -> tlsph_status {
+        return timed([&] { return launch_pass_a(c->st, c->parity, block, L.mixed, stream); }, ms);
+    };
+    struct Plan { int staged, sub, block_b, tile, block_a; float ms; };
+    Plan best{0, 2, 256, c->tile_auto, 256, 1e30f};
+    float bu = 1e30f, au = 1e30f;
+    int bu_sub = 2, bu_blk = 256, au_blk = 256;
+    for (const Cand& k : cand_u) {
+        float t = 0.0f;
+        tlsph_status st = time_b(0, k.sub, k.block, &t);
+        if (st != TLSPH_OK) return st;
+        if (t < bu) { bu = t; bu_sub = k.sub; bu_blk = k.block; }
     }
-    {
-        float best = 1e30f;
-        int pick = c->block_a;
-        for (int b : cand_a) {
-            float t = 0.0f;
-            tlsph_status st = timed([&] {
-                return launch_pass_a(c->st, c->parity, b, L.mixed, stream);
-            }, &t);
-            if (st != TLSPH_OK) return st;
-            if (t < best) {
-                best = t;
-                pick = b;
+    for (int blk : cand_a) {
+        if (blk == 0) continue;
+        float t = 0.0f;
+        tlsph_status st = time_a(blk, &t);
+        if (st != TLSPH_OK) return st;
+        if (t < au) { au = t; au_blk = blk; }
+    }
+    best = Plan{0, bu_sub, bu_blk, c->tile_auto, au_blk, bu + au};
+    if (!(c->flags & TLSPH_NO_STAGING)) {
+        // Tile sizes: the build's, three fixed ones, and for each of those
+        // the size that fills whole rounds at the number of workgroups per
+        // CU its LDS image allows.
+        int dev = 0, lds_cu = 0, n_cu = 0;
+        HIPCHK(c, hipGetDevice(&dev));
+        HIPCHK(c, hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                                        dev));
+        HIPCHK(c, hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+        if (lds_cu < c->max_lds) lds_cu = c->max_lds;
+        if (n_cu < 1) n_cu = 1;
+        std::vector<int> tiles = {c->tile_auto, 128, 96, 64};
+        for (size_t q = 0; q < tiles.size(); ++q) {
+            bool seen = false;
+            for (size_t r = 0; r < q; ++r) seen = seen || tiles[r] == tiles[q];
+            if (seen) continue;
+            tlsph_status ts = set_tile(c, tiles[q], stream);
+            if (ts != TLSPH_OK) return ts;
+            if (!c->staged_ok) continue;
+            float bs = 1e30f, as = 1e30f;
+            int bs_sub = 2;
+            for (int sub : {4, 2, 1}) {
+                if (tiles[q] > staged_tile_max(sub)) continue;
+                float t = 0.0f;
+                tlsph_status st = time_b(1, sub, 0, &t);
+                if (st != TLSPH_OK) return st;
+                if (t < bs) { bs = t; bs_sub = sub; }
+            }
+            if (c->st.staged_lds_a) {
+                tlsph_status st = time_a(0, &as);
+                if (st != TLSPH_OK) return st;
+            }
+            const Plan opts[3] = {{1, bs_sub, 0, tiles[q], au_blk, bs + au},
+                                  {1, bs_sub, 0, tiles[q], 0, bs + as},
+                                  {0, bu_sub, bu_blk, tiles[q], 0, bu + as}};
+            for (const Plan& o : opts)
+                if (o.ms < best.ms) best = o;
+            const int64_t w = (int64_t)lds_cu / (int64_t)c->lds_b;
+            if (w >= 1 && q < 4) {
+                const int64_t slots = w * n_cu;
+                const int64_t rounds = (L.n + (int64_t)tiles[q] * slots - 1) /
+                                       ((int64_t)tiles[q] * slots);
+                const int64_t T1 = (L.n + rounds * slots - 1) / (rounds * slots);
+                if (T1 >= 64 && T1 < tiles[q]) tiles.push_back((int)T1);
             }
         }
-        c->block_a = pick;
+    }
+    // leave the halo lists of the chosen tile size and apply the plan
+    {
+        tlsph_status ts = set_tile(c, best.tile, stream);
+        if (ts != TLSPH_OK) return ts;
+        const bool ok_b = !best.staged || c->staged_ok;
+        const bool ok_a = best.block_a != 0 || c->st.staged_lds_a;
+        c->st.staged = best.staged && ok_b;
+        c->sub_b = ok_b ? best.sub : 2;
+        c->block_b = c->st.staged ? c->st.tile * c->sub_b : (best.staged ? 256 : best.block_b);
+        c->block_a = ok_a ? best.block_a : 256;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -833,8 +848,9 @@ tlsph_status tlsph_set_launch_shape(tlsph_ctx* c, const int32_t shape[5], hipStr
     if (sub != 1 && sub != 2 && sub != 4) return fail(c, TLSPH_E_INVALID_ARG, "lanes per particle");
     if (!staged && (blk_b < 64 || blk_b > 256 || blk_b % 64 != 0))
         return fail(c, TLSPH_E_INVALID_ARG, "force-pass block must be 64, 128, 192 or 256");
-    if (blk_a < 64 || blk_a > 256 || blk_a % 64 != 0)
-        return fail(c, TLSPH_E_INVALID_ARG, "deformation-pass block must be 64, 128, 192 or 256");
+    if (blk_a != 0 && (blk_a < 64 || blk_a > 256 || blk_a % 64 != 0))
+        return fail(c, TLSPH_E_INVALID_ARG,
+                    "deformation-pass block must be 0 (staged), 64, 128, 192 or 256");
     if (staged && (tile < 64 || tile > kTile))
         return fail(c, TLSPH_E_INVALID_ARG, "tile must hold 64 to 256 particles");
     if (staged && tile > staged_tile_max(sub))
@@ -847,6 +863,14 @@ tlsph_status tlsph_set_launch_shape(tlsph_ctx* c, const int32_t shape[5], hipStr
         if (!c->staged_ok)
             return fail(c, TLSPH_E_UNSUPPORTED,
                         "the LDS-staged force pass does not fit this input at this tile size");
+    }
+    if (blk_a == 0) {
+        if (!c->staged_ok || !c->st.staged_lds_a) {
+            tlsph_status ts = set_tile(c, tile, stream);
+            if (ts != TLSPH_OK) return ts;
+        }
+        if (!c->st.staged_lds_a)
+            return fail(c, TLSPH_E_UNSUPPORTED, "the staged deformation pass does not fit LDS");
     }
     c->st.staged = staged;
     c->sub_b = sub;

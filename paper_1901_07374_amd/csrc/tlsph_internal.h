@@ -110,7 +110,7 @@ struct DevState {
     int32_t lds_slots;        // slots per field array of the staged kernel's LDS image
     int32_t model;            // damage model shared by every specimen, -1 if they differ
     int32_t tile;             // particles per tile of the staged force pass (<= kTile)
-    int32_t pad3_;
+    int32_t staged_lds_a;     // 1 when the tile records of the deformation pass fit LDS
 };
 
 enum : uint32_t { kFlagStoreForce = 1u, kFlagGraphs = 2u, kFlagCheckFinite = 4u,
@@ -118,6 +118,8 @@ enum : uint32_t { kFlagStoreForce = 1u, kFlagGraphs = 2u, kFlagCheckFinite = 4u,
 enum : int32_t { kErrNonFinite = 1, kErrNewton = 2 };
 
 // launch helpers implemented in tlsph_kernels.hip
+// Deformation pass: `block` threads per workgroup, or 0 for the variant staged
+// over the force pass's tiles (s.staged_lds_a must be set).
 // Force pass: `sub` lanes per particle (1, 2 or 4); the unstaged variant runs
 // `block` threads per workgroup, the LDS-staged one tile * sub.
 hipError_t launch_pass_b(const DevState& s, int parity, int block, int sub, bool mixed,

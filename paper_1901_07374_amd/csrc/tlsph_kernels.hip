@@ -909,50 +909,55 @@ __global__ void __launch_bounds__(staged_block_max(S)) k_pass_b_staged(DevState 
 // (eq. Crack_approx_Fdot, D at level n), accumulated as
 // M = sum_j V_j (1 - D_j)(v_j - v_i) (x) gradW_ij and dF/dt = M L_i^-1; then
 // the constitutive update and Q_i = P_i L_i^-T (0 for failed particles).
-template <typename R, int DM>
-__device__ __forceinline__ void pass_a_particle(const DevState& s, int64_t i, int sp) {
-    const int64_t np = s.np;
-    const DevSpec& P = s.specs[sp];
-    const D4* __restrict__ XV = s.XV;
-    const D4* __restrict__ VW = s.VW;
-    const D4 xi = XV[i];
-    const D4 vi = VW[i];
-    const R inv_h = R(P.inv_h), wnorm = R(P.wnorm);
-    R M[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    const int cnt = s.nnb[i];
-    const int32_t* __restrict__ cp = s.col + s.slice_ptr[i / kSlice] + (i % kSlice);
-    // neighbours in groups of kGatherA: every index and record load of a
-    // group is issued before its arithmetic (the sum keeps increasing k)
+// A neighbour as the deformation pass needs it: reference position,
+// half-step velocity and V0 (1 - D).
+struct NbrA {
+    double x, y, z, vx, vy, vz, w;
+};
+
+// M = sum_j V_j (1 - D_j)(v_j - v_i) (x) gradW_ij over the neighbours in
+// increasing order, in groups of kGatherA whose index and record loads are
+// all issued before their arithmetic.
+template <typename R, typename IdxOf, typename RecOf>
+__device__ __forceinline__ void gather_fdot(const D4& xi, const D4& vi, int cnt, R inv_h, R wnorm,
+                                            IdxOf idx, RecOf rec, R M[9]) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) M[q] = R(0);
     constexpr int kGatherA = 4;
     for (int k0 = 0; k0 < cnt; k0 += kGatherA) {
-        int32_t j[kGatherA];
-        D4 xj[kGatherA], vj[kGatherA];
+        int j[kGatherA];
+        NbrA nb[kGatherA];
 #pragma unroll
-        for (int t = 0; t < kGatherA; ++t) j[t] = cp[(int64_t)(k0 + t < cnt ? k0 + t : 0) * kSlice];
+        for (int t = 0; t < kGatherA; ++t) j[t] = idx(k0 + t < cnt ? k0 + t : 0);
 #pragma unroll
-        for (int t = 0; t < kGatherA; ++t) {
-            xj[t] = XV[j[t]];
-            vj[t] = VW[j[t]];
-        }
+        for (int t = 0; t < kGatherA; ++t) nb[t] = rec(j[t]);
 #pragma unroll
         for (int t = 0; t < kGatherA; ++t) {
             // past the last neighbour 1/r = 0 makes every term an exact zero
             const bool live = k0 + t < cnt;
-            const R dx = R(xj[t].x - xi.x), dy = R(xj[t].y - xi.y), dz = R(xj[t].z - xi.z);
+            const R dx = R(nb[t].x - xi.x), dy = R(nb[t].y - xi.y), dz = R(nb[t].z - xi.z);
             const R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
             const R ir = live ? rsqrt_nr(r2) : R(0);
             R W, dW;
             spline(r2 * ir, inv_h, wnorm, W, dW);
             const R gs = dW * ir;
             const R gx = gs * dx, gy = gs * dy, gz = gs * dz;
-            const R wj = R(vj[t].w);
-            const R t0 = wj * R(vj[t].x - vi.x), t1 = wj * R(vj[t].y - vi.y),
-                    t2 = wj * R(vj[t].z - vi.z);
+            const R wj = R(nb[t].w);
+            const R t0 = wj * R(nb[t].vx - vi.x), t1 = wj * R(nb[t].vy - vi.y),
+                    t2 = wj * R(nb[t].vz - vi.z);
             M[0] = fma(t0, gx, M[0]); M[1] = fma(t0, gy, M[1]); M[2] = fma(t0, gz, M[2]);
             M[3] = fma(t1, gx, M[3]); M[4] = fma(t1, gy, M[4]); M[5] = fma(t1, gz, M[5]);
             M[6] = fma(t2, gx, M[6]); M[7] = fma(t2, gy, M[7]); M[8] = fma(t2, gz, M[8]);
         }
     }
+}
+
+// The rest of the deformation pass for particle i (specimen sp) given M:
+// dF/dt = M L_i^-1, the constitutive update, Q_i = P_i L_i^-T, stores.
+template <typename R, int DM>
+__device__ __forceinline__ void pass_a_update(const DevState& s, int64_t i, int sp, const R M[9]) {
+    const int64_t np = s.np;
+    const DevSpec& P = s.specs[sp];
     R Li[9];
     if constexpr (std::is_same<R, float>::value) {
 #pragma unroll
@@ -1041,7 +1046,70 @@ __global__ void __launch_bounds__(256) k_pass_a(DevState s, int par) {
     for (;;) {
         const int sp = __builtin_amdgcn_readfirstlane(sp_lane);
         if (sp == sp_lane) {
-            pass_a_particle<R, DM>(s, i, sp);
+            const DevSpec& P = s.specs[sp];
+            const D4* __restrict__ XV = s.XV;
+            const D4* __restrict__ VW = s.VW;
+            const int32_t* __restrict__ cp = s.col + s.slice_ptr[i / kSlice] + (i % kSlice);
+            R M[9];
+            gather_fdot<R>(XV[i], VW[i], s.nnb[i], R(P.inv_h), R(P.wnorm),
+                           [&](int k) { return (int)cp[(int64_t)k * kSlice]; },
+                           [&](int j) {
+                               const D4 x = XV[j], v = VW[j];
+                               return NbrA{x.x, x.y, x.z, v.x, v.y, v.z, v.w};
+                           }, M);
+            pass_a_update<R, DM>(s, i, sp, M);
+            break;
+        }
+    }
+}
+
+// The same pass over the force pass's tiles: the records of the tile and its
+// halo (position, velocity, V0 (1 - D): 56 bytes) are staged in LDS once and
+// the neighbour sums read them through the 16-bit local slots.  Same
+// arithmetic in the same order as k_pass_a.
+constexpr int kLdsABytes = 56;
+template <typename R, int DM>
+__global__ void __launch_bounds__(256) k_pass_a_staged(DevState s, int par) {
+    extern __shared__ __align__(16) unsigned char lds_a[];
+    const int M = s.lds_slots;
+    double2* __restrict__ Lxy = reinterpret_cast<double2*>(lds_a);
+    double2* __restrict__ Lzw = Lxy + M;
+    double2* __restrict__ Lvxy = Lzw + M;
+    double* __restrict__ Lvz = reinterpret_cast<double*>(Lvxy + M);
+    const int T = s.tile;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t start = tile * T;
+    const int nh = s.halo_cnt[tile];
+    const int32_t* __restrict__ hl = s.halo + tile * (int64_t)s.halo_cap;
+    const D4* __restrict__ XV = s.XV;
+    const D4* __restrict__ VW = s.VW;
+    for (int m = threadIdx.x; m < T + nh; m += blockDim.x) {
+        const int64_t g = m < T ? start + m : (int64_t)hl[m - T];
+        if (g < s.n) {
+            const D4 x = XV[g], v = VW[g];
+            Lxy[m] = double2{x.x, x.y};
+            Lzw[m] = double2{x.z, v.w};
+            Lvxy[m] = double2{v.x, v.y};
+            Lvz[m] = v.z;
+        }
+    }
+    __syncthreads();
+    const int64_t i = start + threadIdx.x;
+    if (threadIdx.x >= T || i >= s.n) return;
+    const int sp_lane = s.spec[i];
+    for (;;) {
+        const int sp = __builtin_amdgcn_readfirstlane(sp_lane);
+        if (sp == sp_lane) {
+            const DevSpec& P = s.specs[sp];
+            const uint16_t* __restrict__ lp = s.lcol + s.slice_ptr[i / kSlice] + (i % kSlice);
+            R M9[9];
+            gather_fdot<R>(XV[i], VW[i], s.nnb[i], R(P.inv_h), R(P.wnorm),
+                           [&](int k) { return (int)lp[(int64_t)k * kSlice]; },
+                           [&](int m) {
+                               const double2 a = Lxy[m], b = Lzw[m], c = Lvxy[m];
+                               return NbrA{a.x, a.y, b.x, c.x, c.y, Lvz[m], b.y};
+                           }, M9);
+            pass_a_update<R, DM>(s, i, sp, M9);
             break;
         }
     }
@@ -1102,6 +1170,15 @@ hipError_t prepare_staged(size_t lds_bytes_b) {
 template <int DM>
 static void launch_a(const DevState& s, int parity, unsigned grid, int block, bool mixed,
                      hipStream_t st) {
+    if (block == 0) {   // staged over the force pass's tiles
+        const unsigned tiles = (unsigned)((s.n + s.tile - 1) / s.tile);
+        const size_t lds = (size_t)s.lds_slots * kLdsABytes;
+        if (mixed)
+            k_pass_a_staged<float, DM><<<tiles, s.tile, lds, st>>>(s, parity);
+        else
+            k_pass_a_staged<double, DM><<<tiles, s.tile, lds, st>>>(s, parity);
+        return;
+    }
     if (mixed)
         k_pass_a<float, DM><<<grid, block, 0, st>>>(s, parity);
     else
@@ -1109,7 +1186,8 @@ static void launch_a(const DevState& s, int parity, unsigned grid, int block, bo
 }
 
 hipError_t launch_pass_a(const DevState& s, int parity, int block, bool mixed, hipStream_t st) {
-    const unsigned grid = (unsigned)((s.n + block - 1) / block);
+    if (block == 0 && (!s.staged_lds_a || s.tile > 256)) return hipErrorInvalidValue;
+    const unsigned grid = block > 0 ? (unsigned)((s.n + block - 1) / block) : 0u;
     switch (s.model) {
         case 0: launch_a<0>(s, parity, grid, block, mixed, st); break;
         case 1: launch_a<1>(s, parity, grid, block, mixed, st); break;

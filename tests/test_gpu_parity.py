@@ -186,7 +186,8 @@ def test_bitwise_determinism_graphs_and_autotune(tl):
 SHAPES = [  # (staged, lanes per particle, force block, deformation block, tile)
     (1, 4, 256, 256, 0), (1, 2, 256, 128, 0), (1, 1, 256, 64, 0), (1, 2, 256, 64, 64),
     (1, 4, 256, 64, 96), (1, 1, 256, 128, 256), (0, 4, 256, 256, 0), (0, 4, 64, 192, 0),
-    (0, 2, 128, 128, 0), (0, 1, 64, 64, 0), (0, 1, 256, 256, 0)]
+    (0, 2, 128, 128, 0), (0, 1, 64, 64, 0), (0, 1, 256, 256, 0), (1, 2, 256, 0, 0),
+    (1, 4, 256, 0, 64), (0, 2, 128, 0, 96)]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
