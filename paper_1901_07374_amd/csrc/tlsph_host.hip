@@ -37,7 +37,7 @@ struct Layout {
     size_t XV, spec, bc, perm, iperm, nnb, slice_ptr, col, lcol, halo, halo_cnt, Linv, Linv32,
         specs, bcs, t;
     int64_t n_tiles;
-    size_t GB, U0, U1, VW, sig, eps_p, eps_rate, d_init, w_p, f_void, e, D, force, err,
+    size_t GQ, GH, U0, U1, VW, sig, eps_p, eps_rate, d_init, w_p, f_void, e, D, force, err,
         spec_off, bbox, keys, vals, bc_list, bc_ptr, diag_seg, diag_part, backup;
     int64_t diag_chunk_cap;
     size_t state_begin, backup_bytes;
@@ -82,7 +82,8 @@ Layout make_layout(int64_t n, int32_t n_spec, int32_t n_bc, int32_t k_cap, bool 
     L.t = take((size_t)n_spec * 8);
     // evolving state, contiguous (saved and restored by the autotuner)
     L.state_begin = align_up(cur);
-    L.GB = take(np * (mixed ? sizeof(GBRec<float>) : sizeof(GBRec<double>)));
+    L.GQ = take(np * (mixed ? sizeof(GQRec<float>) : sizeof(GQRec<double>)));
+    L.GH = take(np * (mixed ? sizeof(GHRec<float>) : sizeof(GHRec<double>)));
     L.U0 = take(np * sizeof(D4));
     L.U1 = take(np * sizeof(D4));
     L.VW = take(np * sizeof(D4));
@@ -201,8 +202,10 @@ void wire_state(tlsph_ctx* c) {
     s.specs = at<DevSpec>(c, L.specs);
     s.bcs = at<DevBC>(c, L.bcs);
     s.t = at<double>(c, L.t);
-    s.GB = L.mixed ? nullptr : at<GBRec<double>>(c, L.GB);
-    s.GB32 = L.mixed ? at<GBRec<float>>(c, L.GB) : nullptr;
+    s.GQ = L.mixed ? nullptr : at<GQRec<double>>(c, L.GQ);
+    s.GH = L.mixed ? nullptr : at<GHRec<double>>(c, L.GH);
+    s.GQ32 = L.mixed ? at<GQRec<float>>(c, L.GQ) : nullptr;
+    s.GH32 = L.mixed ? at<GHRec<float>>(c, L.GH) : nullptr;
     s.U[0] = at<D4>(c, L.U0);
     s.U[1] = at<D4>(c, L.U1);
     s.VW = at<D4>(c, L.VW);

@@ -50,14 +50,18 @@ struct alignas(16) D4 {
     double x, y, z, w;
 };
 
-// What the force pass gathers from a neighbour besides geometry: Q = P L^-T,
-// H = F - I and 1 - D.  R is the storage precision (double, or float in the
-// mixed form).
+// What the force pass gathers from a neighbour besides geometry, in two
+// records so that the deformation pass reads only H: Q = P L^-T with 1 - D,
+// and H = F - I.  R is the storage precision (double, or float in the mixed
+// form); each record is 10 values, aligned to two.
 template <typename R>
-struct alignas(16) GBRec {
+struct alignas(2 * sizeof(R)) GQRec {
     R q[9];
-    R h[9];
     R omd;
+};
+template <typename R>
+struct alignas(2 * sizeof(R)) GHRec {
+    R h[9];
     R pad;
 };
 
@@ -85,8 +89,10 @@ struct DevState {
     double* t;
     D4* U[2];                // displacement (x, y, z, 0), two buffers
     D4* VW;                  // half-step velocity and V0 (1 - D) (x, y, z, w)
-    GBRec<double>* GB;       // FP64 form
-    GBRec<float>* GB32;      // mixed form
+    GQRec<double>* GQ;       // FP64 form
+    GHRec<double>* GH;
+    GQRec<float>* GQ32;      // mixed form
+    GHRec<float>* GH32;
     double* sig;             // FP64 form, SoA Voigt
     float* sig32;            // mixed form
     double* eps_p;

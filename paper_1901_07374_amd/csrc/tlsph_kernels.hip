@@ -328,18 +328,22 @@ __global__ void k_init(DevState s) {
     s.U[1][p] = D4{0.0, 0.0, 0.0, 0.0};
     s.VW[p] = D4{0.0, 0.0, 0.0, s.XV[p].w * (1.0 - D0)};
     for (int c = 0; c < 3; ++c) s.force[c * np + p] = 0.0;
-    if (s.GB) {
-        GBRec<double> g;
-        for (int k = 0; k < 9; ++k) { g.q[k] = 0.0; g.h[k] = 0.0; }
+    if (s.GQ) {
+        GQRec<double> g;
+        GHRec<double> h;
+        for (int k = 0; k < 9; ++k) { g.q[k] = 0.0; h.h[k] = 0.0; }
         g.omd = 1.0 - D0;
-        g.pad = 0.0;
-        s.GB[p] = g;
+        h.pad = 0.0;
+        s.GQ[p] = g;
+        s.GH[p] = h;
     } else {
-        GBRec<float> g;
-        for (int k = 0; k < 9; ++k) { g.q[k] = 0.0f; g.h[k] = 0.0f; }
+        GQRec<float> g;
+        GHRec<float> h;
+        for (int k = 0; k < 9; ++k) { g.q[k] = 0.0f; h.h[k] = 0.0f; }
         g.omd = (float)(1.0 - D0);
-        g.pad = 0.0f;
-        s.GB32[p] = g;
+        h.pad = 0.0f;
+        s.GQ32[p] = g;
+        s.GH32[p] = h;
     }
     for (int k = 0; k < 6; ++k) {
         if (s.sig) s.sig[k * np + p] = 0.0;
@@ -546,11 +550,17 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nblk) {
 }
 
 template <typename R>
-__device__ __forceinline__ const GBRec<R>* gb_of(const DevState& s);
+__device__ __forceinline__ GQRec<R>* gq_of(const DevState& s);
 template <>
-__device__ __forceinline__ const GBRec<double>* gb_of<double>(const DevState& s) { return s.GB; }
+__device__ __forceinline__ GQRec<double>* gq_of<double>(const DevState& s) { return s.GQ; }
 template <>
-__device__ __forceinline__ const GBRec<float>* gb_of<float>(const DevState& s) { return s.GB32; }
+__device__ __forceinline__ GQRec<float>* gq_of<float>(const DevState& s) { return s.GQ32; }
+template <typename R>
+__device__ __forceinline__ GHRec<R>* gh_of(const DevState& s);
+template <>
+__device__ __forceinline__ GHRec<double>* gh_of<double>(const DevState& s) { return s.GH; }
+template <>
+__device__ __forceinline__ GHRec<float>* gh_of<float>(const DevState& s) { return s.GH32; }
 
 // Everything the force pass needs of a neighbour (and of the particle
 // itself): reference position and volume, displacement, 1 - D, Q = P L^-T
@@ -570,12 +580,13 @@ struct alignas(16) LRecB<float> {
 };
 
 template <typename R>
-__device__ __forceinline__ LRecB<R> make_recb(const D4& xv, const GBRec<R>& g, const D4& u) {
+__device__ __forceinline__ LRecB<R> make_recb(const D4& xv, const GQRec<R>& g, const GHRec<R>& h,
+                                               const D4& u) {
     LRecB<R> r;
     r.x = xv.x; r.y = xv.y; r.z = xv.z; r.V0 = R(xv.w);
     r.ux = u.x; r.uy = u.y; r.uz = u.z; r.omd = g.omd;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) { r.q[k] = g.q[k]; r.h[k] = g.h[k]; }
+    for (int k = 0; k < 9; ++k) { r.q[k] = g.q[k]; r.h[k] = h.h[k]; }
     return r;
 }
 
@@ -767,18 +778,20 @@ k_pass_b(DevState s, int par) {
     const DevSpec& P = s.specs[sp];
     const D4* __restrict__ XV = s.XV;
     const D4* __restrict__ Uc = s.U[par];
-    const GBRec<R>* __restrict__ GB = gb_of<R>(s);
-    const LRecB<R> ni = make_recb<R>(XV[ii], GB[ii], Uc[ii]);
+    const GQRec<R>* __restrict__ GQ = gq_of<R>(s);
+    const GHRec<R>* __restrict__ GH = gh_of<R>(s);
+    const LRecB<R> ni = make_recb<R>(XV[ii], GQ[ii], GH[ii], Uc[ii]);
     const R inv_h = R(P.inv_h), wnorm = R(P.wnorm);
     const int cnt = in ? s.nnb[i] : 0;
     const int32_t* __restrict__ cp = s.col + s.slice_ptr[ii / kSlice] + (ii % kSlice);
     const ForceAcc<R> A = pair_sums<R, S>(
         ni, cnt, sub, inv_h, wnorm, [&](int k) { return (int)cp[(int64_t)k * kSlice]; },
-        [&](int j) { return make_recb<R>(XV[j], GB[j], Uc[j]); });
+        [&](int j) { return make_recb<R>(XV[j], GQ[j], GH[j], Uc[j]); });
     // the particle's own Q is needed only now: reread it (the compiler barrier
     // keeps the load here) rather than keep it in registers through the loop
     asm volatile("" ::: "memory");
-    if (in && sub == 0) force_finish<R>(s, i, par, P, sp, make_recb<R>(XV[i], GB[i], Uc[i]), A);
+    if (in && sub == 0)
+        force_finish<R>(s, i, par, P, sp, make_recb<R>(XV[i], GQ[i], GH[i], Uc[i]), A);
 }
 
 // Largest workgroup of the staged force pass with S lanes per particle: four
@@ -878,10 +891,11 @@ __global__ void __launch_bounds__(staged_block_max(S)) k_pass_b_staged(DevState 
     const int32_t* __restrict__ hl = s.halo + tile * (int64_t)s.halo_cap;
     const D4* __restrict__ XV = s.XV;
     const D4* __restrict__ Uc = s.U[par];
-    const GBRec<R>* __restrict__ GB = gb_of<R>(s);
+    const GQRec<R>* __restrict__ GQ = gq_of<R>(s);
+    const GHRec<R>* __restrict__ GH = gh_of<R>(s);
     for (int m = threadIdx.x; m < T + nh; m += T * S) {
         const int64_t g = m < T ? start + m : (int64_t)hl[m - T];
-        if (g < s.n) LdsB<R>::put(L, M, m, make_recb<R>(XV[g], GB[g], Uc[g]));
+        if (g < s.n) LdsB<R>::put(L, M, m, make_recb<R>(XV[g], GQ[g], GH[g], Uc[g]));
     }
     __syncthreads();
     const int pl = threadIdx.x / S;
@@ -968,10 +982,11 @@ __device__ __forceinline__ void pass_a_update(const DevState& s, int64_t i, int 
     }
     R Fd[9];
     mm33(M, Li, Fd);
-    GBRec<R>* __restrict__ GB = const_cast<GBRec<R>*>(gb_of<R>(s));
+    GQRec<R>* __restrict__ GQ = gq_of<R>(s);
+    GHRec<R>* __restrict__ GH = gh_of<R>(s);
     R Hn[9], sn[6];
     {
-        const GBRec<R> gi = GB[i];
+        const GHRec<R> gi = GH[i];
 #pragma unroll
         for (int k = 0; k < 9; ++k) Hn[k] = gi.h[k];
     }
@@ -1000,7 +1015,8 @@ __device__ __forceinline__ void pass_a_update(const DevState& s, int64_t i, int 
 #pragma unroll
         for (int k = 0; k < 6; ++k) s.sig[k * np + i] = o.sig[k];
     }
-    GBRec<R> go;
+    GQRec<R> go;
+    GHRec<R> ho;
     const bool failed = o.D >= 1.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a)
@@ -1010,10 +1026,11 @@ __device__ __forceinline__ void pass_a_update(const DevState& s, int64_t i, int 
                                      : o.P[3 * a] * Li[3 * b] + o.P[3 * a + 1] * Li[3 * b + 1] +
                                            o.P[3 * a + 2] * Li[3 * b + 2];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) go.h[k] = o.H[k];
+    for (int k = 0; k < 9; ++k) ho.h[k] = o.H[k];
     go.omd = R(1.0 - o.D);
-    go.pad = R(0);
-    GB[i] = go;
+    ho.pad = R(0);
+    GQ[i] = go;
+    GH[i] = ho;
     if (Di < 1.0) {
         s.eps_p[i] = eps;
         s.eps_rate[i] = rate;
@@ -1222,11 +1239,11 @@ __device__ __forceinline__ FieldRef field_ref(const DevState& s, int field, int 
         case F_U: return {reinterpret_cast<const double*>(s.U[par]), nullptr, 3, 0, 1, 4};
         case F_V: return {reinterpret_cast<const double*>(s.VW), nullptr, 3, 0, 1, 4};
         case F_DEFGRAD:
-            return s.GB ? FieldRef{reinterpret_cast<const double*>(s.GB) + 9, nullptr, 9, 1, 1, 20}
-                        : FieldRef{nullptr, reinterpret_cast<const float*>(s.GB32) + 9, 9, 1, 1, 20};
+            return s.GH ? FieldRef{reinterpret_cast<const double*>(s.GH), nullptr, 9, 1, 1, 10}
+                        : FieldRef{nullptr, reinterpret_cast<const float*>(s.GH32), 9, 1, 1, 10};
         case F_Q:
-            return s.GB ? FieldRef{reinterpret_cast<const double*>(s.GB), nullptr, 9, 0, 1, 20}
-                        : FieldRef{nullptr, reinterpret_cast<const float*>(s.GB32), 9, 0, 1, 20};
+            return s.GQ ? FieldRef{reinterpret_cast<const double*>(s.GQ), nullptr, 9, 0, 1, 10}
+                        : FieldRef{nullptr, reinterpret_cast<const float*>(s.GQ32), 9, 0, 1, 10};
         case F_SIGMA:
             return s.sig ? FieldRef{s.sig, nullptr, 6, 0, np, 1} : FieldRef{nullptr, s.sig32, 6, 0, np, 1};
         case F_EPS_P: return {s.eps_p, nullptr, 1, 0, np, 1};
@@ -1273,7 +1290,7 @@ __global__ void k_set(DevState s, int field, int par, const double* __restrict__
     }
     if (r.kind == 2) {
         const double D = src[i];
-        if (s.GB) s.GB[p].omd = 1.0 - D; else s.GB32[p].omd = (float)(1.0 - D);
+        if (s.GQ) s.GQ[p].omd = 1.0 - D; else s.GQ32[p].omd = (float)(1.0 - D);
         s.VW[p].w = s.XV[p].w * (1.0 - D);
     }
 }

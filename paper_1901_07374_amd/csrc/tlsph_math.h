@@ -348,12 +348,18 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
         sym_from_voigt(s6, Sd);
     }
     {
+        // R = (I - A)^-1 (I + A) for the skew A = dt/2 w, in closed form:
+        // with a the axial vector of A (A x = a x x),
+        // R = ((1 - a.a) I + 2 A + 2 a a^T) / (1 + a.a)
         const R hd = R(0.5) * dt;
-        R Am[9] = {R(1), -hd * w01, -hd * w02, hd * w01, R(1), -hd * w12, hd * w02, hd * w12, R(1)};
-        R Bm[9] = {R(1), hd * w01, hd * w02, -hd * w01, R(1), hd * w12, -hd * w02, -hd * w12, R(1)};
-        R Ai[9], Rm[9], T[9], Sr[9];
-        inv33(Am, Ai);
-        mm33(Ai, Bm, Rm);
+        const R a1 = -hd * w12, a2 = hd * w02, a3 = -hd * w01;
+        const R aa = a1 * a1 + a2 * a2 + a3 * a3;
+        const R c = rcp_nr(R(1) + aa);
+        const R d0 = (R(1) - aa) * c, t2 = R(2) * c;
+        const R Rm[9] = {d0 + t2 * a1 * a1, t2 * (a1 * a2 - a3), t2 * (a1 * a3 + a2),
+                         t2 * (a2 * a1 + a3), d0 + t2 * a2 * a2, t2 * (a2 * a3 - a1),
+                         t2 * (a3 * a1 - a2), t2 * (a3 * a2 + a1), d0 + t2 * a3 * a3};
+        R T[9], Sr[9];
         mm33(Rm, Sd, T);
         mmT33(T, Rm, Sr);
 #pragma unroll
