@@ -1007,13 +1007,24 @@ __device__ __forceinline__ void pass_a_update(const DevState& s, int64_t i, int 
     PointOut<R> o;
     int32_t flags = 0;
     point_update<R, DM>(P, Hn, Fd, sn, eps, rate, dinit, wp, fv, e, Di, o, flags);
-    // stores
+    // stores: the index passes through an empty asm so that store addresses
+    // are formed here rather than kept in registers from the loads above
+    int64_t is = i;
+    asm volatile("" : "+v"(is));
     if constexpr (std::is_same<R, float>::value) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) s.sig32[k * np + i] = o.sig[k];
+        for (int k = 0; k < 6; ++k) s.sig32[k * np + is] = o.sig[k];
     } else {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) s.sig[k * np + i] = o.sig[k];
+        for (int k = 0; k < 6; ++k) s.sig[k * np + is] = o.sig[k];
+    }
+    // L^-1 again (cached), rather than held in registers through the update
+    if constexpr (std::is_same<R, float>::value) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Li[k] = s.Linv32[k * np + is];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Li[k] = s.Linv[k * np + is];
     }
     GQRec<R> go;
     GHRec<R> ho;
@@ -1029,17 +1040,17 @@ __device__ __forceinline__ void pass_a_update(const DevState& s, int64_t i, int 
     for (int k = 0; k < 9; ++k) ho.h[k] = o.H[k];
     go.omd = R(1.0 - o.D);
     ho.pad = R(0);
-    GQ[i] = go;
-    GH[i] = ho;
+    GQ[is] = go;
+    GH[is] = ho;
     if (Di < 1.0) {
-        s.eps_p[i] = eps;
-        s.eps_rate[i] = rate;
-        s.e[i] = e;
-        if (model == 1 || model == 2) s.d_init[i] = dinit;
-        if (model == 1) s.w_p[i] = wp;
-        if (model == 3) s.f_void[i] = fv;
+        s.eps_p[is] = eps;
+        s.eps_rate[is] = rate;
+        s.e[is] = e;
+        if (model == 1 || model == 2) s.d_init[is] = dinit;
+        if (model == 1) s.w_p[is] = wp;
+        if (model == 3) s.f_void[is] = fv;
     }
-    s.D[i] = o.D;
+    s.D[is] = o.D;
     if (i == P.first) s.t[sp] += P.dt;
     if (flags || (s.flags & kFlagCheckFinite)) {
         int32_t fl = flags;
