@@ -18,7 +18,9 @@ from typing import Dict, Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtlsph_oracle.so")
+# TLSPH_ORACLE_LIB points the binding at another build of the same source
+# (the mutation test loads deliberately broken copies this way)
+LIB_PATH = os.environ.get("TLSPH_ORACLE_LIB") or os.path.join(_HERE, "libtlsph_oracle.so")
 SRC = os.path.join(_HERE, "tlsph_oracle.c")
 
 CFLAGS = ["-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-std=c11",

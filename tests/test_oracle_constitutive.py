@@ -398,3 +398,46 @@ def test_principal_max_matches_eigvalsh(orc):
             ref = np.linalg.eigvalsh(a).max()
             assert abs(orc.principal_max(voigt(a)) - ref) < 1e-14 * np.abs(a).max() * 10
     assert orc.principal_max(voigt(np.diag([1.0, 5.0, -2.0]))) == 5.0
+
+
+@pytest.mark.parametrize("model", [I.DMG_JC, I.DMG_GTN])
+def test_elastic_shear_of_a_damaged_point(orc, model):
+    """A damaged point (D > 0) under a small symmetric shear stays elastic;
+    the deviatoric stress takes 2 G (1 - D) times the strain increment
+    d dt, d = sym(dF/dt Fbar^-1) with the midpoint Fbar (Algorithm 1 trial
+    line and Algorithm 2 trial state, Sec. 4-5).  For GTN, D = q1 f*(f)."""
+    m = I.material(1e-3, model)
+    G = G_of(m)
+    f = 0.1
+    D = m["q1"] * orc.fstar(m, f) if model == I.DMG_GTN else 0.3
+    pt = orc.Point(m, D=D, f_void=f, eps_p=0.01)
+    dt = m["dt"]
+    Fd = np.zeros((3, 3))
+    Fd[0, 1] = Fd[1, 0] = 0.5 * 1e3       # symmetric: no spin
+    pt.update(Fd, dt)
+    Fb = np.eye(3) + 0.5 * dt * Fd
+    d = Fd @ np.linalg.inv(Fb)
+    assert pt.eps_p == pytest.approx(0.01, abs=0)      # elastic
+    assert pt.sig[5] == pytest.approx(2 * G * (1 - D) * d[0, 1] * dt, rel=1e-12)
+
+
+@pytest.mark.parametrize("J0,f", [(1.004, 0.05), (1.002, 0.12)])
+def test_gtn_yield_onset_at_high_triaxiality(orc, J0, f):
+    """Algorithm 2 decides elastic or plastic by the sign of the trial yield
+    function Phi = r^2 + 2 q1 f* cosh(3/2 q2 sigma_m / sigma_M) - (1 + q3 f*^2)
+    (eq. yield_GTN with r = sigma_eq / sigma_M).  Trial states 0.1 % inside
+    and outside the surface, at high mean stress, must fall on either side."""
+    m = gtn_mat(n=0.26)
+    fs = orc.fstar(m, f)
+    D = m["q1"] * fs
+    eps_n = 0.05
+    sM = orc.flow_stress(m, eps_n)
+    sm = orc.mean_stress_eos(m, J0, D, 0.0, False)
+    c = (1 + m["q3"] * fs * fs) - 2 * m["q1"] * fs * math.cosh(1.5 * m["q2"] * sm / sM)
+    assert c > 0.05
+    seq0 = sM * math.sqrt(c)
+    shape = np.diag([1.0, -0.5, -0.5])                    # von Mises norm 1.5
+    for scale, plastic in ((0.999, False), (1.001, True)):
+        sd = shape * (scale * seq0 / 1.5)
+        pt = _inject_trial(orc, m, J0, sd, eps_n, f, D)
+        assert (pt.eps_p > eps_n) == plastic, (scale, pt.eps_p - eps_n)

@@ -1,0 +1,81 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case below plants one mistake in a copy of oracle/tlsph_oracle.c (a
+dropped term, a wrong sign, factor or index, a transposed operand), builds
+it, and runs the CPU pin tests against it in a child process: at least one
+pin must fail.  The planted copies live in a temporary directory; the
+oracle itself is never modified."""
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "tlsph_oracle.c")
+PINS = ["tests/test_oracle_kernel_neighbors.py", "tests/test_oracle_constitutive.py",
+        "tests/test_oracle_system.py"]
+
+# (name, text in the oracle, planted replacement)
+MUTANTS = [
+    ("kernel normalisation", "double c = 8.0 / (M_PI * h * h * h);",
+     "double c = 6.0 / (M_PI * h * h * h);"),
+    ("kernel slope term", "*dWdr = c / h * (-12.0 * q + 18.0 * q * q);",
+     "*dWdr = c / h * (-12.0 * q + 16.0 * q * q);"),
+    ("correction matrix without V_j", "Li[3 * a + b] += p->V0[j] * Xij[a] * g[b];",
+     "Li[3 * a + b] += Xij[a] * g[b];"),
+    ("dF/dt weighted by D_i", "double wgt = p->V0[j] * (1.0 - s->D[j]);",
+     "double wgt = p->V0[j] * (1.0 - s->D[i]);"),
+    ("nodal force damage weights swapped",
+     "acc += ((1.0 - Dj) * Qi[3 * a + b] + (1.0 - Di) * Qj[3 * a + b]) * g[b];",
+     "acc += ((1.0 - Di) * Qi[3 * a + b] + (1.0 - Dj) * Qj[3 * a + b]) * g[b];"),
+    ("nodal force drops Q_j", "acc += ((1.0 - Dj) * Qi[3 * a + b] + (1.0 - Di) * Qj[3 * a + b]) * g[b];",
+     "acc += ((1.0 - Dj) * Qi[3 * a + b]) * g[b];"),
+    ("hourglass sign", "double coef = -m->hg_alpha", "double coef = m->hg_alpha"),
+    ("hourglass with F_j transposed", "0.5 * (Fi[3 * a + b] + Fj[3 * a + b]) * Xij[b]",
+     "0.5 * (Fi[3 * a + b] + Fj[3 * b + a]) * Xij[b]"),
+    ("half drift", "for (int a = 0; a < 3; ++a) u[a] += dt * v[a];",
+     "for (int a = 0; a < 3; ++a) u[a] += 0.5 * dt * v[a];"),
+    ("failed particles keep moving", "if (s->D[i] >= 1.0) v[0] = v[1] = v[2] = 0.0;",
+     "if (s->D[i] > 1.0) v[0] = v[1] = v[2] = 0.0;"),
+    ("EOS S_alpha sign", "double den = eta - S * mu;", "double den = eta + S * mu;"),
+    ("radial return with 2G", "*dep = (seq_tr - sf) / (3.0 * G * (1.0 - D));",
+     "*dep = (seq_tr - sf) / (2.0 * G * (1.0 - D));"),
+    ("trial stress without (1 - D)",
+     "for (int k = 0; k < 9; ++k) sd_tr[k] = sd_rot[k] + 2.0 * G * (1.0 - D) * deps_d[k];",
+     "for (int k = 0; k < 9; ++k) sd_tr[k] = sd_rot[k] + 2.0 * G * deps_d[k];"),
+    ("rotation applied transposed", "mul3(R, sd_in, tmp);\n    mul3(tmp, RT, sd_out);",
+     "mul3(RT, sd_in, tmp);\n    mul3(tmp, R, sd_out);"),
+    ("JC failure strain sign of D3", "exp(m->D3 * sstar)", "exp(-m->D3 * sstar)"),
+    ("flow stress rate term", "return (m->A + m->B * pow(eps, m->n)) * (1.0 + m->C * log(rs));",
+     "return (m->A + m->B * pow(eps, m->n)) * (1.0 + m->C * log(rs + 1.0));"),
+    ("GTN yield function factor", "cosh(1.5 * m->q2 * sstar * r)", "cosh(1.0 * m->q2 * sstar * r)"),
+    ("energy from P^{n+1} only", "work += Fdot[k] * 0.5 * (Jn * Pn[k] + P[k]);",
+     "work += Fdot[k] * P[k];"),
+]
+
+
+def build_mutant(tmp, text, repl):
+    src = open(SRC).read()
+    assert src.count(text) == 1, text
+    path = os.path.join(tmp, "mutant.c")
+    with open(path, "w") as fh:
+        fh.write(src.replace(text, repl))
+    sys.path.insert(0, ROOT)
+    import oracle
+    lib = os.path.join(tmp, "libmutant.so")
+    subprocess.check_call(["gcc", *oracle.CFLAGS, "-I", os.path.join(ROOT, "oracle"),
+                           "-o", lib, path, "-lm"])
+    return lib
+
+
+@pytest.mark.parametrize("name,text,repl", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistake(name, text, repl):
+    with tempfile.TemporaryDirectory() as tmp:
+        lib = build_mutant(tmp, text, repl)
+        env = dict(os.environ, TLSPH_ORACLE_LIB=lib, OMP_NUM_THREADS="4")
+        r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-m", "not gpu",
+                            "-p", "no:cacheprovider", *PINS],
+                           cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+        assert r.returncode != 0, f"no pin caught: {name}\n{r.stdout[-2000:]}"
