@@ -434,6 +434,9 @@ tlsph_status tlsph_create(int64_t n, int32_t n_spec, const int64_t* spec_offsets
         d.inv_dt = 1.0 / p.dt;
         d.inv_rho0 = 1.0 / p.rho0;
         d.inv_eps_dot0 = 1.0 / p.eps_dot0;
+        d.grad_k = d.wnorm * d.inv_h;
+        d.hg_k = -p.hg_alpha * p.E * d.wnorm;
+        d.dt_rho0 = p.dt / p.rho0;
         d.damage = p.damage;
         d.has_wall = p.has_wall;
         d.first = spec_offsets[s];
@@ -758,8 +761,9 @@ tlsph_status tlsph_autotune(tlsph_ctx* c, hipStream_t stream) {
     best = Plan{0, bu_sub, bu_blk, c->tile_auto, au_blk, bu + au};
     if (!(c->flags & TLSPH_NO_STAGING)) {
         // Tile sizes: the build's, three fixed ones, and for each of those
-        // the size that fills whole rounds at the number of workgroups per
-        // CU its LDS image allows.
+        // the sizes that fill whole rounds at the number of workgroups per
+        // CU its LDS image allows (the next smaller, and a few percent
+        // larger if that drops a barely started last round).
         int dev = 0, lds_cu = 0, n_cu = 0;
         HIPCHK(c, hipGetDevice(&dev));
         HIPCHK(c, hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
@@ -800,6 +804,12 @@ tlsph_status tlsph_autotune(tlsph_ctx* c, hipStream_t stream) {
                                        ((int64_t)tiles[q] * slots);
                 const int64_t T1 = (L.n + rounds * slots - 1) / (rounds * slots);
                 if (T1 >= 64 && T1 < tiles[q]) tiles.push_back((int)T1);
+                const int64_t full = L.n / ((int64_t)tiles[q] * slots);
+                if (full >= 1) {
+                    const int64_t T2 = (L.n + full * slots - 1) / (full * slots);
+                    if (T2 > tiles[q] && T2 <= kTile && T2 * 100 <= (int64_t)tiles[q] * 108)
+                        tiles.push_back((int)T2);
+                }
             }
         }
     }

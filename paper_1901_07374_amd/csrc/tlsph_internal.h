@@ -31,6 +31,9 @@ struct DevSpec {
     double inv_cell;   // 1 / cell edge, the edge a hair above h so that pairs closer
                        // than h never sit two cells apart after rounding
     double inv_dt, inv_rho0, inv_eps_dot0;
+    double grad_k;     // wnorm / h: the kernel slope's constant factor
+    double hg_k;       // -hg_alpha E wnorm: the hourglass force's constant factor
+    double dt_rho0;    // dt / rho0: the kick per unit force density
     int32_t damage;
     int32_t has_wall;
     int64_t first, last;   // sorted-order particle range [first, last)
@@ -113,7 +116,7 @@ struct DevState {
     const uint16_t* lcol;
     int32_t halo_cap;
     int32_t staged;           // 1 when the staged force pass is in use
-    int32_t lds_slots;        // slots per field array of the staged kernel's LDS image
+    int32_t lds_slots;        // record slots of the staged kernels' LDS images (tile + largest halo)
     int32_t model;            // damage model shared by every specimen, -1 if they differ
     int32_t tile;             // particles per tile of the staged force pass (<= kTile)
     int32_t staged_lds_a;     // 1 when the tile records of the deformation pass fit LDS

@@ -595,38 +595,73 @@ struct ForceAcc {
     R a0 = 0, a1 = 0, a2 = 0, b0 = 0, b1 = 0, b2 = 0, g0 = 0, g1 = 0, g2 = 0;
 };
 
-// One pair of the force pass: a += V_j (1 - D_j) gradW, b += V_j Q_j gradW,
-// and the hourglass sum (1 - D_j) V_j W delta / |X_ij|^2 x_ij / |x_ij|.
+// 1/sqrt(x) and 1/x for x > 0 finite (the refinement of rsqrt_nr and rcp_nr
+// without their 0/infinity passthrough: callers select the zero cases).
+__device__ __forceinline__ double rsqrt_pos(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    return y;
+}
+__device__ __forceinline__ float rsqrt_pos(float x) {
+    const float y = __builtin_amdgcn_rsqf(x);
+    return fmaf(0.5f * y, fmaf(-x * y, y, 1.0f), y);
+}
+__device__ __forceinline__ double rcp_pos(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ float rcp_pos(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
+// One pair of the force pass, with the kernel's constant factors left out
+// (w = W / c and s = h dW/dr / c with c = 8 / (pi h^3); the finish applies
+// c / h to a and b and c to the hourglass sum):
+//   a += V_j (1 - D_j) s X_ij / r,  b += V_j Q_j s X_ij / r,
+//   g += (1 - D_j) V_j w (e_ij . x_ij) / (|X_ij|^2 |x_ij|^2) x_ij
+// with e_ij . x_ij = ((H_i + H_j) X_ij) . x_ij / 2 - (u_j - u_i) . x_ij
+// (the error vector (F_i + F_j) X_ij / 2 - x_ij with F = I + H).  A pair
+// whose current separation is zero adds no hourglass force.
 template <typename R>
 __device__ __forceinline__ void force_pair(const LRecB<R>& ni, const LRecB<R>& nj, R inv_h,
-                                           R wnorm, ForceAcc<R>& A, bool live = true) {
-    // a padding slot (live = false) gets 1/r = 1/|x| = 0: every term it
+                                           ForceAcc<R>& A, bool live = true) {
+    // a padding slot (live = false) gets 1/r = 1/|x|^2 = 0: every term it
     // adds is an exact zero
     const R dx = R(nj.x - ni.x), dy = R(nj.y - ni.y), dz = R(nj.z - ni.z);
     const R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-    const R ir = live ? rsqrt_nr(r2) : R(0);
-    const R r = r2 * ir;
-    R W, dW;
-    spline(r, inv_h, wnorm, W, dW);
-    const R gs = dW * ir;
-    const R gx = gs * dx, gy = gs * dy, gz = gs * dz;
+    const R ir = live ? rsqrt_pos(r2) : R(0);
+    const R q = r2 * ir * inv_h;
+    R w, sl;
+    if (q < R(0.5)) {
+        w = fma(q * q, fma(R(6), q, R(-6)), R(1));
+        sl = q * fma(R(18), q, R(-12));
+    } else {
+        const R a = R(1) - q;
+        const R a2 = a * a;
+        w = (a + a) * a2;
+        sl = R(-6) * a2;
+    }
     const R Vj = nj.V0;
-    const R wj = Vj * nj.omd;
-    A.a0 = fma(wj, gx, A.a0); A.a1 = fma(wj, gy, A.a1); A.a2 = fma(wj, gz, A.a2);
-    A.b0 = fma(Vj, fma(nj.q[0], gx, fma(nj.q[1], gy, nj.q[2] * gz)), A.b0);
-    A.b1 = fma(Vj, fma(nj.q[3], gx, fma(nj.q[4], gy, nj.q[5] * gz)), A.b1);
-    A.b2 = fma(Vj, fma(nj.q[6], gx, fma(nj.q[7], gy, nj.q[8] * gz)), A.b2);
+    const R gv = sl * ir * Vj;
+    const R gx = gv * dx, gy = gv * dy, gz = gv * dz;
+    A.a0 = fma(nj.omd, gx, A.a0); A.a1 = fma(nj.omd, gy, A.a1); A.a2 = fma(nj.omd, gz, A.a2);
+    A.b0 = fma(nj.q[0], gx, fma(nj.q[1], gy, fma(nj.q[2], gz, A.b0)));
+    A.b1 = fma(nj.q[3], gx, fma(nj.q[4], gy, fma(nj.q[5], gz, A.b1)));
+    A.b2 = fma(nj.q[6], gx, fma(nj.q[7], gy, fma(nj.q[8], gz, A.b2)));
     const R du0 = R(nj.ux - ni.ux), du1 = R(nj.uy - ni.uy), du2 = R(nj.uz - ni.uz);
     const R x0 = dx + du0, x1 = dy + du1, x2 = dz + du2;
-    const R irc = live ? rsqrt_nr(fma(x0, x0, fma(x1, x1, x2 * x2))) : R(0);
-    const R e0 = R(0.5) * fma(ni.h[0] + nj.h[0], dx, fma(ni.h[1] + nj.h[1], dy,
-                                                       (ni.h[2] + nj.h[2]) * dz)) - du0;
-    const R e1 = R(0.5) * fma(ni.h[3] + nj.h[3], dx, fma(ni.h[4] + nj.h[4], dy,
-                                                       (ni.h[5] + nj.h[5]) * dz)) - du1;
-    const R e2 = R(0.5) * fma(ni.h[6] + nj.h[6], dx, fma(ni.h[7] + nj.h[7], dy,
-                                                       (ni.h[8] + nj.h[8]) * dz)) - du2;
-    const R delta = fma(e0, x0, fma(e1, x1, e2 * x2)) * irc;
-    const R c = wj * W * delta * ir * ir * irc;
+    const R rc2 = fma(x0, x0, fma(x1, x1, x2 * x2));
+    const R irc2 = (live && rc2 > R(0)) ? rcp_pos(rc2) : R(0);
+    const R v0 = fma(ni.h[0] + nj.h[0], dx, fma(ni.h[1] + nj.h[1], dy, (ni.h[2] + nj.h[2]) * dz));
+    const R v1 = fma(ni.h[3] + nj.h[3], dx, fma(ni.h[4] + nj.h[4], dy, (ni.h[5] + nj.h[5]) * dz));
+    const R v2 = fma(ni.h[6] + nj.h[6], dx, fma(ni.h[7] + nj.h[7], dy, (ni.h[8] + nj.h[8]) * dz));
+    const R hx = fma(v0, x0, fma(v1, x1, v2 * x2));
+    const R ux = fma(du0, x0, fma(du1, x1, du2 * x2));
+    const R ex = fma(R(0.5), hx, -ux);
+    const R c = Vj * nj.omd * w * ex * (ir * ir) * irc2;
     A.g0 = fma(c, x0, A.g0); A.g1 = fma(c, x1, A.g1); A.g2 = fma(c, x2, A.g2);
 }
 
@@ -654,37 +689,46 @@ __device__ __forceinline__ ForceAcc<R> acc_xor(const ForceAcc<R>& x, int m) {
 // particle (S = 1, 2 or 4), lane `sub` holding partials sub, sub + S, ...;
 // every S rounds identically.  All lanes of the wave must call this (the
 // partials are exchanged across lanes); lanes without a particle pass cnt = 0.
+// The first group of neighbour indices of a lane (neighbours sub, sub + S,
+// ... below kSub), loaded apart so that a kernel can issue it early.
+template <int S>
+struct FirstIdx {
+    int q[kSub / S];
+};
+template <int S, typename IdxOf>
+__device__ __forceinline__ FirstIdx<S> first_indices(int cnt, int sub, IdxOf idx) {
+    FirstIdx<S> f;
+#pragma unroll
+    for (int t = 0; t < kSub / S; ++t) {
+        const int k = sub + S * t;
+        f.q[t] = idx(k < cnt ? k : 0);
+    }
+    return f;
+}
+
 template <typename R, int S, typename IdxOf, typename RecOf>
 __device__ __forceinline__ ForceAcc<R> pair_sums(const LRecB<R>& ni, int cnt, int sub, R inv_h,
-                                                 R wnorm, IdxOf idx, RecOf rec) {
+                                                 IdxOf idx, RecOf rec, const FirstIdx<S>& first) {
     static_assert(kSub == 4 && (S == 1 || S == 2 || S == 4), "canonical order has 4 partials");
     constexpr int NP = kSub / S;
     ForceAcc<R> A[NP];
-    // neighbour indices run kAhead groups of kSub ahead of the arithmetic
+    // neighbour indices run one group of kSub ahead of the arithmetic
     // (fetching further ahead measured no faster)
-    constexpr int kAhead = 1;
-    int q[kAhead][NP];
+    int q[NP];
 #pragma unroll
-    for (int d = 0; d < kAhead; ++d)
-#pragma unroll
-        for (int t = 0; t < NP; ++t) {
-            const int k = d * kSub + sub + S * t;
-            q[d][t] = idx(k < cnt ? k : 0);
-        }
+    for (int t = 0; t < NP; ++t) q[t] = first.q[t];
     for (int k0 = 0; k0 < cnt; k0 += kSub) {
         int cur[NP];
 #pragma unroll
         for (int t = 0; t < NP; ++t) {
-            cur[t] = q[0][t];
-#pragma unroll
-            for (int d = 0; d + 1 < kAhead; ++d) q[d][t] = q[d + 1][t];
-            const int kn = k0 + kAhead * kSub + sub + S * t;
-            q[kAhead - 1][t] = idx(kn < cnt ? kn : 0);
+            cur[t] = q[t];
+            const int kn = k0 + kSub + sub + S * t;
+            q[t] = idx(kn < cnt ? kn : 0);
         }
 #pragma unroll
         for (int t = 0; t < NP; ++t) {
             const int k = k0 + sub + S * t;
-            force_pair<R>(ni, rec(cur[t]), inv_h, wnorm, A[t], k < cnt);
+            force_pair<R>(ni, rec(cur[t]), inv_h, A[t], k < cnt);
         }
     }
     if constexpr (S == 1) {
@@ -699,28 +743,41 @@ __device__ __forceinline__ ForceAcc<R> pair_sums(const LRecB<R>& ni, int cnt, in
     }
 }
 
+// What the finish needs of a particle besides its record, loaded before the
+// pair sums so that their latency is spent behind them.
+struct FinishIn {
+    double D, V, vx, vy, vz;
+    double grad_k, hg_k, dt, dt_rho0;
+    int32_t bc, wall;
+};
+__device__ __forceinline__ FinishIn finish_in(const DevState& s, int64_t i, const DevSpec& P) {
+    const D4 v = s.VW[i];
+    return FinishIn{s.D[i], s.XV[i].w, v.x, v.y, v.z, P.grad_k, P.hg_k, P.dt, P.dt_rho0,
+                    s.bc[i], P.has_wall};
+}
+
 // Nodal force, kick, prescribed velocities, failed particles at rest, drift,
-// rigid wall; stores v, V0 (1 - D), u^{n+1} and (for groups) the force.
+// rigid wall; stores v, V0 (1 - D), u^{n+1} and (for groups) the force.  The
+// force per unit volume f / V_i is formed first: the kick is dt / rho0 times
+// it (m = rho0 V_i).
 template <typename R>
 __device__ __forceinline__ void force_finish(const DevState& s, int64_t i, int par, const DevSpec& P,
-                                             int sp, const LRecB<R>& ni, const ForceAcc<R>& A) {
+                                             int sp, const LRecB<R>& ni, const ForceAcc<R>& A,
+                                             const FinishIn& fin) {
     const int64_t np = s.np;
-    const double Di = s.D[i];
+    const double Di = fin.D;
     const R omDi = R(1.0 - Di);
-    const R hgk = R(-P.hg_alpha * P.E) * omDi;
-    const double Vi = s.XV[i].w;
-    const double f0 = Vi * double(ni.q[0] * A.a0 + ni.q[1] * A.a1 + ni.q[2] * A.a2 + omDi * A.b0 + hgk * A.g0);
-    const double f1 = Vi * double(ni.q[3] * A.a0 + ni.q[4] * A.a1 + ni.q[5] * A.a2 + omDi * A.b1 + hgk * A.g1);
-    const double f2 = Vi * double(ni.q[6] * A.a0 + ni.q[7] * A.a1 + ni.q[8] * A.a2 + omDi * A.b2 + hgk * A.g2);
-    const double dt = P.dt;
-    const double m = P.rho0 * Vi;
-    const D4 vo = s.VW[i];
-    double v[3] = {vo.x, vo.y, vo.z};
-    v[0] += dt * f0 / m;
-    v[1] += dt * f1 / m;
-    v[2] += dt * f2 / m;
+    const R ck = R(fin.grad_k);
+    const R hgk = R(fin.hg_k) * omDi;
+    const double Vi = fin.V;
+    const double fv0 = double(ck * (ni.q[0] * A.a0 + ni.q[1] * A.a1 + ni.q[2] * A.a2 + omDi * A.b0) + hgk * A.g0);
+    const double fv1 = double(ck * (ni.q[3] * A.a0 + ni.q[4] * A.a1 + ni.q[5] * A.a2 + omDi * A.b1) + hgk * A.g1);
+    const double fv2 = double(ck * (ni.q[6] * A.a0 + ni.q[7] * A.a1 + ni.q[8] * A.a2 + omDi * A.b2) + hgk * A.g2);
+    const double dt = fin.dt;
+    double v[3] = {fin.vx + fin.dt_rho0 * fv0, fin.vy + fin.dt_rho0 * fv1,
+                   fin.vz + fin.dt_rho0 * fv2};
     const double xi = ni.x, yi = ni.y, zi = ni.z;
-    const int g = s.bc[i];
+    const int g = fin.bc;
     if (g >= 0) {
         const DevBC& B = s.bcs[g];
         const double th = s.t[sp] + 0.5 * dt;
@@ -733,7 +790,7 @@ __device__ __forceinline__ void force_finish(const DevState& s, int64_t i, int p
     }
     if (Di >= 1.0) v[0] = v[1] = v[2] = 0.0;
     double un[3] = {ni.ux + dt * v[0], ni.uy + dt * v[1], ni.uz + dt * v[2]};
-    if (P.has_wall) {
+    if (fin.wall) {
         const double xw[3] = {xi + un[0], yi + un[1], zi + un[2]};
         const double dn = xw[0] * P.wall_n[0] + xw[1] * P.wall_n[1] + xw[2] * P.wall_n[2] - P.wall_d;
         if (dn < 0.0) {
@@ -751,7 +808,7 @@ __device__ __forceinline__ void force_finish(const DevState& s, int64_t i, int p
     s.VW[i] = D4{v[0], v[1], v[2], Vi * (1.0 - Di)};
     s.U[par ^ 1][i] = D4{un[0], un[1], un[2], 0.0};
     if ((s.flags & kFlagStoreForce) || g >= 0) {
-        s.force[i] = f0; s.force[np + i] = f1; s.force[2 * np + i] = f2;
+        s.force[i] = Vi * fv0; s.force[np + i] = Vi * fv1; s.force[2 * np + i] = Vi * fv2;
     }
 }
 
@@ -781,17 +838,19 @@ k_pass_b(DevState s, int par) {
     const GQRec<R>* __restrict__ GQ = gq_of<R>(s);
     const GHRec<R>* __restrict__ GH = gh_of<R>(s);
     const LRecB<R> ni = make_recb<R>(XV[ii], GQ[ii], GH[ii], Uc[ii]);
-    const R inv_h = R(P.inv_h), wnorm = R(P.wnorm);
+    const R inv_h = R(P.inv_h);
     const int cnt = in ? s.nnb[i] : 0;
+    const FinishIn fin = finish_in(s, ii, P);
     const int32_t* __restrict__ cp = s.col + s.slice_ptr[ii / kSlice] + (ii % kSlice);
+    const auto idx = [&](int k) { return (int)cp[(int64_t)k * kSlice]; };
     const ForceAcc<R> A = pair_sums<R, S>(
-        ni, cnt, sub, inv_h, wnorm, [&](int k) { return (int)cp[(int64_t)k * kSlice]; },
-        [&](int j) { return make_recb<R>(XV[j], GQ[j], GH[j], Uc[j]); });
+        ni, cnt, sub, inv_h, idx, [&](int j) { return make_recb<R>(XV[j], GQ[j], GH[j], Uc[j]); },
+        first_indices<S>(cnt, sub, idx));
     // the particle's own Q is needed only now: reread it (the compiler barrier
     // keeps the load here) rather than keep it in registers through the loop
     asm volatile("" ::: "memory");
     if (in && sub == 0)
-        force_finish<R>(s, i, par, P, sp, make_recb<R>(XV[i], GQ[i], GH[i], Uc[i]), A);
+        force_finish<R>(s, i, par, P, sp, make_recb<R>(XV[i], GQ[i], GH[i], Uc[i]), A, fin);
 }
 
 // Largest workgroup of the staged force pass with S lanes per particle: four
@@ -799,52 +858,57 @@ k_pass_b(DevState s, int par) {
 // stays at two waves per SIMD.
 __host__ __device__ constexpr int staged_block_max(int S) { return S == 4 ? 512 : kTile * S; }
 
-// LDS image of the force-pass records of one tile and its halo, stored
-// field-pair-major (array f of 16-byte elements holds one pair of fields for
-// every slot), so 64 lanes reading near-consecutive slots touch each bank at
-// most four times per 128-bit read.
+// LDS image of the force-pass records of one tile and its halo (M slots).
+// FP64: one 208-byte record per slot (13 units of 16 bytes, an odd number, so
+// the slots read by the lanes of one 128-bit access spread over the bank
+// groups as consecutive slots do), every field at a fixed offset from the
+// record's address.  Mixed: 128-byte records would put every slot's field at
+// the same bank group, so the image is field-major there (unit f of slot m
+// at f * M + m).
 template <typename R>
 struct LdsB;
 template <>
 struct LdsB<double> {
-    static constexpr int kPairs = 13;   // 26 doubles
-    __device__ static void put(double2* L, int M, int m, const LRecB<double>& r) {
-        L[0 * M + m] = double2{r.x, r.y};
-        L[1 * M + m] = double2{r.z, r.V0};
-        L[2 * M + m] = double2{r.ux, r.uy};
-        L[3 * M + m] = double2{r.uz, r.omd};
-        L[4 * M + m] = double2{r.q[0], r.q[1]};
-        L[5 * M + m] = double2{r.q[2], r.q[3]};
-        L[6 * M + m] = double2{r.q[4], r.q[5]};
-        L[7 * M + m] = double2{r.q[6], r.q[7]};
-        L[8 * M + m] = double2{r.q[8], r.h[0]};
-        L[9 * M + m] = double2{r.h[1], r.h[2]};
-        L[10 * M + m] = double2{r.h[3], r.h[4]};
-        L[11 * M + m] = double2{r.h[5], r.h[6]};
-        L[12 * M + m] = double2{r.h[7], r.h[8]};
+    static constexpr int kUnits = 13;   // 26 doubles
+    __device__ static void put(double2* L, int, int m, const LRecB<double>& r) {
+        double2* p = L + m * kUnits;
+        p[0] = double2{r.x, r.y};
+        p[1] = double2{r.z, r.V0};
+        p[2] = double2{r.ux, r.uy};
+        p[3] = double2{r.uz, r.omd};
+        p[4] = double2{r.q[0], r.q[1]};
+        p[5] = double2{r.q[2], r.q[3]};
+        p[6] = double2{r.q[4], r.q[5]};
+        p[7] = double2{r.q[6], r.q[7]};
+        p[8] = double2{r.q[8], r.h[0]};
+        p[9] = double2{r.h[1], r.h[2]};
+        p[10] = double2{r.h[3], r.h[4]};
+        p[11] = double2{r.h[5], r.h[6]};
+        p[12] = double2{r.h[7], r.h[8]};
     }
-    __device__ static LRecB<double> get(const double2* L, int M, int m) {
+    __device__ static LRecB<double> get(const double2* L, int, int m) {
+        const double2* p = L + m * kUnits;
         LRecB<double> r;
         double2 t;
-        t = L[0 * M + m]; r.x = t.x; r.y = t.y;
-        t = L[1 * M + m]; r.z = t.x; r.V0 = t.y;
-        t = L[2 * M + m]; r.ux = t.x; r.uy = t.y;
-        t = L[3 * M + m]; r.uz = t.x; r.omd = t.y;
-        t = L[4 * M + m]; r.q[0] = t.x; r.q[1] = t.y;
-        t = L[5 * M + m]; r.q[2] = t.x; r.q[3] = t.y;
-        t = L[6 * M + m]; r.q[4] = t.x; r.q[5] = t.y;
-        t = L[7 * M + m]; r.q[6] = t.x; r.q[7] = t.y;
-        t = L[8 * M + m]; r.q[8] = t.x; r.h[0] = t.y;
-        t = L[9 * M + m]; r.h[1] = t.x; r.h[2] = t.y;
-        t = L[10 * M + m]; r.h[3] = t.x; r.h[4] = t.y;
-        t = L[11 * M + m]; r.h[5] = t.x; r.h[6] = t.y;
-        t = L[12 * M + m]; r.h[7] = t.x; r.h[8] = t.y;
+        t = p[0]; r.x = t.x; r.y = t.y;
+        t = p[1]; r.z = t.x; r.V0 = t.y;
+        t = p[2]; r.ux = t.x; r.uy = t.y;
+        t = p[3]; r.uz = t.x; r.omd = t.y;
+        t = p[4]; r.q[0] = t.x; r.q[1] = t.y;
+        t = p[5]; r.q[2] = t.x; r.q[3] = t.y;
+        t = p[6]; r.q[4] = t.x; r.q[5] = t.y;
+        t = p[7]; r.q[6] = t.x; r.q[7] = t.y;
+        t = p[8]; r.q[8] = t.x; r.h[0] = t.y;
+        t = p[9]; r.h[1] = t.x; r.h[2] = t.y;
+        t = p[10]; r.h[3] = t.x; r.h[4] = t.y;
+        t = p[11]; r.h[5] = t.x; r.h[6] = t.y;
+        t = p[12]; r.h[7] = t.x; r.h[8] = t.y;
         return r;
     }
 };
 template <>
 struct LdsB<float> {
-    static constexpr int kPairs = 8;    // 6 doubles + 20 floats = 8 x 16 bytes
+    static constexpr int kUnits = 8;    // 6 doubles + 20 floats
     __device__ static void put(double2* L, int M, int m, const LRecB<float>& r) {
         L[0 * M + m] = double2{r.x, r.y};
         L[1 * M + m] = double2{r.z, r.ux};
@@ -877,27 +941,41 @@ struct LdsB<float> {
 // workgroup loads every record it needs once, then S lanes per particle run
 // the pair sums from LDS through the 16-bit local neighbour slots.  Same
 // arithmetic in the same order as the unstaged kernel, so results are bitwise
-// identical.  Occupancy is bounded by LDS (one tile per CU); S lanes per
-// particle give the SIMDs several waves to switch between.
+// identical.  Occupancy is bounded by LDS; S lanes per particle give the
+// SIMDs several waves to switch between.
+// Waves per SIMD the staged force pass must leave room for: two workgroups per
+// CU need four (mixed form, two or four lanes per particle: tiles up to 196
+// and 128 particles) or three (FP64, four lanes: tiles up to 96).
 template <typename R, int S>
-__global__ void __launch_bounds__(staged_block_max(S)) k_pass_b_staged(DevState s, int par) {
+__host__ __device__ constexpr int staged_waves_min() {
+    return sizeof(R) == 4 && S >= 2 ? 4 : (S == 4 ? 3 : 1);
+}
+// Whether the finish's inputs are loaded before the staging (their registers
+// then live through the pair sums; the mixed form with two lanes has none to
+// spare within its 128).
+template <typename R, int S>
+__host__ __device__ constexpr bool staged_finish_early() {
+    return !(sizeof(R) == 4 && S == 2);
+}
+
+template <typename R, int S>
+__global__ void __launch_bounds__(staged_block_max(S))
+__attribute__((amdgpu_waves_per_eu(staged_waves_min<R, S>(), 8))) k_pass_b_staged(DevState s, int par) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     double2* __restrict__ L = reinterpret_cast<double2*>(lds_raw);
     const int M = s.lds_slots;
     const int T = s.tile;
+    const int B = T * S;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t start = tile * T;
-    const int nh = s.halo_cnt[tile];
+    const int tot = T + s.halo_cnt[tile];
     const int32_t* __restrict__ hl = s.halo + tile * (int64_t)s.halo_cap;
     const D4* __restrict__ XV = s.XV;
     const D4* __restrict__ Uc = s.U[par];
     const GQRec<R>* __restrict__ GQ = gq_of<R>(s);
     const GHRec<R>* __restrict__ GH = gh_of<R>(s);
-    for (int m = threadIdx.x; m < T + nh; m += T * S) {
-        const int64_t g = m < T ? start + m : (int64_t)hl[m - T];
-        if (g < s.n) LdsB<R>::put(L, M, m, make_recb<R>(XV[g], GQ[g], GH[g], Uc[g]));
-    }
-    __syncthreads();
+    // the particle's own scalars, its first neighbour slots and what its
+    // finish needs are loaded first, so that their latency overlaps the staging
     const int pl = threadIdx.x / S;
     const int sub = threadIdx.x % S;
     const int64_t i = start + pl;
@@ -905,17 +983,38 @@ __global__ void __launch_bounds__(staged_block_max(S)) k_pass_b_staged(DevState 
     const int64_t ii = in ? i : start;
     const int sp = s.spec[ii];
     const DevSpec& P = s.specs[sp];
-    const LRecB<R> ni = LdsB<R>::get(L, M, in ? pl : 0);
-    const R inv_h = R(P.inv_h), wnorm = R(P.wnorm);
+    const R inv_h = R(P.inv_h);
     const int cnt = in ? s.nnb[i] : 0;
     const uint16_t* __restrict__ lp = s.lcol + s.slice_ptr[ii / kSlice] + (ii % kSlice);
+    const auto idx = [&](int k) { return (int)lp[(int64_t)k * kSlice]; };
+    const FirstIdx<S> first = first_indices<S>(cnt, sub, idx);
+    constexpr bool kEarly = staged_finish_early<R, S>();
+    FinishIn fin_early;
+    if constexpr (kEarly) fin_early = finish_in(s, ii, P);
+    // two slots per thread per round, their index loads issued before their
+    // record loads and those before the LDS stores, so that one round costs
+    // two memory latencies; slots past the particle count (last tile) load
+    // the tile's first record and store nothing
+    for (int m0 = threadIdx.x; m0 < tot; m0 += 2 * B) {
+        const int m1 = m0 + B;
+        const int64_t g0 = m0 < T ? start + m0 : (int64_t)hl[m0 - T];
+        const int64_t g1 = m1 >= tot ? s.n : (m1 < T ? start + m1 : (int64_t)hl[m1 - T]);
+        const int64_t l0 = g0 < s.n ? g0 : start, l1 = g1 < s.n ? g1 : start;
+        const LRecB<R> r0 = make_recb<R>(XV[l0], GQ[l0], GH[l0], Uc[l0]);
+        const LRecB<R> r1 = make_recb<R>(XV[l1], GQ[l1], GH[l1], Uc[l1]);
+        if (g0 < s.n) LdsB<R>::put(L, M, m0, r0);
+        if (g1 < s.n) LdsB<R>::put(L, M, m1, r1);
+    }
+    __syncthreads();
+    const LRecB<R> ni = LdsB<R>::get(L, M, in ? pl : 0);
     const ForceAcc<R> A = pair_sums<R, S>(
-        ni, cnt, sub, inv_h, wnorm, [&](int k) { return (int)lp[(int64_t)k * kSlice]; },
-        [&](int m) { return LdsB<R>::get(L, M, m); });
+        ni, cnt, sub, inv_h, idx, [&](int m) { return LdsB<R>::get(L, M, m); }, first);
     // the particle's own Q is needed only now: reread it rather than keep it
     // in registers through the pair loop
     __syncthreads();
-    if (in && sub == 0) force_finish<R>(s, i, par, P, sp, LdsB<R>::get(L, M, pl), A);
+    if (in && sub == 0)
+        force_finish<R>(s, i, par, P, sp, LdsB<R>::get(L, M, pl), A,
+                        kEarly ? fin_early : finish_in(s, i, P));
 }
 
 // Pass A (deformation and constitutive update to t^{n+1}).
@@ -1176,7 +1275,7 @@ hipError_t launch_pass_b(const DevState& s, int parity, int block, int sub, bool
 int staged_tile_max(int sub) { return staged_block_max(sub) / sub; }
 
 size_t staged_record_bytes(bool mixed) {
-    return 16 * (size_t)(mixed ? LdsB<float>::kPairs : LdsB<double>::kPairs);
+    return 16 * (size_t)(mixed ? LdsB<float>::kUnits : LdsB<double>::kUnits);
 }
 
 // Dynamic LDS above the default limit must be allowed per kernel.
