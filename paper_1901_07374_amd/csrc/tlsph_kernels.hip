@@ -1029,19 +1029,28 @@ struct NbrA {
 };
 
 // M = sum_j V_j (1 - D_j)(v_j - v_i) (x) gradW_ij over the neighbours in
-// increasing order, in groups of kGatherA whose index and record loads are
-// all issued before their arithmetic.
+// increasing order, in groups of kGatherA whose record loads are all issued
+// before their arithmetic (indices one group ahead).  The kernel slope enters without its
+// constant factor c / h (c = 8 / (pi h^3)), applied to the sum.
 template <typename R, typename IdxOf, typename RecOf>
-__device__ __forceinline__ void gather_fdot(const D4& xi, const D4& vi, int cnt, R inv_h, R wnorm,
+__device__ __forceinline__ void gather_fdot(const D4& xi, const D4& vi, int cnt, R inv_h, R grad_k,
                                             IdxOf idx, RecOf rec, R M[9]) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) M[q] = R(0);
     constexpr int kGatherA = 4;
+    // the next group's indices are loaded while this group is summed
+    int jn[kGatherA];
+#pragma unroll
+    for (int t = 0; t < kGatherA; ++t) jn[t] = idx(t < cnt ? t : 0);
     for (int k0 = 0; k0 < cnt; k0 += kGatherA) {
         int j[kGatherA];
         NbrA nb[kGatherA];
 #pragma unroll
-        for (int t = 0; t < kGatherA; ++t) j[t] = idx(k0 + t < cnt ? k0 + t : 0);
+        for (int t = 0; t < kGatherA; ++t) {
+            j[t] = jn[t];
+            const int kn = k0 + kGatherA + t;
+            jn[t] = idx(kn < cnt ? kn : 0);
+        }
 #pragma unroll
         for (int t = 0; t < kGatherA; ++t) nb[t] = rec(j[t]);
 #pragma unroll
@@ -1050,19 +1059,25 @@ __device__ __forceinline__ void gather_fdot(const D4& xi, const D4& vi, int cnt,
             const bool live = k0 + t < cnt;
             const R dx = R(nb[t].x - xi.x), dy = R(nb[t].y - xi.y), dz = R(nb[t].z - xi.z);
             const R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-            const R ir = live ? rsqrt_nr(r2) : R(0);
-            R W, dW;
-            spline(r2 * ir, inv_h, wnorm, W, dW);
-            const R gs = dW * ir;
-            const R gx = gs * dx, gy = gs * dy, gz = gs * dz;
-            const R wj = R(nb[t].w);
-            const R t0 = wj * R(nb[t].vx - vi.x), t1 = wj * R(nb[t].vy - vi.y),
-                    t2 = wj * R(nb[t].vz - vi.z);
+            const R ir = live ? rsqrt_pos(r2) : R(0);
+            const R q = r2 * ir * inv_h;
+            R sl;
+            if (q < R(0.5)) {
+                sl = q * fma(R(18), q, R(-12));
+            } else {
+                const R a = R(1) - q;
+                sl = R(-6) * (a * a);
+            }
+            const R gw = sl * ir * R(nb[t].w);
+            const R gx = gw * dx, gy = gw * dy, gz = gw * dz;
+            const R t0 = R(nb[t].vx - vi.x), t1 = R(nb[t].vy - vi.y), t2 = R(nb[t].vz - vi.z);
             M[0] = fma(t0, gx, M[0]); M[1] = fma(t0, gy, M[1]); M[2] = fma(t0, gz, M[2]);
             M[3] = fma(t1, gx, M[3]); M[4] = fma(t1, gy, M[4]); M[5] = fma(t1, gz, M[5]);
             M[6] = fma(t2, gx, M[6]); M[7] = fma(t2, gy, M[7]); M[8] = fma(t2, gz, M[8]);
         }
     }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) M[q] *= grad_k;
 }
 
 // The rest of the deformation pass for particle i (specimen sp) given M:
@@ -1163,10 +1178,19 @@ __device__ __forceinline__ void pass_a_update(const DevState& s, int64_t i, int 
     }
 }
 
+// Waves per SIMD the deformation pass is compiled for: three (at most 168
+// registers) for the JC-type models, whose update fits that; the GTN return
+// and the mixed-model variant need more.
+template <int DM>
+__host__ __device__ constexpr int pass_a_waves_min() {
+    return DM >= 0 && DM <= 2 ? 3 : 1;
+}
+
 // Specimen parameters are read with scalar loads: the lanes of a wave take
 // turns by specimen, one turn unless the wave straddles two specimens.
 template <typename R, int DM>
-__global__ void __launch_bounds__(256) k_pass_a(DevState s, int par) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pass_a_waves_min<DM>(), 8)))
+k_pass_a(DevState s, int par) {
     const int64_t i = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= s.n) return;
     const int sp_lane = s.spec[i];
@@ -1178,7 +1202,7 @@ __global__ void __launch_bounds__(256) k_pass_a(DevState s, int par) {
             const D4* __restrict__ VW = s.VW;
             const int32_t* __restrict__ cp = s.col + s.slice_ptr[i / kSlice] + (i % kSlice);
             R M[9];
-            gather_fdot<R>(XV[i], VW[i], s.nnb[i], R(P.inv_h), R(P.wnorm),
+            gather_fdot<R>(XV[i], VW[i], s.nnb[i], R(P.inv_h), R(P.grad_k),
                            [&](int k) { return (int)cp[(int64_t)k * kSlice]; },
                            [&](int j) {
                                const D4 x = XV[j], v = VW[j];
@@ -1196,7 +1220,8 @@ __global__ void __launch_bounds__(256) k_pass_a(DevState s, int par) {
 // arithmetic in the same order as k_pass_a.
 constexpr int kLdsABytes = 56;
 template <typename R, int DM>
-__global__ void __launch_bounds__(256) k_pass_a_staged(DevState s, int par) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pass_a_waves_min<DM>(), 8)))
+k_pass_a_staged(DevState s, int par) {
     extern __shared__ __align__(16) unsigned char lds_a[];
     const int M = s.lds_slots;
     double2* __restrict__ Lxy = reinterpret_cast<double2*>(lds_a);
@@ -1230,7 +1255,7 @@ __global__ void __launch_bounds__(256) k_pass_a_staged(DevState s, int par) {
             const DevSpec& P = s.specs[sp];
             const uint16_t* __restrict__ lp = s.lcol + s.slice_ptr[i / kSlice] + (i % kSlice);
             R M9[9];
-            gather_fdot<R>(XV[i], VW[i], s.nnb[i], R(P.inv_h), R(P.wnorm),
+            gather_fdot<R>(XV[i], VW[i], s.nnb[i], R(P.inv_h), R(P.grad_k),
                            [&](int k) { return (int)lp[(int64_t)k * kSlice]; },
                            [&](int m) {
                                const double2 a = Lxy[m], b = Lzw[m], c = Lvxy[m];

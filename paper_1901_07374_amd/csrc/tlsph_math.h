@@ -71,6 +71,20 @@ __host__ __device__ __forceinline__ void inv33(const R a[9], R o[9]) {
     o[8] = (a[0] * a[4] - a[1] * a[3]) * inv;
 }
 
+// cofactor matrix cof(a) = det(a) a^-T (no division)
+template <typename R>
+__host__ __device__ __forceinline__ void cof33(const R a[9], R o[9]) {
+    o[0] = a[4] * a[8] - a[5] * a[7];
+    o[1] = a[5] * a[6] - a[3] * a[8];
+    o[2] = a[3] * a[7] - a[4] * a[6];
+    o[3] = a[2] * a[7] - a[1] * a[8];
+    o[4] = a[0] * a[8] - a[2] * a[6];
+    o[5] = a[1] * a[6] - a[0] * a[7];
+    o[6] = a[1] * a[5] - a[2] * a[4];
+    o[7] = a[2] * a[3] - a[0] * a[5];
+    o[8] = a[0] * a[4] - a[1] * a[3];
+}
+
 template <typename R>
 __host__ __device__ __forceinline__ void mm33(const R a[9], const R b[9], R o[9]) {
 #pragma unroll
@@ -165,7 +179,13 @@ __host__ __device__ __forceinline__ R mean_stress(const DevSpec& P, R Jm1, R D, 
 // floored at 0.
 __host__ __device__ __forceinline__ double jc_rate_factor(const DevSpec& P, double rate) {
     const double rs = rate * P.inv_eps_dot0;
-    return 1.0 + P.C * log(rs > 1.0 ? rs : 1.0);
+    return rs > 1.0 ? 1.0 + P.C * log(rs) : 1.0;
+}
+
+// A + B eps^n, the strain-hardening factor of the Johnson-Cook flow stress
+// (A exactly while the point has not yielded)
+__host__ __device__ __forceinline__ double jc_hardening(const DevSpec& P, double eps) {
+    return eps > 0.0 ? P.A + P.B * pow_el(eps, P.n) : P.A;
 }
 
 // Largest eigenvalue of a symmetric tensor (closed form of the cubic's roots).
@@ -314,18 +334,18 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
     }
     // energy per unit mass by the trapezoid rule, dF/dt : (P^n + P^{n+1}) / 2 / rho0:
     // the P^n half now, so F^n and sigma^n need not stay live to the end
+    // (P = J sigma F^-T = sigma cof(F))
     R work0 = R(0);
     {
-        R S0[9], F0[9], F0i[9], P0[9];
+        R S0[9], F0[9], C0[9], P0[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) F0[k] = Hn[k];
         F0[0] += R(1); F0[4] += R(1); F0[8] += R(1);
         sym_from_voigt(sn, S0);
-        inv33(F0, F0i);
-        mmT33(S0, F0i, P0);
-        const R J0 = R(1) + det_ipH_m1(Hn);
+        cof33(F0, C0);
+        mm33(S0, C0, P0);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) work0 += Fd[k] * (J0 * P0[k]);
+        for (int k = 0; k < 9; ++k) work0 += Fd[k] * P0[k];
     }
     R Fb[9], Fbi[9], l[9];
 #pragma unroll
@@ -334,7 +354,6 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
     inv33(Fb, Fbi);
     mm33(Fd, Fbi, l);
     const R Jm1 = det_ipH_m1(o.H);
-    const R J = R(1) + Jm1;
     // rate of deformation (Voigt) and spin
     R d6[6] = {l[0], l[4], l[8], R(0.5) * (l[5] + l[7]), R(0.5) * (l[2] + l[6]),
                R(0.5) * (l[1] + l[3])};
@@ -342,7 +361,7 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
     // stored deviator, rotated by R = (I - dt/2 w)^-1 (I + dt/2 w)
     const R third = R(1.0 / 3.0);
     const R smn = (sn[0] + sn[1] + sn[2]) * third;
-    R Sd[9];
+    R Sd[9], sdr[6];
     {
         R s6[6] = {sn[0] - smn, sn[1] - smn, sn[2] - smn, sn[3], sn[4], sn[5]};
         sym_from_voigt(s6, Sd);
@@ -359,18 +378,19 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
         const R Rm[9] = {d0 + t2 * a1 * a1, t2 * (a1 * a2 - a3), t2 * (a1 * a3 + a2),
                          t2 * (a2 * a1 + a3), d0 + t2 * a2 * a2, t2 * (a2 * a3 - a1),
                          t2 * (a3 * a1 - a2), t2 * (a3 * a2 + a1), d0 + t2 * a3 * a3};
-        R T[9], Sr[9];
+        // R S R^T is symmetric: its upper triangle, in Voigt order
+        R T[9];
         mm33(Rm, Sd, T);
-        mmT33(T, Rm, Sr);
+        constexpr int vi[6] = {0, 1, 2, 1, 0, 0}, vj[6] = {0, 1, 2, 2, 2, 1};
 #pragma unroll
-        for (int k = 0; k < 9; ++k) Sd[k] = Sr[k];
+        for (int k = 0; k < 6; ++k)
+            sdr[k] = T[3 * vi[k]] * Rm[3 * vj[k]] + T[3 * vi[k] + 1] * Rm[3 * vj[k] + 1] +
+                     T[3 * vi[k] + 2] * Rm[3 * vj[k] + 2];
     }
     // deviatoric strain increment
     const R trd = (d6[0] + d6[1] + d6[2]) * third;
     const R de[6] = {(d6[0] - trd) * dt, (d6[1] - trd) * dt, (d6[2] - trd) * dt,
                      d6[3] * dt, d6[4] * dt, d6[5] * dt};
-    R sdr[6];
-    voigt_from_sym(Sd, sdr);
     const R G = R(P.G);
     const R omD = R(1.0 - D);
     R sd[6], sm;
@@ -390,13 +410,16 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
         R st[6];
 #pragma unroll
         for (int k = 0; k < 6; ++k) st[k] = sdr[k] + R(2) * G * omD * de[k];
-        const R seq = mises_voigt(st);
-        const R sf = R((P.A + P.B * pow_el(eps, P.n)) * jc_rate_factor(P, rate)) * omD;
+        // elastic if sigma_eq < sigma_f, decided on the squares (no root)
+        const R q2 = R(1.5) * (st[0] * st[0] + st[1] * st[1] + st[2] * st[2] +
+                               R(2) * (st[3] * st[3] + st[4] * st[4] + st[5] * st[5]));
+        const R sf = R(jc_hardening(P, eps) * jc_rate_factor(P, rate)) * omD;
         R dep = R(0);
-        if (seq < sf) {
+        if (q2 < sf * sf) {
 #pragma unroll
             for (int k = 0; k < 6; ++k) sd[k] = st[k];
         } else {
+            const R seq = sqrt(q2);
             dep = (seq - sf) * rcp_nr(R(3) * G * omD);
             const R sc = sf * rcp_nr(seq);
 #pragma unroll
@@ -406,7 +429,9 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
         rate = double(dep) * P.inv_dt;
         if (dep > R(0) && (model == 1 || model == 2)) {
             if (model == 2) {
-                const R sstar = sm * rcp_nr(mises_voigt(sd));
+                // the returned deviator lies on the yield surface: its
+                // equivalent stress is sf
+                const R sstar = sm * rcp_nr(sf);
                 const double ef = (P.D1 + P.D2 * exp(P.D3 * double(sstar))) *
                                   pow_el(1.0 + rate * P.inv_eps_dot0, P.D4);
                 dinit += double(dep) * rcp_nr(ef);
@@ -428,16 +453,14 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
         o.sig[0] = sd[0] + sm; o.sig[1] = sd[1] + sm; o.sig[2] = sd[2] + sm;
         o.sig[3] = sd[3]; o.sig[4] = sd[4]; o.sig[5] = sd[5];
     }
-    // P^{n+1} = J sigma F^{-T}
-    R S1[9], F1[9], Fi[9];
+    // P^{n+1} = J sigma F^{-T} = sigma cof(F)
+    R S1[9], F1[9], C1[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) F1[k] = o.H[k];
     F1[0] += R(1); F1[4] += R(1); F1[8] += R(1);
     sym_from_voigt(o.sig, S1);
-    inv33(F1, Fi);
-    mmT33(S1, Fi, o.P);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) o.P[k] *= J;
+    cof33(F1, C1);
+    mm33(S1, C1, o.P);
     // the P^{n+1} half of the energy update
     R work1 = R(0);
 #pragma unroll
