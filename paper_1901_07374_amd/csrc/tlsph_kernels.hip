@@ -1231,32 +1231,57 @@ k_pass_a_staged(DevState s, int par) {
     const int T = s.tile;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t start = tile * T;
-    const int nh = s.halo_cnt[tile];
+    const int tot = T + s.halo_cnt[tile];
     const int32_t* __restrict__ hl = s.halo + tile * (int64_t)s.halo_cap;
     const D4* __restrict__ XV = s.XV;
     const D4* __restrict__ VW = s.VW;
-    for (int m = threadIdx.x; m < T + nh; m += blockDim.x) {
-        const int64_t g = m < T ? start + m : (int64_t)hl[m - T];
-        if (g < s.n) {
-            const D4 x = XV[g], v = VW[g];
-            Lxy[m] = double2{x.x, x.y};
-            Lzw[m] = double2{x.z, v.w};
-            Lvxy[m] = double2{v.x, v.y};
-            Lvz[m] = v.z;
+    // the particle's own scalars first, then up to four slots per thread per
+    // round: index loads, record loads, LDS stores (two memory latencies a
+    // round); slots past the particle count load the tile's first record and
+    // store nothing
+    const int64_t i = start + threadIdx.x;
+    const bool in = i < s.n;
+    const int64_t ii = in ? i : start;
+    const int sp_lane = s.spec[ii];
+    const int cnt = s.nnb[ii];
+    const uint16_t* __restrict__ lp = s.lcol + s.slice_ptr[ii / kSlice] + (ii % kSlice);
+    constexpr int kU = 4;
+    for (int m0 = threadIdx.x; m0 < tot; m0 += kU * T) {
+        int64_t g[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int m = m0 + u * T;
+            g[u] = m >= tot ? s.n : (m < T ? start + m : (int64_t)hl[m - T]);
+        }
+        D4 x[kU], v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int64_t l = g[u] < s.n ? g[u] : start;
+            x[u] = XV[l];
+            v[u] = VW[l];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int m = m0 + u * T;
+            if (g[u] < s.n) {
+                Lxy[m] = double2{x[u].x, x[u].y};
+                Lzw[m] = double2{x[u].z, v[u].w};
+                Lvxy[m] = double2{v[u].x, v[u].y};
+                Lvz[m] = v[u].z;
+            }
         }
     }
     __syncthreads();
-    const int64_t i = start + threadIdx.x;
-    if (threadIdx.x >= T || i >= s.n) return;
-    const int sp_lane = s.spec[i];
+    if (threadIdx.x >= T || !in) return;
     for (;;) {
         const int sp = __builtin_amdgcn_readfirstlane(sp_lane);
         if (sp == sp_lane) {
             const DevSpec& P = s.specs[sp];
-            const uint16_t* __restrict__ lp = s.lcol + s.slice_ptr[i / kSlice] + (i % kSlice);
+            const int t = threadIdx.x;
+            const double2 a = Lxy[t], b = Lzw[t], c = Lvxy[t];
             R M9[9];
-            gather_fdot<R>(XV[i], VW[i], s.nnb[i], R(P.inv_h), R(P.grad_k),
-                           [&](int k) { return (int)lp[(int64_t)k * kSlice]; },
+            gather_fdot<R>(D4{a.x, a.y, b.x, 0.0}, D4{c.x, c.y, Lvz[t], 0.0}, cnt, R(P.inv_h),
+                           R(P.grad_k), [&](int k) { return (int)lp[(int64_t)k * kSlice]; },
                            [&](int m) {
                                const double2 a = Lxy[m], b = Lzw[m], c = Lvxy[m];
                                return NbrA{a.x, a.y, b.x, c.x, c.y, Lvz[m], b.y};
