@@ -320,23 +320,45 @@ double orc_mean_stress_eos(const orc_material *m, double J, double D, double e,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Sec. 4, eq. JC_viscoplastic_model without the (1 - D) factor.            */
+/* Sec. 4, eq. JC_viscoplastic_model without the (1 - D) factor, and the    */
+/* other hardening laws Sec. 4 names (forms in the header, readings).       */
 /* Readings: isothermal (T* = 0, so the factor 1 - T*^m is 1); reference    */
-/* rate eps_dot0 is a parameter; ln of the normalised rate is floored at 0. */
+/* rate eps_dot0 is a parameter; ln of the normalised rate is floored at 0; */
+/* the rate factor multiplies every law (C = 0: rate independent).          */
 /* ------------------------------------------------------------------------ */
-double orc_flow_stress(const orc_material *m, double eps, double eps_rate) {
-    double rs = eps_rate / m->eps_dot0;
-    if (rs < 1.0) rs = 1.0;
-    return (m->A + m->B * pow(eps, m->n)) * (1.0 + m->C * log(rs));
+static double hardening(const orc_material *m, double eps) {
+    switch (m->flow) {
+    case ORC_FLOW_LINEAR: return m->A + m->B * eps;
+    case ORC_FLOW_SWIFT: return m->B * pow(m->flow_e0 + eps, m->n);
+    case ORC_FLOW_VOCE: return m->A - m->B * expm1(-m->flow_beta * eps);
+    default: return m->A + m->B * pow(eps, m->n);
+    }
 }
 
-/* d sigma_f / d eps (same rate factor).  Reading: 0 at eps = 0 where the  */
-/* hardening slope is unbounded for n < 1.                                  */
-static double flow_stress_slope(const orc_material *m, double eps, double eps_rate) {
-    if (!(eps > 0.0)) return 0.0;
+/* dh/deps.  Reading: the Johnson-Cook slope is taken as 0 at eps = 0,      */
+/* where it is unbounded for n < 1.                                         */
+static double hardening_slope(const orc_material *m, double eps) {
+    switch (m->flow) {
+    case ORC_FLOW_LINEAR: return m->B;
+    case ORC_FLOW_SWIFT: return m->B * m->n * pow(m->flow_e0 + eps, m->n - 1.0);
+    case ORC_FLOW_VOCE: return m->B * m->flow_beta * exp(-m->flow_beta * eps);
+    default: return eps > 0.0 ? m->B * m->n * pow(eps, m->n - 1.0) : 0.0;
+    }
+}
+
+static double rate_factor(const orc_material *m, double eps_rate) {
     double rs = eps_rate / m->eps_dot0;
     if (rs < 1.0) rs = 1.0;
-    return m->B * m->n * pow(eps, m->n - 1.0) * (1.0 + m->C * log(rs));
+    return 1.0 + m->C * log(rs);
+}
+
+double orc_flow_stress(const orc_material *m, double eps, double eps_rate) {
+    return hardening(m, eps) * rate_factor(m, eps_rate);
+}
+
+/* d sigma_f / d eps at a fixed rate */
+static double flow_stress_slope(const orc_material *m, double eps, double eps_rate) {
+    return hardening_slope(m, eps) * rate_factor(m, eps_rate);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -416,23 +438,60 @@ void orc_hughes_winget(double dt, const double w[9], const double sd_in[9],
 /* Readings: sigma_y of the plastic-strain line is the damaged flow stress  */
 /* sigma_f(eps_n, rate_n)(1 - D) of the yield test (explicit hardening);    */
 /* the increment is divided by 3G(1 - D), matching the 2G(1 - D) trial.     */
+/*                                                                          */
+/* Implicit variant (m->implicit_return): the increment d solves the        */
+/* consistency condition with the flow stress at the end of the step,       */
+/*   sigma_eq,tr - 3G(1 - D) d = (1 - D) sigma_f(eps_n + d, d / dt),         */
+/* yielding if sigma_eq,tr >= (1 - D) sigma_f(eps_n, 0).  The left side     */
+/* falls and the right side rises with d, so the root is unique in          */
+/* [0, (sigma_eq,tr - (1 - D) sigma_f(eps_n, 0)) / (3G(1 - D))]; it is found  */
+/* by Newton steps kept inside a shrinking bracket (bisection when a step   */
+/* leaves it), to a step of 1e-14 relative, at most 100 iterations.         */
 /* ------------------------------------------------------------------------ */
-static void jc_return(const orc_material *m, double G, double D, const double sd_n[9],
-                      const double deps_d[9], double eps_p, double eps_rate,
-                      double sd_out[9], double *dep, int32_t *yielded) {
+static double implicit_increment(const orc_material *m, double k3, double omD, double seq_tr,
+                                 double eps_p, double dt, double d_max, int32_t *failed) {
+    double lo = 0.0, hi = d_max, d = d_max;
+    for (int it = 0; it < 100; ++it) {
+        double rate = d / dt;
+        double h = hardening(m, eps_p + d), rf = rate_factor(m, rate);
+        double g = seq_tr - k3 * d - omD * h * rf;
+        if (g > 0.0) lo = d; else hi = d;
+        /* d/dd of the rate factor: C / d above the reference rate */
+        double drf = rate / m->eps_dot0 > 1.0 ? m->C / d : 0.0;
+        double dg = -k3 - omD * (hardening_slope(m, eps_p + d) * rf + h * drf);
+        double nd = d - g / dg;
+        if (!(nd > lo && nd < hi)) nd = 0.5 * (lo + hi);
+        double step = fabs(nd - d);
+        d = nd;
+        if (step <= 1e-14 * d || hi - lo <= 1e-14 * hi) return d;
+    }
+    *failed = 1;
+    return d;
+}
+
+static void alg1_return(const orc_material *m, double G, double D, double dt,
+                        const double sd_n[9], const double deps_d[9], double eps_p,
+                        double eps_rate, double sd_out[9], double *dep, int32_t *yielded,
+                        int32_t *newton_failed) {
     double sd_tr[9];
     for (int k = 0; k < 9; ++k) sd_tr[k] = sd_n[k] + 2.0 * G * (1.0 - D) * deps_d[k];
     double seq_tr = von_mises(sd_tr);
-    double sf = orc_flow_stress(m, eps_p, eps_rate) * (1.0 - D);
+    double sf = orc_flow_stress(m, eps_p, m->implicit_return ? 0.0 : eps_rate) * (1.0 - D);
     if (seq_tr < sf) {
         memcpy(sd_out, sd_tr, sizeof sd_tr);
         *dep = 0.0;
         *yielded = 0;
-    } else {
-        *dep = (seq_tr - sf) / (3.0 * G * (1.0 - D));
-        for (int k = 0; k < 9; ++k) sd_out[k] = sf / seq_tr * sd_tr[k];
-        *yielded = 1;
+        return;
     }
+    double k3 = 3.0 * G * (1.0 - D);
+    double sy = sf;
+    *dep = (seq_tr - sf) / k3;
+    if (m->implicit_return) {
+        *dep = implicit_increment(m, k3, 1.0 - D, seq_tr, eps_p, dt, *dep, newton_failed);
+        sy = seq_tr - k3 * *dep;
+    }
+    for (int k = 0; k < 9; ++k) sd_out[k] = sy / seq_tr * sd_tr[k];
+    *yielded = 1;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -593,7 +652,8 @@ void orc_point_update(const orc_material *m, double dt, const double Fdot[9],
         sm = orc_mean_stress_eos(m, J, D, pt->e, 1);
         double dep;
         int32_t y;
-        jc_return(m, G, D, sd_rot, deps_d, pt->eps_p, pt->eps_p_rate, sd_new, &dep, &y);
+        alg1_return(m, G, D, dt, sd_rot, deps_d, pt->eps_p, pt->eps_p_rate, sd_new, &dep, &y,
+                    &info->newton_failed);
         info->yielded = y;
         info->dep = dep;
         pt->eps_p += dep;

@@ -22,6 +22,12 @@ extern "C" {
 #endif
 
 enum { ORC_DMG_NONE = 0, ORC_DMG_CL = 1, ORC_DMG_JC = 2, ORC_DMG_GTN = 3 };
+/* Strain-hardening law of the flow stress (Sec. 4 names linear plastic,
+ * Johnson-Cook, Swift and Voce; the forms are readings):
+ *   JC      A + B eps^n          LINEAR  A + B eps
+ *   SWIFT   B (e0 + eps)^n       VOCE    A + B (1 - exp(-beta eps))
+ * each times the rate factor 1 + C ln max(eps_rate / eps_dot0, 1). */
+enum { ORC_FLOW_JC = 0, ORC_FLOW_LINEAR = 1, ORC_FLOW_SWIFT = 2, ORC_FLOW_VOCE = 3 };
 
 /* Per-specimen material and run parameters. */
 typedef struct {
@@ -34,6 +40,9 @@ typedef struct {
     double h, dt, hg_alpha;                    /* support radius, step, hourglass */
     int32_t has_wall;
     double wall_n[3], wall_d;                  /* rigid plane x.n = d */
+    int32_t flow;                              /* ORC_FLOW_* */
+    int32_t implicit_return;                   /* 1: hardening at the end of the step */
+    double flow_e0, flow_beta;                 /* Swift offset strain, Voce rate */
 } orc_material;
 
 /* Prescribed-velocity group: component c (bit c of mask) is set to

@@ -24,6 +24,9 @@ SEED_BASE = 190107374
 
 # damage model identifiers (same numbering on both sides of the boundary)
 DMG_NONE, DMG_CL, DMG_JC, DMG_GTN = 0, 1, 2, 3
+# strain-hardening laws of the flow stress: Johnson-Cook A + B eps^n, linear
+# A + B eps, Swift B (flow_e0 + eps)^n, Voce A + B (1 - exp(-flow_beta eps))
+FLOW_JC, FLOW_LINEAR, FLOW_SWIFT, FLOW_VOCE = 0, 1, 2, 3
 
 # Field order of one per-specimen parameter record.
 MATERIAL_KEYS = (
@@ -32,6 +35,7 @@ MATERIAL_KEYS = (
     "damage", "Wcr", "D1", "D2", "D3", "D4", "D5",
     "q1", "q2", "q3", "f0", "fN", "eN", "sN", "fc", "fF", "k_omega",
     "h", "dt", "hg_alpha", "has_wall", "wall_n", "wall_d",
+    "flow", "implicit_return", "flow_e0", "flow_beta",
 )
 
 # Steel used by every synthetic workload (rho, E, nu and the Johnson-Cook
@@ -56,7 +60,8 @@ def material(dx: float, damage: int = DMG_NONE, **over) -> Dict:
     m.update(dict(damage=damage, Wcr=0.0, D1=0.0, D2=0.0, D3=0.0, D4=0.0, D5=0.0,
                   q1=1.0, q2=1.0, q3=1.0, f0=0.0, fN=0.0, eN=0.0, sN=1.0,
                   fc=1.0, fF=1.0, k_omega=0.0, hg_alpha=1.0, has_wall=0,
-                  wall_n=(0.0, 0.0, 1.0), wall_d=0.0))
+                  wall_n=(0.0, 0.0, 1.0), wall_d=0.0, flow=FLOW_JC, implicit_return=0,
+                  flow_e0=0.0, flow_beta=0.0))
     if damage == DMG_JC:
         m.update(JC_DAMAGE)
     if damage == DMG_GTN:

@@ -15,7 +15,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "tlsph_oracle.c")
 PINS = ["tests/test_oracle_kernel_neighbors.py", "tests/test_oracle_constitutive.py",
-        "tests/test_oracle_system.py"]
+        "tests/test_oracle_flow.py", "tests/test_oracle_system.py"]
 
 # (name, text in the oracle, planted replacement)
 MUTANTS = [
@@ -40,17 +40,24 @@ MUTANTS = [
     ("failed particles keep moving", "if (s->D[i] >= 1.0) v[0] = v[1] = v[2] = 0.0;",
      "if (s->D[i] > 1.0) v[0] = v[1] = v[2] = 0.0;"),
     ("EOS S_alpha sign", "double den = eta - S * mu;", "double den = eta + S * mu;"),
-    ("radial return with 2G", "*dep = (seq_tr - sf) / (3.0 * G * (1.0 - D));",
-     "*dep = (seq_tr - sf) / (2.0 * G * (1.0 - D));"),
+    ("radial return with 2G", "double k3 = 3.0 * G * (1.0 - D);",
+     "double k3 = 2.0 * G * (1.0 - D);"),
     ("trial stress without (1 - D)",
      "for (int k = 0; k < 9; ++k) sd_tr[k] = sd_rot[k] + 2.0 * G * (1.0 - D) * deps_d[k];",
      "for (int k = 0; k < 9; ++k) sd_tr[k] = sd_rot[k] + 2.0 * G * deps_d[k];"),
     ("rotation applied transposed", "mul3(R, sd_in, tmp);\n    mul3(tmp, RT, sd_out);",
      "mul3(RT, sd_in, tmp);\n    mul3(tmp, R, sd_out);"),
     ("JC failure strain sign of D3", "exp(m->D3 * sstar)", "exp(-m->D3 * sstar)"),
-    ("flow stress rate term", "return (m->A + m->B * pow(eps, m->n)) * (1.0 + m->C * log(rs));",
-     "return (m->A + m->B * pow(eps, m->n)) * (1.0 + m->C * log(rs + 1.0));"),
+    ("flow stress rate term", "return 1.0 + m->C * log(rs);", "return 1.0 + m->C * log(rs + 1.0);"),
     ("GTN yield function factor", "cosh(1.5 * m->q2 * sstar * r)", "cosh(1.0 * m->q2 * sstar * r)"),
+    ("Voce law sign", "return m->A - m->B * expm1(-m->flow_beta * eps);",
+     "return m->A + m->B * expm1(-m->flow_beta * eps);"),
+    ("Swift offset dropped", "return m->B * pow(m->flow_e0 + eps, m->n);",
+     "return m->B * pow(eps, m->n);"),
+    ("implicit return without (1 - D) on the flow stress",
+     "double g = seq_tr - k3 * d - omD * h * rf;", "double g = seq_tr - k3 * d - h * rf;"),
+    ("implicit return with the rate of the step's start", "double rate = d / dt;",
+     "double rate = 0.0 * d / dt;"),
     ("energy from P^{n+1} only", "work += Fdot[k] * 0.5 * (Jn * Pn[k] + P[k]);",
      "work += Fdot[k] * P[k];"),
 ]
