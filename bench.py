@@ -60,13 +60,16 @@ def algorithmic_bytes(kernel: str, mixed: bool, damage: int, n: int, nnz: int) -
     return per * n + 4 * nnz
 
 
-def kernel_symbol(kernel: str, info: dict, mixed: bool, damage: int) -> str:
-    """Kernel name as rocprofv3 reports it (template arguments included)."""
+def kernel_symbol(kernel: str, info: dict, mixed: bool, model: int) -> str:
+    """Kernel name as rocprofv3 reports it (template arguments included);
+    model is the damage model the deformation pass is compiled for (-1: the
+    general variant)."""
     r = "float" if mixed else "double"
     if kernel == "force_pass":
         name = "k_pass_b_staged" if info["staged"] else "k_pass_b"
         return f"{name}<{r}, {info['lanes_per_particle']}>"
-    return f"k_pass_a<{r}, {damage}>"
+    name = "k_pass_a_staged" if info["block_deformation"] == 0 else "k_pass_a"
+    return f"{name}<{r}, {model}>"
 
 
 def counter_traffic(symbol: str, workload: str):
@@ -193,13 +196,13 @@ def kernel_table(kt, mixed, damage, n, nnz):
                                               / (v * 1e-3) / 1e9, 1)} for k, v in kts.items()}
 
 
-def roofline_of(run, damage, n, workload, mixed=False):
+def roofline_of(run, damage, n, workload, mixed=False, model=None):
     nnz = run["info"]["nnz"]
     kts, _ = kernel_table(run["kernel_times"], mixed, damage, n, nnz)
     dom = max(kts, key=kts.get)
     bytes_launch = algorithmic_bytes(dom, mixed, damage, n, nnz)
     achieved = bytes_launch / (kts[dom] * 1e-3) / 1e9
-    symbol = kernel_symbol(dom, run["info"], mixed, damage)
+    symbol = kernel_symbol(dom, run["info"], mixed, damage if model is None else model)
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": counter_traffic(symbol, workload), "kernel": dom, "symbol": symbol,
@@ -252,10 +255,12 @@ def shape_of(info):
 # --------------------------------------------------------------------------
 # workloads
 # --------------------------------------------------------------------------
-def bench_notched_bar(args, torch, I, T):
-    prob = I.notched_bar()
+FLOW_NAMES = {0: "johnson-cook", 1: "linear", 2: "swift", 3: "voce"}
+
+
+def bench_notched_bar(args, torch, I, T, workload="notched_bar_200k", **mat_over):
+    prob = I.notched_bar(**mat_over)
     damage = prob.materials[0]["damage"]
-    workload = "notched_bar_200k"
     flags = T.NO_STAGING if args.unstaged else 0
     tune = not args.no_autotune
 
@@ -270,12 +275,17 @@ def bench_notched_bar(args, torch, I, T):
     out = base_line(args, workload, prob.n * args.steps / fp["seconds"],
                     fp["seconds"] / args.steps * 1e3, "f64",
                     dict({"particles": prob.n, "neighbour_pairs": nnz, "damage": "johnson-cook",
+                          "flow": FLOW_NAMES[prob.materials[0]["flow"]],
+                          "return": "implicit" if prob.materials[0]["implicit_return"] else
+                                    "explicit (Algorithm 1)",
                           "precision": "fp64", "steps_from_rest": args.warmup + args.steps,
                           "dt_s": prob.materials[0]["dt"]}, **shape_of(fp["info"])))
     step_bytes = sum(algorithmic_bytes(k, False, damage, prob.n, nnz) for k in ktab)
     out["step_algorithmic_GBs"] = round(step_bytes * args.steps / fp["seconds"] / 1e9, 1)
     out["kernels"] = ktab
-    out["roofline"] = roofline_of(fp, damage, prob.n, workload)
+    m0 = prob.materials[0]
+    model = damage if m0["flow"] == I.FLOW_JC and not m0["implicit_return"] else -1
+    out["roofline"] = roofline_of(fp, damage, prob.n, workload, model=model)
     r64, s64 = curve(fp)
     fd64 = fd_mm(s64, r64)
     out["fp64_failure_displacement_mm"] = fd64
@@ -458,7 +468,17 @@ def bench_batch(args, torch, I, T):
     return out
 
 
+def bench_notched_bar_voce(args, torch, I, T):
+    """The headline bar with Voce hardening (fitted near the Johnson-Cook
+    curve: A = 792 MPa, B = 510 MPa, beta = 5) and the implicit return: the
+    general deformation-pass variant."""
+    return bench_notched_bar(args, torch, I, T, "notched_bar_200k_voce_implicit",
+                             flow=I.FLOW_VOCE, A=792e6, B=510e6, flow_beta=5.0,
+                             implicit_return=1)
+
+
 WORKLOADS = {"notched_bar_200k": (bench_notched_bar, 42000, 1000),
+             "notched_bar_200k_voce_implicit": (bench_notched_bar_voce, 42000, 1000),
              "taylor_bar_1m": (bench_taylor, 4900, 100),
              "gtn_plate_4m": (bench_plate, 1900, 100),
              "batch_256_bars": (bench_batch, 400, 50)}

@@ -72,6 +72,15 @@ typedef enum {
     TLSPH_DMG_GTN = 3     /* Gurson-Tvergaard-Needleman (Sec. 5.4, Alg. 2)     */
 } tlsph_damage;
 
+typedef enum {
+    TLSPH_FLOW_JC = 0,      /* A + B eps^n (eq. JC_viscoplastic_model)             */
+    TLSPH_FLOW_LINEAR = 1,  /* A + B eps                                         */
+    TLSPH_FLOW_SWIFT = 2,   /* B (flow_e0 + eps)^n                               */
+    TLSPH_FLOW_VOCE = 3     /* A + B (1 - exp(-flow_beta eps))                   */
+} tlsph_flow;   /* strain-hardening law of the flow stress (Sec. 4 names all four; the
+                   forms are readings); every law is multiplied by the rate factor
+                   1 + C ln max(eps_rate / eps_dot0, 1) and by 1 - D */
+
 /* create() flags */
 #define TLSPH_STORE_FORCE   1u  /* keep the nodal force of every particle (else only
                                    of particles in a prescribed-velocity group) */
@@ -93,6 +102,15 @@ typedef struct {
     double hg_alpha;                          /* hourglass control coefficient      */
     int32_t has_wall;                         /* 1: rigid frictionless plane        */
     double wall_n[3], wall_d;                 /* plane x . n = d, n unit normal     */
+    int32_t flow;                             /* tlsph_flow                         */
+    int32_t implicit_return;                  /* 0: Algorithm 1 with the flow stress at
+                                                 the step's start (explicit hardening);
+                                                 1: the plastic increment solves the
+                                                 consistency condition with the flow
+                                                 stress at the step's end (hardening and
+                                                 rate); no effect under GTN            */
+    double flow_e0;                           /* Swift offset strain (> 0)          */
+    double flow_beta;                         /* Voce saturation rate (>= 0)        */
 } tlsph_specimen;
 
 /* Prescribed-velocity group.  At mid-step time t the velocity component c of

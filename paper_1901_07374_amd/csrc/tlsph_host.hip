@@ -396,6 +396,11 @@ tlsph_status tlsph_create(int64_t n, int32_t n_spec, const int64_t* spec_offsets
             !finite_pos(p.eps_dot0) || !(p.A >= 0.0) || !(p.hg_alpha >= 0.0))
             return TLSPH_E_INVALID_ARG;
         if (p.damage == TLSPH_DMG_CL && !finite_pos(p.Wcr)) return TLSPH_E_INVALID_ARG;
+        if (p.flow < TLSPH_FLOW_JC || p.flow > TLSPH_FLOW_VOCE ||
+            (p.implicit_return != 0 && p.implicit_return != 1) ||
+            (p.flow == TLSPH_FLOW_SWIFT && !finite_pos(p.flow_e0)) ||
+            (p.flow == TLSPH_FLOW_VOCE && !(p.flow_beta >= 0.0 && p.flow_beta <= 1e300)))
+            return TLSPH_E_INVALID_ARG;
         if (p.damage == TLSPH_DMG_GTN &&
             (!finite_pos(p.q1) || !finite_pos(p.sN) || !(p.fF > p.fc) || !(p.fc > 0.0)))
             return TLSPH_E_INVALID_ARG;
@@ -439,15 +444,23 @@ tlsph_status tlsph_create(int64_t n, int32_t n_spec, const int64_t* spec_offsets
         d.dt_rho0 = p.dt / p.rho0;
         d.damage = p.damage;
         d.has_wall = p.has_wall;
+        d.flow = p.flow;
+        d.implicit_return = p.implicit_return;
+        d.flow_e0 = p.flow_e0;
+        d.flow_beta = p.flow_beta;
         d.first = spec_offsets[s];
         d.last = spec_offsets[s + 1];
     }
     c->bcs.resize(n_bc > 0 ? n_bc : 1);
     for (int32_t g = 0; g < n_bc; ++g) c->bcs[g] = to_dev(bc[g]);
     wire_state(c);
+    // the kernels compiled per damage model run Johnson-Cook hardening with
+    // Algorithm 1's explicit return; anything else takes the general variant
     c->st.model = spec[0].damage;
-    for (int32_t q = 1; q < n_spec; ++q)
-        if (spec[q].damage != spec[0].damage) c->st.model = -1;
+    for (int32_t q = 0; q < n_spec; ++q)
+        if (spec[q].damage != spec[0].damage || spec[q].flow != TLSPH_FLOW_JC ||
+            spec[q].implicit_return != 0)
+            c->st.model = -1;
     const Layout& L = c->L;
     hipError_t e = hipMemcpyAsync(c->ws + L.specs, c->specs.data(), n_spec * sizeof(DevSpec),
                                   hipMemcpyHostToDevice, stream);

@@ -36,6 +36,9 @@ struct DevSpec {
     double dt_rho0;    // dt / rho0: the kick per unit force density
     int32_t damage;
     int32_t has_wall;
+    int32_t flow;              // strain-hardening law (tlsph_flow)
+    int32_t implicit_return;   // 1: flow stress at the step's end in Algorithm 1
+    double flow_e0, flow_beta; // Swift offset strain, Voce saturation rate
     int64_t first, last;   // sorted-order particle range [first, last)
 };
 

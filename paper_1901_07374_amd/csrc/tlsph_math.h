@@ -188,6 +188,64 @@ __host__ __device__ __forceinline__ double jc_hardening(const DevSpec& P, double
     return eps > 0.0 ? P.A + P.B * pow_el(eps, P.n) : P.A;
 }
 
+// Strain-hardening factor h(eps) of the flow stress for the laws Sec. 4
+// names: Johnson-Cook A + B eps^n, linear A + B eps, Swift B (e0 + eps)^n,
+// Voce A + B (1 - exp(-beta eps)).  kGen = false compiles Johnson-Cook only.
+template <bool kGen>
+__host__ __device__ __forceinline__ double hardening(const DevSpec& P, double eps) {
+    if constexpr (kGen) {
+        switch (P.flow) {
+            case 1: return P.A + P.B * eps;
+            case 2: return P.B * pow_el(P.flow_e0 + eps, P.n);
+            case 3: return P.A - P.B * expm1(-P.flow_beta * eps);
+            default: break;
+        }
+    }
+    return jc_hardening(P, eps);
+}
+
+// dh/deps (the Johnson-Cook slope taken as 0 at eps = 0)
+template <bool kGen>
+__host__ __device__ __forceinline__ double hardening_slope(const DevSpec& P, double eps) {
+    if constexpr (kGen) {
+        switch (P.flow) {
+            case 1: return P.B;
+            case 2: return P.B * P.n * pow_el(P.flow_e0 + eps, P.n - 1.0);
+            case 3: return P.B * P.flow_beta * exp(-P.flow_beta * eps);
+            default: break;
+        }
+    }
+    return eps > 0.0 ? P.B * P.n * pow_el(eps, P.n - 1.0) : 0.0;
+}
+
+// Algorithm 1 with the flow stress at the end of the step: the plastic
+// increment d solves seq - k3 d = omD sigma_f(eps + d, d / dt) (k3 = 3G(1 - D),
+// omD = 1 - D).  The left side falls and the right side rises with d, so the
+// root in [0, d_max] (d_max: the increment at the step's-start flow stress) is
+// unique; Newton steps are kept inside the shrinking bracket (bisection when
+// a step leaves it), to a step of 1e-14 relative, at most 100 iterations.
+__host__ __device__ inline double implicit_increment(const DevSpec& P, double k3, double omD,
+                                                     double seq, double eps, double d_max,
+                                                     int32_t& flags) {
+    double lo = 0.0, hi = d_max, d = d_max;
+    for (int it = 0; it < 100; ++it) {
+        const double rs = d * P.inv_dt * P.inv_eps_dot0;
+        const double rf = rs > 1.0 ? 1.0 + P.C * log(rs) : 1.0;
+        const double h = hardening<true>(P, eps + d);
+        const double g = seq - k3 * d - omD * h * rf;
+        if (g > 0.0) lo = d; else hi = d;
+        const double drf = rs > 1.0 ? P.C / d : 0.0;
+        const double dg = -k3 - omD * (hardening_slope<true>(P, eps + d) * rf + h * drf);
+        double nd = d - g / dg;
+        if (!(nd > lo && nd < hi)) nd = 0.5 * (lo + hi);
+        const double step = fabs(nd - d);
+        d = nd;
+        if (step <= 1e-14 * d || hi - lo <= 1e-14 * hi) return d;
+    }
+    flags |= kErrNewton;
+    return d;
+}
+
 // Largest eigenvalue of a symmetric tensor (closed form of the cubic's roots).
 template <typename R>
 __host__ __device__ __forceinline__ R max_principal(const R s[6]) {
@@ -219,12 +277,13 @@ __host__ __device__ __forceinline__ double gtn_D(const DevSpec& P, double f) {
 // GTN return mapping (Algorithm 2), double precision.  In: trial deviator
 // (Voigt) and trial mean stress, state (eps_M, its last rate, f), damage D.
 // Out: returned deviator and mean stress, updated eps_M, rate, f.
+template <bool kGen>
 __host__ __device__ inline void gtn_return(const DevSpec& P, double D, double dt, const double sdt[6],
                                   double smt, double& epsM, double& rate, double& f,
                                   double sd[6], double& sm, int32_t& flags) {
     const double seq = mises_voigt(sdt);
     const double rf = jc_rate_factor(P, rate);
-    const double sM0 = (P.A + P.B * pow(epsM, P.n)) * rf;
+    const double sM0 = hardening<kGen>(P, epsM) * rf;
     const double fs = gtn_fstar(P, f);
     const double q1 = P.q1, q2 = P.q2, q3 = P.q3;
     bool plastic = false;
@@ -261,8 +320,8 @@ __host__ __device__ inline void gtn_return(const DevSpec& P, double D, double dt
     double dem = c * (seq - x * sM0);
     for (it = 0; it < 50; ++it) {
         const double e1 = epsM + dem;
-        const double hard = (e1 > 0.0) ? P.B * P.n * pow(e1, P.n - 1.0) * rf : 0.0;
-        const double sf = (P.A + P.B * pow(e1, P.n)) * rf;
+        const double hard = hardening_slope<kGen>(P, e1) * rf;
+        const double sf = hardening<kGen>(P, e1) * rf;
         const double g = dem - c * (seq - x * sf);
         double nx = dem - g / (1.0 + c * x * hard);
         if (nx < 0.0) nx = 0.5 * dem;
@@ -272,7 +331,7 @@ __host__ __device__ inline void gtn_return(const DevSpec& P, double D, double dt
     }
     if (it == 50) flags |= kErrNewton;
     epsM += dem;
-    const double sM = (P.A + P.B * pow(epsM, P.n)) * rf;
+    const double sM = hardening<kGen>(P, epsM) * rf;
     const double sy = x * sM;
     const double scale = sy / seq;
 #pragma unroll
@@ -321,6 +380,9 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
                                              double& dinit, double& wp, double& fv, double& e,
                                              double D, PointOut<R>& o, int32_t& flags) {
     const int model = DM >= 0 ? DM : P.damage;
+    // the general variant (DM < 0) also runs the other hardening laws and the
+    // implicit return
+    constexpr bool kGen = DM < 0;
     const R dt = R(P.dt);
 #pragma unroll
     for (int k = 0; k < 9; ++k) o.H[k] = Hn[k] + dt * Fd[k];
@@ -400,7 +462,7 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
 #pragma unroll
         for (int k = 0; k < 6; ++k) sdt[k] = double(sdr[k] + R(2) * G * omD * de[k]);
         const double smt = double(mean_stress<R>(P, Jm1, R(D), R(e), false));
-        gtn_return(P, D, P.dt, sdt, smt, eps, rate, fv, sdo, smo, flags);
+        gtn_return<kGen>(P, D, P.dt, sdt, smt, eps, rate, fv, sdo, smo, flags);
 #pragma unroll
         for (int k = 0; k < 6; ++k) sd[k] = R(sdo[k]);
         sm = R(smo);
@@ -413,32 +475,45 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
         // elastic if sigma_eq < sigma_f, decided on the squares (no root)
         const R q2 = R(1.5) * (st[0] * st[0] + st[1] * st[1] + st[2] * st[2] +
                                R(2) * (st[3] * st[3] + st[4] * st[4] + st[5] * st[5]));
-        const R sf = R(jc_hardening(P, eps) * jc_rate_factor(P, rate)) * omD;
+        const bool impl = kGen && P.implicit_return;
+        const double h0 = hardening<kGen>(P, eps);
+        const R sf = R(h0 * (impl ? 1.0 : jc_rate_factor(P, rate))) * omD;
         R dep = R(0);
+        double depd = 0.0;
+        R sret = sf;   // equivalent stress after the return
         if (q2 < sf * sf) {
 #pragma unroll
             for (int k = 0; k < 6; ++k) sd[k] = st[k];
         } else {
             const R seq = sqrt(q2);
-            dep = (seq - sf) * rcp_nr(R(3) * G * omD);
-            const R sc = sf * rcp_nr(seq);
+            if (impl) {
+                const double omDd = 1.0 - D, k3 = 3.0 * P.G * omDd;
+                depd = implicit_increment(P, k3, omDd, double(seq), eps,
+                                          (double(seq) - omDd * h0) / k3, flags);
+                dep = R(depd);
+                sret = R(double(seq) - k3 * depd);
+            } else {
+                dep = (seq - sf) * rcp_nr(R(3) * G * omD);
+                depd = double(dep);
+            }
+            const R sc = sret * rcp_nr(seq);
 #pragma unroll
             for (int k = 0; k < 6; ++k) sd[k] = sc * st[k];
         }
-        eps += double(dep);
-        rate = double(dep) * P.inv_dt;
-        if (dep > R(0) && (model == 1 || model == 2)) {
+        eps += depd;
+        rate = depd * P.inv_dt;
+        if (depd > 0.0 && (model == 1 || model == 2)) {
             if (model == 2) {
                 // the returned deviator lies on the yield surface: its
-                // equivalent stress is sf
-                const R sstar = sm * rcp_nr(sf);
+                // equivalent stress is sret
+                const R sstar = sm * rcp_nr(sret);
                 const double ef = (P.D1 + P.D2 * exp(P.D3 * double(sstar))) *
                                   pow_el(1.0 + rate * P.inv_eps_dot0, P.D4);
-                dinit += double(dep) * rcp_nr(ef);
+                dinit += depd * rcp_nr(ef);
             } else {
                 R full6[6] = {sd[0] + sm, sd[1] + sm, sd[2] + sm, sd[3], sd[4], sd[5]};
                 const R s1 = max_principal(full6);
-                wp += double(s1 > R(0) ? s1 : R(0)) * double(dep);
+                wp += double(s1 > R(0) ? s1 : R(0)) * depd;
                 dinit = wp / P.Wcr;
             }
             double dn = 10.0 * (dinit - 1.0);

@@ -44,7 +44,9 @@ class Specimen(C.Structure):
                [(k, C.c_double) for k in ("Wcr", "D1", "D2", "D3", "D4", "D5", "q1", "q2",
                                           "q3", "f0", "fN", "eN", "sN", "fc", "fF",
                                           "k_omega", "h", "dt", "hg_alpha")] + \
-               [("has_wall", C.c_int32), ("wall_n", C.c_double * 3), ("wall_d", C.c_double)]
+               [("has_wall", C.c_int32), ("wall_n", C.c_double * 3), ("wall_d", C.c_double),
+                ("flow", C.c_int32), ("implicit_return", C.c_int32), ("flow_e0", C.c_double),
+                ("flow_beta", C.c_double)]
 
 
 class BCGroup(C.Structure):

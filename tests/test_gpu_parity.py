@@ -39,8 +39,31 @@ def no_bc(p, **over):
                      p.v_init, p.steps, p.dx)
 
 
+# the other hardening laws (linear, Swift, Voce) and the implicit return
+SWIFT = dict(flow=I.FLOW_SWIFT, B=1100e6, n=0.2, flow_e0=0.002)
+VOCE = dict(flow=I.FLOW_VOCE, A=700e6, B=450e6, flow_beta=12.0)
+LINEAR = dict(flow=I.FLOW_LINEAR, B=2.0e9)
+
+
+def remat(p, *overs):
+    """Specimen s takes the parameter overrides overs[s % len(overs)]."""
+    mats = [dict(m, **overs[s % len(overs)]) for s, m in enumerate(p.materials)]
+    return I.Problem(p.name, p.X, p.V0, p.spec_offsets, mats, p.bc_group, p.bc_groups,
+                     p.v_init, p.steps, p.dx)
+
+
 CASES = {
     "cube_jc_nodamage": lambda: I.cube(),
+    "bar_swift_implicit": lambda: remat(I.notched_bar(dx=0.8e-3), dict(SWIFT, implicit_return=1)),
+    "bar_voce_implicit_cl": lambda: remat(I.notched_bar(dx=0.8e-3, damage=I.DMG_CL, Wcr=300e6),
+                                          dict(VOCE, implicit_return=1)),
+    "bar_linear": lambda: remat(I.notched_bar(dx=0.8e-3), LINEAR),
+    "bar_jc_implicit": lambda: remat(I.notched_bar(dx=0.8e-3), dict(implicit_return=1)),
+    "plate_gtn_voce": lambda: remat(I.holed_plate(dx=0.8e-3, W=30e-3, H=12e-3, T=2.4e-3,
+                                                  hole_d=4e-3), VOCE),
+    "batch3_laws": lambda: remat(I.subset(I.bar_batch(n_spec=3, lo=2000, hi=6000), [0, 1, 2]),
+                                 dict(SWIFT, implicit_return=1), VOCE,
+                                 dict(LINEAR, implicit_return=1)),
     "bar_jc_damage": lambda: I.notched_bar(dx=0.8e-3),
     "bar_cl": lambda: I.notched_bar(dx=0.8e-3, damage=I.DMG_CL, Wcr=300e6),
     "plate_gtn": lambda: I.holed_plate(dx=0.8e-3, W=30e-3, H=12e-3, T=2.4e-3, hole_d=4e-3),
@@ -141,6 +164,25 @@ def test_cube_trajectory_100_steps(tl, orc, precision):
     say(errs)
     tol = 1e-10 if precision == "fp64" else 1e-4
     assert all(v <= tol for v in errs.values()), errs
+
+
+@pytest.mark.parametrize("law", ["swift_implicit", "voce_implicit", "jc_implicit", "linear"])
+def test_cube_trajectory_flow_laws(tl, orc, law):
+    over = {"swift_implicit": dict(SWIFT, implicit_return=1),
+            "voce_implicit": dict(VOCE, implicit_return=1),
+            "jc_implicit": dict(implicit_return=1), "linear": LINEAR}[law]
+    # a faster cube (5 m/s ends) so that it yields within the run
+    p = remat(I.cube(v=5.0), over)
+    say("cube trajectory", law)
+    g = tl.Sim(p, flags=tl.STORE_FORCE)
+    o = orc.Sim(p)
+    for _ in range(4):
+        g.step(25)
+        o.step(25)
+    assert o.get("eps_p").max() > 0.0
+    errs = compare(g, o, skip=("d_init", "w_p", "f_void", "D"))
+    say(errs)
+    assert all(v <= 1e-10 for v in errs.values()), errs
 
 
 def test_full_size_notched_bar_one_step(tl, orc):
