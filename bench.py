@@ -60,16 +60,16 @@ def algorithmic_bytes(kernel: str, mixed: bool, damage: int, n: int, nnz: int) -
     return per * n + 4 * nnz
 
 
-def kernel_symbol(kernel: str, info: dict, mixed: bool, model: int) -> str:
+def kernel_symbol(kernel: str, info: dict, mixed: bool, model: int, flow_general=False) -> str:
     """Kernel name as rocprofv3 reports it (template arguments included);
-    model is the damage model the deformation pass is compiled for (-1: the
-    general variant)."""
+    model is the damage model the deformation pass is compiled for (-1: any),
+    flow_general whether it is the variant with every flow law."""
     r = "float" if mixed else "double"
     if kernel == "force_pass":
         name = "k_pass_b_staged" if info["staged"] else "k_pass_b"
         return f"{name}<{r}, {info['lanes_per_particle']}>"
     name = "k_pass_a_staged" if info["block_deformation"] == 0 else "k_pass_a"
-    return f"{name}<{r}, {model}>"
+    return f"{name}<{r}, {model}, {'true' if flow_general else 'false'}>"
 
 
 def counter_traffic(symbol: str, workload: str):
@@ -196,13 +196,13 @@ def kernel_table(kt, mixed, damage, n, nnz):
                                               / (v * 1e-3) / 1e9, 1)} for k, v in kts.items()}
 
 
-def roofline_of(run, damage, n, workload, mixed=False, model=None):
+def roofline_of(run, damage, n, workload, mixed=False, flow_general=False):
     nnz = run["info"]["nnz"]
     kts, _ = kernel_table(run["kernel_times"], mixed, damage, n, nnz)
     dom = max(kts, key=kts.get)
     bytes_launch = algorithmic_bytes(dom, mixed, damage, n, nnz)
     achieved = bytes_launch / (kts[dom] * 1e-3) / 1e9
-    symbol = kernel_symbol(dom, run["info"], mixed, damage if model is None else model)
+    symbol = kernel_symbol(dom, run["info"], mixed, damage, flow_general)
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": counter_traffic(symbol, workload), "kernel": dom, "symbol": symbol,
@@ -284,8 +284,8 @@ def bench_notched_bar(args, torch, I, T, workload="notched_bar_200k", **mat_over
     out["step_algorithmic_GBs"] = round(step_bytes * args.steps / fp["seconds"] / 1e9, 1)
     out["kernels"] = ktab
     m0 = prob.materials[0]
-    model = damage if m0["flow"] == I.FLOW_JC and not m0["implicit_return"] else -1
-    out["roofline"] = roofline_of(fp, damage, prob.n, workload, model=model)
+    out["roofline"] = roofline_of(fp, damage, prob.n, workload,
+                                  flow_general=m0["flow"] != I.FLOW_JC or m0["implicit_return"])
     r64, s64 = curve(fp)
     fd64 = fd_mm(s64, r64)
     out["fp64_failure_displacement_mm"] = fd64

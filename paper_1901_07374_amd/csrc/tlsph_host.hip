@@ -454,13 +454,14 @@ tlsph_status tlsph_create(int64_t n, int32_t n_spec, const int64_t* spec_offsets
     c->bcs.resize(n_bc > 0 ? n_bc : 1);
     for (int32_t g = 0; g < n_bc; ++g) c->bcs[g] = to_dev(bc[g]);
     wire_state(c);
-    // the kernels compiled per damage model run Johnson-Cook hardening with
-    // Algorithm 1's explicit return; anything else takes the general variant
+    // the deformation pass is compiled per damage model (or for any) and
+    // with Johnson-Cook hardening and the explicit return only (or any law)
     c->st.model = spec[0].damage;
-    for (int32_t q = 0; q < n_spec; ++q)
-        if (spec[q].damage != spec[0].damage || spec[q].flow != TLSPH_FLOW_JC ||
-            spec[q].implicit_return != 0)
-            c->st.model = -1;
+    c->st.flow_general = 0;
+    for (int32_t q = 0; q < n_spec; ++q) {
+        if (spec[q].damage != spec[0].damage) c->st.model = -1;
+        if (spec[q].flow != TLSPH_FLOW_JC || spec[q].implicit_return != 0) c->st.flow_general = 1;
+    }
     const Layout& L = c->L;
     hipError_t e = hipMemcpyAsync(c->ws + L.specs, c->specs.data(), n_spec * sizeof(DevSpec),
                                   hipMemcpyHostToDevice, stream);

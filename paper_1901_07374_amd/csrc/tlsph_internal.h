@@ -121,6 +121,7 @@ struct DevState {
     int32_t staged;           // 1 when the staged force pass is in use
     int32_t lds_slots;        // record slots of the staged kernels' LDS images (tile + largest halo)
     int32_t model;            // damage model shared by every specimen, -1 if they differ
+    int32_t flow_general;     // 1 if a specimen uses another law than JC or the implicit return
     int32_t tile;             // particles per tile of the staged force pass (<= kTile)
     int32_t staged_lds_a;     // 1 when the tile records of the deformation pass fit LDS
 };

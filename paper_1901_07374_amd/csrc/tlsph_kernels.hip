@@ -1082,7 +1082,7 @@ __device__ __forceinline__ void gather_fdot(const D4& xi, const D4& vi, int cnt,
 
 // The rest of the deformation pass for particle i (specimen sp) given M:
 // dF/dt = M L_i^-1, the constitutive update, Q_i = P_i L_i^-T, stores.
-template <typename R, int DM>
+template <typename R, int DM, bool kFlow>
 __device__ __forceinline__ void pass_a_update(const DevState& s, int64_t i, int sp, const R M[9]) {
     const int64_t np = s.np;
     const DevSpec& P = s.specs[sp];
@@ -1120,7 +1120,7 @@ __device__ __forceinline__ void pass_a_update(const DevState& s, int64_t i, int 
     const double Di = s.D[i];
     PointOut<R> o;
     int32_t flags = 0;
-    point_update<R, DM>(P, Hn, Fd, sn, eps, rate, dinit, wp, fv, e, Di, o, flags);
+    point_update<R, DM, kFlow>(P, Hn, Fd, sn, eps, rate, dinit, wp, fv, e, Di, o, flags);
     // stores: the index passes through an empty asm so that store addresses
     // are formed here rather than kept in registers from the loads above
     int64_t is = i;
@@ -1179,17 +1179,19 @@ __device__ __forceinline__ void pass_a_update(const DevState& s, int64_t i, int 
 }
 
 // Waves per SIMD the deformation pass is compiled for: three (at most 168
-// registers) for the JC-type models, whose update fits that; the GTN return
-// and the mixed-model variant need more.
-template <int DM>
+// registers) for the JC-type models with Johnson-Cook hardening and the
+// explicit return, whose update fits that, and for the mixed form with the
+// other flow laws (JC or no damage); the GTN return, the mixed-model variant
+// and the FP64 form with the other flow laws need more.
+template <typename R, int DM, bool kFlow>
 __host__ __device__ constexpr int pass_a_waves_min() {
-    return DM >= 0 && DM <= 2 ? 3 : 1;
+    return DM >= 0 && DM <= 2 && (!kFlow || (sizeof(R) == 4 && DM != 1)) ? 3 : 1;
 }
 
 // Specimen parameters are read with scalar loads: the lanes of a wave take
 // turns by specimen, one turn unless the wave straddles two specimens.
-template <typename R, int DM>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pass_a_waves_min<DM>(), 8)))
+template <typename R, int DM, bool kFlow>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pass_a_waves_min<R, DM, kFlow>(), 8)))
 k_pass_a(DevState s, int par) {
     const int64_t i = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= s.n) return;
@@ -1208,7 +1210,7 @@ k_pass_a(DevState s, int par) {
                                const D4 x = XV[j], v = VW[j];
                                return NbrA{x.x, x.y, x.z, v.x, v.y, v.z, v.w};
                            }, M);
-            pass_a_update<R, DM>(s, i, sp, M);
+            pass_a_update<R, DM, kFlow>(s, i, sp, M);
             break;
         }
     }
@@ -1219,8 +1221,8 @@ k_pass_a(DevState s, int par) {
 // the neighbour sums read them through the 16-bit local slots.  Same
 // arithmetic in the same order as k_pass_a.
 constexpr int kLdsABytes = 56;
-template <typename R, int DM>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pass_a_waves_min<DM>(), 8)))
+template <typename R, int DM, bool kFlow>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pass_a_waves_min<R, DM, kFlow>(), 8)))
 k_pass_a_staged(DevState s, int par) {
     extern __shared__ __align__(16) unsigned char lds_a[];
     const int M = s.lds_slots;
@@ -1286,7 +1288,7 @@ k_pass_a_staged(DevState s, int par) {
                                const double2 a = Lxy[m], b = Lzw[m], c = Lvxy[m];
                                return NbrA{a.x, a.y, b.x, c.x, c.y, Lvz[m], b.y};
                            }, M9);
-            pass_a_update<R, DM>(s, i, sp, M9);
+            pass_a_update<R, DM, kFlow>(s, i, sp, M9);
             break;
         }
     }
@@ -1344,33 +1346,43 @@ hipError_t prepare_staged(size_t lds_bytes_b) {
     return hipSuccess;
 }
 
-template <int DM>
+template <int DM, bool kFlow>
 static void launch_a(const DevState& s, int parity, unsigned grid, int block, bool mixed,
                      hipStream_t st) {
     if (block == 0) {   // staged over the force pass's tiles
         const unsigned tiles = (unsigned)((s.n + s.tile - 1) / s.tile);
         const size_t lds = (size_t)s.lds_slots * kLdsABytes;
         if (mixed)
-            k_pass_a_staged<float, DM><<<tiles, s.tile, lds, st>>>(s, parity);
+            k_pass_a_staged<float, DM, kFlow><<<tiles, s.tile, lds, st>>>(s, parity);
         else
-            k_pass_a_staged<double, DM><<<tiles, s.tile, lds, st>>>(s, parity);
+            k_pass_a_staged<double, DM, kFlow><<<tiles, s.tile, lds, st>>>(s, parity);
         return;
     }
     if (mixed)
-        k_pass_a<float, DM><<<grid, block, 0, st>>>(s, parity);
+        k_pass_a<float, DM, kFlow><<<grid, block, 0, st>>>(s, parity);
     else
-        k_pass_a<double, DM><<<grid, block, 0, st>>>(s, parity);
+        k_pass_a<double, DM, kFlow><<<grid, block, 0, st>>>(s, parity);
 }
 
 hipError_t launch_pass_a(const DevState& s, int parity, int block, bool mixed, hipStream_t st) {
     if (block == 0 && (!s.staged_lds_a || s.tile > 256)) return hipErrorInvalidValue;
     const unsigned grid = block > 0 ? (unsigned)((s.n + block - 1) / block) : 0u;
-    switch (s.model) {
-        case 0: launch_a<0>(s, parity, grid, block, mixed, st); break;
-        case 1: launch_a<1>(s, parity, grid, block, mixed, st); break;
-        case 2: launch_a<2>(s, parity, grid, block, mixed, st); break;
-        case 3: launch_a<3>(s, parity, grid, block, mixed, st); break;
-        default: launch_a<-1>(s, parity, grid, block, mixed, st); break;
+    if (s.flow_general) {
+        switch (s.model) {
+            case 0: launch_a<0, true>(s, parity, grid, block, mixed, st); break;
+            case 1: launch_a<1, true>(s, parity, grid, block, mixed, st); break;
+            case 2: launch_a<2, true>(s, parity, grid, block, mixed, st); break;
+            case 3: launch_a<3, true>(s, parity, grid, block, mixed, st); break;
+            default: launch_a<-1, true>(s, parity, grid, block, mixed, st); break;
+        }
+    } else {
+        switch (s.model) {
+            case 0: launch_a<0, false>(s, parity, grid, block, mixed, st); break;
+            case 1: launch_a<1, false>(s, parity, grid, block, mixed, st); break;
+            case 2: launch_a<2, false>(s, parity, grid, block, mixed, st); break;
+            case 3: launch_a<3, false>(s, parity, grid, block, mixed, st); break;
+            default: launch_a<-1, false>(s, parity, grid, block, mixed, st); break;
+        }
     }
     return hipGetLastError();
 }

@@ -190,10 +190,10 @@ __host__ __device__ __forceinline__ double jc_hardening(const DevSpec& P, double
 
 // Strain-hardening factor h(eps) of the flow stress for the laws Sec. 4
 // names: Johnson-Cook A + B eps^n, linear A + B eps, Swift B (e0 + eps)^n,
-// Voce A + B (1 - exp(-beta eps)).  kGen = false compiles Johnson-Cook only.
-template <bool kGen>
+// Voce A + B (1 - exp(-beta eps)).  kFlow = false compiles Johnson-Cook only.
+template <bool kFlow>
 __host__ __device__ __forceinline__ double hardening(const DevSpec& P, double eps) {
-    if constexpr (kGen) {
+    if constexpr (kFlow) {
         switch (P.flow) {
             case 1: return P.A + P.B * eps;
             case 2: return P.B * pow_el(P.flow_e0 + eps, P.n);
@@ -205,9 +205,9 @@ __host__ __device__ __forceinline__ double hardening(const DevSpec& P, double ep
 }
 
 // dh/deps (the Johnson-Cook slope taken as 0 at eps = 0)
-template <bool kGen>
+template <bool kFlow>
 __host__ __device__ __forceinline__ double hardening_slope(const DevSpec& P, double eps) {
-    if constexpr (kGen) {
+    if constexpr (kFlow) {
         switch (P.flow) {
             case 1: return P.B;
             case 2: return P.B * P.n * pow_el(P.flow_e0 + eps, P.n - 1.0);
@@ -216,6 +216,41 @@ __host__ __device__ __forceinline__ double hardening_slope(const DevSpec& P, dou
         }
     }
     return eps > 0.0 ? P.B * P.n * pow_el(eps, P.n - 1.0) : 0.0;
+}
+
+// h(eps) and dh/deps together, each law's transcendental evaluated once
+// (the Johnson-Cook slope taken as 0 at eps = 0)
+__host__ __device__ __forceinline__ void hardening_and_slope(const DevSpec& P, double eps,
+                                                             double& h, double& hp) {
+    switch (P.flow) {
+        case 1:
+            h = P.A + P.B * eps;
+            hp = P.B;
+            return;
+        case 2: {
+            const double x = P.flow_e0 + eps, b = P.B * pow_el(x, P.n);
+            h = b;
+            hp = P.n * b * rcp_nr(x);
+            return;
+        }
+        case 3: {
+            const double em1 = expm1(-P.flow_beta * eps);
+            h = P.A - P.B * em1;
+            hp = P.B * P.flow_beta * (em1 + 1.0);
+            return;
+        }
+        default: {
+            if (eps > 0.0) {
+                const double b = P.B * pow_el(eps, P.n);
+                h = P.A + b;
+                hp = P.n * b * rcp_nr(eps);
+            } else {
+                h = P.A;
+                hp = 0.0;
+            }
+            return;
+        }
+    }
 }
 
 // Algorithm 1 with the flow stress at the end of the step: the plastic
@@ -230,13 +265,15 @@ __host__ __device__ inline double implicit_increment(const DevSpec& P, double k3
     double lo = 0.0, hi = d_max, d = d_max;
     for (int it = 0; it < 100; ++it) {
         const double rs = d * P.inv_dt * P.inv_eps_dot0;
-        const double rf = rs > 1.0 ? 1.0 + P.C * log(rs) : 1.0;
-        const double h = hardening<true>(P, eps + d);
+        const bool fast = rs > 1.0 && P.C != 0.0;
+        const double rf = fast ? 1.0 + P.C * log(rs) : 1.0;
+        double h, hp;
+        hardening_and_slope(P, eps + d, h, hp);
         const double g = seq - k3 * d - omD * h * rf;
         if (g > 0.0) lo = d; else hi = d;
-        const double drf = rs > 1.0 ? P.C / d : 0.0;
-        const double dg = -k3 - omD * (hardening_slope<true>(P, eps + d) * rf + h * drf);
-        double nd = d - g / dg;
+        const double drf = fast ? P.C * rcp_nr(d) : 0.0;
+        const double dg = -k3 - omD * (hp * rf + h * drf);
+        double nd = d - g * rcp_nr(dg);
         if (!(nd > lo && nd < hi)) nd = 0.5 * (lo + hi);
         const double step = fabs(nd - d);
         d = nd;
@@ -277,13 +314,13 @@ __host__ __device__ __forceinline__ double gtn_D(const DevSpec& P, double f) {
 // GTN return mapping (Algorithm 2), double precision.  In: trial deviator
 // (Voigt) and trial mean stress, state (eps_M, its last rate, f), damage D.
 // Out: returned deviator and mean stress, updated eps_M, rate, f.
-template <bool kGen>
+template <bool kFlow>
 __host__ __device__ inline void gtn_return(const DevSpec& P, double D, double dt, const double sdt[6],
                                   double smt, double& epsM, double& rate, double& f,
                                   double sd[6], double& sm, int32_t& flags) {
     const double seq = mises_voigt(sdt);
     const double rf = jc_rate_factor(P, rate);
-    const double sM0 = hardening<kGen>(P, epsM) * rf;
+    const double sM0 = hardening<kFlow>(P, epsM) * rf;
     const double fs = gtn_fstar(P, f);
     const double q1 = P.q1, q2 = P.q2, q3 = P.q3;
     bool plastic = false;
@@ -320,8 +357,8 @@ __host__ __device__ inline void gtn_return(const DevSpec& P, double D, double dt
     double dem = c * (seq - x * sM0);
     for (it = 0; it < 50; ++it) {
         const double e1 = epsM + dem;
-        const double hard = hardening_slope<kGen>(P, e1) * rf;
-        const double sf = hardening<kGen>(P, e1) * rf;
+        const double hard = hardening_slope<kFlow>(P, e1) * rf;
+        const double sf = hardening<kFlow>(P, e1) * rf;
         const double g = dem - c * (seq - x * sf);
         double nx = dem - g / (1.0 + c * x * hard);
         if (nx < 0.0) nx = 0.5 * dem;
@@ -331,7 +368,7 @@ __host__ __device__ inline void gtn_return(const DevSpec& P, double D, double dt
     }
     if (it == 50) flags |= kErrNewton;
     epsM += dem;
-    const double sM = hardening<kGen>(P, epsM) * rf;
+    const double sM = hardening<kFlow>(P, epsM) * rf;
     const double sy = x * sM;
     const double scale = sy / seq;
 #pragma unroll
@@ -373,16 +410,16 @@ struct PointOut {
 // failed particles stress free, energy by the trapezoid rule on P,
 // P = J sigma F^-T.
 // DM >= 0 fixes the damage model at compile time (the other models' code is
-// dropped); DM = -1 reads it from the specimen.
-template <typename R, int DM = -1>
+// dropped); DM = -1 reads it from the specimen.  kFlow = false compiles the
+// Johnson-Cook law with Algorithm 1's explicit hardening only; true reads the
+// law and the return from the specimen.
+template <typename R, int DM = -1, bool kFlow = true>
 __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R Hn[9], const R Fd[9],
                                              const R sn[6], double& eps, double& rate,
                                              double& dinit, double& wp, double& fv, double& e,
                                              double D, PointOut<R>& o, int32_t& flags) {
     const int model = DM >= 0 ? DM : P.damage;
-    // the general variant (DM < 0) also runs the other hardening laws and the
-    // implicit return
-    constexpr bool kGen = DM < 0;
+    // kFlow: the other hardening laws and the implicit return are compiled in
     const R dt = R(P.dt);
 #pragma unroll
     for (int k = 0; k < 9; ++k) o.H[k] = Hn[k] + dt * Fd[k];
@@ -462,7 +499,7 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
 #pragma unroll
         for (int k = 0; k < 6; ++k) sdt[k] = double(sdr[k] + R(2) * G * omD * de[k]);
         const double smt = double(mean_stress<R>(P, Jm1, R(D), R(e), false));
-        gtn_return<kGen>(P, D, P.dt, sdt, smt, eps, rate, fv, sdo, smo, flags);
+        gtn_return<kFlow>(P, D, P.dt, sdt, smt, eps, rate, fv, sdo, smo, flags);
 #pragma unroll
         for (int k = 0; k < 6; ++k) sd[k] = R(sdo[k]);
         sm = R(smo);
@@ -475,8 +512,8 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
         // elastic if sigma_eq < sigma_f, decided on the squares (no root)
         const R q2 = R(1.5) * (st[0] * st[0] + st[1] * st[1] + st[2] * st[2] +
                                R(2) * (st[3] * st[3] + st[4] * st[4] + st[5] * st[5]));
-        const bool impl = kGen && P.implicit_return;
-        const double h0 = hardening<kGen>(P, eps);
+        const bool impl = kFlow && P.implicit_return;
+        const double h0 = hardening<kFlow>(P, eps);
         const R sf = R(h0 * (impl ? 1.0 : jc_rate_factor(P, rate))) * omD;
         R dep = R(0);
         double depd = 0.0;
