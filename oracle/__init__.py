@@ -45,7 +45,7 @@ class Material(C.Structure):
                                           "k_omega", "h", "dt", "hg_alpha")] + \
                [("has_wall", C.c_int32), ("wall_n", C.c_double * 3), ("wall_d", C.c_double),
                 ("flow", C.c_int32), ("implicit_return", C.c_int32), ("flow_e0", C.c_double),
-                ("flow_beta", C.c_double)]
+                ("flow_beta", C.c_double), ("av_q1", C.c_double), ("av_q2", C.c_double)]
 
 
 class BC(C.Structure):
@@ -66,7 +66,7 @@ class ProblemC(C.Structure):
 
 
 STATE_FIELDS = ("t", "u", "v", "F", "sig", "eps_p", "eps_p_rate", "d_init", "w_p",
-                "f_void", "D", "e", "Q", "force")
+                "f_void", "D", "e", "Q", "force", "fvisc")
 
 
 class StateC(C.Structure):
@@ -279,7 +279,7 @@ class Sim:
         if bad >= 0:
             raise OracleError(f"singular correction matrix at particle {bad}")
         shapes = dict(t=(prob.n_spec,), u=(n, 3), v=(n, 3), F=(n, 9), sig=(n, 6), Q=(n, 9),
-                      force=(n, 3))
+                      force=(n, 3), fvisc=(n, 3))
         self.state = {k: np.zeros(shapes.get(k, (n,))) for k in STATE_FIELDS}
         self.sc = StateC(*[_p(self.state[k]) for k in STATE_FIELDS])
         vi = np.ascontiguousarray(prob.v_init if v_init is None else v_init, np.float64)

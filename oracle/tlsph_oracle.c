@@ -720,6 +720,7 @@ void orc_init_state(const orc_problem *p, const double *v_init, orc_state *s) {
             s->u[3 * i + a] = 0.0;
             s->v[3 * i + a] = v_init ? v_init[3 * i + a] : 0.0;
             s->force[3 * i + a] = 0.0;
+            s->fvisc[3 * i + a] = 0.0;
         }
         for (int k = 0; k < 9; ++k) {
             s->F[9 * i + k] = (k % 4 == 0) ? 1.0 : 0.0;
@@ -783,7 +784,7 @@ void orc_step(const orc_problem *p, orc_state *s) {
                           (r0 * r0);
             for (int a = 0; a < 3; ++a) fhg[a] += coef * xij[a] / r;
         }
-        for (int a = 0; a < 3; ++a) s->force[3 * i + a] = fi[a] + fhg[a];
+        for (int a = 0; a < 3; ++a) s->force[3 * i + a] = fi[a] + fhg[a] + s->fvisc[3 * i + a];
     }
 
     /* 2-3. kick, prescribed velocities, failed particles at rest, drift,   */
@@ -825,12 +826,21 @@ void orc_step(const orc_problem *p, orc_state *s) {
 
     /* 4. eq. Crack_approx_Fdot: dF/dt = sum_j V_j (1 - D_j)(v_j - v_i)     */
     /*    (x) gradW_i(X_ij) L_i^-1, with D at level n.                      */
+    /*    With it, the artificial particle-velocity damping Sec. 2 says     */
+    /*    TLSPH needs against rank deficiency (no formula given).  Reading: */
+    /*    the Monaghan viscosity on the reference pair geometry,            */
+    /*      mu_ij = h (v_ij . X_ij) / (|X_ij|^2 + 0.01 h^2),                */
+    /*      Pi_ij = (-Q1 c0 mu_ij + Q2 mu_ij^2) / rho0 for v_ij . X_ij < 0  */
+    /*      (else 0),                                                       */
+    /*      f_i = sum_j m_i m_j (1 - D_i)(1 - D_j) Pi_ij gradW_ij,          */
+    /*    with v = v^{n+1/2} and D at level n, applied in the next kick.    */
     double *Fdot = (double *)malloc((size_t)n * 9 * sizeof(double));
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         const orc_material *m = &p->mat[p->spec[i]];
         const double *Li = &p->Linv[9 * i];
-        double Fd[9] = {0};
+        double Fd[9] = {0}, fv[3] = {0, 0, 0};
+        const int av = m->av_q1 != 0.0 || m->av_q2 != 0.0;
         for (int64_t t = p->row_ptr[i]; t < p->row_ptr[i + 1]; ++t) {
             int32_t j = p->col[t];
             double Xij[3], g[3], gh[3];
@@ -844,8 +854,23 @@ void orc_step(const orc_problem *p, orc_state *s) {
                 double dv = s->v[3 * j + a] - s->v[3 * i + a];
                 for (int b = 0; b < 3; ++b) Fd[3 * a + b] += wgt * dv * gh[b];
             }
+            if (av) {
+                double vx = 0.0, r2 = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    vx += (s->v[3 * j + a] - s->v[3 * i + a]) * Xij[a];
+                    r2 += Xij[a] * Xij[a];
+                }
+                if (vx < 0.0) {
+                    double mu = m->h * vx / (r2 + 0.01 * m->h * m->h);
+                    double Pi = (-m->av_q1 * m->c0 * mu + m->av_q2 * mu * mu) / m->rho0;
+                    double mm = m->rho0 * p->V0[i] * m->rho0 * p->V0[j] *
+                                (1.0 - s->D[i]) * (1.0 - s->D[j]);
+                    for (int a = 0; a < 3; ++a) fv[a] += mm * Pi * g[a];
+                }
+            }
         }
         memcpy(&Fdot[9 * i], Fd, sizeof Fd);
+        for (int a = 0; a < 3; ++a) s->fvisc[3 * i + a] = fv[a];
     }
 
     /* 5-13. constitutive update, Q_i = P_i L_i^-T */

@@ -43,6 +43,7 @@ typedef struct {
     int32_t flow;                              /* ORC_FLOW_* */
     int32_t implicit_return;                   /* 1: hardening at the end of the step */
     double flow_e0, flow_beta;                 /* Swift offset strain, Voce rate */
+    double av_q1, av_q2;                       /* artificial viscosity (0: off) */
 } orc_material;
 
 /* Prescribed-velocity group: component c (bit c of mask) is set to
@@ -76,7 +77,10 @@ typedef struct {
     double *d_init, *w_p;       /* [n] damage initiation, CL plastic work   */
     double *f_void, *D, *e;     /* [n] void fraction, damage, energy/mass   */
     double *Q;                  /* [n][9] P L^-T                            */
-    double *force;              /* [n][3] internal + hourglass force        */
+    double *force;              /* [n][3] internal + hourglass (+ viscous)  */
+    double *fvisc;              /* [n][3] artificial viscous force, computed */
+                                /* from v^{n+1/2} and applied in the next   */
+                                /* step's kick                              */
 } orc_state;
 
 /* One material point, for the constitutive pieces on their own. */

@@ -15,7 +15,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "tlsph_oracle.c")
 PINS = ["tests/test_oracle_kernel_neighbors.py", "tests/test_oracle_constitutive.py",
-        "tests/test_oracle_flow.py", "tests/test_oracle_system.py"]
+        "tests/test_oracle_flow.py", "tests/test_oracle_viscosity.py",
+        "tests/test_oracle_system.py"]
 
 # (name, text in the oracle, planted replacement)
 MUTANTS = [
@@ -58,6 +59,15 @@ MUTANTS = [
      "double g = seq_tr - k3 * d - omD * h * rf;", "double g = seq_tr - k3 * d - h * rf;"),
     ("implicit return with the rate of the step's start", "double rate = d / dt;",
      "double rate = 0.0 * d / dt;"),
+    ("viscosity on separating pairs", "if (vx < 0.0) {", "if (vx > 0.0) {"),
+    ("viscosity quadratic term linear", "m->av_q2 * mu * mu) / m->rho0;",
+     "m->av_q2 * mu) / m->rho0;"),
+    ("viscosity applied with the wrong sign",
+     "for (int a = 0; a < 3; ++a) fv[a] += mm * Pi * g[a];",
+     "for (int a = 0; a < 3; ++a) fv[a] -= mm * Pi * g[a];"),
+    ("viscosity not in the next kick",
+     "s->force[3 * i + a] = fi[a] + fhg[a] + s->fvisc[3 * i + a];",
+     "s->force[3 * i + a] = fi[a] + fhg[a];"),
     ("energy from P^{n+1} only", "work += Fdot[k] * 0.5 * (Jn * Pn[k] + P[k]);",
      "work += Fdot[k] * P[k];"),
 ]
