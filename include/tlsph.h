@@ -111,6 +111,15 @@ typedef struct {
                                                  rate); no effect under GTN            */
     double flow_e0;                           /* Swift offset strain (> 0)          */
     double flow_beta;                         /* Voce saturation rate (>= 0)        */
+    double av_q1, av_q2;                      /* artificial particle-velocity damping
+                                                 (Sec. 2; both 0: off): Monaghan
+                                                 viscosity on the reference pair
+                                                 geometry, mu = h v_ij.X_ij /
+                                                 (|X_ij|^2 + 0.01 h^2), Pi = (-av_q1 c0
+                                                 mu + av_q2 mu^2) / rho0 for approaching
+                                                 pairs, f_i = sum_j m_i m_j (1 - D_i)
+                                                 (1 - D_j) Pi gradW_ij, from v^{n+1/2},
+                                                 applied in the next kick            */
 } tlsph_specimen;
 
 /* Prescribed-velocity group.  At mid-step time t the velocity component c of
@@ -140,7 +149,8 @@ typedef enum {
     TLSPH_F_FORCE = 12,     /* 3  nodal force of the last step (get only)          */
     TLSPH_F_Q = 13,         /* 9  Q = P L^-T used by the next force evaluation     */
     TLSPH_F_TIME = 14,      /* n_spec time of each specimen (not per particle)     */
-    TLSPH_F_LINV = 15       /* 9  inverse correction matrix (get only)             */
+    TLSPH_F_LINV = 15,      /* 9  inverse correction matrix (get only)             */
+    TLSPH_F_VISC = 16       /* 3  artificial viscous force for the next kick        */
 } tlsph_field;
 
 #define TLSPH_N_DIAG 8

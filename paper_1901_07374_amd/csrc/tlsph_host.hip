@@ -37,7 +37,7 @@ struct Layout {
     size_t XV, spec, bc, perm, iperm, nnb, slice_ptr, col, lcol, halo, halo_cnt, Linv, Linv32,
         specs, bcs, t;
     int64_t n_tiles;
-    size_t GQ, GH, U0, U1, VW, sig, eps_p, eps_rate, d_init, w_p, f_void, e, D, force, err,
+    size_t GQ, GH, U0, U1, VW, sig, eps_p, eps_rate, d_init, w_p, f_void, e, D, force, fvisc, err,
         spec_off, bbox, keys, vals, bc_list, bc_ptr, diag_seg, diag_part, backup;
     int64_t diag_chunk_cap;
     size_t state_begin, backup_bytes;
@@ -96,6 +96,7 @@ Layout make_layout(int64_t n, int32_t n_spec, int32_t n_bc, int32_t k_cap, bool 
     L.e = take(np * 8);
     L.D = take(np * 8);
     L.force = take(3 * np * 8);
+    L.fvisc = take(3 * np * 8);
     L.backup_bytes = align_up(cur) - L.state_begin;
     L.err = take(8 * 4);
     L.spec_off = take(((size_t)n_spec + 1) * 8);
@@ -219,6 +220,7 @@ void wire_state(tlsph_ctx* c) {
     s.e = at<double>(c, L.e);
     s.D = at<double>(c, L.D);
     s.force = at<double>(c, L.force);
+    s.fvisc = at<double>(c, L.fvisc);
     s.err = at<int32_t>(c, L.err);
 }
 
@@ -334,7 +336,8 @@ tlsph_status set_tile(tlsph_ctx* c, int T, hipStream_t stream) {
 
 int field_comps(int f, int32_t n_spec) {
     switch (f) {
-        case TLSPH_F_X: case TLSPH_F_U: case TLSPH_F_V: case TLSPH_F_FORCE: return 3;
+        case TLSPH_F_X: case TLSPH_F_U: case TLSPH_F_V: case TLSPH_F_FORCE: case TLSPH_F_VISC:
+            return 3;
         case TLSPH_F_DEFGRAD: case TLSPH_F_Q: case TLSPH_F_LINV: return 9;
         case TLSPH_F_SIGMA: return 6;
         case TLSPH_F_TIME: return -n_spec;
@@ -399,7 +402,8 @@ tlsph_status tlsph_create(int64_t n, int32_t n_spec, const int64_t* spec_offsets
         if (p.flow < TLSPH_FLOW_JC || p.flow > TLSPH_FLOW_VOCE ||
             (p.implicit_return != 0 && p.implicit_return != 1) ||
             (p.flow == TLSPH_FLOW_SWIFT && !finite_pos(p.flow_e0)) ||
-            (p.flow == TLSPH_FLOW_VOCE && !(p.flow_beta >= 0.0 && p.flow_beta <= 1e300)))
+            (p.flow == TLSPH_FLOW_VOCE && !(p.flow_beta >= 0.0 && p.flow_beta <= 1e300)) ||
+            !(p.av_q1 >= 0.0 && p.av_q1 <= 1e300) || !(p.av_q2 >= 0.0 && p.av_q2 <= 1e300))
             return TLSPH_E_INVALID_ARG;
         if (p.damage == TLSPH_DMG_GTN &&
             (!finite_pos(p.q1) || !finite_pos(p.sN) || !(p.fF > p.fc) || !(p.fc > 0.0)))
@@ -448,6 +452,8 @@ tlsph_status tlsph_create(int64_t n, int32_t n_spec, const int64_t* spec_offsets
         d.implicit_return = p.implicit_return;
         d.flow_e0 = p.flow_e0;
         d.flow_beta = p.flow_beta;
+        d.av_q1 = p.av_q1;
+        d.av_q2 = p.av_q2;
         d.first = spec_offsets[s];
         d.last = spec_offsets[s + 1];
     }
@@ -458,9 +464,12 @@ tlsph_status tlsph_create(int64_t n, int32_t n_spec, const int64_t* spec_offsets
     // with Johnson-Cook hardening and the explicit return only (or any law)
     c->st.model = spec[0].damage;
     c->st.flow_general = 0;
+    c->st.av = 0;
     for (int32_t q = 0; q < n_spec; ++q) {
         if (spec[q].damage != spec[0].damage) c->st.model = -1;
-        if (spec[q].flow != TLSPH_FLOW_JC || spec[q].implicit_return != 0) c->st.flow_general = 1;
+        if (spec[q].av_q1 != 0.0 || spec[q].av_q2 != 0.0) c->st.av = 1;
+        if (spec[q].flow != TLSPH_FLOW_JC || spec[q].implicit_return != 0 || c->st.av)
+            c->st.flow_general = 1;
     }
     const Layout& L = c->L;
     hipError_t e = hipMemcpyAsync(c->ws + L.specs, c->specs.data(), n_spec * sizeof(DevSpec),

@@ -327,7 +327,10 @@ __global__ void k_init(DevState s) {
     s.U[0][p] = D4{0.0, 0.0, 0.0, 0.0};
     s.U[1][p] = D4{0.0, 0.0, 0.0, 0.0};
     s.VW[p] = D4{0.0, 0.0, 0.0, s.XV[p].w * (1.0 - D0)};
-    for (int c = 0; c < 3; ++c) s.force[c * np + p] = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        s.force[c * np + p] = 0.0;
+        s.fvisc[c * np + p] = 0.0;
+    }
     if (s.GQ) {
         GQRec<double> g;
         GHRec<double> h;
@@ -770,9 +773,15 @@ __device__ __forceinline__ void force_finish(const DevState& s, int64_t i, int p
     const R ck = R(fin.grad_k);
     const R hgk = R(fin.hg_k) * omDi;
     const double Vi = fin.V;
-    const double fv0 = double(ck * (ni.q[0] * A.a0 + ni.q[1] * A.a1 + ni.q[2] * A.a2 + omDi * A.b0) + hgk * A.g0);
-    const double fv1 = double(ck * (ni.q[3] * A.a0 + ni.q[4] * A.a1 + ni.q[5] * A.a2 + omDi * A.b1) + hgk * A.g1);
-    const double fv2 = double(ck * (ni.q[6] * A.a0 + ni.q[7] * A.a1 + ni.q[8] * A.a2 + omDi * A.b2) + hgk * A.g2);
+    double fv0 = double(ck * (ni.q[0] * A.a0 + ni.q[1] * A.a1 + ni.q[2] * A.a2 + omDi * A.b0) + hgk * A.g0);
+    double fv1 = double(ck * (ni.q[3] * A.a0 + ni.q[4] * A.a1 + ni.q[5] * A.a2 + omDi * A.b1) + hgk * A.g1);
+    double fv2 = double(ck * (ni.q[6] * A.a0 + ni.q[7] * A.a1 + ni.q[8] * A.a2 + omDi * A.b2) + hgk * A.g2);
+    if (s.av) {   // the artificial viscous force of the last deformation pass
+        const double iv = rcp_nr(Vi);
+        fv0 += s.fvisc[i] * iv;
+        fv1 += s.fvisc[np + i] * iv;
+        fv2 += s.fvisc[2 * np + i] * iv;
+    }
     const double dt = fin.dt;
     double v[3] = {fin.vx + fin.dt_rho0 * fv0, fin.vy + fin.dt_rho0 * fv1,
                    fin.vz + fin.dt_rho0 * fv2};
@@ -1032,11 +1041,27 @@ struct NbrA {
 // increasing order, in groups of kGatherA whose record loads are all issued
 // before their arithmetic (indices one group ahead).  The kernel slope enters without its
 // constant factor c / h (c = 8 / (pi h^3)), applied to the sum.
-template <typename R, typename IdxOf, typename RecOf>
+// Artificial viscosity of one specimen as the gather uses it: pair factor
+// -Q1 c0 mu + Q2 mu^2 (Pi rho0) for approaching pairs, mu = h v_ij.X_ij /
+// (|X_ij|^2 + 0.01 h^2).
+template <typename R>
+struct AvPar {
+    R q1c0, q2, h, eh2;
+    bool on;
+};
+template <typename R>
+__device__ __forceinline__ AvPar<R> av_par(const DevSpec& P) {
+    return AvPar<R>{R(P.av_q1 * P.c0), R(P.av_q2), R(P.h), R(0.01 * P.h * P.h),
+                    P.av_q1 != 0.0 || P.av_q2 != 0.0};
+}
+
+template <typename R, bool kExt, typename IdxOf, typename RecOf>
 __device__ __forceinline__ void gather_fdot(const D4& xi, const D4& vi, int cnt, R inv_h, R grad_k,
-                                            IdxOf idx, RecOf rec, R M[9]) {
+                                            IdxOf idx, RecOf rec, R M[9], const AvPar<R>& av,
+                                            R AV[3]) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) M[q] = R(0);
+    AV[0] = AV[1] = AV[2] = R(0);
     constexpr int kGatherA = 4;
     // the next group's indices are loaded while this group is summed
     int jn[kGatherA];
@@ -1074,16 +1099,33 @@ __device__ __forceinline__ void gather_fdot(const D4& xi, const D4& vi, int cnt,
             M[0] = fma(t0, gx, M[0]); M[1] = fma(t0, gy, M[1]); M[2] = fma(t0, gz, M[2]);
             M[3] = fma(t1, gx, M[3]); M[4] = fma(t1, gy, M[4]); M[5] = fma(t1, gz, M[5]);
             M[6] = fma(t2, gx, M[6]); M[7] = fma(t2, gy, M[7]); M[8] = fma(t2, gz, M[8]);
+            if constexpr (kExt) {
+                // sum_j (-Q1 c0 mu + Q2 mu^2) V_j (1 - D_j) gradW_ij over approaching pairs
+                if (av.on) {
+                    const R vx = fma(t0, dx, fma(t1, dy, t2 * dz));
+                    if (vx < R(0)) {
+                        const R mu = av.h * vx * rcp_nr(r2 + av.eh2);
+                        const R pi = mu * fma(av.q2, mu, -av.q1c0);
+                        AV[0] = fma(pi, gx, AV[0]);
+                        AV[1] = fma(pi, gy, AV[1]);
+                        AV[2] = fma(pi, gz, AV[2]);
+                    }
+                }
+            }
         }
     }
 #pragma unroll
     for (int q = 0; q < 9; ++q) M[q] *= grad_k;
+    if constexpr (kExt) {
+        AV[0] *= grad_k; AV[1] *= grad_k; AV[2] *= grad_k;
+    }
 }
 
 // The rest of the deformation pass for particle i (specimen sp) given M:
 // dF/dt = M L_i^-1, the constitutive update, Q_i = P_i L_i^-T, stores.
 template <typename R, int DM, bool kFlow>
-__device__ __forceinline__ void pass_a_update(const DevState& s, int64_t i, int sp, const R M[9]) {
+__device__ __forceinline__ void pass_a_update(const DevState& s, int64_t i, int sp, const R M[9],
+                                              double wi, const R AV[3]) {
     const int64_t np = s.np;
     const DevSpec& P = s.specs[sp];
     R Li[9];
@@ -1165,6 +1207,16 @@ __device__ __forceinline__ void pass_a_update(const DevState& s, int64_t i, int 
         if (model == 3) s.f_void[is] = fv;
     }
     s.D[is] = o.D;
+    if constexpr (kFlow) {
+        // artificial viscous force for the next kick: rho0 V_i (1 - D_i) times
+        // the gathered sum (w_i = V_i (1 - D_i^n))
+        if (s.av) {
+            const double k = P.rho0 * wi;
+            s.fvisc[is] = k * double(AV[0]);
+            s.fvisc[np + is] = k * double(AV[1]);
+            s.fvisc[2 * np + is] = k * double(AV[2]);
+        }
+    }
     if (i == P.first) s.t[sp] += P.dt;
     if (flags || (s.flags & kFlagCheckFinite)) {
         int32_t fl = flags;
@@ -1203,14 +1255,15 @@ k_pass_a(DevState s, int par) {
             const D4* __restrict__ XV = s.XV;
             const D4* __restrict__ VW = s.VW;
             const int32_t* __restrict__ cp = s.col + s.slice_ptr[i / kSlice] + (i % kSlice);
-            R M[9];
-            gather_fdot<R>(XV[i], VW[i], s.nnb[i], R(P.inv_h), R(P.grad_k),
-                           [&](int k) { return (int)cp[(int64_t)k * kSlice]; },
-                           [&](int j) {
-                               const D4 x = XV[j], v = VW[j];
-                               return NbrA{x.x, x.y, x.z, v.x, v.y, v.z, v.w};
-                           }, M);
-            pass_a_update<R, DM, kFlow>(s, i, sp, M);
+            R M[9], AV[3];
+            const D4 vi = VW[i];
+            gather_fdot<R, kFlow>(XV[i], vi, s.nnb[i], R(P.inv_h), R(P.grad_k),
+                                  [&](int k) { return (int)cp[(int64_t)k * kSlice]; },
+                                  [&](int j) {
+                                      const D4 x = XV[j], v = VW[j];
+                                      return NbrA{x.x, x.y, x.z, v.x, v.y, v.z, v.w};
+                                  }, M, av_par<R>(P), AV);
+            pass_a_update<R, DM, kFlow>(s, i, sp, M, vi.w, AV);
             break;
         }
     }
@@ -1281,14 +1334,15 @@ k_pass_a_staged(DevState s, int par) {
             const DevSpec& P = s.specs[sp];
             const int t = threadIdx.x;
             const double2 a = Lxy[t], b = Lzw[t], c = Lvxy[t];
-            R M9[9];
-            gather_fdot<R>(D4{a.x, a.y, b.x, 0.0}, D4{c.x, c.y, Lvz[t], 0.0}, cnt, R(P.inv_h),
-                           R(P.grad_k), [&](int k) { return (int)lp[(int64_t)k * kSlice]; },
-                           [&](int m) {
-                               const double2 a = Lxy[m], b = Lzw[m], c = Lvxy[m];
-                               return NbrA{a.x, a.y, b.x, c.x, c.y, Lvz[m], b.y};
-                           }, M9);
-            pass_a_update<R, DM, kFlow>(s, i, sp, M9);
+            R M9[9], AV[3];
+            gather_fdot<R, kFlow>(D4{a.x, a.y, b.x, 0.0}, D4{c.x, c.y, Lvz[t], b.y}, cnt,
+                                  R(P.inv_h), R(P.grad_k),
+                                  [&](int k) { return (int)lp[(int64_t)k * kSlice]; },
+                                  [&](int m) {
+                                      const double2 a = Lxy[m], b = Lzw[m], c = Lvxy[m];
+                                      return NbrA{a.x, a.y, b.x, c.x, c.y, Lvz[m], b.y};
+                                  }, M9, av_par<R>(P), AV);
+            pass_a_update<R, DM, kFlow>(s, i, sp, M9, b.y, AV);
             break;
         }
     }
@@ -1393,7 +1447,7 @@ hipError_t launch_pass_a(const DevState& s, int parity, int block, bool mixed, h
 
 enum Field {
     F_X = 0, F_U, F_V, F_DEFGRAD, F_SIGMA, F_EPS_P, F_EPS_P_RATE, F_D_INIT, F_W_P, F_VOID,
-    F_D, F_E_INT, F_FORCE, F_Q, F_TIME, F_LINV
+    F_D, F_E_INT, F_FORCE, F_Q, F_TIME, F_LINV, F_VISC
 };
 
 struct FieldRef {
@@ -1427,6 +1481,7 @@ __device__ __forceinline__ FieldRef field_ref(const DevState& s, int field, int 
         case F_E_INT: return {s.e, nullptr, 1, 0, np, 1};
         case F_FORCE: return {s.force, nullptr, 3, 0, np, 1};
         case F_LINV: return {s.Linv, nullptr, 9, 0, np, 1};
+        case F_VISC: return {s.fvisc, nullptr, 3, 0, np, 1};
         default: return {nullptr, nullptr, 0, 0, 0, 0};
     }
 }

@@ -8,10 +8,10 @@ import numpy as np
 
 FLOORS = {"u": 1e-12, "v": 1e-9, "F": 1e-9, "sig": 1.0, "Q": 1.0, "force": 1e-9,
           "eps_p": 1e-12, "eps_p_rate": 1e-6, "d_init": 1e-12, "w_p": 1.0, "f_void": 1e-12,
-          "D": 1e-12, "e": 1e-9, "t": 1e-12, "Linv": 1e-12}
+          "D": 1e-12, "e": 1e-9, "t": 1e-12, "Linv": 1e-12, "fvisc": 1e-12}
 
 STEP_FIELDS = ("u", "v", "F", "sig", "Q", "force", "eps_p", "eps_p_rate", "d_init", "w_p",
-               "f_void", "D", "e", "t")
+               "f_void", "D", "e", "t", "fvisc")
 
 
 def rel_err(name, got, ref):

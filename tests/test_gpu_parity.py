@@ -43,6 +43,8 @@ def no_bc(p, **over):
 SWIFT = dict(flow=I.FLOW_SWIFT, B=1100e6, n=0.2, flow_e0=0.002)
 VOCE = dict(flow=I.FLOW_VOCE, A=700e6, B=450e6, flow_beta=12.0)
 LINEAR = dict(flow=I.FLOW_LINEAR, B=2.0e9)
+# artificial particle-velocity damping
+AV = dict(av_q1=1.0, av_q2=2.0)
 
 
 def remat(p, *overs):
@@ -61,6 +63,8 @@ CASES = {
     "bar_jc_implicit": lambda: remat(I.notched_bar(dx=0.8e-3), dict(implicit_return=1)),
     "plate_gtn_voce": lambda: remat(I.holed_plate(dx=0.8e-3, W=30e-3, H=12e-3, T=2.4e-3,
                                                   hole_d=4e-3), VOCE),
+    "bar_av": lambda: remat(I.notched_bar(dx=0.8e-3), AV),
+    "taylor_wall_cl_av": lambda: remat(I.taylor_bar(dx=0.6e-3, R=2.5e-3, L=6e-3), AV),
     "batch3_laws": lambda: remat(I.subset(I.bar_batch(n_spec=3, lo=2000, hi=6000), [0, 1, 2]),
                                  dict(SWIFT, implicit_return=1), VOCE,
                                  dict(LINEAR, implicit_return=1)),
@@ -101,6 +105,8 @@ def consistent_gtn(orc, p, st, f_hi=0.248, seed=0):
 def injected_state(orc, p, seed):
     st = I.random_state(p, seed=seed)
     st["t"] = np.full(p.n_spec, 3.3e-6)
+    if any(m["av_q1"] or m["av_q2"] for m in p.materials):
+        st["fvisc"] = np.random.default_rng(seed + 1).uniform(-1e-3, 1e-3, (p.n, 3))
     if p.materials[0]["damage"] == I.DMG_GTN:
         consistent_gtn(orc, p, st, seed=seed)
     return st
@@ -166,11 +172,12 @@ def test_cube_trajectory_100_steps(tl, orc, precision):
     assert all(v <= tol for v in errs.values()), errs
 
 
-@pytest.mark.parametrize("law", ["swift_implicit", "voce_implicit", "jc_implicit", "linear"])
+@pytest.mark.parametrize("law", ["swift_implicit", "voce_implicit", "jc_implicit", "linear",
+                                 "jc_av"])
 def test_cube_trajectory_flow_laws(tl, orc, law):
     over = {"swift_implicit": dict(SWIFT, implicit_return=1),
             "voce_implicit": dict(VOCE, implicit_return=1),
-            "jc_implicit": dict(implicit_return=1), "linear": LINEAR}[law]
+            "jc_implicit": dict(implicit_return=1), "linear": LINEAR, "jc_av": AV}[law]
     # a faster cube (5 m/s ends) so that it yields within the run
     p = remat(I.cube(v=5.0), over)
     say("cube trajectory", law)
