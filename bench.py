@@ -380,8 +380,13 @@ def bench_single(args, torch, I, T, workload, prob, label, damage_name, result):
                     dict({"particles": prob.n, "neighbour_pairs": nnz, "damage": damage_name,
                           "precision": "fp64", "steps_total": args.warmup + args.steps,
                           "dt_s": prob.materials[0]["dt"]}, **shape_of(fp["info"])))
+    m0 = prob.materials[0]
+    if m0["av_q1"] or m0["av_q2"]:
+        out["config"]["artificial_viscosity"] = {"q1": m0["av_q1"], "q2": m0["av_q2"]}
     out["kernels"] = ktab
-    out["roofline"] = roofline_of(fp, damage, prob.n, workload)
+    out["roofline"] = roofline_of(fp, damage, prob.n, workload,
+                                  flow_general=bool(m0["flow"] != I.FLOW_JC or m0["implicit_return"]
+                                                    or m0["av_q1"] or m0["av_q2"]))
     res64 = result(fp)
     out["fp64_result"] = res64
     del fp["sim"]
@@ -406,6 +411,18 @@ def bench_taylor(args, torch, I, T):
     return bench_single(args, torch, I, T, "taylor_bar_1m", prob,
                         "Taylor bar on a rigid wall, CL damage", "cockcroft-latham",
                         lambda r: final_shape(r["sim"], prob))
+
+
+def bench_taylor_av(args, torch, I, T):
+    """The Taylor bar with the artificial particle-velocity damping on
+    (Q1 = 1, Q2 = 2): the general deformation-pass variant."""
+    p = I.taylor_bar()
+    mats = [dict(m, av_q1=1.0, av_q2=2.0) for m in p.materials]
+    prob = I.Problem(p.name, p.X, p.V0, p.spec_offsets, mats, p.bc_group, p.bc_groups,
+                     p.v_init, p.steps, p.dx)
+    return bench_single(args, torch, I, T, "taylor_bar_1m_av", prob,
+                        "Taylor bar on a rigid wall, CL damage, artificial viscosity",
+                        "cockcroft-latham", lambda r: final_shape(r["sim"], prob))
 
 
 def bench_plate(args, torch, I, T):
@@ -480,6 +497,7 @@ def bench_notched_bar_voce(args, torch, I, T):
 WORKLOADS = {"notched_bar_200k": (bench_notched_bar, 42000, 1000),
              "notched_bar_200k_voce_implicit": (bench_notched_bar_voce, 42000, 1000),
              "taylor_bar_1m": (bench_taylor, 4900, 100),
+             "taylor_bar_1m_av": (bench_taylor_av, 4900, 100),
              "gtn_plate_4m": (bench_plate, 1900, 100),
              "batch_256_bars": (bench_batch, 400, 50)}
 
