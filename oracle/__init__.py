@@ -45,7 +45,8 @@ class Material(C.Structure):
                                           "k_omega", "h", "dt", "hg_alpha")] + \
                [("has_wall", C.c_int32), ("wall_n", C.c_double * 3), ("wall_d", C.c_double),
                 ("flow", C.c_int32), ("implicit_return", C.c_int32), ("flow_e0", C.c_double),
-                ("flow_beta", C.c_double), ("av_q1", C.c_double), ("av_q2", C.c_double)]
+                ("flow_beta", C.c_double), ("av_q1", C.c_double), ("av_q2", C.c_double),
+                ("h_per_spacing", C.c_double)]
 
 
 class BC(C.Structure):
@@ -62,7 +63,7 @@ class ProblemC(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_spec", C.c_int32), ("spec", _ip),
                 ("mat", C.POINTER(Material)), ("X", _dp), ("V0", _dp), ("bc", _ip),
                 ("n_bc", C.c_int32), ("bcs", C.POINTER(BC)), ("row_ptr", _lp), ("col", _ip),
-                ("Linv", _dp)]
+                ("Linv", _dp), ("hs", _dp)]
 
 
 STATE_FIELDS = ("t", "u", "v", "F", "sig", "eps_p", "eps_p_rate", "d_init", "w_p",
@@ -95,8 +96,9 @@ def lib():
             build()
         L = C.CDLL(LIB_PATH)
         L.orc_kernel.argtypes = [C.c_double, C.c_double, _dp, _dp]
-        L.orc_build_neighbors.argtypes = [C.c_int64, _dp, _ip, C.POINTER(Material), _lp, _ip,
-                                          C.c_int64]
+        L.orc_support_radii.argtypes = [C.c_int64, _dp, _ip, C.POINTER(Material), _dp]
+        L.orc_build_neighbors.argtypes = [C.c_int64, _dp, _ip, C.POINTER(Material), _dp, _lp,
+                                          _ip, C.c_int64]
         L.orc_build_neighbors.restype = C.c_int64
         L.orc_shape_matrices.argtypes = [C.POINTER(ProblemC), _dp, _dp]
         L.orc_shape_matrices.restype = C.c_int64
@@ -236,16 +238,28 @@ class Point:
 # --------------------------------------------------------------------------
 # whole problem
 # --------------------------------------------------------------------------
-def neighbors(X: np.ndarray, spec: np.ndarray, materials) -> tuple:
+def support_radii(V0: np.ndarray, spec: np.ndarray, materials) -> np.ndarray:
+    V0 = np.ascontiguousarray(V0, np.float64)
+    spec = np.ascontiguousarray(spec, np.int32)
+    mats = (Material * len(materials))(*[material_struct(m) for m in materials])
+    hs = np.zeros(V0.shape[0])
+    lib().orc_support_radii(V0.shape[0], _p(V0), _p(spec, C.c_int32), mats, _p(hs))
+    return hs
+
+
+def neighbors(X: np.ndarray, spec: np.ndarray, materials, hs=None) -> tuple:
+    """Reference neighbour lists; hs: per-particle support radii (None: each
+    specimen's h)."""
     X = np.ascontiguousarray(X, np.float64)
     spec = np.ascontiguousarray(spec, np.int32)
     mats = (Material * len(materials))(*[material_struct(m) for m in materials])
+    hp = None if hs is None else _p(np.ascontiguousarray(hs, np.float64))
     n = X.shape[0]
     row_ptr = np.zeros(n + 1, np.int64)
-    nnz = lib().orc_build_neighbors(n, _p(X), _p(spec, C.c_int32), mats, _p(row_ptr, C.c_int64),
-                                    None, 0)
+    nnz = lib().orc_build_neighbors(n, _p(X), _p(spec, C.c_int32), mats, hp,
+                                    _p(row_ptr, C.c_int64), None, 0)
     col = np.zeros(max(nnz, 1), np.int32)
-    lib().orc_build_neighbors(n, _p(X), _p(spec, C.c_int32), mats, _p(row_ptr, C.c_int64),
+    lib().orc_build_neighbors(n, _p(X), _p(spec, C.c_int32), mats, hp, _p(row_ptr, C.c_int64),
                               _p(col, C.c_int32), nnz)
     return row_ptr, col[:nnz]
 
@@ -267,14 +281,16 @@ class Sim:
         self.mats = (Material * prob.n_spec)(*[material_struct(m) for m in prob.materials])
         nb = max(len(prob.bc_groups), 1)
         self.bcs = (BC * nb)(*[bc_struct(g) for g in prob.bc_groups])
-        self.row_ptr, self.col = neighbors(self.X, self.spec, prob.materials)
+        self.hs = support_radii(self.V0, self.spec, prob.materials)
+        self.row_ptr, self.col = neighbors(self.X, self.spec, prob.materials, self.hs)
         if self.col.size == 0:
             self.col = np.zeros(1, np.int32)
         self.L = np.zeros((n, 9))
         self.Linv = np.zeros((n, 9))
         self.pc = ProblemC(n, prob.n_spec, _p(self.spec, C.c_int32), self.mats, _p(self.X),
                            _p(self.V0), _p(self.bc, C.c_int32), len(prob.bc_groups), self.bcs,
-                           _p(self.row_ptr, C.c_int64), _p(self.col, C.c_int32), _p(self.Linv))
+                           _p(self.row_ptr, C.c_int64), _p(self.col, C.c_int32), _p(self.Linv),
+                           _p(self.hs))
         bad = lib().orc_shape_matrices(C.byref(self.pc), _p(self.L), _p(self.Linv))
         if bad >= 0:
             raise OracleError(f"singular correction matrix at particle {bad}")

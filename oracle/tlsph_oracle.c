@@ -126,8 +126,24 @@ static void kernel_gradient(const double Xij[3], double h, double gradW[3], doub
 /* Sec. 2 / Sec. 7: the neighbour set S_i is fixed in the reference          */
 /* configuration for the whole run.  Reading: S_i = {j != i in the same      */
 /* specimen with |X_j - X_i| < h}; r = h is excluded (W and W' vanish there).*/
-/* A uniform cell grid of edge h per specimen finds the candidates.          */
+/* Graded spacing (the paper's finest specimens refine towards the notch):  */
+/* reading, each particle has its own support h_i = k V_i^(1/3) and a pair   */
+/* uses h_ij = (h_i + h_j) / 2 for membership and for its kernel, so S_i is   */
+/* symmetric and gradW_ji = -gradW_ij.                                      */
+/* A uniform cell grid of edge max h per specimen finds the candidates.      */
 /* ------------------------------------------------------------------------ */
+void orc_support_radii(int64_t n, const double *V0, const int32_t *spec,
+                       const orc_material *mat, double *hs) {
+    for (int64_t i = 0; i < n; ++i) {
+        const orc_material *m = &mat[spec[i]];
+        hs[i] = m->h_per_spacing > 0.0 ? m->h_per_spacing * cbrt(V0[i]) : m->h;
+    }
+}
+
+/* support radius of the pair (i, j) */
+static double pair_h(const orc_problem *p, int64_t i, int64_t j) {
+    return p->hs ? 0.5 * (p->hs[i] + p->hs[j]) : p->mat[p->spec[i]].h;
+}
 static int cmp_i32(const void *a, const void *b) {
     int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
     return (x > y) - (x < y);
@@ -151,7 +167,7 @@ static int64_t cell_of(const cell_grid *g, const double x[3], double h, int64_t 
 }
 
 static int64_t neighbours_of(int64_t i, const double *X, const cell_grid *g, double h,
-                             int32_t *buf) {
+                             const double *hs, int32_t *buf) {
     int64_t c[3];
     cell_of(g, &X[3 * i], h, c);
     int64_t k = 0;
@@ -171,7 +187,12 @@ static int64_t neighbours_of(int64_t i, const double *X, const cell_grid *g, dou
                     double d1 = X[3 * j + 1] - X[3 * i + 1];
                     double d2 = X[3 * j + 2] - X[3 * i + 2];
                     double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-                    if (r2 < h2) {
+                    double lim = h2;
+                    if (hs) {
+                        double hij = 0.5 * (hs[i] + hs[j]);
+                        lim = hij * hij;
+                    }
+                    if (r2 < lim) {
                         if (buf) buf[k] = j;
                         ++k;
                     }
@@ -182,17 +203,24 @@ static int64_t neighbours_of(int64_t i, const double *X, const cell_grid *g, dou
 }
 
 int64_t orc_build_neighbors(int64_t n, const double *X, const int32_t *spec,
-                            const orc_material *mat, int64_t *row_ptr, int32_t *col,
-                            int64_t cap) {
+                            const orc_material *mat, const double *hs, int64_t *row_ptr,
+                            int32_t *col, int64_t cap) {
     int32_t n_spec = 0;
     for (int64_t i = 0; i < n; ++i)
         if (spec[i] + 1 > n_spec) n_spec = spec[i] + 1;
     int64_t *cnt = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
     cell_grid *grids = (cell_grid *)calloc((size_t)(n_spec > 0 ? n_spec : 1), sizeof(cell_grid));
-    /* one grid per specimen */
+    double *edge = (double *)calloc((size_t)(n_spec > 0 ? n_spec : 1), sizeof(double));
+    /* one grid per specimen, cells of edge max h_i */
     for (int32_t s = 0; s < n_spec; ++s) {
         cell_grid *g = &grids[s];
         double h = mat[s].h;
+        if (hs) {
+            h = 0.0;
+            for (int64_t i = 0; i < n; ++i)
+                if (spec[i] == s && hs[i] > h) h = hs[i];
+        }
+        edge[s] = h;
         double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
         int64_t ns = 0;
         for (int64_t i = 0; i < n; ++i) {
@@ -224,20 +252,21 @@ int64_t orc_build_neighbors(int64_t n, const double *X, const int32_t *spec,
     }
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i)
-        cnt[i] = neighbours_of(i, X, &grids[spec[i]], mat[spec[i]].h, NULL);
+        cnt[i] = neighbours_of(i, X, &grids[spec[i]], edge[spec[i]], hs, NULL);
     row_ptr[0] = 0;
     for (int64_t i = 0; i < n; ++i) row_ptr[i + 1] = row_ptr[i] + cnt[i];
     int64_t nnz = row_ptr[n];
     if (nnz <= cap && col) {
 #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i)
-            neighbours_of(i, X, &grids[spec[i]], mat[spec[i]].h, &col[row_ptr[i]]);
+            neighbours_of(i, X, &grids[spec[i]], edge[spec[i]], hs, &col[row_ptr[i]]);
     }
     for (int32_t s = 0; s < n_spec; ++s) {
         free(grids[s].start);
         free(grids[s].items);
     }
     free(grids);
+    free(edge);
     free(cnt);
     return nnz;
 }
@@ -251,13 +280,12 @@ int64_t orc_build_neighbors(int64_t n, const double *X, const int32_t *spec,
 int64_t orc_shape_matrices(const orc_problem *p, double *L, double *Linv) {
     int64_t bad = -1;
     for (int64_t i = 0; i < p->n; ++i) {
-        const orc_material *m = &p->mat[p->spec[i]];
         double Li[9] = {0};
         for (int64_t t = p->row_ptr[i]; t < p->row_ptr[i + 1]; ++t) {
             int32_t j = p->col[t];
             double Xij[3], g[3];
             for (int a = 0; a < 3; ++a) Xij[a] = p->X[3 * j + a] - p->X[3 * i + a];
-            kernel_gradient(Xij, m->h, g, NULL);
+            kernel_gradient(Xij, pair_h(p, i, j), g, NULL);
             for (int a = 0; a < 3; ++a)
                 for (int b = 0; b < 3; ++b) Li[3 * a + b] += p->V0[j] * Xij[a] * g[b];
         }
@@ -760,7 +788,7 @@ void orc_step(const orc_problem *p, orc_state *s) {
             double Dj = s->D[j], Vj = p->V0[j];
             double Xij[3], g[3], W;
             for (int a = 0; a < 3; ++a) Xij[a] = p->X[3 * j + a] - p->X[3 * i + a];
-            kernel_gradient(Xij, m->h, g, &W);
+            kernel_gradient(Xij, pair_h(p, i, j), g, &W);
             for (int a = 0; a < 3; ++a) {
                 double acc = 0.0;
                 for (int b = 0; b < 3; ++b)
@@ -844,8 +872,9 @@ void orc_step(const orc_problem *p, orc_state *s) {
         for (int64_t t = p->row_ptr[i]; t < p->row_ptr[i + 1]; ++t) {
             int32_t j = p->col[t];
             double Xij[3], g[3], gh[3];
+            const double hij = pair_h(p, i, j);
             for (int a = 0; a < 3; ++a) Xij[a] = p->X[3 * j + a] - p->X[3 * i + a];
-            kernel_gradient(Xij, m->h, g, NULL);
+            kernel_gradient(Xij, hij, g, NULL);
             /* corrected gradient: row vector gradW times L^-1 */
             for (int b = 0; b < 3; ++b)
                 gh[b] = g[0] * Li[0 * 3 + b] + g[1] * Li[1 * 3 + b] + g[2] * Li[2 * 3 + b];
@@ -861,7 +890,7 @@ void orc_step(const orc_problem *p, orc_state *s) {
                     r2 += Xij[a] * Xij[a];
                 }
                 if (vx < 0.0) {
-                    double mu = m->h * vx / (r2 + 0.01 * m->h * m->h);
+                    double mu = hij * vx / (r2 + 0.01 * hij * hij);
                     double Pi = (-m->av_q1 * m->c0 * mu + m->av_q2 * mu * mu) / m->rho0;
                     double mm = m->rho0 * p->V0[i] * m->rho0 * p->V0[j] *
                                 (1.0 - s->D[i]) * (1.0 - s->D[j]);

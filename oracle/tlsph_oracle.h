@@ -44,6 +44,9 @@ typedef struct {
     int32_t implicit_return;                   /* 1: hardening at the end of the step */
     double flow_e0, flow_beta;                 /* Swift offset strain, Voce rate */
     double av_q1, av_q2;                       /* artificial viscosity (0: off) */
+    double h_per_spacing;                      /* > 0: support h_i = this times   */
+                                               /* V_i^(1/3) per particle (graded  */
+                                               /* spacing); 0: h for all          */
 } orc_material;
 
 /* Prescribed-velocity group: component c (bit c of mask) is set to
@@ -66,6 +69,7 @@ typedef struct {
     const int64_t *row_ptr;     /* [n+1] neighbour list (ascending rows)    */
     const int32_t *col;         /* [nnz]                                    */
     const double *Linv;         /* [n][9] inverse correction matrices       */
+    const double *hs;           /* [n] support radius of each particle      */
 } orc_problem;
 
 typedef struct {
@@ -99,10 +103,15 @@ typedef struct {
 /* Cubic-spline kernel with compact support of radius h. */
 void orc_kernel(double r, double h, double *W, double *dWdr);
 
-/* Neighbour sets S_i = { j != i, same specimen, |X_j - X_i| < h }.
+/* Support radius of each particle: mat.h, or h_per_spacing V_i^(1/3). */
+void orc_support_radii(int64_t n, const double *V0, const int32_t *spec,
+                       const orc_material *mat, double *hs);
+
+/* Neighbour sets S_i = { j != i, same specimen, |X_j - X_i| < h_ij } with
+ * h_ij = (h_i + h_j) / 2 (hs; NULL: the specimen's h).
  * Rows ascending.  Returns nnz; if nnz > cap only row_ptr is written. */
 int64_t orc_build_neighbors(int64_t n, const double *X, const int32_t *spec,
-                            const orc_material *mat, int64_t *row_ptr,
+                            const orc_material *mat, const double *hs, int64_t *row_ptr,
                             int32_t *col, int64_t cap);
 
 /* Correction matrices L_i and their inverses.  Returns -1, or the index of

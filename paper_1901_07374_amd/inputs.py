@@ -35,7 +35,7 @@ MATERIAL_KEYS = (
     "damage", "Wcr", "D1", "D2", "D3", "D4", "D5",
     "q1", "q2", "q3", "f0", "fN", "eN", "sN", "fc", "fF", "k_omega",
     "h", "dt", "hg_alpha", "has_wall", "wall_n", "wall_d",
-    "flow", "implicit_return", "flow_e0", "flow_beta", "av_q1", "av_q2",
+    "flow", "implicit_return", "flow_e0", "flow_beta", "av_q1", "av_q2", "h_per_spacing",
 )
 
 # Steel used by every synthetic workload (rho, E, nu and the Johnson-Cook
@@ -61,7 +61,7 @@ def material(dx: float, damage: int = DMG_NONE, **over) -> Dict:
                   q1=1.0, q2=1.0, q3=1.0, f0=0.0, fN=0.0, eN=0.0, sN=1.0,
                   fc=1.0, fF=1.0, k_omega=0.0, hg_alpha=1.0, has_wall=0,
                   wall_n=(0.0, 0.0, 1.0), wall_d=0.0, flow=FLOW_JC, implicit_return=0,
-                  flow_e0=0.0, flow_beta=0.0, av_q1=0.0, av_q2=0.0))
+                  flow_e0=0.0, flow_beta=0.0, av_q1=0.0, av_q2=0.0, h_per_spacing=0.0))
     if damage == DMG_JC:
         m.update(JC_DAMAGE)
     if damage == DMG_GTN:
@@ -181,6 +181,60 @@ def notched_bar(dx: float = 0.25e-3, jitter: float = 0.03, v_max: float = 10.0,
     return Problem("notched_bar", X, np.full(n, dx ** 3), np.array([0, n], np.int64),
                    [material(dx, damage, **mat_over)], bc, groups, np.zeros((n, 3)),
                    steps=steps, dx=np.array([dx]))
+
+
+# ----------------------------------------------------------------------------
+# graded notched bar: a round bar with a semicircular notch (radius rho) at
+# mid-length, the particle spacing refined towards the notch plane in axial
+# zones (finest first); each zone is a cubic lattice of its own spacing, so
+# the lattices meet unconformingly at the zone boundaries.  V_i = dx^3 of the
+# particle's zone and the support radius is 1.75 times the local spacing.
+# ----------------------------------------------------------------------------
+def graded_notched_bar(R: float = 5e-3, L: float = 7e-3, rho: float = 0.4e-3,
+                       spacings=(0.1e-3, 0.2e-3, 0.4e-3, 0.8e-3),
+                       bounds=(0.5e-3, 1.5e-3, 2.5e-3), jitter: float = 0.03,
+                       v_max: float = 10.0, tau: float = 1e-3, damage: int = DMG_JC,
+                       seed: int = SEED_BASE + 6, steps: int = 2000, **mat_over) -> Problem:
+    """Zones |z| < bounds[0] at spacings[0], ..., the last up to L / 2; the
+    prescribed-velocity grips are the particles of the coarsest zone.  The
+    support is 1.75 times the local spacing: at 1.5 the particles next to a
+    zone boundary keep too few neighbours (down to four) for a stable
+    correction matrix."""
+    rng = np.random.default_rng(seed)
+    edges = [0.0, *bounds, L / 2]
+    pts, vol, zone = [], [], []
+    for q, dx in enumerate(spacings):
+        z0, z1 = edges[q], edges[q + 1]
+        nz = max(1, int(round((z1 - z0) / dx)))
+        nr = int(math.ceil(2 * R / dx))
+        i, j, k = _lattice(nr, nr, nz)
+        x = (i + 0.5) * dx - nr * dx / 2
+        y = (j + 0.5) * dx - nr * dx / 2
+        z = z0 + (k + 0.5) * (z1 - z0) / nz
+        r = np.sqrt(x * x + y * y)
+        for sgn in (1.0, -1.0):
+            zz = sgn * z
+            az = np.abs(zz)
+            rmax = np.where(az < rho, R - np.sqrt(np.maximum(rho * rho - az * az, 0.0)), R)
+            keep = r < rmax
+            lat = np.stack([x[keep], y[keep], zz[keep]], axis=1)
+            pts.append(_jitter(rng, lat, dx, jitter))
+            vol.append(np.full(lat.shape[0], dx ** 3))
+            zone.append(np.full(lat.shape[0], q))
+    X = np.concatenate(pts)
+    V0 = np.concatenate(vol)
+    zone = np.concatenate(zone)
+    n = X.shape[0]
+    bc = np.full(n, -1, np.int32)
+    last = len(spacings) - 1
+    bc[(zone == last) & (X[:, 2] < 0)] = 0
+    bc[(zone == last) & (X[:, 2] > 0)] = 1
+    groups = [bc_group(4, (0.0, 0.0, -v_max), tau), bc_group(4, (0.0, 0.0, v_max), tau)]
+    dxm = min(spacings)
+    m = material(dxm, damage, **dict(dict(h_per_spacing=1.75), **mat_over))
+    m["h"] = 1.5 * max(spacings)
+    return Problem("graded_notched_bar", X, V0, np.array([0, n], np.int64), [m], bc, groups,
+                   np.zeros((n, 3)), steps=steps, dx=np.array([dxm]))
 
 
 # ----------------------------------------------------------------------------

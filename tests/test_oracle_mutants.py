@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "tlsph_oracle.c")
 PINS = ["tests/test_oracle_kernel_neighbors.py", "tests/test_oracle_constitutive.py",
         "tests/test_oracle_flow.py", "tests/test_oracle_viscosity.py",
-        "tests/test_oracle_system.py"]
+        "tests/test_oracle_graded.py", "tests/test_oracle_system.py"]
 
 # (name, text in the oracle, planted replacement)
 MUTANTS = [
@@ -68,6 +68,11 @@ MUTANTS = [
     ("viscosity not in the next kick",
      "s->force[3 * i + a] = fi[a] + fhg[a] + s->fvisc[3 * i + a];",
      "s->force[3 * i + a] = fi[a] + fhg[a];"),
+    ("pair kernel with the particle's own support",
+     "return p->hs ? 0.5 * (p->hs[i] + p->hs[j]) : p->mat[p->spec[i]].h;",
+     "return p->hs ? p->hs[i] : p->mat[p->spec[i]].h;"),
+    ("neighbour rule with the larger support", "double hij = 0.5 * (hs[i] + hs[j]);",
+     "double hij = hs[i] > hs[j] ? hs[i] : hs[j];"),
     ("energy from P^{n+1} only", "work += Fdot[k] * 0.5 * (Jn * Pn[k] + P[k]);",
      "work += Fdot[k] * P[k];"),
 ]
