@@ -120,6 +120,11 @@ typedef struct {
                                                  pairs, f_i = sum_j m_i m_j (1 - D_i)
                                                  (1 - D_j) Pi gradW_ij, from v^{n+1/2},
                                                  applied in the next kick            */
+    double h_per_spacing;                     /* > 0: graded spacing, each particle's
+                                                 support h_i = h_per_spacing V_i^(1/3)
+                                                 and a pair's (h_i + h_j) / 2 (membership
+                                                 and kernel); the step then runs the
+                                                 unstaged kernels.  0: h for all     */
 } tlsph_specimen;
 
 /* Prescribed-velocity group.  At mid-step time t the velocity component c of

@@ -37,7 +37,7 @@ struct Layout {
     size_t XV, spec, bc, perm, iperm, nnb, slice_ptr, col, lcol, halo, halo_cnt, Linv, Linv32,
         specs, bcs, t;
     int64_t n_tiles;
-    size_t GQ, GH, U0, U1, VW, sig, eps_p, eps_rate, d_init, w_p, f_void, e, D, force, fvisc, err,
+    size_t GQ, GH, U0, U1, VW, sig, eps_p, eps_rate, d_init, w_p, f_void, e, D, force, fvisc, hs, err,
         spec_off, bbox, keys, vals, bc_list, bc_ptr, diag_seg, diag_part, backup;
     int64_t diag_chunk_cap;
     size_t state_begin, backup_bytes;
@@ -76,6 +76,7 @@ Layout make_layout(int64_t n, int32_t n_spec, int32_t n_bc, int32_t k_cap, bool 
     L.halo = take(((size_t)n + kTile) * k_cap * 4);
     L.halo_cnt = take((size_t)L.n_tiles * 4);
     L.Linv = take(9 * np * 8);
+    L.hs = take(np * 8);
     L.Linv32 = take(mixed ? 9 * np * 4 : 0);
     L.specs = take((size_t)n_spec * sizeof(DevSpec));
     L.bcs = take((size_t)(n_bc > 0 ? n_bc : 1) * sizeof(DevBC));
@@ -100,7 +101,7 @@ Layout make_layout(int64_t n, int32_t n_spec, int32_t n_bc, int32_t k_cap, bool 
     L.backup_bytes = align_up(cur) - L.state_begin;
     L.err = take(8 * 4);
     L.spec_off = take(((size_t)n_spec + 1) * 8);
-    L.bbox = take((size_t)n_spec * 6 * 8);
+    L.bbox = take((size_t)n_spec * 8 * 8);
     L.keys = take((size_t)L.n_pow2 * 8);
     L.vals = take((size_t)L.n_pow2 * 4);
     L.bc_list = take(np * 4);
@@ -221,6 +222,7 @@ void wire_state(tlsph_ctx* c) {
     s.D = at<double>(c, L.D);
     s.force = at<double>(c, L.force);
     s.fvisc = at<double>(c, L.fvisc);
+    s.hs = at<double>(c, L.hs);
     s.err = at<int32_t>(c, L.err);
 }
 
@@ -314,7 +316,9 @@ tlsph_status set_tile(tlsph_ctx* c, int T, hipStream_t stream) {
     c->st.halo_cap = T * L.k_cap;
     int E = 256;
     while (E < T * L.k_cap) E <<= 1;
-    if ((2 * (size_t)E + 257) * 4 > (size_t)c->max_lds || (c->flags & TLSPH_NO_STAGING))
+    // graded spacing runs the unstaged kernels (per-pair supports)
+    if ((2 * (size_t)E + 257) * 4 > (size_t)c->max_lds || (c->flags & TLSPH_NO_STAGING) ||
+        c->st.var_h)
         return TLSPH_OK;
     const int32_t zero = 0;
     HIPCHK(c, hipMemcpyAsync(c->ws + L.err + 16, &zero, 4, hipMemcpyHostToDevice, stream));
@@ -403,7 +407,8 @@ tlsph_status tlsph_create(int64_t n, int32_t n_spec, const int64_t* spec_offsets
             (p.implicit_return != 0 && p.implicit_return != 1) ||
             (p.flow == TLSPH_FLOW_SWIFT && !finite_pos(p.flow_e0)) ||
             (p.flow == TLSPH_FLOW_VOCE && !(p.flow_beta >= 0.0 && p.flow_beta <= 1e300)) ||
-            !(p.av_q1 >= 0.0 && p.av_q1 <= 1e300) || !(p.av_q2 >= 0.0 && p.av_q2 <= 1e300))
+            !(p.av_q1 >= 0.0 && p.av_q1 <= 1e300) || !(p.av_q2 >= 0.0 && p.av_q2 <= 1e300) ||
+            !(p.h_per_spacing >= 0.0 && p.h_per_spacing <= 1e300))
             return TLSPH_E_INVALID_ARG;
         if (p.damage == TLSPH_DMG_GTN &&
             (!finite_pos(p.q1) || !finite_pos(p.sN) || !(p.fF > p.fc) || !(p.fc > 0.0)))
@@ -454,6 +459,7 @@ tlsph_status tlsph_create(int64_t n, int32_t n_spec, const int64_t* spec_offsets
         d.flow_beta = p.flow_beta;
         d.av_q1 = p.av_q1;
         d.av_q2 = p.av_q2;
+        d.h_per_spacing = p.h_per_spacing;
         d.first = spec_offsets[s];
         d.last = spec_offsets[s + 1];
     }
@@ -465,7 +471,9 @@ tlsph_status tlsph_create(int64_t n, int32_t n_spec, const int64_t* spec_offsets
     c->st.model = spec[0].damage;
     c->st.flow_general = 0;
     c->st.av = 0;
+    c->st.var_h = 0;
     for (int32_t q = 0; q < n_spec; ++q) {
+        if (spec[q].h_per_spacing > 0.0) c->st.var_h = 1;
         if (spec[q].damage != spec[0].damage) c->st.model = -1;
         if (spec[q].av_q1 != 0.0 || spec[q].av_q2 != 0.0) c->st.av = 1;
         if (spec[q].flow != TLSPH_FLOW_JC || spec[q].implicit_return != 0 || c->st.av)
@@ -889,6 +897,8 @@ tlsph_status tlsph_set_launch_shape(tlsph_ctx* c, const int32_t shape[5], hipStr
                     "deformation-pass block must be 0 (staged), 64, 128, 192 or 256");
     if (staged && (tile < 64 || tile > kTile))
         return fail(c, TLSPH_E_INVALID_ARG, "tile must hold 64 to 256 particles");
+    if (c->st.var_h && (staged || blk_a == 0))
+        return fail(c, TLSPH_E_UNSUPPORTED, "graded spacing runs the unstaged kernels only");
     if (staged && tile > staged_tile_max(sub))
         return fail(c, TLSPH_E_UNSUPPORTED, "four lanes per particle run tiles of at most 128");
     if (staged) {

@@ -40,6 +40,7 @@ struct DevSpec {
     int32_t implicit_return;   // 1: flow stress at the step's end in Algorithm 1
     double flow_e0, flow_beta; // Swift offset strain, Voce saturation rate
     double av_q1, av_q2;       // artificial viscosity coefficients (0: off)
+    double h_per_spacing;      // > 0: per-particle support h_i = this V_i^(1/3)
     int64_t first, last;   // sorted-order particle range [first, last)
 };
 
@@ -111,6 +112,7 @@ struct DevState {
     double* D;
     double* force;           // SoA [3][np]
     double* fvisc;           // SoA [3][np] artificial viscous force for the next kick
+    double* hs;              // [np] support radius of each particle (build)
     int32_t* err;    // [0] first singular (sorted), [1] max count, [2] sticky flags,
                      // [3] build status, [4] largest tile halo
     // LDS staging: per tile of `tile` particles, the sorted outside neighbours
@@ -126,6 +128,7 @@ struct DevState {
     int32_t flow_general;     // 1 if a specimen uses another law than JC, the implicit
                               // return or the artificial viscosity
     int32_t av;               // 1 if a specimen uses the artificial viscosity
+    int32_t var_h;            // 1 if a specimen has graded spacing (per-particle support)
     int32_t tile;             // particles per tile of the staged force pass (<= kTile)
     int32_t staged_lds_a;     // 1 when the tile records of the deformation pass fit LDS
 };

@@ -30,32 +30,50 @@ __device__ __forceinline__ uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) 
     return m;
 }
 
-// per-specimen bounding box (caller order, particles contiguous per specimen)
-__global__ void k_bbox(const double* __restrict__ X, int64_t n, const int64_t* __restrict__ off,
+// Per-specimen record of 8 doubles (caller order, particles contiguous per
+// specimen): bounding box lo[3], hi[3], then 1 / cell edge.  The edge is the
+// specimen's h, or with graded spacing the largest support h_per_spacing
+// (max V0)^(1/3), each a hair larger so that pairs closer than the support
+// never sit two cells apart after rounding.
+constexpr int kBBox = 8;
+__global__ void k_bbox(const double* __restrict__ X, const double* __restrict__ V0, int64_t n,
+                       const int64_t* __restrict__ off, const DevSpec* __restrict__ specs,
                        double* __restrict__ bbox) {
-    __shared__ double red[6][256];
+    __shared__ double red[7][256];
     const int s = blockIdx.x;
-    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-    for (int64_t i = off[s] + threadIdx.x; i < off[s + 1]; i += blockDim.x)
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300}, vmax = 0.0;
+    for (int64_t i = off[s] + threadIdx.x; i < off[s + 1]; i += blockDim.x) {
         for (int c = 0; c < 3; ++c) {
             const double x = X[c * n + i];
             lo[c] = x < lo[c] ? x : lo[c];
             hi[c] = x > hi[c] ? x : hi[c];
         }
+        vmax = V0[i] > vmax ? V0[i] : vmax;
+    }
     for (int c = 0; c < 3; ++c) {
         red[c][threadIdx.x] = lo[c];
         red[3 + c][threadIdx.x] = hi[c];
     }
+    red[6][threadIdx.x] = vmax;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
+        if (threadIdx.x < w) {
             for (int c = 0; c < 3; ++c) {
                 red[c][threadIdx.x] = fmin(red[c][threadIdx.x], red[c][threadIdx.x + w]);
                 red[3 + c][threadIdx.x] = fmax(red[3 + c][threadIdx.x], red[3 + c][threadIdx.x + w]);
             }
+            red[6][threadIdx.x] = fmax(red[6][threadIdx.x], red[6][threadIdx.x + w]);
+        }
         __syncthreads();
     }
-    if (threadIdx.x < 6) bbox[6 * s + threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x < 6) bbox[kBBox * s + threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x == 6) {
+        const DevSpec& P = specs[s];
+        bbox[kBBox * s + 6] = P.h_per_spacing > 0.0
+                                  ? 1.0 / (P.h_per_spacing * cbrt(red[6][0]) * (1.0 + 1e-9))
+                                  : P.inv_cell;
+        bbox[kBBox * s + 7] = 0.0;
+    }
 }
 
 __device__ __forceinline__ int spec_of(const int64_t* off, int n_spec, int64_t i) {
@@ -67,11 +85,11 @@ __device__ __forceinline__ int spec_of(const int64_t* off, int n_spec, int64_t i
     return lo;
 }
 
-__device__ __forceinline__ void cell_of(const DevSpec& P, const double* bb, double x, double y,
-                                        double z, int32_t c[3]) {
+__device__ __forceinline__ void cell_of(const double* bb, double x, double y, double z,
+                                        int32_t c[3]) {
     const double xs[3] = {x, y, z};
     for (int a = 0; a < 3; ++a) {
-        const double q = floor((xs[a] - bb[a]) * P.inv_cell);
+        const double q = floor((xs[a] - bb[a]) * bb[6]);
         c[a] = q < 0.0 ? 0 : (int32_t)q;
     }
 }
@@ -89,7 +107,7 @@ __global__ void k_keys(const double* __restrict__ X, int64_t n, int64_t n_pow2,
     }
     const int s = spec_of(off, n_spec, i);
     int32_t c[3];
-    cell_of(specs[s], bbox + 6 * s, X[i], X[n + i], X[2 * n + i], c);
+    cell_of(bbox + kBBox * s, X[i], X[n + i], X[2 * n + i], c);
     if (c[0] >= (1 << kMortonBits) || c[1] >= (1 << kMortonBits) || c[2] >= (1 << kMortonBits))
         atomicOr(&err[3], 1);
     keys[i] = ((uint64_t)s << kSpecShift) | morton3(c[0], c[1], c[2]);
@@ -133,9 +151,13 @@ __global__ void k_apply_perm(DevState s, const double* __restrict__ X_in,
             g = -1;
         }
         bcs[p] = g;
-        specs_out[p] = (int32_t)(keys[p] >> kSpecShift);
+        const int32_t sp = (int32_t)(keys[p] >> kSpecShift);
+        specs_out[p] = sp;
+        const DevSpec& P = s.specs[sp];
+        s.hs[p] = P.h_per_spacing > 0.0 ? P.h_per_spacing * cbrt(V0_in[o]) : P.h;
     } else {
         perm[p] = -1;
+        s.hs[p] = 0.0;
         XV[p] = D4{0.0, 0.0, 0.0, 0.0};
         bcs[p] = -1;
         specs_out[p] = 0;
@@ -172,7 +194,8 @@ __device__ __forceinline__ int for_neighbours(const DevState& s, const uint64_t*
     const D4 xp = s.XV[p];
     const double xi = xp.x, yi = xp.y, zi = xp.z;
     int32_t c[3];
-    cell_of(P, bbox + 6 * sp, xi, yi, zi, c);
+    cell_of(bbox + kBBox * sp, xi, yi, zi, c);
+    const double hp = s.hs[p];
     int count = 0;
     for (int dz = -1; dz <= 1; ++dz)
         for (int dy = -1; dy <= 1; ++dy)
@@ -194,7 +217,12 @@ __device__ __forceinline__ int for_neighbours(const DevState& s, const uint64_t*
                     const double d1 = xq.y - yi;
                     const double d2 = xq.z - zi;
                     const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-                    if (r2 < P.h2) visit(count++, (int32_t)q);
+                    double lim = P.h2;
+                    if (s.var_h) {   // graded spacing: the pair's support (h_p + h_q) / 2
+                        const double hpq = 0.5 * (hp + s.hs[q]);
+                        lim = hpq * hpq;
+                    }
+                    if (r2 < lim) visit(count++, (int32_t)q);
                 }
             }
     return count;
@@ -293,7 +321,12 @@ __global__ void k_shape(DevState s, double* __restrict__ Linv, float* __restrict
         const double d[3] = {xj.x - xp.x, xj.y - xp.y, xj.z - xp.z};
         const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         double W, dW;
-        spline(r, P.inv_h, P.wnorm, W, dW);
+        if (s.var_h) {   // the pair's support
+            const double h = 0.5 * (s.hs[p] + s.hs[j]);
+            spline(r, 1.0 / h, 8.0 / (M_PI * h * h * h), W, dW);
+        } else {
+            spline(r, P.inv_h, P.wnorm, W, dW);
+        }
         const double g = xj.w * dW / r;
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) L[3 * a + b] += d[a] * g * d[b];
@@ -363,7 +396,7 @@ __global__ void k_init(DevState s) {
 
 hipError_t launch_build_count(DevState& s, const BuildBuffers& b, hipStream_t st) {
     const int T = 256;
-    k_bbox<<<s.n_spec, 256, 0, st>>>(b.X_in, s.n, b.spec_off, b.bbox);
+    k_bbox<<<s.n_spec, 256, 0, st>>>(b.X_in, b.V0_in, s.n, b.spec_off, s.specs, b.bbox);
     k_keys<<<(unsigned)((b.n_pow2 + T - 1) / T), T, 0, st>>>(b.X_in, s.n, b.n_pow2, b.spec_off,
                                                              s.n_spec, s.specs, b.bbox, b.keys,
                                                              b.vals, s.err);
@@ -574,12 +607,14 @@ template <>
 struct alignas(16) LRecB<double> {
     double x, y, z, V0, ux, uy, uz, omd;
     double q[9], h[9];
+    double hs;   // support radius (graded spacing only; not in the LDS image)
 };
 template <>
 struct alignas(16) LRecB<float> {
     double x, y, z, ux, uy, uz;   // positions and displacements stay double
     float V0, omd;
     float q[9], h[9];
+    double hs;   // support radius (graded spacing only; not in the LDS image)
 };
 
 template <typename R>
@@ -627,8 +662,11 @@ __device__ __forceinline__ float rcp_pos(float x) {
 //   g += (1 - D_j) V_j w (e_ij . x_ij) / (|X_ij|^2 |x_ij|^2) x_ij
 // with e_ij . x_ij = ((H_i + H_j) X_ij) . x_ij / 2 - (u_j - u_i) . x_ij
 // (the error vector (F_i + F_j) X_ij / 2 - x_ij with F = I + H).  A pair
-// whose current separation is zero adds no hourglass force.
-template <typename R>
+// whose current separation is zero adds no hourglass force.  With graded
+// spacing (kVarH) each pair has its own support h_ij = (h_i + h_j) / 2, so
+// the constant factors c / h_ij and c = 8 / (pi h_ij^3) enter per pair and the
+// finish applies none.
+template <typename R, bool kVarH = false>
 __device__ __forceinline__ void force_pair(const LRecB<R>& ni, const LRecB<R>& nj, R inv_h,
                                            ForceAcc<R>& A, bool live = true) {
     // a padding slot (live = false) gets 1/r = 1/|x|^2 = 0: every term it
@@ -636,6 +674,12 @@ __device__ __forceinline__ void force_pair(const LRecB<R>& ni, const LRecB<R>& n
     const R dx = R(nj.x - ni.x), dy = R(nj.y - ni.y), dz = R(nj.z - ni.z);
     const R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
     const R ir = live ? rsqrt_pos(r2) : R(0);
+    R kg = R(1), kw = R(1);
+    if constexpr (kVarH) {
+        inv_h = rcp_nr(R(0.5 * (ni.hs + nj.hs)));
+        kw = R(8.0 / M_PI) * inv_h * inv_h * inv_h;
+        kg = kw * inv_h;
+    }
     const R q = r2 * ir * inv_h;
     R w, sl;
     if (q < R(0.5)) {
@@ -648,7 +692,11 @@ __device__ __forceinline__ void force_pair(const LRecB<R>& ni, const LRecB<R>& n
         sl = R(-6) * a2;
     }
     const R Vj = nj.V0;
-    const R gv = sl * ir * Vj;
+    R gv = sl * ir * Vj;
+    if constexpr (kVarH) {
+        gv *= kg;
+        w *= kw;
+    }
     const R gx = gv * dx, gy = gv * dy, gz = gv * dz;
     A.a0 = fma(nj.omd, gx, A.a0); A.a1 = fma(nj.omd, gy, A.a1); A.a2 = fma(nj.omd, gz, A.a2);
     A.b0 = fma(nj.q[0], gx, fma(nj.q[1], gy, fma(nj.q[2], gz, A.b0)));
@@ -709,7 +757,7 @@ __device__ __forceinline__ FirstIdx<S> first_indices(int cnt, int sub, IdxOf idx
     return f;
 }
 
-template <typename R, int S, typename IdxOf, typename RecOf>
+template <typename R, int S, bool kVarH = false, typename IdxOf, typename RecOf>
 __device__ __forceinline__ ForceAcc<R> pair_sums(const LRecB<R>& ni, int cnt, int sub, R inv_h,
                                                  IdxOf idx, RecOf rec, const FirstIdx<S>& first) {
     static_assert(kSub == 4 && (S == 1 || S == 2 || S == 4), "canonical order has 4 partials");
@@ -731,7 +779,7 @@ __device__ __forceinline__ ForceAcc<R> pair_sums(const LRecB<R>& ni, int cnt, in
 #pragma unroll
         for (int t = 0; t < NP; ++t) {
             const int k = k0 + sub + S * t;
-            force_pair<R>(ni, rec(cur[t]), inv_h, A[t], k < cnt);
+            force_pair<R, kVarH>(ni, rec(cur[t]), inv_h, A[t], k < cnt);
         }
     }
     if constexpr (S == 1) {
@@ -753,10 +801,12 @@ struct FinishIn {
     double grad_k, hg_k, dt, dt_rho0;
     int32_t bc, wall;
 };
+template <bool kVarH = false>
 __device__ __forceinline__ FinishIn finish_in(const DevState& s, int64_t i, const DevSpec& P) {
     const D4 v = s.VW[i];
-    return FinishIn{s.D[i], s.XV[i].w, v.x, v.y, v.z, P.grad_k, P.hg_k, P.dt, P.dt_rho0,
-                    s.bc[i], P.has_wall};
+    // graded spacing: the pair sums carry the kernel's constant factors
+    return FinishIn{s.D[i], s.XV[i].w, v.x, v.y, v.z, kVarH ? 1.0 : P.grad_k,
+                    kVarH ? -P.hg_alpha * P.E : P.hg_k, P.dt, P.dt_rho0, s.bc[i], P.has_wall};
 }
 
 // Nodal force, kick, prescribed velocities, failed particles at rest, drift,
@@ -832,7 +882,7 @@ __device__ __forceinline__ void force_finish(const DevState& s, int64_t i, int p
 // u^{n+1} = u^n + dt v (into the other displacement buffer), rigid wall, and
 // the record (v, V0 (1 - D)) the deformation pass gathers.  This variant
 // gathers neighbours straight from global memory.
-template <typename R, int S>
+template <typename R, int S, bool kVarH = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S < 2 ? S : 2, 8)))
 k_pass_b(DevState s, int par) {
     const int64_t t = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
@@ -846,14 +896,20 @@ k_pass_b(DevState s, int par) {
     const D4* __restrict__ Uc = s.U[par];
     const GQRec<R>* __restrict__ GQ = gq_of<R>(s);
     const GHRec<R>* __restrict__ GH = gh_of<R>(s);
-    const LRecB<R> ni = make_recb<R>(XV[ii], GQ[ii], GH[ii], Uc[ii]);
+    LRecB<R> ni = make_recb<R>(XV[ii], GQ[ii], GH[ii], Uc[ii]);
+    if constexpr (kVarH) ni.hs = s.hs[ii];
     const R inv_h = R(P.inv_h);
     const int cnt = in ? s.nnb[i] : 0;
-    const FinishIn fin = finish_in(s, ii, P);
+    const FinishIn fin = finish_in<kVarH>(s, ii, P);
     const int32_t* __restrict__ cp = s.col + s.slice_ptr[ii / kSlice] + (ii % kSlice);
     const auto idx = [&](int k) { return (int)cp[(int64_t)k * kSlice]; };
-    const ForceAcc<R> A = pair_sums<R, S>(
-        ni, cnt, sub, inv_h, idx, [&](int j) { return make_recb<R>(XV[j], GQ[j], GH[j], Uc[j]); },
+    const ForceAcc<R> A = pair_sums<R, S, kVarH>(
+        ni, cnt, sub, inv_h, idx,
+        [&](int j) {
+            LRecB<R> r = make_recb<R>(XV[j], GQ[j], GH[j], Uc[j]);
+            if constexpr (kVarH) r.hs = s.hs[j];
+            return r;
+        },
         first_indices<S>(cnt, sub, idx));
     // the particle's own Q is needed only now: reread it (the compiler barrier
     // keeps the load here) rather than keep it in registers through the loop
@@ -1035,6 +1091,7 @@ __attribute__((amdgpu_waves_per_eu(staged_waves_min<R, S>(), 8))) k_pass_b_stage
 // half-step velocity and V0 (1 - D).
 struct NbrA {
     double x, y, z, vx, vy, vz, w;
+    double hs;   // support radius (graded spacing only)
 };
 
 // M = sum_j V_j (1 - D_j)(v_j - v_i) (x) gradW_ij over the neighbours in
@@ -1055,10 +1112,12 @@ __device__ __forceinline__ AvPar<R> av_par(const DevSpec& P) {
                     P.av_q1 != 0.0 || P.av_q2 != 0.0};
 }
 
-template <typename R, bool kExt, typename IdxOf, typename RecOf>
+// Graded spacing (kVarH): each pair has its own support h_ij = (h_i + h_j)/2
+// (h_i = hi), and the kernel's constant factor enters per pair (grad_k = 1).
+template <typename R, bool kExt, bool kVarH = false, typename IdxOf, typename RecOf>
 __device__ __forceinline__ void gather_fdot(const D4& xi, const D4& vi, int cnt, R inv_h, R grad_k,
                                             IdxOf idx, RecOf rec, R M[9], const AvPar<R>& av,
-                                            R AV[3]) {
+                                            R AV[3], double hi = 0.0) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) M[q] = R(0);
     AV[0] = AV[1] = AV[2] = R(0);
@@ -1085,7 +1144,12 @@ __device__ __forceinline__ void gather_fdot(const D4& xi, const D4& vi, int cnt,
             const R dx = R(nb[t].x - xi.x), dy = R(nb[t].y - xi.y), dz = R(nb[t].z - xi.z);
             const R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
             const R ir = live ? rsqrt_pos(r2) : R(0);
-            const R q = r2 * ir * inv_h;
+            R ih = inv_h, hpair = av.h;
+            if constexpr (kVarH) {
+                hpair = R(0.5 * (hi + nb[t].hs));
+                ih = rcp_nr(hpair);
+            }
+            const R q = r2 * ir * ih;
             R sl;
             if (q < R(0.5)) {
                 sl = q * fma(R(18), q, R(-12));
@@ -1093,7 +1157,8 @@ __device__ __forceinline__ void gather_fdot(const D4& xi, const D4& vi, int cnt,
                 const R a = R(1) - q;
                 sl = R(-6) * (a * a);
             }
-            const R gw = sl * ir * R(nb[t].w);
+            R gw = sl * ir * R(nb[t].w);
+            if constexpr (kVarH) gw *= R(8.0 / M_PI) * ih * ih * ih * ih;
             const R gx = gw * dx, gy = gw * dy, gz = gw * dz;
             const R t0 = R(nb[t].vx - vi.x), t1 = R(nb[t].vy - vi.y), t2 = R(nb[t].vz - vi.z);
             M[0] = fma(t0, gx, M[0]); M[1] = fma(t0, gy, M[1]); M[2] = fma(t0, gz, M[2]);
@@ -1104,7 +1169,8 @@ __device__ __forceinline__ void gather_fdot(const D4& xi, const D4& vi, int cnt,
                 if (av.on) {
                     const R vx = fma(t0, dx, fma(t1, dy, t2 * dz));
                     if (vx < R(0)) {
-                        const R mu = av.h * vx * rcp_nr(r2 + av.eh2);
+                        const R eh2 = kVarH ? R(0.01) * hpair * hpair : av.eh2;
+                        const R mu = hpair * vx * rcp_nr(r2 + eh2);
                         const R pi = mu * fma(av.q2, mu, -av.q1c0);
                         AV[0] = fma(pi, gx, AV[0]);
                         AV[1] = fma(pi, gy, AV[1]);
@@ -1242,7 +1308,7 @@ __host__ __device__ constexpr int pass_a_waves_min() {
 
 // Specimen parameters are read with scalar loads: the lanes of a wave take
 // turns by specimen, one turn unless the wave straddles two specimens.
-template <typename R, int DM, bool kFlow>
+template <typename R, int DM, bool kFlow, bool kVarH = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pass_a_waves_min<R, DM, kFlow>(), 8)))
 k_pass_a(DevState s, int par) {
     const int64_t i = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
@@ -1257,12 +1323,14 @@ k_pass_a(DevState s, int par) {
             const int32_t* __restrict__ cp = s.col + s.slice_ptr[i / kSlice] + (i % kSlice);
             R M[9], AV[3];
             const D4 vi = VW[i];
-            gather_fdot<R, kFlow>(XV[i], vi, s.nnb[i], R(P.inv_h), R(P.grad_k),
-                                  [&](int k) { return (int)cp[(int64_t)k * kSlice]; },
-                                  [&](int j) {
-                                      const D4 x = XV[j], v = VW[j];
-                                      return NbrA{x.x, x.y, x.z, v.x, v.y, v.z, v.w};
-                                  }, M, av_par<R>(P), AV);
+            gather_fdot<R, kFlow, kVarH>(XV[i], vi, s.nnb[i], R(P.inv_h),
+                                         kVarH ? R(1) : R(P.grad_k),
+                                         [&](int k) { return (int)cp[(int64_t)k * kSlice]; },
+                                         [&](int j) {
+                                             const D4 x = XV[j], v = VW[j];
+                                             return NbrA{x.x, x.y, x.z, v.x, v.y, v.z, v.w,
+                                                         kVarH ? s.hs[j] : 0.0};
+                                         }, M, av_par<R>(P), AV, kVarH ? s.hs[i] : 0.0);
             pass_a_update<R, DM, kFlow>(s, i, sp, M, vi.w, AV);
             break;
         }
@@ -1360,6 +1428,13 @@ static hipError_t launch_b(const DevState& s, int parity, int block, bool mixed,
         return hipGetLastError();
     }
     const unsigned grid = (unsigned)((s.n * S + block - 1) / block);
+    if (s.var_h) {   // graded spacing: per-pair supports
+        if (mixed)
+            k_pass_b<float, S, true><<<grid, block, 0, st>>>(s, parity);
+        else
+            k_pass_b<double, S, true><<<grid, block, 0, st>>>(s, parity);
+        return hipGetLastError();
+    }
     if (mixed)
         k_pass_b<float, S><<<grid, block, 0, st>>>(s, parity);
     else
@@ -1400,7 +1475,7 @@ hipError_t prepare_staged(size_t lds_bytes_b) {
     return hipSuccess;
 }
 
-template <int DM, bool kFlow>
+template <int DM, bool kFlow, bool kVarH = false>
 static void launch_a(const DevState& s, int parity, unsigned grid, int block, bool mixed,
                      hipStream_t st) {
     if (block == 0) {   // staged over the force pass's tiles
@@ -1413,14 +1488,18 @@ static void launch_a(const DevState& s, int parity, unsigned grid, int block, bo
         return;
     }
     if (mixed)
-        k_pass_a<float, DM, kFlow><<<grid, block, 0, st>>>(s, parity);
+        k_pass_a<float, DM, kFlow, kVarH><<<grid, block, 0, st>>>(s, parity);
     else
-        k_pass_a<double, DM, kFlow><<<grid, block, 0, st>>>(s, parity);
+        k_pass_a<double, DM, kFlow, kVarH><<<grid, block, 0, st>>>(s, parity);
 }
 
 hipError_t launch_pass_a(const DevState& s, int parity, int block, bool mixed, hipStream_t st) {
-    if (block == 0 && (!s.staged_lds_a || s.tile > 256)) return hipErrorInvalidValue;
+    if (block == 0 && (!s.staged_lds_a || s.tile > 256 || s.var_h)) return hipErrorInvalidValue;
     const unsigned grid = block > 0 ? (unsigned)((s.n + block - 1) / block) : 0u;
+    if (s.var_h) {   // graded spacing: the general variant with per-pair supports
+        launch_a<-1, true, true>(s, parity, grid, block, mixed, st);
+        return hipGetLastError();
+    }
     if (s.flow_general) {
         switch (s.model) {
             case 0: launch_a<0, true>(s, parity, grid, block, mixed, st); break;

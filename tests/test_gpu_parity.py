@@ -47,6 +47,18 @@ LINEAR = dict(flow=I.FLOW_LINEAR, B=2.0e9)
 AV = dict(av_q1=1.0, av_q2=2.0)
 
 
+def small_graded(**over):
+    """Graded spacing (0.05 / 0.1 / 0.2 mm zones), about 5 400 particles."""
+    return I.graded_notched_bar(R=0.6e-3, L=2.0e-3, rho=0.15e-3,
+                                spacings=(0.05e-3, 0.1e-3, 0.2e-3),
+                                bounds=(0.25e-3, 0.6e-3), **over)
+
+
+def kcap(p):
+    """Neighbour capacity: graded spacing at 1.75 dx reaches about 40."""
+    return 64 if any(m["h_per_spacing"] for m in p.materials) else 32
+
+
 def remat(p, *overs):
     """Specimen s takes the parameter overrides overs[s % len(overs)]."""
     mats = [dict(m, **overs[s % len(overs)]) for s, m in enumerate(p.materials)]
@@ -65,6 +77,8 @@ CASES = {
                                                   hole_d=4e-3), VOCE),
     "bar_av": lambda: remat(I.notched_bar(dx=0.8e-3), AV),
     "taylor_wall_cl_av": lambda: remat(I.taylor_bar(dx=0.6e-3, R=2.5e-3, L=6e-3), AV),
+    "graded_bar": lambda: small_graded(),
+    "graded_bar_voce_av": lambda: small_graded(**dict(VOCE, implicit_return=1, **AV)),
     "batch3_laws": lambda: remat(I.subset(I.bar_batch(n_spec=3, lo=2000, hi=6000), [0, 1, 2]),
                                  dict(SWIFT, implicit_return=1), VOCE,
                                  dict(LINEAR, implicit_return=1)),
@@ -80,7 +94,7 @@ CASES = {
 def test_neighbours_bit_exact(tl, orc, case):
     p = CASES[case]()
     say("neighbours", case, p.n)
-    g = tl.Sim(p)
+    g = tl.Sim(p, k_cap=kcap(p))
     o = orc.Sim(p)
     rp, col = g.neighbors()
     assert np.array_equal(rp, o.row_ptr)
@@ -118,7 +132,7 @@ def test_one_step_from_injected_state(tl, orc, case, precision):
     p = CASES[case]()
     say("one step", case, precision, p.n)
     prec = tl.FP64 if precision == "fp64" else tl.MIXED
-    g = tl.Sim(p, precision=prec, flags=tl.STORE_FORCE)
+    g = tl.Sim(p, precision=prec, flags=tl.STORE_FORCE, k_cap=kcap(p))
     o = orc.Sim(p)
     st = injected_state(orc, p, 1234)
     o.set_state(st)
@@ -190,6 +204,24 @@ def test_cube_trajectory_flow_laws(tl, orc, law):
     errs = compare(g, o, skip=("d_init", "w_p", "f_void", "D"))
     say(errs)
     assert all(v <= 1e-10 for v in errs.values()), errs
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graded_bar_trajectory_100_steps(tl, orc, precision):
+    p = small_graded(v_max=20.0, tau=2e-6)
+    say("graded trajectory", precision, p.n)
+    prec = tl.FP64 if precision == "fp64" else tl.MIXED
+    g = tl.Sim(p, precision=prec, flags=tl.STORE_FORCE, k_cap=kcap(p))
+    assert not g.info()["staged"]
+    o = orc.Sim(p)
+    for _ in range(4):
+        g.step(25)
+        o.step(25)
+    assert np.abs(o.get("v")).max() > 1.0
+    errs = compare(g, o, skip=("d_init", "w_p", "f_void", "D", "eps_p", "eps_p_rate"))
+    say(errs)
+    tol = 1e-10 if precision == "fp64" else 1e-4
+    assert all(v <= tol for v in errs.values()), errs
 
 
 def test_full_size_notched_bar_one_step(tl, orc):
