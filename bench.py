@@ -139,11 +139,11 @@ def log(*a):
 
 
 def run_form(prob, precision, steps, warmup, torch, T, flags=0, autotune=True, stream=None,
-             diag=True, shape=None):
+             diag=True, shape=None, k_cap=32):
     """Warm up, autotune (or apply a given launch shape), then time `steps`
     steps; diagnostics every DIAG_EVERY steps (inside the timed region)."""
     log(f"{prob.name}: {prob.n} particles, precision {precision}, flags {flags}")
-    sim = T.Sim(prob, precision=precision, flags=flags, stream=stream)
+    sim = T.Sim(prob, precision=precision, flags=flags, stream=stream, k_cap=k_cap)
     if shape is not None:
         sim.set_launch_shape(*shape)
     n_rec = (warmup + steps) // DIAG_EVERY + 1 if diag else 0
@@ -368,11 +368,11 @@ def final_shape(sim, prob):
             "failed": int(np.sum(~alive))}
 
 
-def bench_single(args, torch, I, T, workload, prob, label, damage_name, result):
+def bench_single(args, torch, I, T, workload, prob, label, damage_name, result, k_cap=32):
     """One large specimen: FP64, then mixed, each with its end-state summary."""
     damage = prob.materials[0]["damage"]
     tune = not args.no_autotune
-    fp = run_form(prob, T.FP64, args.steps, args.warmup, torch, T, 0, tune)
+    fp = run_form(prob, T.FP64, args.steps, args.warmup, torch, T, 0, tune, k_cap=k_cap)
     nnz = fp["info"]["nnz"]
     _, ktab = kernel_table(fp["kernel_times"], False, damage, prob.n, nnz)
     out = base_line(args, workload, prob.n * args.steps / fp["seconds"],
@@ -391,7 +391,7 @@ def bench_single(args, torch, I, T, workload, prob, label, damage_name, result):
     out["fp64_result"] = res64
     del fp["sim"]
     if not args.no_mixed:
-        mx = run_form(prob, T.MIXED, args.steps, args.warmup, torch, T, 0, tune)
+        mx = run_form(prob, T.MIXED, args.steps, args.warmup, torch, T, 0, tune, k_cap=k_cap)
         _, mtab = kernel_table(mx["kernel_times"], True, damage, prob.n, nnz)
         resm = result(mx)
         out["mixed"] = {
@@ -423,6 +423,22 @@ def bench_taylor_av(args, torch, I, T):
     return bench_single(args, torch, I, T, "taylor_bar_1m_av", prob,
                         "Taylor bar on a rigid wall, CL damage, artificial viscosity",
                         "cockcroft-latham", lambda r: final_shape(r["sim"], prob))
+
+
+def bench_graded(args, torch, I, T):
+    """The graded notched bar (0.1 / 0.2 / 0.4 / 0.8 mm zones, 92 774
+    particles, per-particle supports): the unstaged kernels with per-pair
+    supports."""
+    prob = I.graded_notched_bar()
+
+    def result(r):
+        bd, sd = r["bd"], r["sd"]
+        eps = r["sim"].get("eps_p")
+        return {"reaction_kN": float(-bd[-1, 1, 2]) / 1e3,
+                "grip_separation_mm": float(bd[-1, 1, 5] - bd[-1, 0, 5]) * 1e3,
+                "eps_p_max": float(eps.max()), "max_D": float(sd[-1, 0, 3])}
+    return bench_single(args, torch, I, T, "graded_bar_93k", prob,
+                        "graded notched bar, JC damage", "johnson-cook", result, k_cap=64)
 
 
 def bench_plate(args, torch, I, T):
@@ -498,6 +514,7 @@ WORKLOADS = {"notched_bar_200k": (bench_notched_bar, 42000, 1000),
              "notched_bar_200k_voce_implicit": (bench_notched_bar_voce, 42000, 1000),
              "taylor_bar_1m": (bench_taylor, 4900, 100),
              "taylor_bar_1m_av": (bench_taylor_av, 4900, 100),
+             "graded_bar_93k": (bench_graded, 4900, 100),
              "gtn_plate_4m": (bench_plate, 1900, 100),
              "batch_256_bars": (bench_batch, 400, 50)}
 
