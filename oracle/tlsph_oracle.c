@@ -767,6 +767,97 @@ void orc_init_state(const orc_problem *p, const double *v_init, orc_state *s) {
 /* t^{n+1/2}, failed particles at rest (Sec. 3.1), drift, then dF/dt from    */
 /* v^{n+1/2} and D^n and the constitutive update to t^{n+1}.                 */
 /* ------------------------------------------------------------------------ */
+static int is_reference_neighbour(const orc_problem *p, int64_t i, int32_t j) {
+    int64_t lo = p->row_ptr[i], hi = p->row_ptr[i + 1];
+    while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (p->col[mid] < j) lo = mid + 1; else hi = mid;
+    }
+    return lo < p->row_ptr[i + 1] && p->col[lo] == j;
+}
+
+static void contact_forces(const orc_problem *p, orc_state *s) {
+    const int64_t n = p->n;
+    int any = 0;
+    for (int32_t k = 0; k < p->n_spec; ++k) any |= p->mat[k].contact_k > 0.0;
+    if (!any || n == 0) return;
+    /* current positions, radii; a uniform grid of edge 2 max a over all */
+    double *x = (double *)malloc((size_t)n * 3 * sizeof(double));
+    double *rad = (double *)malloc((size_t)n * sizeof(double));
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double amax = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        rad[i] = 0.5 * cbrt(p->V0[i]);
+        if (rad[i] > amax) amax = rad[i];
+        for (int a = 0; a < 3; ++a) {
+            x[3 * i + a] = p->X[3 * i + a] + s->u[3 * i + a];
+            if (x[3 * i + a] < lo[a]) lo[a] = x[3 * i + a];
+            if (x[3 * i + a] > hi[a]) hi[a] = x[3 * i + a];
+        }
+    }
+    cell_grid g;
+    const double edge = 2.0 * amax;
+    int64_t ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+        g.lo[a] = lo[a];
+        g.dim[a] = (int64_t)floor((hi[a] - lo[a]) / edge) + 1;
+        ncell *= g.dim[a];
+    }
+    g.start = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+    g.items = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    int64_t c[3];
+    for (int64_t i = 0; i < n; ++i) g.start[cell_of(&g, &x[3 * i], edge, c) + 1] += 1;
+    for (int64_t k = 0; k < ncell; ++k) g.start[k + 1] += g.start[k];
+    int64_t *fill = (int64_t *)malloc((size_t)ncell * sizeof(int64_t));
+    memcpy(fill, g.start, (size_t)ncell * sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) g.items[fill[cell_of(&g, &x[3 * i], edge, c)]++] = (int32_t)i;
+    free(fill);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        const orc_material *mi = &p->mat[p->spec[i]];
+        int64_t ci[3];
+        cell_of(&g, &x[3 * i], edge, ci);
+        double f[3] = {0, 0, 0};
+        for (int64_t dz = -1; dz <= 1; ++dz)
+            for (int64_t dy = -1; dy <= 1; ++dy)
+                for (int64_t dx = -1; dx <= 1; ++dx) {
+                    int64_t cx = ci[0] + dx, cy = ci[1] + dy, cz = ci[2] + dz;
+                    if (cx < 0 || cy < 0 || cz < 0 || cx >= g.dim[0] || cy >= g.dim[1] ||
+                        cz >= g.dim[2])
+                        continue;
+                    int64_t id = cx + g.dim[0] * (cy + g.dim[1] * cz);
+                    for (int64_t t = g.start[id]; t < g.start[id + 1]; ++t) {
+                        int32_t j = g.items[t];
+                        if (j == i) continue;
+                        const orc_material *mj = &p->mat[p->spec[j]];
+                        double kc = 0.5 * (mi->contact_k + mj->contact_k);
+                        if (!(kc > 0.0)) continue;
+                        double d[3], r2 = 0.0;
+                        for (int a = 0; a < 3; ++a) {
+                            d[a] = x[3 * j + a] - x[3 * i + a];
+                            r2 += d[a] * d[a];
+                        }
+                        double rc = rad[i] + rad[j];
+                        if (!(r2 < rc * rc) || !(r2 > 0.0)) continue;
+                        if (p->spec[i] == p->spec[j] && s->D[i] < 1.0 && s->D[j] < 1.0 &&
+                            is_reference_neighbour(p, i, j))
+                            continue;
+                        double r = sqrt(r2), delta = rc - r;
+                        double Es = 1.0 / ((1.0 - mi->nu * mi->nu) / mi->E +
+                                           (1.0 - mj->nu * mj->nu) / mj->E);
+                        double F = kc * (4.0 / 3.0) * Es * sqrt(rad[i] * rad[j] / rc) *
+                                   delta * sqrt(delta);
+                        for (int a = 0; a < 3; ++a) f[a] -= F * d[a] / r;
+                    }
+                }
+        for (int a = 0; a < 3; ++a) s->force[3 * i + a] += f[a];
+    }
+    free(g.start);
+    free(g.items);
+    free(x);
+    free(rad);
+}
+
 void orc_step(const orc_problem *p, orc_state *s) {
     const int64_t n = p->n;
 
@@ -814,6 +905,16 @@ void orc_step(const orc_problem *p, orc_state *s) {
         }
         for (int a = 0; a < 3; ++a) s->force[3 * i + a] = fi[a] + fhg[a] + s->fvisc[3 * i + a];
     }
+
+    /* 1b. penalty contact (SURVEY's follow-on to the kinematic wall; the    */
+    /* paper has none).  Reading: particles are spheres of radius            */
+    /* a_i = V_i^(1/3) / 2; two particles closer than a_i + a_j in the current */
+    /* configuration repel by the Hertz law of two such spheres,             */
+    /* F = k (4/3) E* sqrt(a_i a_j / (a_i + a_j)) delta^(3/2),               */
+    /* delta = a_i + a_j - |x_ij|, 1/E* = (1-nu_i^2)/E_i + (1-nu_j^2)/E_j,     */
+    /* k = (k_i + k_j)/2, along x_ij; reference neighbours that are both     */
+    /* intact interact through the SPH forces only.  Positions at t^n.       */
+    contact_forces(p, s);
 
     /* 2-3. kick, prescribed velocities, failed particles at rest, drift,   */
     /* rigid frictionless wall (projection onto the plane, inward normal    */

@@ -47,6 +47,7 @@ typedef struct {
     double h_per_spacing;                      /* > 0: support h_i = this times   */
                                                /* V_i^(1/3) per particle (graded  */
                                                /* spacing); 0: h for all          */
+    double contact_k;                          /* penalty contact factor (0: off) */
 } orc_material;
 
 /* Prescribed-velocity group: component c (bit c of mask) is set to

@@ -36,6 +36,7 @@ MATERIAL_KEYS = (
     "q1", "q2", "q3", "f0", "fN", "eN", "sN", "fc", "fF", "k_omega",
     "h", "dt", "hg_alpha", "has_wall", "wall_n", "wall_d",
     "flow", "implicit_return", "flow_e0", "flow_beta", "av_q1", "av_q2", "h_per_spacing",
+    "contact_k",
 )
 
 # Steel used by every synthetic workload (rho, E, nu and the Johnson-Cook
@@ -61,7 +62,8 @@ def material(dx: float, damage: int = DMG_NONE, **over) -> Dict:
                   q1=1.0, q2=1.0, q3=1.0, f0=0.0, fN=0.0, eN=0.0, sN=1.0,
                   fc=1.0, fF=1.0, k_omega=0.0, hg_alpha=1.0, has_wall=0,
                   wall_n=(0.0, 0.0, 1.0), wall_d=0.0, flow=FLOW_JC, implicit_return=0,
-                  flow_e0=0.0, flow_beta=0.0, av_q1=0.0, av_q2=0.0, h_per_spacing=0.0))
+                  flow_e0=0.0, flow_beta=0.0, av_q1=0.0, av_q2=0.0, h_per_spacing=0.0,
+                  contact_k=0.0))
     if damage == DMG_JC:
         m.update(JC_DAMAGE)
     if damage == DMG_GTN:
@@ -235,6 +237,40 @@ def graded_notched_bar(R: float = 5e-3, L: float = 7e-3, rho: float = 0.4e-3,
     m["h"] = 1.5 * max(spacings)
     return Problem("graded_notched_bar", X, V0, np.array([0, n], np.int64), [m], bc, groups,
                    np.zeros((n, 3)), steps=steps, dx=np.array([dxm]))
+
+
+# ----------------------------------------------------------------------------
+# two bars meeting head on (two specimens): they interact only through the
+# penalty contact; bar 0 below z = -gap/2 moving up, bar 1 above gap/2 moving
+# down, each at v0
+# ----------------------------------------------------------------------------
+def bar_collision(dx: float = 0.2e-3, R: float = 2.5e-3, L: float = 10e-3, gap: float = 0.1e-3,
+                  v0: float = 100.0, jitter: float = 0.03, damage: int = DMG_CL,
+                  Wcr: float = 300e6, contact_k: float = 1.0, seed: int = SEED_BASE + 7,
+                  steps: int = 2000, **mat_over) -> Problem:
+    rng = np.random.default_rng(seed)
+    nr = int(math.ceil(2 * R / dx))
+    nz = int(round(L / dx))
+    i, j, k = _lattice(nr, nr, nz)
+    x = (i + 0.5) * dx - nr * dx / 2
+    y = (j + 0.5) * dx - nr * dx / 2
+    z = (k + 0.5) * dx
+    keep = np.sqrt(x * x + y * y) < R
+    lat = np.stack([x[keep], y[keep], z[keep]], axis=1)
+    lo = lat.copy()
+    lo[:, 2] = -gap / 2 - lo[:, 2]
+    hi = lat.copy()
+    hi[:, 2] = gap / 2 + hi[:, 2]
+    X = np.concatenate([_jitter(rng, lo, dx, jitter), _jitter(rng, hi, dx, jitter)])
+    n0 = lo.shape[0]
+    n = X.shape[0]
+    v = np.zeros((n, 3))
+    v[:n0, 2] = v0
+    v[n0:, 2] = -v0
+    m = material(dx, damage, **dict(dict(Wcr=Wcr, contact_k=contact_k), **mat_over))
+    return Problem("bar_collision", X, np.full(n, dx ** 3), np.array([0, n0, n], np.int64),
+                   [m, dict(m)], np.full(n, -1, np.int32), [], v, steps=steps,
+                   dx=np.array([dx, dx]))
 
 
 # ----------------------------------------------------------------------------

@@ -1,0 +1,97 @@
+"""Oracle pins for the penalty contact (SURVEY's follow-on to the kinematic
+wall; the paper has none): Hertz law between spheres of radius V^(1/3)/2,
+reading stated in the oracle.  Momentum balance through a collision, the
+3/2 power of the overlap, linearity in the factor, symmetry of the combined
+modulus, intact reference neighbours excluded, failed ones included.
+Host only."""
+import numpy as np
+import pytest
+
+from paper_1901_07374_amd import inputs as I
+
+
+def two_cubes(dx=1e-3, nside=4, gap=0.0, k=1.0, mats=None):
+    """Two perfect-lattice cubes, the upper one's bottom layer a distance
+    dx - gap above the lower one's top layer (facing particles overlap by
+    gap when gap > 0)."""
+    i, j, l = I._lattice(nside, nside, nside)
+    lat = np.stack([(i + 0.5) * dx, (j + 0.5) * dx, (l + 0.5) * dx], axis=1)
+    up = lat.copy()
+    up[:, 2] += nside * dx - gap
+    X = np.concatenate([lat, up])
+    n0 = lat.shape[0]
+    n = X.shape[0]
+    m0 = I.material(dx, I.DMG_NONE, contact_k=k)
+    m1 = dict(m0)
+    if mats:
+        m0.update(mats[0])
+        m1.update(mats[1])
+    return I.Problem("two_cubes", X, np.full(n, dx ** 3), np.array([0, n0, n], np.int64),
+                     [m0, m1], np.full(n, -1, np.int32), [], np.zeros((n, 3)), dx=np.array([dx, dx]))
+
+
+def contact_force_on_upper(orc, p):
+    """Net force on the upper cube after one step from rest (no stress, no
+    strain: the contact is the only force)."""
+    s = orc.Sim(p)
+    s.step(1)
+    f = s.get("force")
+    return f[p.spec_offsets[1]:].sum(axis=0), f
+
+
+def test_collision_conserves_momentum(orc):
+    p = I.bar_collision(dx=0.25e-3, R=1.0e-3, L=2e-3, gap=0.02e-3)
+    s = orc.Sim(p)
+    m = p.materials[0]["rho0"] * p.V0
+    p_one = abs((m[:, None] * p.v_init)[: p.spec_offsets[1]].sum(axis=0)[2])
+    for _ in range(4):
+        s.step(40)
+        P = (m[:, None] * s.get("v")).sum(axis=0)
+        assert np.abs(P).max() <= 1e-12 * p_one
+    # the bars have met: the lower one has slowed down
+    v0 = s.get("v")[: p.spec_offsets[1], 2].mean()
+    assert v0 < 0.9 * p.v_init[0, 2]
+
+
+def test_hertz_power_and_factor(orc):
+    dx, d = 1e-3, 2e-6
+    f1, _ = contact_force_on_upper(orc, two_cubes(dx, gap=d))
+    f4, _ = contact_force_on_upper(orc, two_cubes(dx, gap=4 * d))
+    f1k, _ = contact_force_on_upper(orc, two_cubes(dx, gap=d, k=2.0))
+    assert f1[2] > 0.0 and abs(f1[0]) < 1e-9 * f1[2] and abs(f1[1]) < 1e-9 * f1[2]
+    assert f4[2] == pytest.approx(8.0 * f1[2], rel=1e-9)      # delta^(3/2)
+    assert f1k[2] == pytest.approx(2.0 * f1[2], rel=1e-12)
+    # no overlap, no force
+    f0, fall = contact_force_on_upper(orc, two_cubes(dx, gap=-1e-6))
+    assert not fall.any()
+
+
+def test_combined_modulus_is_symmetric(orc):
+    mats = [dict(E=200e9, nu=0.3), dict(E=70e9, nu=0.33)]
+    fa, _ = contact_force_on_upper(orc, two_cubes(gap=3e-6, mats=mats))
+    fb, _ = contact_force_on_upper(orc, two_cubes(gap=3e-6, mats=mats[::-1]))
+    assert fa[2] == pytest.approx(fb[2], rel=1e-13)
+    # softer partner, smaller force than steel on steel
+    fs, _ = contact_force_on_upper(orc, two_cubes(gap=3e-6))
+    assert fa[2] < fs[2]
+
+
+def test_reference_neighbours_only_when_failed(orc):
+    # one jittered cube: overlapping pairs are all reference neighbours, so
+    # the intact cube feels no contact; failed particles do
+    p = I.cube(nside=6, jitter=0.05, contact_k=1.0)
+    base = I.cube(nside=6, jitter=0.05)
+    a, b = orc.Sim(p), orc.Sim(base)
+    a.step(1)
+    b.step(1)
+    assert np.array_equal(a.get("force"), b.get("force"))
+    D = np.zeros(p.n)
+    D[::7] = 1.0
+    a, b = orc.Sim(p), orc.Sim(base)
+    a.set("D", D)
+    b.set("D", D)
+    a.step(1)
+    b.step(1)
+    df = a.get("force") - b.get("force")
+    assert np.abs(df).max() > 0.0
+    assert np.abs(df.sum(axis=0)).max() <= 1e-12 * np.abs(df).sum()

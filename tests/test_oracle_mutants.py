@@ -16,7 +16,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "tlsph_oracle.c")
 PINS = ["tests/test_oracle_kernel_neighbors.py", "tests/test_oracle_constitutive.py",
         "tests/test_oracle_flow.py", "tests/test_oracle_viscosity.py",
-        "tests/test_oracle_graded.py", "tests/test_oracle_system.py"]
+        "tests/test_oracle_graded.py", "tests/test_oracle_contact.py",
+        "tests/test_oracle_system.py"]
 
 # (name, text in the oracle, planted replacement)
 MUTANTS = [
@@ -73,6 +74,11 @@ MUTANTS = [
      "return p->hs ? p->hs[i] : p->mat[p->spec[i]].h;"),
     ("neighbour rule with the larger support", "double hij = 0.5 * (hs[i] + hs[j]);",
      "double hij = hs[i] > hs[j] ? hs[i] : hs[j];"),
+    ("contact force linear in the overlap", "delta * sqrt(delta);", "delta;"),
+    ("contact ignores failure", "if (p->spec[i] == p->spec[j] && s->D[i] < 1.0 && s->D[j] < 1.0 &&",
+     "if (p->spec[i] == p->spec[j] &&"),
+    ("contact attractive", "for (int a = 0; a < 3; ++a) f[a] -= F * d[a] / r;",
+     "for (int a = 0; a < 3; ++a) f[a] += F * d[a] / r;"),
     ("energy from P^{n+1} only", "work += Fdot[k] * 0.5 * (Jn * Pn[k] + P[k]);",
      "work += Fdot[k] * P[k];"),
 ]
@@ -92,12 +98,51 @@ def build_mutant(tmp, text, repl):
     return lib
 
 
+# the pin file expected to catch each mistake runs first (the run stops at
+# the first failure); the others follow
+HOME = {
+    'kernel normalisation': 'kernel_neighbors',
+    'kernel slope term': 'kernel_neighbors',
+    'correction matrix without V_j': 'kernel_neighbors',
+    'dF/dt weighted by D_i': 'system',
+    'nodal force damage weights swapped': 'system',
+    'nodal force drops Q_j': 'system',
+    'hourglass sign': 'system',
+    'hourglass with F_j transposed': 'system',
+    'half drift': 'system',
+    'failed particles keep moving': 'system',
+    'EOS S_alpha sign': 'constitutive',
+    'radial return with 2G': 'constitutive',
+    'trial stress without (1 - D)': 'constitutive',
+    'rotation applied transposed': 'constitutive',
+    'JC failure strain sign of D3': 'constitutive',
+    'flow stress rate term': 'constitutive',
+    'GTN yield function factor': 'constitutive',
+    'Voce law sign': 'flow',
+    'Swift offset dropped': 'flow',
+    'implicit return without (1 - D) on the flow stress': 'flow',
+    "implicit return with the rate of the step's start": 'flow',
+    'viscosity on separating pairs': 'viscosity',
+    'viscosity quadratic term linear': 'viscosity',
+    'viscosity applied with the wrong sign': 'viscosity',
+    'viscosity not in the next kick': 'viscosity',
+    "pair kernel with the particle's own support": 'graded',
+    'neighbour rule with the larger support': 'graded',
+    'contact force linear in the overlap': 'contact',
+    'contact ignores failure': 'contact',
+    'contact attractive': 'contact',
+    'energy from P^{n+1} only': 'system',
+}
+
+
 @pytest.mark.parametrize("name,text,repl", MUTANTS, ids=[m[0] for m in MUTANTS])
 def test_pins_catch_planted_mistake(name, text, repl):
+    first = f"tests/test_oracle_{HOME[name]}.py"
+    order = [first] + [f for f in PINS if f != first]
     with tempfile.TemporaryDirectory() as tmp:
         lib = build_mutant(tmp, text, repl)
         env = dict(os.environ, TLSPH_ORACLE_LIB=lib, OMP_NUM_THREADS="4")
         r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-m", "not gpu",
-                            "-p", "no:cacheprovider", *PINS],
+                            "-p", "no:cacheprovider", *order],
                            cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
         assert r.returncode != 0, f"no pin caught: {name}\n{r.stdout[-2000:]}"
