@@ -139,11 +139,13 @@ def log(*a):
 
 
 def run_form(prob, precision, steps, warmup, torch, T, flags=0, autotune=True, stream=None,
-             diag=True, shape=None, k_cap=32):
+             diag=True, shape=None, k_cap=32, setup=None):
     """Warm up, autotune (or apply a given launch shape), then time `steps`
     steps; diagnostics every DIAG_EVERY steps (inside the timed region)."""
     log(f"{prob.name}: {prob.n} particles, precision {precision}, flags {flags}")
     sim = T.Sim(prob, precision=precision, flags=flags, stream=stream, k_cap=k_cap)
+    if setup is not None:
+        setup(sim)
     if shape is not None:
         sim.set_launch_shape(*shape)
     n_rec = (warmup + steps) // DIAG_EVERY + 1 if diag else 0
@@ -368,11 +370,13 @@ def final_shape(sim, prob):
             "failed": int(np.sum(~alive))}
 
 
-def bench_single(args, torch, I, T, workload, prob, label, damage_name, result, k_cap=32):
+def bench_single(args, torch, I, T, workload, prob, label, damage_name, result, k_cap=32,
+                 setup=None):
     """One large specimen: FP64, then mixed, each with its end-state summary."""
     damage = prob.materials[0]["damage"]
     tune = not args.no_autotune
-    fp = run_form(prob, T.FP64, args.steps, args.warmup, torch, T, 0, tune, k_cap=k_cap)
+    fp = run_form(prob, T.FP64, args.steps, args.warmup, torch, T, 0, tune, k_cap=k_cap,
+                  setup=setup)
     nnz = fp["info"]["nnz"]
     _, ktab = kernel_table(fp["kernel_times"], False, damage, prob.n, nnz)
     out = base_line(args, workload, prob.n * args.steps / fp["seconds"],
@@ -391,7 +395,8 @@ def bench_single(args, torch, I, T, workload, prob, label, damage_name, result, 
     out["fp64_result"] = res64
     del fp["sim"]
     if not args.no_mixed:
-        mx = run_form(prob, T.MIXED, args.steps, args.warmup, torch, T, 0, tune, k_cap=k_cap)
+        mx = run_form(prob, T.MIXED, args.steps, args.warmup, torch, T, 0, tune, k_cap=k_cap,
+                      setup=setup)
         _, mtab = kernel_table(mx["kernel_times"], True, damage, prob.n, nnz)
         resm = result(mx)
         out["mixed"] = {
@@ -439,6 +444,30 @@ def bench_graded(args, torch, I, T):
                 "eps_p_max": float(eps.max()), "max_D": float(sd[-1, 0, 3])}
     return bench_single(args, torch, I, T, "graded_bar_93k", prob,
                         "graded notched bar, JC damage", "johnson-cook", result, k_cap=64)
+
+
+def bench_collision(args, torch, I, T):
+    """Two bars (R 2.5 mm, 10 mm long, dx 0.1 mm, 395 200 particles) meeting
+    head on at 100 m/s each, CL damage, penalty contact with candidate lists
+    rebuilt every 10 steps (skin 0.2 dx)."""
+    dx = 0.1e-3
+    prob = I.bar_collision(dx=dx, R=2.5e-3, L=10e-3, gap=0.05e-3, v0=100.0)
+    n0 = int(prob.spec_offsets[1])
+    m = prob.materials[0]["rho0"] * prob.V0
+
+    def result(r):
+        v = r["sim"].get("v")
+        ke = 0.5 * float(np.sum(m[:, None] * v * v))
+        ke0 = 0.5 * float(np.sum(m[:, None] * prob.v_init ** 2))
+        return {"v_lower_bar": float(v[:n0, 2].mean()), "v_upper_bar": float(v[n0:, 2].mean()),
+                "kinetic_energy_ratio": ke / ke0,
+                "eps_p_max": float(r["sim"].get("eps_p").max()),
+                "failed": int((r["sim"].get("D") >= 1.0).sum())}
+    out = bench_single(args, torch, I, T, "bar_collision_395k", prob,
+                       "two bars meeting head on, CL damage, penalty contact", "cockcroft-latham",
+                       result, setup=lambda sim: sim.set_contact(10, 0.2 * dx))
+    out["config"]["contact"] = {"rebuild_every": 10, "skin_m": 0.2 * dx}
+    return out
 
 
 def bench_plate(args, torch, I, T):
@@ -515,6 +544,7 @@ WORKLOADS = {"notched_bar_200k": (bench_notched_bar, 42000, 1000),
              "taylor_bar_1m": (bench_taylor, 4900, 100),
              "taylor_bar_1m_av": (bench_taylor_av, 4900, 100),
              "graded_bar_93k": (bench_graded, 4900, 100),
+             "bar_collision_395k": (bench_collision, 1900, 100),
              "gtn_plate_4m": (bench_plate, 1900, 100),
              "batch_256_bars": (bench_batch, 400, 50)}
 

@@ -125,6 +125,15 @@ typedef struct {
                                                  and a pair's (h_i + h_j) / 2 (membership
                                                  and kernel); the step then runs the
                                                  unstaged kernels.  0: h for all     */
+    double contact_k;                         /* penalty contact factor (0: off): particles
+                                                 are spheres of radius V_i^(1/3)/2; two
+                                                 closer than a_i + a_j in the current
+                                                 configuration repel by the Hertz law
+                                                 F = k (4/3) E* sqrt(a_i a_j/(a_i+a_j))
+                                                 delta^(3/2), k the mean of the two
+                                                 factors; intact reference neighbours
+                                                 interact through SPH only (see
+                                                 tlsph_set_contact)                   */
 } tlsph_specimen;
 
 /* Prescribed-velocity group.  At mid-step time t the velocity component c of
@@ -264,7 +273,9 @@ tlsph_status tlsph_kernel_times(tlsph_ctx *ctx, double ms[2], int64_t launches[2
  * (negative when the LDS-staged variant is in use), [1] of the deformation
  * pass, [2] neighbour pairs, [3] padded slots of the sliced neighbour layout,
  * [4] particles, [5] sticky device error flags (bit 0 non-finite, bit 1 GTN
- * Newton not converged), [6] lanes per particle of the force pass, [7] LDS
+ * Newton not converged, bit 2 a contact list missed a pair: a particle had
+ * more than 32 contact candidates, left the list's skin, or the contact grid
+ * outgrew 2^14 cells per axis), [6] lanes per particle of the force pass, [7] LDS
  * bytes per workgroup of the staged force pass (0 when unstaged), [8]
  * particles per tile of the staged force pass (0 when unstaged). */
 tlsph_status tlsph_info(tlsph_ctx *ctx, int64_t out[9]);
@@ -282,6 +293,15 @@ tlsph_status tlsph_info(tlsph_ctx *ctx, int64_t out[9]);
  * UNSUPPORTED (staged requested where a tile and its halo do not fit in
  * LDS), HIP. */
 tlsph_status tlsph_set_launch_shape(tlsph_ctx *ctx, const int32_t shape[5], hipStream_t stream);
+
+/* Penalty contact (specimens with contact_k > 0): the candidate list of
+ * each particle (particles within a_i + a_j + skin in the current
+ * configuration, at most 32) is rebuilt on the stream every `every` steps;
+ * between rebuilds it is valid while no particle moves more than skin / 2,
+ * which the force pass checks (info flag bit 2 otherwise).  Default every = 1,
+ * skin = 0: rebuilt every step, exact.  Steps with contact run without
+ * graphs.  Errors: INVALID_ARG (every < 1, skin < 0 or not finite). */
+tlsph_status tlsph_set_contact(tlsph_ctx *ctx, int32_t every, double skin);
 
 /* Free the host-side context (not the workspace).  Null is accepted. */
 void tlsph_destroy(tlsph_ctx *ctx);

@@ -38,6 +38,7 @@ struct Layout {
         specs, bcs, t;
     int64_t n_tiles;
     size_t GQ, GH, U0, U1, VW, sig, eps_p, eps_rate, d_init, w_p, f_void, e, D, force, fvisc, hs, err,
+        arad, ccnt, ccol, ubuild, cbox,
         spec_off, bbox, keys, vals, bc_list, bc_ptr, diag_seg, diag_part, backup;
     int64_t diag_chunk_cap;
     size_t state_begin, backup_bytes;
@@ -77,6 +78,12 @@ Layout make_layout(int64_t n, int32_t n_spec, int32_t n_bc, int32_t k_cap, bool 
     L.halo_cnt = take((size_t)L.n_tiles * 4);
     L.Linv = take(9 * np * 8);
     L.hs = take(np * 8);
+    L.arad = take(np * 8);
+    // contact candidate lists (rebuilt from the state, so outside the saved region)
+    L.ccnt = take(np * 4);
+    L.ccol = take((size_t)kContactCap * np * 4);
+    L.ubuild = take(3 * np * 8);
+    L.cbox = take(8 * 8);
     L.Linv32 = take(mixed ? 9 * np * 4 : 0);
     L.specs = take((size_t)n_spec * sizeof(DevSpec));
     L.bcs = take((size_t)(n_bc > 0 ? n_bc : 1) * sizeof(DevBC));
@@ -143,6 +150,8 @@ struct tlsph_ctx {
     bool timing = false;
     int32_t timing_stride = 1;
     int64_t step_count = 0;
+    int32_t contact_every = 1;     // steps between contact-list rebuilds
+    int32_t contact_age = 1 << 30; // steps since the last rebuild (large: stale)
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<std::pair<int, size_t>> ev_marks;  // (kernel, index of start event)
@@ -223,6 +232,10 @@ void wire_state(tlsph_ctx* c) {
     s.force = at<double>(c, L.force);
     s.fvisc = at<double>(c, L.fvisc);
     s.hs = at<double>(c, L.hs);
+    s.arad = at<double>(c, L.arad);
+    s.ccnt = at<int32_t>(c, L.ccnt);
+    s.ccol = at<int32_t>(c, L.ccol);
+    s.ubuild = at<double>(c, L.ubuild);
     s.err = at<int32_t>(c, L.err);
 }
 
@@ -244,9 +257,25 @@ hipEvent_t next_event(tlsph_ctx* c) {
     return c->ev_pool[c->ev_used++];
 }
 
+// Contact candidate lists from the current state (positions at t^n).
+tlsph_status contact_rebuild(tlsph_ctx* c, hipStream_t stream) {
+    const Layout& L = c->L;
+    hipError_t e = launch_contact_build(c->st, c->parity, at<uint64_t>(c, L.keys),
+                                        at<int32_t>(c, L.vals), L.n_pow2, at<double>(c, L.cbox),
+                                        stream);
+    if (e != hipSuccess) return hip_fail(c, e, "contact list");
+    c->contact_age = 0;
+    return TLSPH_OK;
+}
+
 tlsph_status run_steps_eager(tlsph_ctx* c, int32_t n_steps, hipStream_t stream) {
     const bool mixed = c->L.mixed;
     for (int32_t k = 0; k < n_steps; ++k) {
+        if (c->st.contact && c->contact_age >= c->contact_every) {
+            tlsph_status cs = contact_rebuild(c, stream);
+            if (cs != TLSPH_OK) return cs;
+        }
+        if (c->contact_age < (1 << 30)) ++c->contact_age;
         const bool timed = c->timing && (c->step_count++ % c->timing_stride) == 0;
         for (int pass = 0; pass < 2; ++pass) {
             hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -408,7 +437,8 @@ tlsph_status tlsph_create(int64_t n, int32_t n_spec, const int64_t* spec_offsets
             (p.flow == TLSPH_FLOW_SWIFT && !finite_pos(p.flow_e0)) ||
             (p.flow == TLSPH_FLOW_VOCE && !(p.flow_beta >= 0.0 && p.flow_beta <= 1e300)) ||
             !(p.av_q1 >= 0.0 && p.av_q1 <= 1e300) || !(p.av_q2 >= 0.0 && p.av_q2 <= 1e300) ||
-            !(p.h_per_spacing >= 0.0 && p.h_per_spacing <= 1e300))
+            !(p.h_per_spacing >= 0.0 && p.h_per_spacing <= 1e300) ||
+            !(p.contact_k >= 0.0 && p.contact_k <= 1e300))
             return TLSPH_E_INVALID_ARG;
         if (p.damage == TLSPH_DMG_GTN &&
             (!finite_pos(p.q1) || !finite_pos(p.sN) || !(p.fF > p.fc) || !(p.fc > 0.0)))
@@ -460,6 +490,8 @@ tlsph_status tlsph_create(int64_t n, int32_t n_spec, const int64_t* spec_offsets
         d.av_q1 = p.av_q1;
         d.av_q2 = p.av_q2;
         d.h_per_spacing = p.h_per_spacing;
+        d.contact_k = p.contact_k;
+        d.contact_comp = (1.0 - p.nu * p.nu) / p.E;
         d.first = spec_offsets[s];
         d.last = spec_offsets[s + 1];
     }
@@ -472,8 +504,11 @@ tlsph_status tlsph_create(int64_t n, int32_t n_spec, const int64_t* spec_offsets
     c->st.flow_general = 0;
     c->st.av = 0;
     c->st.var_h = 0;
+    c->st.contact = 0;
+    c->st.contact_skin = 0.0;
     for (int32_t q = 0; q < n_spec; ++q) {
         if (spec[q].h_per_spacing > 0.0) c->st.var_h = 1;
+        if (spec[q].contact_k > 0.0) c->st.contact = 1;
         if (spec[q].damage != spec[0].damage) c->st.model = -1;
         if (spec[q].av_q1 != 0.0 || spec[q].av_q2 != 0.0) c->st.av = 1;
         if (spec[q].flow != TLSPH_FLOW_JC || spec[q].implicit_return != 0 || c->st.av)
@@ -596,6 +631,11 @@ tlsph_status tlsph_build_neighbors(tlsph_ctx* c, const double* X, const double* 
     c->nnz = nnz;
     c->slots = total_slots;
     c->built = true;
+    if (c->st.contact) {   // a valid list before any force pass (autotune included)
+        tlsph_status cs = contact_rebuild(c, stream);
+        if (cs != TLSPH_OK) return cs;
+        c->contact_age = 1 << 30;
+    }
     return TLSPH_OK;
 }
 
@@ -603,7 +643,9 @@ tlsph_status tlsph_step(tlsph_ctx* c, int32_t n_steps, hipStream_t stream) {
     if (!c) return TLSPH_E_INVALID_ARG;
     if (!c->built) return fail(c, TLSPH_E_BAD_STATE, "step before build");
     if (n_steps < 0) return fail(c, TLSPH_E_INVALID_ARG, "negative step count");
-    bool graphs = (c->flags & TLSPH_USE_GRAPHS) && !c->timing && n_steps >= 2 && stream != nullptr;
+    // (contact lists are rebuilt on a schedule: no graphs)
+    bool graphs = (c->flags & TLSPH_USE_GRAPHS) && !c->timing && n_steps >= 2 &&
+                  stream != nullptr && !c->st.contact;
     if (graphs) {
         // a caller that is capturing already records the plain launches
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -657,6 +699,17 @@ tlsph_status tlsph_set_state(tlsph_ctx* c, tlsph_field field, const double* src,
         return TLSPH_OK;
     }
     HIPCHK(c, launch_set_field(c->st, field, c->parity, c->L.mixed, src, stream));
+    c->contact_age = 1 << 30;   // positions may have changed
+    return TLSPH_OK;
+}
+
+tlsph_status tlsph_set_contact(tlsph_ctx* c, int32_t every, double skin) {
+    if (!c) return TLSPH_E_INVALID_ARG;
+    if (every < 1 || !(skin >= 0.0 && skin <= 1e300))
+        return fail(c, TLSPH_E_INVALID_ARG, "contact: every >= 1 and a finite skin >= 0");
+    c->contact_every = every;
+    c->st.contact_skin = skin;
+    c->contact_age = 1 << 30;
     return TLSPH_OK;
 }
 
@@ -861,6 +914,7 @@ tlsph_status tlsph_autotune(tlsph_ctx* c, hipStream_t stream) {
     HIPCHK(c, hipMemcpyAsync(c->st.t, backup + L.backup_bytes, L.n_spec * 8,
                              hipMemcpyDeviceToDevice, stream));
     HIPCHK(c, hipStreamSynchronize(stream));
+    c->contact_age = 1 << 30;
     return TLSPH_OK;
 }
 

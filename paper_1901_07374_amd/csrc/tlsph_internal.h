@@ -14,6 +14,7 @@ constexpr int kNDiag = 8;          // doubles per diagnostics record
 constexpr int kDiagChunk = 2048;   // particles per partial sum of the diagnostics
 constexpr int kTile = 256;         // most particles per workgroup tile of the LDS-staged pass
 constexpr int kHaloSortMax = 8192; // tile entries sorted in LDS at build (kTile * k_cap)
+constexpr int kContactCap = 32;    // contact candidates per particle
 
 // Per-specimen parameters as the kernels read them (raw + derived).
 struct DevSpec {
@@ -41,6 +42,8 @@ struct DevSpec {
     double flow_e0, flow_beta; // Swift offset strain, Voce saturation rate
     double av_q1, av_q2;       // artificial viscosity coefficients (0: off)
     double h_per_spacing;      // > 0: per-particle support h_i = this V_i^(1/3)
+    double contact_k;          // penalty contact factor (0: off)
+    double contact_comp;       // (1 - nu^2) / E: the specimen's share of 1 / E*
     int64_t first, last;   // sorted-order particle range [first, last)
 };
 
@@ -113,6 +116,12 @@ struct DevState {
     double* force;           // SoA [3][np]
     double* fvisc;           // SoA [3][np] artificial viscous force for the next kick
     double* hs;              // [np] support radius of each particle (build)
+    double* arad;            // [np] contact radius V_i^(1/3) / 2 (build)
+    int32_t* ccnt;           // [np] contact candidates
+    int32_t* ccol;           // [kContactCap][np] candidate (sorted index, bit 31: a
+                             // reference neighbour of the same specimen)
+    double* ubuild;          // [3][np] displacement when the list was built
+    double contact_skin;     // skin of the candidate list
     int32_t* err;    // [0] first singular (sorted), [1] max count, [2] sticky flags,
                      // [3] build status, [4] largest tile halo
     // LDS staging: per tile of `tile` particles, the sorted outside neighbours
@@ -129,13 +138,14 @@ struct DevState {
                               // return or the artificial viscosity
     int32_t av;               // 1 if a specimen uses the artificial viscosity
     int32_t var_h;            // 1 if a specimen has graded spacing (per-particle support)
+    int32_t contact;          // 1 if a specimen has penalty contact
     int32_t tile;             // particles per tile of the staged force pass (<= kTile)
     int32_t staged_lds_a;     // 1 when the tile records of the deformation pass fit LDS
 };
 
 enum : uint32_t { kFlagStoreForce = 1u, kFlagGraphs = 2u, kFlagCheckFinite = 4u,
                   kFlagNoStaging = 8u };
-enum : int32_t { kErrNonFinite = 1, kErrNewton = 2 };
+enum : int32_t { kErrNonFinite = 1, kErrNewton = 2, kErrContact = 4 };
 
 // launch helpers implemented in tlsph_kernels.hip
 // Deformation pass: `block` threads per workgroup, or 0 for the variant staged
@@ -178,6 +188,10 @@ hipError_t launch_diagnostics(const DevState& s, int parity, const int32_t* bc_l
                               const int64_t* bc_ptr, const int64_t* seg, int32_t n_seg,
                               int64_t n_chunks, double* part, double* spec_diag, double* bc_diag,
                               hipStream_t st);
+// Contact candidate lists from the current configuration (keys, vals: n_pow2
+// scratch; cbox: 8 doubles).
+hipError_t launch_contact_build(const DevState& s, int parity, uint64_t* keys, int32_t* vals,
+                                int64_t n_pow2, double* cbox, hipStream_t st);
 hipError_t launch_bc_lists(const DevState& s, uint64_t* keys, int32_t* vals, int64_t n_pow2,
                            int32_t* bc_list, int64_t* bc_ptr, hipStream_t st);
 

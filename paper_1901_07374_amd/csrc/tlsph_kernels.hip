@@ -155,9 +155,11 @@ __global__ void k_apply_perm(DevState s, const double* __restrict__ X_in,
         specs_out[p] = sp;
         const DevSpec& P = s.specs[sp];
         s.hs[p] = P.h_per_spacing > 0.0 ? P.h_per_spacing * cbrt(V0_in[o]) : P.h;
+        s.arad[p] = 0.5 * cbrt(V0_in[o]);
     } else {
         perm[p] = -1;
         s.hs[p] = 0.0;
+        s.arad[p] = 0.0;
         XV[p] = D4{0.0, 0.0, 0.0, 0.0};
         bcs[p] = -1;
         specs_out[p] = 0;
@@ -364,6 +366,7 @@ __global__ void k_init(DevState s) {
         s.force[c * np + p] = 0.0;
         s.fvisc[c * np + p] = 0.0;
     }
+    s.ccnt[p] = 0;
     if (s.GQ) {
         GQRec<double> g;
         GHRec<double> h;
@@ -794,6 +797,49 @@ __device__ __forceinline__ ForceAcc<R> pair_sums(const LRecB<R>& ni, int cnt, in
     }
 }
 
+// Penalty contact force on particle i at its position (xi, yi, zi) at t^n:
+// the Hertz law of two spheres of radii a_i, a_j over every listed candidate
+// closer than a_i + a_j, except reference neighbours of the same specimen
+// that are both intact; F = k (4/3) E* sqrt(a_i a_j / (a_i + a_j)) delta^(3/2)
+// along x_ij, k the mean of the two factors, 1/E* the sum of the shares.
+// Also flags a particle that has left the list's skin.
+__device__ __forceinline__ void contact_force(const DevState& s, int64_t i, int par, int sp,
+                                              double xi, double yi, double zi, double Di,
+                                              double f[3]) {
+    const int64_t np = s.np;
+    f[0] = f[1] = f[2] = 0.0;
+    const DevSpec& Pi = s.specs[sp];
+    const double ai = s.arad[i];
+    const D4* __restrict__ Uc = s.U[par];
+    const D4 ui = Uc[i];
+    const double b0 = ui.x - s.ubuild[i], b1 = ui.y - s.ubuild[np + i],
+                 b2 = ui.z - s.ubuild[2 * np + i];
+    if (4.0 * (b0 * b0 + b1 * b1 + b2 * b2) > s.contact_skin * s.contact_skin)
+        atomicOr(&s.err[2], kErrContact);
+    const int cnt = s.ccnt[i];
+    for (int k = 0; k < cnt; ++k) {
+        const uint32_t e = (uint32_t)s.ccol[(int64_t)k * np + i];
+        const int32_t q = (int32_t)(e & 0x7fffffffu);
+        const bool ref = (e >> 31) != 0;
+        if (ref && Di < 1.0 && s.D[q] < 1.0) continue;
+        const DevSpec& Pq = s.specs[s.spec[q]];
+        const double kc = 0.5 * (Pi.contact_k + Pq.contact_k);
+        if (!(kc > 0.0)) continue;
+        const D4 xq = s.XV[q], uq = Uc[q];
+        const double d0 = (xq.x + uq.x) - xi, d1 = (xq.y + uq.y) - yi, d2 = (xq.z + uq.z) - zi;
+        const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+        const double aq = s.arad[q], rc = ai + aq;
+        if (!(r2 < rc * rc) || !(r2 > 0.0)) continue;
+        const double r = sqrt(r2), delta = rc - r;
+        const double es = 1.0 / (Pi.contact_comp + Pq.contact_comp);
+        const double F = kc * (4.0 / 3.0) * es * sqrt(ai * aq / rc) * delta * sqrt(delta);
+        const double g = F / r;
+        f[0] -= g * d0;
+        f[1] -= g * d1;
+        f[2] -= g * d2;
+    }
+}
+
 // What the finish needs of a particle besides its record, loaded before the
 // pair sums so that their latency is spent behind them.
 struct FinishIn {
@@ -831,6 +877,14 @@ __device__ __forceinline__ void force_finish(const DevState& s, int64_t i, int p
         fv0 += s.fvisc[i] * iv;
         fv1 += s.fvisc[np + i] * iv;
         fv2 += s.fvisc[2 * np + i] * iv;
+    }
+    if (s.contact) {   // penalty contact with the listed candidates
+        double fc[3];
+        contact_force(s, i, par, sp, ni.x + ni.ux, ni.y + ni.uy, ni.z + ni.uz, Di, fc);
+        const double iv = rcp_nr(Vi);
+        fv0 += fc[0] * iv;
+        fv1 += fc[1] * iv;
+        fv2 += fc[2] * iv;
     }
     const double dt = fin.dt;
     double v[3] = {fin.vx + fin.dt_rho0 * fv0, fin.vy + fin.dt_rho0 * fv1,
@@ -1709,6 +1763,155 @@ __global__ void k_bc_ptr(DevState s, const uint64_t* __restrict__ keys, int64_t 
         bc_ptr[t] = lo;
     }
     if (t < n && keys[t] != ~0ull) bc_list[t] = vals[t];
+}
+
+// ===========================================================================
+// penalty contact: candidate lists from the current configuration
+// ===========================================================================
+
+// Bounding box of the current positions and the largest contact radius over
+// every particle (one block): cbox = lo[3], hi[3], 1 / cell edge, cell edge,
+// with the edge 2 max a + skin (a hair larger).
+__global__ void __launch_bounds__(1024) k_cbox(DevState s, int par, double* __restrict__ cbox) {
+    __shared__ double red[7][1024];
+    const D4* __restrict__ Uc = s.U[par];
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300}, am = 0.0;
+    for (int64_t p = threadIdx.x; p < s.n; p += blockDim.x) {
+        const D4 x = s.XV[p], u = Uc[p];
+        const double c[3] = {x.x + u.x, x.y + u.y, x.z + u.z};
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fmin(lo[a], c[a]);
+            hi[a] = fmax(hi[a], c[a]);
+        }
+        am = fmax(am, s.arad[p]);
+    }
+    for (int a = 0; a < 3; ++a) {
+        red[a][threadIdx.x] = lo[a];
+        red[3 + a][threadIdx.x] = hi[a];
+    }
+    red[6][threadIdx.x] = am;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            for (int a = 0; a < 3; ++a) {
+                red[a][threadIdx.x] = fmin(red[a][threadIdx.x], red[a][threadIdx.x + w]);
+                red[3 + a][threadIdx.x] = fmax(red[3 + a][threadIdx.x], red[3 + a][threadIdx.x + w]);
+            }
+            red[6][threadIdx.x] = fmax(red[6][threadIdx.x], red[6][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) cbox[threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x == 6) {
+        const double edge = (2.0 * red[6][0] + s.contact_skin) * (1.0 + 1e-9);
+        cbox[6] = 1.0 / edge;
+        cbox[7] = edge;
+    }
+}
+
+__device__ __forceinline__ bool contact_cell(const double* cb, double x, double y, double z,
+                                             int32_t c[3]) {
+    const double xs[3] = {x, y, z};
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) {
+        const double q = floor((xs[a] - cb[a]) * cb[6]);
+        int32_t k = q < 0.0 ? 0 : (q >= (double)((1 << kMortonBits) - 1) ? (1 << kMortonBits) - 1
+                                                                          : (int32_t)q);
+        if (q >= (double)((1 << kMortonBits) - 1)) ok = false;
+        c[a] = k;
+    }
+    return ok;
+}
+
+__global__ void k_ckeys(DevState s, int par, const double* __restrict__ cbox, int64_t n_pow2,
+                        uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pow2) return;
+    if (i >= s.n) {
+        keys[i] = ~0ull;
+        vals[i] = 0x7fffffff;
+        return;
+    }
+    const D4 x = s.XV[i], u = s.U[par][i];
+    int32_t c[3];
+    if (!contact_cell(cbox, x.x + u.x, x.y + u.y, x.z + u.z, c)) atomicOr(&s.err[2], kErrContact);
+    keys[i] = morton3(c[0], c[1], c[2]);
+    vals[i] = (int32_t)i;
+}
+
+// Candidates of particle p: particles q != p within a_p + a_q + skin, over
+// the 27 cells around p (cells sorted by key, particles by index within a
+// cell); bit 31 marks a reference neighbour of the same specimen.  More than
+// kContactCap candidates: flagged, the rest dropped.
+__global__ void k_cfill(DevState s, int par, const double* __restrict__ cbox,
+                        const uint64_t* __restrict__ keys, const int32_t* __restrict__ vals) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= s.np) return;
+    const int64_t np = s.np;
+    if (p >= s.n) {
+        s.ccnt[p] = 0;
+        return;
+    }
+    const D4* __restrict__ Uc = s.U[par];
+    const D4 xp = s.XV[p], up = Uc[p];
+    const double px = xp.x + up.x, py = xp.y + up.y, pz = xp.z + up.z;
+    s.ubuild[p] = up.x;
+    s.ubuild[np + p] = up.y;
+    s.ubuild[2 * np + p] = up.z;
+    const double ap = s.arad[p], skin = s.contact_skin;
+    const int sp = s.spec[p];
+    const int nn = s.nnb[p];
+    const int32_t* __restrict__ cp = s.col + s.slice_ptr[p / kSlice] + (p % kSlice);
+    int32_t c[3];
+    contact_cell(cbox, px, py, pz, c);
+    int cnt = 0;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int32_t cx = c[0] + dx, cy = c[1] + dy, cz = c[2] + dz;
+                if (cx < 0 || cy < 0 || cz < 0 || cx >= (1 << kMortonBits) ||
+                    cy >= (1 << kMortonBits) || cz >= (1 << kMortonBits))
+                    continue;
+                const uint64_t key = morton3(cx, cy, cz);
+                int64_t lo = 0, hi = s.n;
+                while (lo < hi) {
+                    const int64_t mid = (lo + hi) >> 1;
+                    if (keys[mid] < key) lo = mid + 1; else hi = mid;
+                }
+                for (int64_t t = lo; t < s.n && keys[t] == key; ++t) {
+                    const int32_t q = vals[t];
+                    if (q == p) continue;
+                    const D4 xq = s.XV[q], uq = Uc[q];
+                    const double d0 = (xq.x + uq.x) - px, d1 = (xq.y + uq.y) - py,
+                                 d2 = (xq.z + uq.z) - pz;
+                    const double rr = ap + s.arad[q] + skin;
+                    if (!(d0 * d0 + d1 * d1 + d2 * d2 < rr * rr)) continue;
+                    bool ref = false;
+                    if (s.spec[q] == sp)
+                        for (int k = 0; k < nn; ++k)
+                            ref = ref || cp[(int64_t)k * kSlice] == q;
+                    if (cnt < kContactCap)
+                        s.ccol[(int64_t)cnt * np + p] = (int32_t)((uint32_t)q | (ref ? 0x80000000u : 0u));
+                    ++cnt;
+                }
+            }
+    if (cnt > kContactCap) {
+        atomicOr(&s.err[2], kErrContact);
+        cnt = kContactCap;
+    }
+    s.ccnt[p] = cnt;
+}
+
+hipError_t launch_contact_build(const DevState& s, int parity, uint64_t* keys, int32_t* vals,
+                                int64_t n_pow2, double* cbox, hipStream_t st) {
+    k_cbox<<<1, 1024, 0, st>>>(s, parity, cbox);
+    constexpr int T = 256;
+    k_ckeys<<<(unsigned)((n_pow2 + T - 1) / T), T, 0, st>>>(s, parity, cbox, n_pow2, keys, vals);
+    for (int64_t k = 2; k <= n_pow2; k <<= 1)
+        for (int64_t j = k >> 1; j > 0; j >>= 1)
+            k_bitonic<<<(unsigned)((n_pow2 + T - 1) / T), T, 0, st>>>(keys, vals, n_pow2, j, k);
+    k_cfill<<<(unsigned)((s.np + T - 1) / T), T, 0, st>>>(s, parity, cbox, keys, vals);
+    return hipGetLastError();
 }
 
 hipError_t launch_bc_lists(const DevState& s, uint64_t* keys, int32_t* vals, int64_t n_pow2,

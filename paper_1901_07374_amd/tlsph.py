@@ -48,7 +48,7 @@ class Specimen(C.Structure):
                [("has_wall", C.c_int32), ("wall_n", C.c_double * 3), ("wall_d", C.c_double),
                 ("flow", C.c_int32), ("implicit_return", C.c_int32), ("flow_e0", C.c_double),
                 ("flow_beta", C.c_double), ("av_q1", C.c_double), ("av_q2", C.c_double),
-                ("h_per_spacing", C.c_double)]
+                ("h_per_spacing", C.c_double), ("contact_k", C.c_double)]
 
 
 class BCGroup(C.Structure):
@@ -78,6 +78,7 @@ def lib():
                                    C.c_size_t, _vp, C.POINTER(_vp)]
         L.tlsph_build_neighbors.argtypes = [_vp, _vp, _vp, _vp, _vp]
         L.tlsph_step.argtypes = [_vp, C.c_int32, _vp]
+        L.tlsph_set_contact.argtypes = [_vp, C.c_int32, C.c_double]
         L.tlsph_get_state.argtypes = [_vp, C.c_int, _vp, C.c_size_t, _vp]
         L.tlsph_set_state.argtypes = [_vp, C.c_int, _vp, C.c_size_t, _vp]
         L.tlsph_neighbor_count.argtypes = [_vp, C.POINTER(C.c_int64)]
@@ -284,6 +285,13 @@ class Sim:
         return dict(block_force=abs(out[0]), staged=out[0] < 0, block_deformation=out[1],
                     nnz=out[2], slots=out[3], n=out[4], flags=out[5],
                     lanes_per_particle=out[6], lds_bytes=out[7], tile=out[8])
+
+    def set_contact(self, every: int = 1, skin: float = 0.0):
+        """Rebuild the penalty-contact candidate lists every `every` steps
+        with the given skin (valid while no particle moves more than
+        skin / 2 between rebuilds; flagged otherwise)."""
+        self._check(lib().tlsph_set_contact(self.ctx, int(every), float(skin)),
+                    "tlsph_set_contact")
 
     def set_launch_shape(self, staged: bool, lanes: int, block_force: int = 256,
                          block_deformation: int = 256, tile: int = 0):

@@ -224,6 +224,62 @@ def test_graded_bar_trajectory_100_steps(tl, orc, precision):
     assert all(v <= tol for v in errs.values()), errs
 
 
+@pytest.mark.parametrize("precision,every", [("fp64", 1), ("mixed", 1), ("fp64", 10)])
+def test_contact_collision_trajectory(tl, orc, precision, every):
+    """Two bars meeting head on at 5 m/s each (elastic): they interact only
+    through the penalty contact.  Candidate lists rebuilt every step, or
+    every 10 steps with a skin of a fifth of the spacing."""
+    p = I.bar_collision(dx=0.25e-3, R=1.0e-3, L=2e-3, gap=0.01e-3, v0=5.0)
+    say("collision", precision, every, p.n)
+    prec = tl.FP64 if precision == "fp64" else tl.MIXED
+    g = tl.Sim(p, precision=prec, flags=tl.STORE_FORCE)
+    if every > 1:
+        g.set_contact(every, 0.2 * 0.25e-3)
+    o = orc.Sim(p)
+    for _ in range(8):
+        g.step(25)
+        o.step(25)
+    # the bars have met and pushed each other back
+    v = o.get("v")
+    assert v[: p.spec_offsets[1], 2].mean() < 4.0
+    errs = compare(g, o, skip=("d_init", "w_p", "f_void", "D", "eps_p", "eps_p_rate"))
+    say(errs)
+    assert g.info()["flags"] & 4 == 0
+    tol = 1e-10 if precision == "fp64" else 1e-4
+    # mixed: the energy per unit mass sums float stress-power increments of
+    # alternating sign through the elastic collision (about 1e-4 after 200
+    # steps); every other field stays within 1e-4
+    tols = {"e": 5e-4} if precision == "mixed" else {}
+    assert all(v <= tols.get(k, tol) for k, v in errs.items()), errs
+
+
+def test_contact_overlap_one_step(tl, orc):
+    """Two cubes (two specimens) overlapping by a few micrometres from
+    injected states: the contact force of one step, FP64 and mixed."""
+    dx, n = 1e-3, 5
+    i, j, k = I._lattice(n, n, n)
+    lat = np.stack([(i + 0.5) * dx, (j + 0.5) * dx, (k + 0.5) * dx], axis=1)
+    up = lat.copy()
+    up[:, 2] += n * dx - 4e-6
+    X = np.concatenate([lat, up])
+    m = I.material(dx, I.DMG_NONE, contact_k=1.0)
+    N = X.shape[0]
+    p = I.Problem("two_cubes", X, np.full(N, dx ** 3), np.array([0, lat.shape[0], N], np.int64),
+                  [m, dict(m)], np.full(N, -1, np.int32), [], np.zeros((N, 3)),
+                  dx=np.array([dx, dx]))
+    st = I.random_state(p, seed=31, u_scale=1e-7, frac_failed=0.1)
+    for prec, tol in ((tl.FP64, TOL_FP64), (tl.MIXED, TOL_MIXED)):
+        g = tl.Sim(p, precision=prec, flags=tl.STORE_FORCE)
+        o = orc.Sim(p)
+        g.set_state(st)
+        o.set_state(st)
+        g.step(1)
+        o.step(1)
+        errs = compare(g, o)
+        say("contact overlap", prec, errs)
+        assert all(v <= tol for v in errs.values()), errs
+
+
 def test_full_size_notched_bar_one_step(tl, orc):
     p = I.notched_bar()
     assert p.n == 200216
