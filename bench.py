@@ -421,10 +421,7 @@ def bench_taylor(args, torch, I, T):
 def bench_taylor_av(args, torch, I, T):
     """The Taylor bar with the artificial particle-velocity damping on
     (Q1 = 1, Q2 = 2): the general deformation-pass variant."""
-    p = I.taylor_bar()
-    mats = [dict(m, av_q1=1.0, av_q2=2.0) for m in p.materials]
-    prob = I.Problem(p.name, p.X, p.V0, p.spec_offsets, mats, p.bc_group, p.bc_groups,
-                     p.v_init, p.steps, p.dx)
+    prob = I.with_materials(I.taylor_bar(), **I.DAMPING)
     return bench_single(args, torch, I, T, "taylor_bar_1m_av", prob,
                         "Taylor bar on a rigid wall, CL damage, artificial viscosity",
                         "cockcroft-latham", lambda r: final_shape(r["sim"], prob))
@@ -450,8 +447,8 @@ def bench_collision(args, torch, I, T):
     """Two bars (R 2.5 mm, 10 mm long, dx 0.1 mm, 395 200 particles) meeting
     head on at 100 m/s each, CL damage, penalty contact with candidate lists
     rebuilt every 10 steps (skin 0.2 dx)."""
-    dx = 0.1e-3
-    prob = I.bar_collision(dx=dx, R=2.5e-3, L=10e-3, gap=0.05e-3, v0=100.0)
+    prob = I.bar_collision_395k()
+    dx = float(prob.dx[0])
     n0 = int(prob.spec_offsets[1])
     m = prob.materials[0]["rho0"] * prob.V0
 
@@ -535,8 +532,7 @@ def bench_notched_bar_voce(args, torch, I, T):
     curve: A = 792 MPa, B = 510 MPa, beta = 5) and the implicit return: the
     general deformation-pass variant."""
     return bench_notched_bar(args, torch, I, T, "notched_bar_200k_voce_implicit",
-                             flow=I.FLOW_VOCE, A=792e6, B=510e6, flow_beta=5.0,
-                             implicit_return=1)
+                             **I.VOCE_IMPLICIT)
 
 
 WORKLOADS = {"notched_bar_200k": (bench_notched_bar, 42000, 1000),

@@ -365,6 +365,29 @@ def bar_batch(n_spec: int = 256, lo: int = 2000, hi: int = 60000, jitter: float 
                    dx=np.array(dxs))
 
 
+# ----------------------------------------------------------------------------
+# variants of the generators above that the benchmark times and the full-size
+# tests check
+# ----------------------------------------------------------------------------
+# Voce hardening fitted near the Johnson-Cook curve, implicit return
+VOCE_IMPLICIT = dict(flow=FLOW_VOCE, A=792e6, B=510e6, flow_beta=5.0, implicit_return=1)
+# artificial particle-velocity damping coefficients (Q1, Q2)
+DAMPING = dict(av_q1=1.0, av_q2=2.0)
+
+
+def with_materials(p: Problem, **over) -> Problem:
+    """The problem with every specimen's parameters overridden."""
+    mats = [dict(m, **over) for m in p.materials]
+    return Problem(p.name, p.X, p.V0, p.spec_offsets, mats, p.bc_group, p.bc_groups, p.v_init,
+                   p.steps, p.dx)
+
+
+def bar_collision_395k() -> Problem:
+    """Two bars (R 2.5 mm, 10 mm long, dx 0.1 mm, 395 200 particles) 0.05 mm
+    apart, meeting head on at 100 m/s each."""
+    return bar_collision(dx=0.1e-3, R=2.5e-3, L=10e-3, gap=0.05e-3, v0=100.0)
+
+
 def subset(p: Problem, specs) -> Problem:
     """The given specimens of a batch as a problem of their own (group ids remapped)."""
     specs = list(specs)
