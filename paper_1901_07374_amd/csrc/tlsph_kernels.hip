@@ -1093,36 +1093,52 @@ __attribute__((amdgpu_waves_per_eu(staged_waves_min<R, S>(), 8))) k_pass_b_stage
     const D4* __restrict__ Uc = s.U[par];
     const GQRec<R>* __restrict__ GQ = gq_of<R>(s);
     const GHRec<R>* __restrict__ GH = gh_of<R>(s);
-    // the particle's own scalars, its first neighbour slots and what its
-    // finish needs are loaded first, so that their latency overlaps the staging
+    // Two slots per thread per round, their index loads issued before their
+    // record loads and those before the LDS stores.  The first round's halo
+    // indices are loaded before anything else; the particle's own scalars, its
+    // first neighbour slots and what its finish needs follow, so that their
+    // latencies overlap those of the staging (two memory latencies before the
+    // barrier rather than four).  Slots past the image load nothing; slots
+    // past the particle count (last tile) load the tile's first record and
+    // store nothing.
+    // (the halo entry is loaded unconditionally, at an index inside the
+    // tile's list, and blended in with masks: a select on a loaded value may
+    // be turned into a branch, whose join would wait for the load)
+    const auto particle_of = [&](int m) -> int64_t {
+        const int h = m - T;
+        const int64_t hv = hl[h >= 0 && m < tot ? h : 0];
+        const int64_t in_tile = -(int64_t)(h < 0), past = -(int64_t)(m >= tot);
+        const int64_t g = ((start + m) & in_tile) | (hv & ~in_tile);
+        return (s.n & past) | (g & ~past);
+    };
+    int m0 = threadIdx.x;
+    int64_t g0 = particle_of(m0), g1 = particle_of(m0 + B);
     const int pl = threadIdx.x / S;
     const int sub = threadIdx.x % S;
     const int64_t i = start + pl;
     const bool in = i < s.n;
     const int64_t ii = in ? i : start;
+    // (the loads that others depend on first: count, slice start, specimen)
+    const int cnt = in ? s.nnb[i] : 0;
+    const int64_t slice0 = s.slice_ptr[ii / kSlice];
     const int sp = s.spec[ii];
     const DevSpec& P = s.specs[sp];
     const R inv_h = R(P.inv_h);
-    const int cnt = in ? s.nnb[i] : 0;
-    const uint16_t* __restrict__ lp = s.lcol + s.slice_ptr[ii / kSlice] + (ii % kSlice);
+    const uint16_t* __restrict__ lp = s.lcol + slice0 + (ii % kSlice);
     const auto idx = [&](int k) { return (int)lp[(int64_t)k * kSlice]; };
     const FirstIdx<S> first = first_indices<S>(cnt, sub, idx);
     constexpr bool kEarly = staged_finish_early<R, S>();
     FinishIn fin_early;
     if constexpr (kEarly) fin_early = finish_in(s, ii, P);
-    // two slots per thread per round, their index loads issued before their
-    // record loads and those before the LDS stores, so that one round costs
-    // two memory latencies; slots past the particle count (last tile) load
-    // the tile's first record and store nothing
-    for (int m0 = threadIdx.x; m0 < tot; m0 += 2 * B) {
-        const int m1 = m0 + B;
-        const int64_t g0 = m0 < T ? start + m0 : (int64_t)hl[m0 - T];
-        const int64_t g1 = m1 >= tot ? s.n : (m1 < T ? start + m1 : (int64_t)hl[m1 - T]);
+    while (m0 < tot) {
         const int64_t l0 = g0 < s.n ? g0 : start, l1 = g1 < s.n ? g1 : start;
         const LRecB<R> r0 = make_recb<R>(XV[l0], GQ[l0], GH[l0], Uc[l0]);
         const LRecB<R> r1 = make_recb<R>(XV[l1], GQ[l1], GH[l1], Uc[l1]);
         if (g0 < s.n) LdsB<R>::put(L, M, m0, r0);
-        if (g1 < s.n) LdsB<R>::put(L, M, m1, r1);
+        if (g1 < s.n) LdsB<R>::put(L, M, m0 + B, r1);
+        m0 += 2 * B;
+        g0 = particle_of(m0);
+        g1 = particle_of(m0 + B);
     }
     __syncthreads();
     const LRecB<R> ni = LdsB<R>::get(L, M, in ? pl : 0);
