@@ -1145,8 +1145,10 @@ __attribute__((amdgpu_waves_per_eu(staged_waves_min<R, S>(), 8))) k_pass_b_stage
     const ForceAcc<R> A = pair_sums<R, S>(
         ni, cnt, sub, inv_h, idx, [&](int m) { return LdsB<R>::get(L, M, m); }, first);
     // the particle's own Q is needed only now: reread it rather than keep it
-    // in registers through the pair loop
-    __syncthreads();
+    // in registers through the pair loop (the image is not written after the
+    // barrier above, so a compiler barrier suffices: waves go on to their
+    // finish as their own sums end)
+    asm volatile("" ::: "memory");
     if (in && sub == 0)
         force_finish<R>(s, i, par, P, sp, LdsB<R>::get(L, M, pl), A,
                         kEarly ? fin_early : finish_in(s, i, P));

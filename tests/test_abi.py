@@ -82,6 +82,9 @@ def test_create_rejects_bad_arguments_without_hip(L):
     assert _create(L, p, ws=256 * 1024 + 8)[0] == 1                 # misaligned
     assert _create(L, p, nbytes=1024)[0] == 1                         # too small
     assert _create(L, p, offs=[0, p.n - 1])[0] == 1                   # offsets do not cover n
+    two = I.Problem(p.name, p.X, p.V0, np.array([0, 0, p.n], np.int64),
+                    [p.materials[0], dict(p.materials[0])], p.bc_group, p.bc_groups, p.v_init)
+    assert _create(L, two)[0] == 1                                    # a specimen without particles
     assert _create(L, p, flags=64)[0] == 1
     bad = dict(p.materials[0])
     for k, v in [("rho0", 0.0), ("E", -1.0), ("nu", 0.5), ("h", 0.0), ("dt", float("nan")),

@@ -66,8 +66,16 @@ def remat(p, *overs):
                      p.v_init, p.steps, p.dx)
 
 
+def free(p):
+    """The problem without prescribed-velocity groups."""
+    return I.Problem(p.name, p.X, p.V0, p.spec_offsets, p.materials, np.full(p.n, -1, np.int32),
+                     [], p.v_init, p.steps, p.dx)
+
+
 CASES = {
     "cube_jc_nodamage": lambda: I.cube(),
+    # fewer particles than a wave and than a tile
+    "cube_27_jc_damage": lambda: free(I.cube(nside=3, damage=I.DMG_JC)),
     "bar_swift_implicit": lambda: remat(I.notched_bar(dx=0.8e-3), dict(SWIFT, implicit_return=1)),
     "bar_voce_implicit_cl": lambda: remat(I.notched_bar(dx=0.8e-3, damage=I.DMG_CL, Wcr=300e6),
                                           dict(VOCE, implicit_return=1)),
