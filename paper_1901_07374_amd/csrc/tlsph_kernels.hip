@@ -972,6 +972,21 @@ k_pass_b(DevState s, int par) {
         force_finish<R>(s, i, par, P, sp, make_recb<R>(XV[i], GQ[i], GH[i], Uc[i]), A, fin);
 }
 
+// Particle of slot m of a tile's LDS image (the tile's T particles from
+// `start`, then its halo list hl): n for slots past the image.  The halo entry
+// is loaded unconditionally, at an index inside the tile's list, and blended
+// in with masks: a select on a loaded value may be turned into a branch, whose
+// join waits for the load, and the staging wants all its index loads in
+// flight together.
+__device__ __forceinline__ int64_t slot_particle(int m, int T, int tot, int64_t start, int64_t n,
+                                                 const int32_t* __restrict__ hl) {
+    const int h = m - T;
+    const int64_t hv = hl[h >= 0 && m < tot ? h : 0];
+    const int64_t in_tile = -(int64_t)(h < 0), past = -(int64_t)(m >= tot);
+    const int64_t g = ((start + m) & in_tile) | (hv & ~in_tile);
+    return (n & past) | (g & ~past);
+}
+
 // Largest workgroup of the staged force pass with S lanes per particle: four
 // lanes run tiles of at most 128 particles, so that the register budget
 // stays at two waves per SIMD.
@@ -1098,19 +1113,9 @@ __attribute__((amdgpu_waves_per_eu(staged_waves_min<R, S>(), 8))) k_pass_b_stage
     // indices are loaded before anything else; the particle's own scalars, its
     // first neighbour slots and what its finish needs follow, so that their
     // latencies overlap those of the staging (two memory latencies before the
-    // barrier rather than four).  Slots past the image load nothing; slots
-    // past the particle count (last tile) load the tile's first record and
-    // store nothing.
-    // (the halo entry is loaded unconditionally, at an index inside the
-    // tile's list, and blended in with masks: a select on a loaded value may
-    // be turned into a branch, whose join would wait for the load)
-    const auto particle_of = [&](int m) -> int64_t {
-        const int h = m - T;
-        const int64_t hv = hl[h >= 0 && m < tot ? h : 0];
-        const int64_t in_tile = -(int64_t)(h < 0), past = -(int64_t)(m >= tot);
-        const int64_t g = ((start + m) & in_tile) | (hv & ~in_tile);
-        return (s.n & past) | (g & ~past);
-    };
+    // barrier rather than four).  Slots past the image, and past the particle
+    // count (last tile), load the tile's first record and store nothing.
+    const auto particle_of = [&](int m) { return slot_particle(m, T, tot, start, s.n, hl); };
     int m0 = threadIdx.x;
     int64_t g0 = particle_of(m0), g1 = particle_of(m0 + B);
     const int pl = threadIdx.x / S;
@@ -1430,24 +1435,24 @@ k_pass_a_staged(DevState s, int par) {
     const int32_t* __restrict__ hl = s.halo + tile * (int64_t)s.halo_cap;
     const D4* __restrict__ XV = s.XV;
     const D4* __restrict__ VW = s.VW;
-    // the particle's own scalars first, then up to four slots per thread per
-    // round: index loads, record loads, LDS stores (two memory latencies a
-    // round); slots past the particle count load the tile's first record and
-    // store nothing
+    // Up to four slots per thread per round: index loads, record loads, LDS
+    // stores (two memory latencies a round).  The first round's index loads
+    // go out before the particle's own scalars, whose latency then overlaps
+    // them.  Slots past the image, and past the particle count (last tile),
+    // load the tile's first record and store nothing.
+    constexpr int kU = 4;
+    int m0 = threadIdx.x;
+    int64_t g[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) g[u] = slot_particle(m0 + u * T, T, tot, start, s.n, hl);
     const int64_t i = start + threadIdx.x;
     const bool in = i < s.n;
     const int64_t ii = in ? i : start;
-    const int sp_lane = s.spec[ii];
     const int cnt = s.nnb[ii];
-    const uint16_t* __restrict__ lp = s.lcol + s.slice_ptr[ii / kSlice] + (ii % kSlice);
-    constexpr int kU = 4;
-    for (int m0 = threadIdx.x; m0 < tot; m0 += kU * T) {
-        int64_t g[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int m = m0 + u * T;
-            g[u] = m >= tot ? s.n : (m < T ? start + m : (int64_t)hl[m - T]);
-        }
+    const int64_t slice0 = s.slice_ptr[ii / kSlice];
+    const int sp_lane = s.spec[ii];
+    const uint16_t* __restrict__ lp = s.lcol + slice0 + (ii % kSlice);
+    while (m0 < tot) {
         D4 x[kU], v[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
@@ -1465,6 +1470,9 @@ k_pass_a_staged(DevState s, int par) {
                 Lvz[m] = v[u].z;
             }
         }
+        m0 += kU * T;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) g[u] = slot_particle(m0 + u * T, T, tot, start, s.n, hl);
     }
     __syncthreads();
     if (threadIdx.x >= T || !in) return;
