@@ -1297,6 +1297,7 @@ __device__ __forceinline__ void pass_a_update(const DevState& s, int64_t i, int 
         for (int k = 0; k < 6; ++k) sn[k] = s.sig[k * np + i];
     }
     double eps = s.eps_p[i], rate = s.eps_rate[i], e = s.e[i];
+    const double rate0 = rate;
     double dinit = 0.0, wp = 0.0, fv = 0.0;
     const int model = DM >= 0 ? DM : P.damage;
     if (model == 1 || model == 2) dinit = s.d_init[i];
@@ -1341,15 +1342,23 @@ __device__ __forceinline__ void pass_a_update(const DevState& s, int64_t i, int 
     ho.pad = R(0);
     GQ[is] = go;
     GH[is] = ho;
+    // The plastic strain and its accumulators change only where the particle
+    // yields (rate = increment / dt is then nonzero; a zero increment leaves
+    // every one of them as it was), the rate also where it stops yielding, D
+    // only where it grows: the other particles (most, in an elastic body)
+    // store none of them, and memory lines holding no changed value are not
+    // written.
     if (Di < 1.0) {
-        s.eps_p[is] = eps;
-        s.eps_rate[is] = rate;
         s.e[is] = e;
-        if (model == 1 || model == 2) s.d_init[is] = dinit;
-        if (model == 1) s.w_p[is] = wp;
-        if (model == 3) s.f_void[is] = fv;
+        if (rate != 0.0) {
+            s.eps_p[is] = eps;
+            if (model == 1 || model == 2) s.d_init[is] = dinit;
+            if (model == 1) s.w_p[is] = wp;
+            if (model == 3) s.f_void[is] = fv;
+        }
+        if (rate != rate0) s.eps_rate[is] = rate;
     }
-    s.D[is] = o.D;
+    if (o.D != Di) s.D[is] = o.D;
     if constexpr (kFlow) {
         // artificial viscous force for the next kick: rho0 V_i (1 - D_i) times
         // the gathered sum (w_i = V_i (1 - D_i^n))
