@@ -57,7 +57,7 @@ __global__ void k_bbox(const double* __restrict__ X, const double* __restrict__ 
     red[6][threadIdx.x] = vmax;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
+        if ((int)threadIdx.x < w) {
             for (int c = 0; c < 3; ++c) {
                 red[c][threadIdx.x] = fmin(red[c][threadIdx.x], red[c][threadIdx.x + w]);
                 red[3 + c][threadIdx.x] = fmax(red[3 + c][threadIdx.x], red[3 + c][threadIdx.x + w]);
@@ -95,7 +95,7 @@ __device__ __forceinline__ void cell_of(const double* bb, double x, double y, do
 }
 
 __global__ void k_keys(const double* __restrict__ X, int64_t n, int64_t n_pow2,
-                       const int64_t* __restrict__ off, int n_spec, const DevSpec* __restrict__ specs,
+                       const int64_t* __restrict__ off, int n_spec,
                        const double* __restrict__ bbox, uint64_t* __restrict__ keys,
                        int32_t* __restrict__ vals, int32_t* __restrict__ err) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -401,8 +401,8 @@ hipError_t launch_build_count(DevState& s, const BuildBuffers& b, hipStream_t st
     const int T = 256;
     k_bbox<<<s.n_spec, 256, 0, st>>>(b.X_in, b.V0_in, s.n, b.spec_off, s.specs, b.bbox);
     k_keys<<<(unsigned)((b.n_pow2 + T - 1) / T), T, 0, st>>>(b.X_in, s.n, b.n_pow2, b.spec_off,
-                                                             s.n_spec, s.specs, b.bbox, b.keys,
-                                                             b.vals, s.err);
+                                                             s.n_spec, b.bbox, b.keys, b.vals,
+                                                             s.err);
     for (int64_t k = 2; k <= b.n_pow2; k <<= 1)
         for (int64_t j = k >> 1; j > 0; j >>= 1)
             k_bitonic<<<(unsigned)((b.n_pow2 + T - 1) / T), T, 0, st>>>(b.keys, b.vals, b.n_pow2,
@@ -1396,7 +1396,7 @@ __host__ __device__ constexpr int pass_a_waves_min() {
 // turns by specimen, one turn unless the wave straddles two specimens.
 template <typename R, int DM, bool kFlow, bool kVarH = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pass_a_waves_min<R, DM, kFlow>(), 8)))
-k_pass_a(DevState s, int par) {
+k_pass_a(DevState s, int /* displacement buffer: unused here */) {
     const int64_t i = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= s.n) return;
     const int sp_lane = s.spec[i];
@@ -1430,7 +1430,7 @@ k_pass_a(DevState s, int par) {
 constexpr int kLdsABytes = 56;
 template <typename R, int DM, bool kFlow>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pass_a_waves_min<R, DM, kFlow>(), 8)))
-k_pass_a_staged(DevState s, int par) {
+k_pass_a_staged(DevState s, int /* displacement buffer: unused here */) {
     extern __shared__ __align__(16) unsigned char lds_a[];
     const int M = s.lds_slots;
     double2* __restrict__ Lxy = reinterpret_cast<double2*>(lds_a);
@@ -1484,7 +1484,7 @@ k_pass_a_staged(DevState s, int par) {
         for (int u = 0; u < kU; ++u) g[u] = slot_particle(m0 + u * T, T, tot, start, s.n, hl);
     }
     __syncthreads();
-    if (threadIdx.x >= T || !in) return;
+    if ((int)threadIdx.x >= T || !in) return;
     for (;;) {
         const int sp = __builtin_amdgcn_readfirstlane(sp_lane);
         if (sp == sp_lane) {
@@ -1497,7 +1497,7 @@ k_pass_a_staged(DevState s, int par) {
                                   [&](int k) { return (int)lp[(int64_t)k * kSlice]; },
                                   [&](int m) {
                                       const double2 a = Lxy[m], b = Lzw[m], c = Lvxy[m];
-                                      return NbrA{a.x, a.y, b.x, c.x, c.y, Lvz[m], b.y};
+                                      return NbrA{a.x, a.y, b.x, c.x, c.y, Lvz[m], b.y, 0.0};
                                   }, M9, av_par<R>(P), AV);
             pass_a_update<R, DM, kFlow>(s, i, sp, M9, b.y, AV);
             break;
@@ -1967,7 +1967,7 @@ __device__ __forceinline__ void block_reduce(double (*red)[256], double v[NV], c
     for (int q = 0; q < NV; ++q) red[q][threadIdx.x] = v[q];
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
+        if ((int)threadIdx.x < w)
             for (int q = 0; q < NV; ++q)
                 red[q][threadIdx.x] = is_max[q] ? fmax(red[q][threadIdx.x], red[q][threadIdx.x + w])
                                                 : red[q][threadIdx.x] + red[q][threadIdx.x + w];
