@@ -1,13 +1,16 @@
 """Write notched_bar_small_oracle.json: the FP64 oracle's run of the small
 notched bar (0.5 mm lattice, Johnson-Cook plasticity and damage, grips at
-+-10 m/s with a 1 ms ramp) from rest to past failure.
++-10 m/s with a 1 ms ramp) from rest to past failure; with --full, write
+notched_bar_oracle.json, the same run of the full-size bar (0.25 mm lattice,
+200 216 particles).
 
 Every 20 steps it records the reaction on the top grip (minus the sum of the
 axial nodal forces of its particles) and the grip separation (difference of
 the two grips' mean axial displacements).  Only the oracle and the seeded
 input generator are used.
 
-Usage: python tests/golden/make_notched_bar_small.py  (about a minute on 8 cores)
+Usage: python tests/golden/make_notched_bar_small.py [--full]
+(about a minute on 8 cores; with --full about an hour on 8 cores)
 """
 import json
 import os
@@ -24,12 +27,14 @@ import oracle  # noqa: E402
 from paper_1901_07374_amd import inputs as I  # noqa: E402
 
 EVERY = 20
-DX = 0.5e-3
 MAX_STEPS = 60000
 
 
 def main():
-    p = I.notched_bar(dx=DX)
+    full = "--full" in sys.argv
+    dx = 0.25e-3 if full else 0.5e-3
+    name = "notched_bar_oracle.json" if full else "notched_bar_small_oracle.json"
+    p = I.notched_bar(dx=dx)
     o = oracle.Sim(p)
     top, bot = p.bc_group == 1, p.bc_group == 0
     steps, reac, sep = [], [], []
@@ -55,14 +60,16 @@ def main():
             print(f"step {k} sep {s * 1e3:.4f} mm reaction {r / 1e3:.3f} kN "
                   f"({time.time() - t0:.0f} s)", flush=True)
     out = {
-        "what": "FP64 oracle run of the small notched bar to past failure",
-        "workload": "notched_bar(dx=0.5e-3): R 5 mm, L 40 mm, 90-degree V-notch 1 mm deep, "
+        "what": f"FP64 oracle run of the {'full-size' if full else 'small'} notched bar to "
+                "past failure",
+        "workload": f"notched_bar(dx={dx:g}): R 5 mm, L 40 mm, 90-degree V-notch 1 mm deep, "
                     "jitter 3 %, JC plasticity + JC damage, grips +-10 m/s (1 - exp(-t/1 ms))",
-        "written_by": "tests/golden/make_notched_bar_small.py (oracle only)",
+        "written_by": "tests/golden/make_notched_bar_small.py" + (" --full" if full else "") +
+                      " (oracle only)",
         "particles": p.n, "dt_s": p.materials[0]["dt"], "diag_every": EVERY,
         "step": steps, "reaction_N": reac, "separation_m": sep,
     }
-    with open(os.path.join(HERE, "notched_bar_small_oracle.json"), "w") as fh:
+    with open(os.path.join(HERE, name), "w") as fh:
         json.dump(out, fh)
     print("wrote", len(steps), "samples, peak", peak, "N", flush=True)
 

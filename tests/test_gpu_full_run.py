@@ -1,6 +1,8 @@
-"""Full runs against the oracle: the small notched bar (25 000 particles,
-JC plasticity and damage) from rest to past failure, FP64 and mixed, compared
-with the oracle's run stored by tests/golden/make_notched_bar_small.py.
+"""Full runs against the oracle: the small notched bar (25 000 particles)
+and the full-size bar of the benchmark (200 216 particles), JC plasticity and
+damage, from rest to past failure, FP64 and mixed, compared with the oracle's
+runs stored by tests/golden/make_notched_bar_small.py (with --full for the
+full-size bar).
 
 While the bar is elastic (reaction below 20 % of the peak) the reaction
 curve must follow the oracle's to rounding (FP64) or to the mixed form's
@@ -48,9 +50,8 @@ def fd(sep, reac, level):
     return None
 
 
-@pytest.fixture(scope="module")
-def golden():
-    with open(os.path.join(HERE, "golden", "notched_bar_small_oracle.json")) as fh:
+def golden(name):
+    with open(os.path.join(HERE, "golden", name)) as fh:
         return json.load(fh)
 
 
@@ -81,8 +82,7 @@ def tl():
     return tlsph
 
 
-def test_small_bar_to_failure_against_oracle(tl, golden):
-    p = I.notched_bar(dx=0.5e-3)
+def check_run(tl, p, golden):
     assert p.n == golden["particles"]
     ro = np.array(golden["reaction_N"])
     so = np.array(golden["separation_m"])
@@ -120,3 +120,11 @@ def test_small_bar_to_failure_against_oracle(tl, golden):
         allv = fds[lvl] + fdm[lvl]
         med, rng = float(np.median(allv)), max(allv) - min(allv)
         assert med - rng <= fo[lvl] <= med + rng, (lvl, fo[lvl], allv)
+
+
+def test_small_bar_to_failure_against_oracle(tl):
+    check_run(tl, I.notched_bar(dx=0.5e-3), golden("notched_bar_small_oracle.json"))
+
+
+def test_full_size_bar_to_failure_against_oracle(tl):
+    check_run(tl, I.notched_bar(), golden("notched_bar_oracle.json"))
