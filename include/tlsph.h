@@ -123,8 +123,9 @@ typedef struct {
     double h_per_spacing;                     /* > 0: graded spacing, each particle's
                                                  support h_i = h_per_spacing V_i^(1/3)
                                                  and a pair's (h_i + h_j) / 2 (membership
-                                                 and kernel); the step then runs the
-                                                 unstaged kernels.  0: h for all     */
+                                                 and kernel); the staged kernels then
+                                                 carry each slot's support in LDS.
+                                                 0: h for all                        */
     double contact_k;                         /* penalty contact factor (0: off): particles
                                                  are spheres of radius V_i^(1/3)/2; two
                                                  closer than a_i + a_j in the current

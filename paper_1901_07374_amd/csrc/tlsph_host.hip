@@ -345,9 +345,7 @@ tlsph_status set_tile(tlsph_ctx* c, int T, hipStream_t stream) {
     c->st.halo_cap = T * L.k_cap;
     int E = 256;
     while (E < T * L.k_cap) E <<= 1;
-    // graded spacing runs the unstaged kernels (per-pair supports)
-    if ((2 * (size_t)E + 257) * 4 > (size_t)c->max_lds || (c->flags & TLSPH_NO_STAGING) ||
-        c->st.var_h)
+    if ((2 * (size_t)E + 257) * 4 > (size_t)c->max_lds || (c->flags & TLSPH_NO_STAGING))
         return TLSPH_OK;
     const int32_t zero = 0;
     HIPCHK(c, hipMemcpyAsync(c->ws + L.err + 16, &zero, 4, hipMemcpyHostToDevice, stream));
@@ -355,14 +353,16 @@ tlsph_status set_tile(tlsph_ctx* c, int T, hipStream_t stream) {
     int32_t largest = 0;
     HIPCHK(c, hipMemcpyAsync(&largest, c->ws + L.err + 16, 4, hipMemcpyDeviceToHost, stream));
     HIPCHK(c, hipStreamSynchronize(stream));
-    const size_t lds = (size_t)(T + largest) * staged_record_bytes(L.mixed);
+    const bool var_h = c->st.var_h != 0;
+    const size_t lds = (size_t)(T + largest) * staged_record_bytes(L.mixed, var_h);
     if (lds <= (size_t)c->max_lds && T + largest <= 65536) {
         HIPCHK(c, prepare_staged(lds));
         c->staged_ok = true;
         c->lds_b = lds;
         c->st.lds_slots = T + largest;
-        // the deformation pass's records (56 bytes) within the default LDS limit
-        c->st.staged_lds_a = (size_t)(T + largest) * 56 <= 65536 ? 1 : 0;
+        // the deformation pass's records (56 bytes, 64 with graded spacing)
+        // within the default LDS limit
+        c->st.staged_lds_a = (size_t)(T + largest) * staged_a_record_bytes(var_h) <= 65536 ? 1 : 0;
     }
     return TLSPH_OK;
 }
@@ -951,8 +951,6 @@ tlsph_status tlsph_set_launch_shape(tlsph_ctx* c, const int32_t shape[5], hipStr
                     "deformation-pass block must be 0 (staged), 64, 128, 192 or 256");
     if (staged && (tile < 64 || tile > kTile))
         return fail(c, TLSPH_E_INVALID_ARG, "tile must hold 64 to 256 particles");
-    if (c->st.var_h && (staged || blk_a == 0))
-        return fail(c, TLSPH_E_UNSUPPORTED, "graded spacing runs the unstaged kernels only");
     if (staged && tile > staged_tile_max(sub))
         return fail(c, TLSPH_E_UNSUPPORTED, "four lanes per particle run tiles of at most 128");
     if (staged) {

@@ -173,7 +173,10 @@ hipError_t launch_halo(const DevState& s, int k_cap, hipStream_t st);
 hipError_t prepare_staged(size_t lds_bytes_b);
 // Largest tile the staged force pass runs with `sub` lanes per particle.
 int staged_tile_max(int sub);
-size_t staged_record_bytes(bool mixed);
+// LDS bytes per slot of the staged force pass and the staged deformation pass
+// (graded spacing adds the slot's support radius).
+size_t staged_record_bytes(bool mixed, bool var_h);
+size_t staged_a_record_bytes(bool var_h);
 hipError_t launch_shape_and_init(const DevState& s, bool mixed, hipStream_t st);
 hipError_t launch_get_field(const DevState& s, int field, int parity, bool mixed, double* dst,
                             hipStream_t st);

@@ -1079,10 +1079,11 @@ struct LdsB<float> {
 // SIMDs several waves to switch between.
 // Waves per SIMD the staged force pass must leave room for: two workgroups per
 // CU need four (mixed form, two or four lanes per particle: tiles up to 196
-// and 128 particles) or three (FP64, four lanes: tiles up to 96).
-template <typename R, int S>
+// and 128 particles) or three (FP64, four lanes: tiles up to 96).  With graded
+// spacing the mixed form needs more than 128 registers: three.
+template <typename R, int S, bool kVarH = false>
 __host__ __device__ constexpr int staged_waves_min() {
-    return sizeof(R) == 4 && S >= 2 ? 4 : (S == 4 ? 3 : 1);
+    return sizeof(R) == 4 && S >= 2 ? (kVarH ? 3 : 4) : (S == 4 ? 3 : 1);
 }
 // Whether the finish's inputs are loaded before the staging (their registers
 // then live through the pair sums; the mixed form with two lanes has none to
@@ -1092,12 +1093,15 @@ __host__ __device__ constexpr bool staged_finish_early() {
     return !(sizeof(R) == 4 && S == 2);
 }
 
-template <typename R, int S>
+// Graded spacing (kVarH): the slots' support radii follow the records in LDS
+// (one double per slot).
+template <typename R, int S, bool kVarH = false>
 __global__ void __launch_bounds__(staged_block_max(S))
-__attribute__((amdgpu_waves_per_eu(staged_waves_min<R, S>(), 8))) k_pass_b_staged(DevState s, int par) {
+__attribute__((amdgpu_waves_per_eu(staged_waves_min<R, S, kVarH>(), 8))) k_pass_b_staged(DevState s, int par) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     double2* __restrict__ L = reinterpret_cast<double2*>(lds_raw);
     const int M = s.lds_slots;
+    double* __restrict__ Lhs = reinterpret_cast<double*>(L + (size_t)M * LdsB<R>::kUnits);
     const int T = s.tile;
     const int B = T * S;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -1134,21 +1138,36 @@ __attribute__((amdgpu_waves_per_eu(staged_waves_min<R, S>(), 8))) k_pass_b_stage
     const FirstIdx<S> first = first_indices<S>(cnt, sub, idx);
     constexpr bool kEarly = staged_finish_early<R, S>();
     FinishIn fin_early;
-    if constexpr (kEarly) fin_early = finish_in(s, ii, P);
+    if constexpr (kEarly) fin_early = finish_in<kVarH>(s, ii, P);
     while (m0 < tot) {
         const int64_t l0 = g0 < s.n ? g0 : start, l1 = g1 < s.n ? g1 : start;
         const LRecB<R> r0 = make_recb<R>(XV[l0], GQ[l0], GH[l0], Uc[l0]);
         const LRecB<R> r1 = make_recb<R>(XV[l1], GQ[l1], GH[l1], Uc[l1]);
-        if (g0 < s.n) LdsB<R>::put(L, M, m0, r0);
-        if (g1 < s.n) LdsB<R>::put(L, M, m0 + B, r1);
+        double h0 = 0.0, h1 = 0.0;
+        if constexpr (kVarH) {
+            h0 = s.hs[l0];
+            h1 = s.hs[l1];
+        }
+        if (g0 < s.n) {
+            LdsB<R>::put(L, M, m0, r0);
+            if constexpr (kVarH) Lhs[m0] = h0;
+        }
+        if (g1 < s.n) {
+            LdsB<R>::put(L, M, m0 + B, r1);
+            if constexpr (kVarH) Lhs[m0 + B] = h1;
+        }
         m0 += 2 * B;
         g0 = particle_of(m0);
         g1 = particle_of(m0 + B);
     }
     __syncthreads();
-    const LRecB<R> ni = LdsB<R>::get(L, M, in ? pl : 0);
-    const ForceAcc<R> A = pair_sums<R, S>(
-        ni, cnt, sub, inv_h, idx, [&](int m) { return LdsB<R>::get(L, M, m); }, first);
+    const auto rec = [&](int m) {
+        LRecB<R> r = LdsB<R>::get(L, M, m);
+        if constexpr (kVarH) r.hs = Lhs[m];
+        return r;
+    };
+    const LRecB<R> ni = rec(in ? pl : 0);
+    const ForceAcc<R> A = pair_sums<R, S, kVarH>(ni, cnt, sub, inv_h, idx, rec, first);
     // the particle's own Q is needed only now: reread it rather than keep it
     // in registers through the pair loop (the image is not written after the
     // barrier above, so a compiler barrier suffices: waves go on to their
@@ -1156,7 +1175,7 @@ __attribute__((amdgpu_waves_per_eu(staged_waves_min<R, S>(), 8))) k_pass_b_stage
     asm volatile("" ::: "memory");
     if (in && sub == 0)
         force_finish<R>(s, i, par, P, sp, LdsB<R>::get(L, M, pl), A,
-                        kEarly ? fin_early : finish_in(s, i, P));
+                        kEarly ? fin_early : finish_in<kVarH>(s, i, P));
 }
 
 // Pass A (deformation and constitutive update to t^{n+1}).
@@ -1427,8 +1446,9 @@ k_pass_a(DevState s, int /* displacement buffer: unused here */) {
 // halo (position, velocity, V0 (1 - D): 56 bytes) are staged in LDS once and
 // the neighbour sums read them through the 16-bit local slots.  Same
 // arithmetic in the same order as k_pass_a.
+// Graded spacing (kVarH): the support radius follows (64 bytes).
 constexpr int kLdsABytes = 56;
-template <typename R, int DM, bool kFlow>
+template <typename R, int DM, bool kFlow, bool kVarH = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pass_a_waves_min<R, DM, kFlow>(), 8)))
 k_pass_a_staged(DevState s, int /* displacement buffer: unused here */) {
     extern __shared__ __align__(16) unsigned char lds_a[];
@@ -1437,6 +1457,7 @@ k_pass_a_staged(DevState s, int /* displacement buffer: unused here */) {
     double2* __restrict__ Lzw = Lxy + M;
     double2* __restrict__ Lvxy = Lzw + M;
     double* __restrict__ Lvz = reinterpret_cast<double*>(Lvxy + M);
+    double* __restrict__ Lhs = Lvz + M;
     const int T = s.tile;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t start = tile * T;
@@ -1463,11 +1484,13 @@ k_pass_a_staged(DevState s, int /* displacement buffer: unused here */) {
     const uint16_t* __restrict__ lp = s.lcol + slice0 + (ii % kSlice);
     while (m0 < tot) {
         D4 x[kU], v[kU];
+        double hv[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             const int64_t l = g[u] < s.n ? g[u] : start;
             x[u] = XV[l];
             v[u] = VW[l];
+            if constexpr (kVarH) hv[u] = s.hs[l];
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
@@ -1477,6 +1500,7 @@ k_pass_a_staged(DevState s, int /* displacement buffer: unused here */) {
                 Lzw[m] = double2{x[u].z, v[u].w};
                 Lvxy[m] = double2{v[u].x, v[u].y};
                 Lvz[m] = v[u].z;
+                if constexpr (kVarH) Lhs[m] = hv[u];
             }
         }
         m0 += kU * T;
@@ -1492,13 +1516,14 @@ k_pass_a_staged(DevState s, int /* displacement buffer: unused here */) {
             const int t = threadIdx.x;
             const double2 a = Lxy[t], b = Lzw[t], c = Lvxy[t];
             R M9[9], AV[3];
-            gather_fdot<R, kFlow>(D4{a.x, a.y, b.x, 0.0}, D4{c.x, c.y, Lvz[t], b.y}, cnt,
-                                  R(P.inv_h), R(P.grad_k),
-                                  [&](int k) { return (int)lp[(int64_t)k * kSlice]; },
-                                  [&](int m) {
-                                      const double2 a = Lxy[m], b = Lzw[m], c = Lvxy[m];
-                                      return NbrA{a.x, a.y, b.x, c.x, c.y, Lvz[m], b.y, 0.0};
-                                  }, M9, av_par<R>(P), AV);
+            gather_fdot<R, kFlow, kVarH>(D4{a.x, a.y, b.x, 0.0}, D4{c.x, c.y, Lvz[t], b.y}, cnt,
+                                         R(P.inv_h), kVarH ? R(1) : R(P.grad_k),
+                                         [&](int k) { return (int)lp[(int64_t)k * kSlice]; },
+                                         [&](int m) {
+                                             const double2 a = Lxy[m], b = Lzw[m], c = Lvxy[m];
+                                             return NbrA{a.x, a.y, b.x, c.x, c.y, Lvz[m], b.y,
+                                                         kVarH ? Lhs[m] : 0.0};
+                                         }, M9, av_par<R>(P), AV, kVarH ? Lhs[t] : 0.0);
             pass_a_update<R, DM, kFlow>(s, i, sp, M9, b.y, AV);
             break;
         }
@@ -1510,10 +1535,16 @@ static hipError_t launch_b(const DevState& s, int parity, int block, bool mixed,
                            size_t lds_bytes) {
     if (s.staged) {
         const unsigned grid = (unsigned)((s.n + s.tile - 1) / s.tile);
-        if (mixed)
+        if (s.var_h) {   // graded spacing: per-pair supports
+            if (mixed)
+                k_pass_b_staged<float, S, true><<<grid, s.tile * S, lds_bytes, st>>>(s, parity);
+            else
+                k_pass_b_staged<double, S, true><<<grid, s.tile * S, lds_bytes, st>>>(s, parity);
+        } else if (mixed) {
             k_pass_b_staged<float, S><<<grid, s.tile * S, lds_bytes, st>>>(s, parity);
-        else
+        } else {
             k_pass_b_staged<double, S><<<grid, s.tile * S, lds_bytes, st>>>(s, parity);
+        }
         return hipGetLastError();
     }
     const unsigned grid = (unsigned)((s.n * S + block - 1) / block);
@@ -1544,18 +1575,26 @@ hipError_t launch_pass_b(const DevState& s, int parity, int block, int sub, bool
 
 int staged_tile_max(int sub) { return staged_block_max(sub) / sub; }
 
-size_t staged_record_bytes(bool mixed) {
-    return 16 * (size_t)(mixed ? LdsB<float>::kUnits : LdsB<double>::kUnits);
+size_t staged_record_bytes(bool mixed, bool var_h) {
+    return 16 * (size_t)(mixed ? LdsB<float>::kUnits : LdsB<double>::kUnits) + (var_h ? 8 : 0);
 }
+
+size_t staged_a_record_bytes(bool var_h) { return kLdsABytes + (var_h ? 8 : 0); }
 
 // Dynamic LDS above the default limit must be allowed per kernel.
 hipError_t prepare_staged(size_t lds_bytes_b) {
-    const void* fns[6] = {reinterpret_cast<const void*>(&k_pass_b_staged<double, 1>),
-                          reinterpret_cast<const void*>(&k_pass_b_staged<float, 1>),
-                          reinterpret_cast<const void*>(&k_pass_b_staged<double, 2>),
-                          reinterpret_cast<const void*>(&k_pass_b_staged<float, 2>),
-                          reinterpret_cast<const void*>(&k_pass_b_staged<double, 4>),
-                          reinterpret_cast<const void*>(&k_pass_b_staged<float, 4>)};
+    const void* fns[12] = {reinterpret_cast<const void*>(&k_pass_b_staged<double, 1>),
+                           reinterpret_cast<const void*>(&k_pass_b_staged<float, 1>),
+                           reinterpret_cast<const void*>(&k_pass_b_staged<double, 2>),
+                           reinterpret_cast<const void*>(&k_pass_b_staged<float, 2>),
+                           reinterpret_cast<const void*>(&k_pass_b_staged<double, 4>),
+                           reinterpret_cast<const void*>(&k_pass_b_staged<float, 4>),
+                           reinterpret_cast<const void*>(&k_pass_b_staged<double, 1, true>),
+                           reinterpret_cast<const void*>(&k_pass_b_staged<float, 1, true>),
+                           reinterpret_cast<const void*>(&k_pass_b_staged<double, 2, true>),
+                           reinterpret_cast<const void*>(&k_pass_b_staged<float, 2, true>),
+                           reinterpret_cast<const void*>(&k_pass_b_staged<double, 4, true>),
+                           reinterpret_cast<const void*>(&k_pass_b_staged<float, 4, true>)};
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds_bytes_b);
@@ -1569,11 +1608,11 @@ static void launch_a(const DevState& s, int parity, unsigned grid, int block, bo
                      hipStream_t st) {
     if (block == 0) {   // staged over the force pass's tiles
         const unsigned tiles = (unsigned)((s.n + s.tile - 1) / s.tile);
-        const size_t lds = (size_t)s.lds_slots * kLdsABytes;
+        const size_t lds = (size_t)s.lds_slots * staged_a_record_bytes(kVarH);
         if (mixed)
-            k_pass_a_staged<float, DM, kFlow><<<tiles, s.tile, lds, st>>>(s, parity);
+            k_pass_a_staged<float, DM, kFlow, kVarH><<<tiles, s.tile, lds, st>>>(s, parity);
         else
-            k_pass_a_staged<double, DM, kFlow><<<tiles, s.tile, lds, st>>>(s, parity);
+            k_pass_a_staged<double, DM, kFlow, kVarH><<<tiles, s.tile, lds, st>>>(s, parity);
         return;
     }
     if (mixed)
@@ -1583,7 +1622,7 @@ static void launch_a(const DevState& s, int parity, unsigned grid, int block, bo
 }
 
 hipError_t launch_pass_a(const DevState& s, int parity, int block, bool mixed, hipStream_t st) {
-    if (block == 0 && (!s.staged_lds_a || s.tile > 256 || s.var_h)) return hipErrorInvalidValue;
+    if (block == 0 && (!s.staged_lds_a || s.tile > 256)) return hipErrorInvalidValue;
     const unsigned grid = block > 0 ? (unsigned)((s.n + block - 1) / block) : 0u;
     if (s.var_h) {   // graded spacing: the general variant with per-pair supports
         launch_a<-1, true, true>(s, parity, grid, block, mixed, st);

@@ -220,7 +220,7 @@ def test_graded_bar_trajectory_100_steps(tl, orc, precision):
     say("graded trajectory", precision, p.n)
     prec = tl.FP64 if precision == "fp64" else tl.MIXED
     g = tl.Sim(p, precision=prec, flags=tl.STORE_FORCE, k_cap=kcap(p))
-    assert not g.info()["staged"]
+    assert g.info()["staged"]   # LDS-staged tiles with per-slot supports
     o = orc.Sim(p)
     for _ in range(4):
         g.step(25)
@@ -361,27 +361,36 @@ SHAPES = [  # (staged, lanes per particle, force block, deformation block, tile)
     (1, 4, 256, 0, 64), (0, 2, 128, 0, 96)]
 
 
+@pytest.mark.parametrize("case", ["batch3", "graded_bar_voce_av"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_every_launch_shape_is_bitwise_identical(tl, orc, precision):
+def test_every_launch_shape_is_bitwise_identical(tl, orc, precision, case):
     """LDS staging, lanes per particle and block sizes change where records
     come from and which lane sums what, not the arithmetic or its order (one
     canonical order of the neighbour sums): results are bitwise equal, on
     several tiles with a ragged last tile, after steps that leave particles
-    damaged."""
-    p = CASES["batch3"]()
+    damaged; also with graded spacing (per-pair supports), where a staged
+    image that does not fit LDS at a tile size is refused and skipped."""
+    p = CASES[case]()
     prec = tl.FP64 if precision == "fp64" else tl.MIXED
     st = injected_state(orc, p, 31)
-    outs = []
+    outs, ran = [], []
     for shape in SHAPES:
-        g = tl.Sim(p, precision=prec, flags=tl.STORE_FORCE)
-        g.set_launch_shape(*shape)
+        g = tl.Sim(p, precision=prec, flags=tl.STORE_FORCE, k_cap=kcap(p))
+        try:
+            g.set_launch_shape(*shape)
+        except tl.TLSPHError as e:
+            assert e.status == 7 and case.startswith("graded"), (shape, e)
+            continue
         inf = g.info()
         assert inf["staged"] == bool(shape[0]) and inf["lanes_per_particle"] == shape[1]
         assert inf["tile"] == (shape[4] or inf["tile"]) if shape[0] else inf["tile"] == 0
         g.set_state(st)
         g.step(3)
         outs.append({k: g.get(k) for k in ("force", "v", "u", "F", "Q", "sig", "D")})
-    for o, shape in zip(outs[1:], SHAPES[1:]):
+        ran.append(shape)
+    say(case, precision, "shapes run", len(ran), "staged", sum(1 for r in ran if r[0]))
+    assert len(ran) >= 10 and sum(1 for r in ran if r[0]) >= 4
+    for o, shape in zip(outs[1:], ran[1:]):
         for k in outs[0]:
             assert np.array_equal(outs[0][k], o[k]), (shape, k)
 
