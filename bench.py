@@ -60,16 +60,21 @@ def algorithmic_bytes(kernel: str, mixed: bool, damage: int, n: int, nnz: int) -
     return per * n + 4 * nnz
 
 
-def kernel_symbol(kernel: str, info: dict, mixed: bool, model: int, flow_general=False) -> str:
+def kernel_symbol(kernel: str, info: dict, mixed: bool, model: int, flow_general=False,
+                  var_h=False) -> str:
     """Kernel name as rocprofv3 reports it (template arguments included);
     model is the damage model the deformation pass is compiled for (-1: any),
-    flow_general whether it is the variant with every flow law."""
+    flow_general whether it is the variant with every flow law, var_h whether
+    the kernels take per-pair supports (graded spacing: the general variant)."""
     r = "float" if mixed else "double"
+    vh = "true" if var_h else "false"
     if kernel == "force_pass":
         name = "k_pass_b_staged" if info["staged"] else "k_pass_b"
-        return f"{name}<{r}, {info['lanes_per_particle']}>"
+        return f"{name}<{r}, {info['lanes_per_particle']}, {vh}>"
     name = "k_pass_a_staged" if info["block_deformation"] == 0 else "k_pass_a"
-    return f"{name}<{r}, {model}, {'true' if flow_general else 'false'}>"
+    if var_h:
+        model, flow_general = -1, True
+    return f"{name}<{r}, {model}, {'true' if flow_general else 'false'}, {vh}>"
 
 
 def counter_traffic(symbol: str, workload: str):
@@ -198,13 +203,13 @@ def kernel_table(kt, mixed, damage, n, nnz):
                                               / (v * 1e-3) / 1e9, 1)} for k, v in kts.items()}
 
 
-def roofline_of(run, damage, n, workload, mixed=False, flow_general=False):
+def roofline_of(run, damage, n, workload, mixed=False, flow_general=False, var_h=False):
     nnz = run["info"]["nnz"]
     kts, _ = kernel_table(run["kernel_times"], mixed, damage, n, nnz)
     dom = max(kts, key=kts.get)
     bytes_launch = algorithmic_bytes(dom, mixed, damage, n, nnz)
     achieved = bytes_launch / (kts[dom] * 1e-3) / 1e9
-    symbol = kernel_symbol(dom, run["info"], mixed, damage, flow_general)
+    symbol = kernel_symbol(dom, run["info"], mixed, damage, flow_general, var_h)
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": counter_traffic(symbol, workload), "kernel": dom, "symbol": symbol,
@@ -390,7 +395,8 @@ def bench_single(args, torch, I, T, workload, prob, label, damage_name, result, 
     out["kernels"] = ktab
     out["roofline"] = roofline_of(fp, damage, prob.n, workload,
                                   flow_general=bool(m0["flow"] != I.FLOW_JC or m0["implicit_return"]
-                                                    or m0["av_q1"] or m0["av_q2"]))
+                                                    or m0["av_q1"] or m0["av_q2"]),
+                                  var_h=bool(m0["h_per_spacing"]))
     res64 = result(fp)
     out["fp64_result"] = res64
     del fp["sim"]
