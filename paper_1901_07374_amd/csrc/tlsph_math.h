@@ -258,7 +258,10 @@ __host__ __device__ __forceinline__ void hardening_and_slope(const DevSpec& P, d
 // omD = 1 - D).  The left side falls and the right side rises with d, so the
 // root in [0, d_max] (d_max: the increment at the step's-start flow stress) is
 // unique; Newton steps are kept inside the shrinking bracket (bisection when
-// a step leaves it), to a step of 1e-14 relative, at most 100 iterations.
+// a step leaves it), at most 100 iterations.  The iteration ends on a Newton
+// step below 1e-8 of d (Newton converges quadratically here, g being smooth
+// with |g''| d of the order of |g'|, so the next correction would be below
+// about 1e-16 d), on any step below 1e-14 of d, or on a bracket that narrow.
 __host__ __device__ inline double implicit_increment(const DevSpec& P, double k3, double omD,
                                                      double seq, double eps, double d_max,
                                                      int32_t& flags) {
@@ -274,10 +277,12 @@ __host__ __device__ inline double implicit_increment(const DevSpec& P, double k3
         const double drf = fast ? P.C * rcp_nr(d) : 0.0;
         const double dg = -k3 - omD * (hp * rf + h * drf);
         double nd = d - g * rcp_nr(dg);
-        if (!(nd > lo && nd < hi)) nd = 0.5 * (lo + hi);
+        const bool newton = nd > lo && nd < hi;
+        if (!newton) nd = 0.5 * (lo + hi);
         const double step = fabs(nd - d);
         d = nd;
-        if (step <= 1e-14 * d || hi - lo <= 1e-14 * hi) return d;
+        if ((newton && step <= 1e-8 * d) || step <= 1e-14 * d || hi - lo <= 1e-14 * hi)
+            return d;
     }
     flags |= kErrNewton;
     return d;
