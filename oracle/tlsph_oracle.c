@@ -906,10 +906,11 @@ void orc_step(const orc_problem *p, orc_state *s) {
         for (int a = 0; a < 3; ++a) s->force[3 * i + a] = fi[a] + fhg[a] + s->fvisc[3 * i + a];
     }
 
-    /* 1b. penalty contact (SURVEY's follow-on to the kinematic wall; the    */
-    /* paper has none).  Reading: particles are spheres of radius            */
-    /* a_i = V_i^(1/3) / 2; two particles closer than a_i + a_j in the current */
-    /* configuration repel by the Hertz law of two such spheres,             */
+    /* 1b. penalty contact between bodies and across cracks, beyond the      */
+    /* kinematic wall (the paper has none).  Reading: particles are spheres  */
+    /* of radius a_i = V_i^(1/3) / 2; two particles closer than a_i + a_j    */
+    /* in the current configuration repel by the Hertz law of two such       */
+    /* spheres,                                                              */
     /* F = k (4/3) E* sqrt(a_i a_j / (a_i + a_j)) delta^(3/2),               */
     /* delta = a_i + a_j - |x_ij|, 1/E* = (1-nu_i^2)/E_i + (1-nu_j^2)/E_j,     */
     /* k = (k_i + k_j)/2, along x_ij; reference neighbours that are both     */

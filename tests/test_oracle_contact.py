@@ -1,5 +1,5 @@
-"""Oracle pins for the penalty contact (SURVEY's follow-on to the kinematic
-wall; the paper has none): Hertz law between spheres of radius V^(1/3)/2,
+"""Oracle pins for the penalty contact between bodies and across cracks,
+beyond the kinematic wall (the paper has none): Hertz law between spheres of radius V^(1/3)/2,
 reading stated in the oracle.  Momentum balance through a collision, the
 3/2 power of the overlap, linearity in the factor, symmetry of the combined
 modulus, intact reference neighbours excluded, failed ones included.
