@@ -92,7 +92,7 @@ typedef enum {
 /* One specimen: material (Sec. 4 and Tables 1-3) and run parameters. */
 typedef struct {
     double rho0, E, nu, c0, S_alpha, Gamma0;  /* Mie-Grueneisen EOS (eq. pH)        */
-    double A, B, n, C, eps_dot0;              /* Johnson-Cook flow (isothermal)     */
+    double A, B, n, C, eps_dot0;              /* Johnson-Cook flow                  */
     int32_t damage;                           /* tlsph_damage                       */
     double Wcr;                               /* Cockcroft-Latham critical work     */
     double D1, D2, D3, D4, D5;                /* Johnson-Cook failure strain        */
@@ -135,6 +135,13 @@ typedef struct {
                                                  factors; intact reference neighbours
                                                  interact through SPH only (see
                                                  tlsph_set_contact)                   */
+    double T_star, m;                         /* homologous temperature T* in [0, 1),
+                                                 held constant, and the thermal
+                                                 exponent m (> 0 when T* > 0): the flow
+                                                 stress carries 1 - T*^m (eq.
+                                                 JC_viscoplastic_model), the JC failure
+                                                 strain 1 + D5 T* (Sec. 5.2); T* = 0:
+                                                 isothermal                           */
 } tlsph_specimen;
 
 /* Prescribed-velocity group.  At mid-step time t the velocity component c of

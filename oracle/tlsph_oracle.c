@@ -350,11 +350,17 @@ double orc_mean_stress_eos(const orc_material *m, double J, double D, double e,
 /* ------------------------------------------------------------------------ */
 /* Sec. 4, eq. JC_viscoplastic_model without the (1 - D) factor, and the    */
 /* other hardening laws Sec. 4 names (forms in the header, readings).       */
-/* Readings: isothermal (T* = 0, so the factor 1 - T*^m is 1); reference    */
-/* rate eps_dot0 is a parameter; ln of the normalised rate is floored at 0; */
-/* the rate factor multiplies every law (C = 0: rate independent).          */
+/* Readings: the homologous temperature T* is a constant of the specimen   */
+/* (0 by default: isothermal) and its factor 1 - T*^m multiplies every law; */
+/* reference rate eps_dot0 is a parameter; ln of the normalised rate is     */
+/* floored at 0; the rate factor multiplies every law (C = 0: rate         */
+/* independent).                                                            */
 /* ------------------------------------------------------------------------ */
-static double hardening(const orc_material *m, double eps) {
+static double thermal_factor(const orc_material *m) {
+    return m->T_star > 0.0 ? 1.0 - pow(m->T_star, m->m) : 1.0;
+}
+
+static double hardening_law(const orc_material *m, double eps) {
     switch (m->flow) {
     case ORC_FLOW_LINEAR: return m->A + m->B * eps;
     case ORC_FLOW_SWIFT: return m->B * pow(m->flow_e0 + eps, m->n);
@@ -363,15 +369,23 @@ static double hardening(const orc_material *m, double eps) {
     }
 }
 
+static double hardening(const orc_material *m, double eps) {
+    return thermal_factor(m) * hardening_law(m, eps);
+}
+
 /* dh/deps.  Reading: the Johnson-Cook slope is taken as 0 at eps = 0,      */
 /* where it is unbounded for n < 1.                                         */
-static double hardening_slope(const orc_material *m, double eps) {
+static double hardening_slope_law(const orc_material *m, double eps) {
     switch (m->flow) {
     case ORC_FLOW_LINEAR: return m->B;
     case ORC_FLOW_SWIFT: return m->B * m->n * pow(m->flow_e0 + eps, m->n - 1.0);
     case ORC_FLOW_VOCE: return m->B * m->flow_beta * exp(-m->flow_beta * eps);
     default: return eps > 0.0 ? m->B * m->n * pow(eps, m->n - 1.0) : 0.0;
     }
+}
+
+static double hardening_slope(const orc_material *m, double eps) {
+    return thermal_factor(m) * hardening_slope_law(m, eps);
 }
 
 static double rate_factor(const orc_material *m, double eps_rate) {
@@ -690,10 +704,10 @@ void orc_point_update(const orc_material *m, double dt, const double Fdot[9],
             if (m->damage == ORC_DMG_JC) {
                 /* Sec. 5.2: D_init = sum d_eps / eps_f; Reading: d_eps_eq is
                  * the plastic increment, triaxiality sigma_m / sigma_eq and the
-                 * rate at the end of the step, T* = 0 */
+                 * rate at the end of the step, T* the specimen's constant */
                 double seq = von_mises(sd_new);
                 double sstar = sm / seq;
-                double Tstar = 0.0;
+                double Tstar = m->T_star;
                 double ef = (m->D1 + m->D2 * exp(m->D3 * sstar)) *
                             pow(1.0 + pt->eps_p_rate / m->eps_dot0, m->D4) *
                             (1.0 + m->D5 * Tstar);

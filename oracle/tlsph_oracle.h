@@ -48,6 +48,9 @@ typedef struct {
                                                /* V_i^(1/3) per particle (graded  */
                                                /* spacing); 0: h for all          */
     double contact_k;                          /* penalty contact factor (0: off) */
+    double T_star, m;                          /* homologous temperature (held    */
+                                               /* constant; 0: isothermal) and    */
+                                               /* thermal exponent, Sec. 4        */
 } orc_material;
 
 /* Prescribed-velocity group: component c (bit c of mask) is set to

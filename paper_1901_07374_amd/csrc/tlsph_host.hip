@@ -438,7 +438,8 @@ tlsph_status tlsph_create(int64_t n, int32_t n_spec, const int64_t* spec_offsets
             (p.flow == TLSPH_FLOW_VOCE && !(p.flow_beta >= 0.0 && p.flow_beta <= 1e300)) ||
             !(p.av_q1 >= 0.0 && p.av_q1 <= 1e300) || !(p.av_q2 >= 0.0 && p.av_q2 <= 1e300) ||
             !(p.h_per_spacing >= 0.0 && p.h_per_spacing <= 1e300) ||
-            !(p.contact_k >= 0.0 && p.contact_k <= 1e300))
+            !(p.contact_k >= 0.0 && p.contact_k <= 1e300) ||
+            !(p.T_star >= 0.0 && p.T_star < 1.0) || (p.T_star > 0.0 && !finite_pos(p.m)))
             return TLSPH_E_INVALID_ARG;
         if (p.damage == TLSPH_DMG_GTN &&
             (!finite_pos(p.q1) || !finite_pos(p.sN) || !(p.fF > p.fc) || !(p.fc > 0.0)))
@@ -463,8 +464,14 @@ tlsph_status tlsph_create(int64_t n, int32_t n_spec, const int64_t* spec_offsets
         const tlsph_specimen& p = spec[s];
         DevSpec& d = c->specs[s];
         d.rho0 = p.rho0; d.E = p.E; d.nu = p.nu; d.c0 = p.c0; d.S_alpha = p.S_alpha;
-        d.Gamma0 = p.Gamma0; d.A = p.A; d.B = p.B; d.n = p.n; d.C = p.C; d.eps_dot0 = p.eps_dot0;
-        d.Wcr = p.Wcr; d.D1 = p.D1; d.D2 = p.D2; d.D3 = p.D3; d.D4 = p.D4; d.D5 = p.D5;
+        // a constant homologous temperature multiplies every flow law by
+        // 1 - T*^m (eq. JC_viscoplastic_model) and the Johnson-Cook failure
+        // strain by 1 + D5 T* (Sec. 5.2): both are folded into the constants
+        const double theta = p.T_star > 0.0 ? 1.0 - pow(p.T_star, p.m) : 1.0;
+        const double tf = 1.0 + p.D5 * p.T_star;
+        d.Gamma0 = p.Gamma0; d.A = p.A * theta; d.B = p.B * theta; d.n = p.n; d.C = p.C;
+        d.eps_dot0 = p.eps_dot0;
+        d.Wcr = p.Wcr; d.D1 = p.D1 * tf; d.D2 = p.D2 * tf; d.D3 = p.D3; d.D4 = p.D4; d.D5 = p.D5;
         d.q1 = p.q1; d.q2 = p.q2; d.q3 = p.q3; d.f0 = p.f0; d.fN = p.fN; d.eN = p.eN;
         d.sN = p.sN; d.fc = p.fc; d.fF = p.fF; d.k_omega = p.k_omega;
         d.h = p.h; d.dt = p.dt; d.hg_alpha = p.hg_alpha;

@@ -48,7 +48,8 @@ class Specimen(C.Structure):
                [("has_wall", C.c_int32), ("wall_n", C.c_double * 3), ("wall_d", C.c_double),
                 ("flow", C.c_int32), ("implicit_return", C.c_int32), ("flow_e0", C.c_double),
                 ("flow_beta", C.c_double), ("av_q1", C.c_double), ("av_q2", C.c_double),
-                ("h_per_spacing", C.c_double), ("contact_k", C.c_double)]
+                ("h_per_spacing", C.c_double), ("contact_k", C.c_double),
+                ("T_star", C.c_double), ("m", C.c_double)]
 
 
 class BCGroup(C.Structure):

@@ -93,6 +93,8 @@ def test_create_rejects_bad_arguments_without_hip(L):
         assert _create(L, p, mats=[m])[0] == 1, k
     cl = dict(bad, damage=I.DMG_CL, Wcr=0.0)
     assert _create(L, p, mats=[cl])[0] == 1
+    for over in (dict(T_star=1.0), dict(T_star=-0.1), dict(T_star=0.3, m=0.0)):
+        assert _create(L, p, mats=[dict(bad, **over)])[0] == 1, over
     wall = dict(bad, has_wall=1, wall_n=(0.0, 0.0, 2.0))
     assert _create(L, p, mats=[wall])[0] == 1
     q = I.Problem(p.name, p.X, p.V0, p.spec_offsets, p.materials, p.bc_group,

@@ -81,6 +81,8 @@ CASES = {
                                           dict(VOCE, implicit_return=1)),
     "bar_linear": lambda: remat(I.notched_bar(dx=0.8e-3), LINEAR),
     "bar_jc_implicit": lambda: remat(I.notched_bar(dx=0.8e-3), dict(implicit_return=1)),
+    # a constant homologous temperature (flow stress and failure strain)
+    "bar_jc_thermal": lambda: remat(I.notched_bar(dx=0.8e-3), dict(T_star=0.2, m=1.03)),
     "plate_gtn_voce": lambda: remat(I.holed_plate(dx=0.8e-3, W=30e-3, H=12e-3, T=2.4e-3,
                                                   hole_d=4e-3), VOCE),
     "bar_av": lambda: remat(I.notched_bar(dx=0.8e-3), AV),

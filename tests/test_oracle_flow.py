@@ -195,3 +195,40 @@ def test_gtn_without_voids_is_the_implicit_return(orc, flow):
         pa = trial(orc, a1, over * sy0, eps_n)
         assert pg.eps_p == pytest.approx(pa.eps_p, rel=1e-11)
         assert vm(pg.sig) == pytest.approx(vm(pa.sig), rel=1e-11)
+
+
+# --------------------------------------------------------------------------
+# a constant homologous temperature (eq. JC_viscoplastic_model, Sec. 5.2)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("flow", [I.FLOW_JC, I.FLOW_LINEAR, I.FLOW_SWIFT, I.FLOW_VOCE])
+def test_thermal_softening_factor(orc, flow):
+    # sigma_f carries 1 - T*^m for every law, at every strain and rate
+    for Ts, m_exp in ((0.25, 0.8), (0.6, 1.7)):
+        hot = mat(flow, C=0.02, T_star=Ts, m=m_exp)
+        cold = mat(flow, C=0.02)
+        theta = 1.0 - math.pow(Ts, m_exp)
+        for eps in (0.0, 0.05, 0.4):
+            for rate in (0.0, 300.0):
+                assert orc.flow_stress(hot, eps, rate) == pytest.approx(
+                    theta * orc.flow_stress(cold, eps, rate), rel=1e-15)
+    # T* = 0 is isothermal whatever the exponent (no 0^0)
+    for m_exp in (0.0, 1.0, 2.5):
+        z = mat(flow, T_star=0.0, m=m_exp)
+        assert orc.flow_stress(z, 0.1, 10.0) == orc.flow_stress(mat(flow), 0.1, 10.0)
+
+
+def test_thermal_factor_of_the_failure_strain(orc):
+    # Johnson-Cook failure strain times 1 + D5 T*: with the flow stress held
+    # equal (A scaled by 1 - T*^m at T* = 0), the same plastic increment
+    # raises D_init by 1 / (1 + D5 T*) times as much
+    Ts, m_exp = 0.3, 1.2
+    theta = 1.0 - math.pow(Ts, m_exp)
+    jc = dict(damage=I.DMG_JC, D1=0.05, D2=3.44, D3=-2.12, D4=0.002, D5=0.61)
+    hot = dict(mat(I.FLOW_LINEAR, implicit=0, A=792e6, B=0.0, T_star=Ts, m=m_exp), **jc)
+    cold = dict(mat(I.FLOW_LINEAR, implicit=0, A=792e6 * theta, B=0.0), **jc)
+    seq = 1.4 * 792e6 * theta
+    a = trial(orc, hot, seq, 0.1, 0.0)
+    b = trial(orc, cold, seq, 0.1, 0.0)
+    assert a.eps_p == b.eps_p and a.eps_p > 0.1
+    assert np.array_equal(a.sig, b.sig)
+    assert a.d_init * (1.0 + 0.61 * Ts) == pytest.approx(b.d_init, rel=1e-14)

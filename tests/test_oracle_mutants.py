@@ -81,6 +81,10 @@ MUTANTS = [
      "for (int a = 0; a < 3; ++a) f[a] += F * d[a] / r;"),
     ("energy from P^{n+1} only", "work += Fdot[k] * 0.5 * (Jn * Pn[k] + P[k]);",
      "work += Fdot[k] * P[k];"),
+    ("thermal factor without its exponent",
+     "return m->T_star > 0.0 ? 1.0 - pow(m->T_star, m->m) : 1.0;",
+     "return m->T_star > 0.0 ? 1.0 - m->T_star : 1.0;"),
+    ("failure strain temperature factor sign", "(1.0 + m->D5 * Tstar);", "(1.0 - m->D5 * Tstar);"),
 ]
 
 
@@ -132,6 +136,8 @@ HOME = {
     'contact ignores failure': 'contact',
     'contact attractive': 'contact',
     'energy from P^{n+1} only': 'system',
+    'thermal factor without its exponent': 'flow',
+    'failure strain temperature factor sign': 'flow',
 }
 
 
