@@ -4,7 +4,9 @@ condition solved with the flow stress at the end of the step).  The laws are
 pinned against each other where one reduces to another, the return against
 closed forms and against a bracketing root finder on its defining equation,
 and against the GTN return of Algorithm 2, an independent Newton solver,
-which without voids must give the same point.  Host only."""
+which without voids must give the same point.  Also the factors of a
+constant homologous temperature (flow stress and JC failure strain) against
+their closed forms.  Host only."""
 import math
 
 import numpy as np
