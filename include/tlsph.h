@@ -172,7 +172,8 @@ typedef enum {
     TLSPH_F_Q = 13,         /* 9  Q = P L^-T used by the next force evaluation     */
     TLSPH_F_TIME = 14,      /* n_spec time of each specimen (not per particle)     */
     TLSPH_F_LINV = 15,      /* 9  inverse correction matrix (get only)             */
-    TLSPH_F_VISC = 16       /* 3  artificial viscous force for the next kick        */
+    TLSPH_F_VISC = 16,      /* 3  artificial viscous force for the next kick        */
+    TLSPH_F_H = 17          /* 9  F - I as stored (exact round trip: checkpoints)   */
 } tlsph_field;
 
 #define TLSPH_N_DIAG 8

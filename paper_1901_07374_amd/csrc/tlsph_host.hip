@@ -371,7 +371,7 @@ int field_comps(int f, int32_t n_spec) {
     switch (f) {
         case TLSPH_F_X: case TLSPH_F_U: case TLSPH_F_V: case TLSPH_F_FORCE: case TLSPH_F_VISC:
             return 3;
-        case TLSPH_F_DEFGRAD: case TLSPH_F_Q: case TLSPH_F_LINV: return 9;
+        case TLSPH_F_DEFGRAD: case TLSPH_F_Q: case TLSPH_F_LINV: case TLSPH_F_H: return 9;
         case TLSPH_F_SIGMA: return 6;
         case TLSPH_F_TIME: return -n_spec;
         case TLSPH_F_EPS_P: case TLSPH_F_EPS_P_RATE: case TLSPH_F_D_INIT: case TLSPH_F_W_P:

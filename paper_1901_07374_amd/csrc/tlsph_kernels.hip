@@ -1654,7 +1654,7 @@ hipError_t launch_pass_a(const DevState& s, int parity, int block, bool mixed, h
 
 enum Field {
     F_X = 0, F_U, F_V, F_DEFGRAD, F_SIGMA, F_EPS_P, F_EPS_P_RATE, F_D_INIT, F_W_P, F_VOID,
-    F_D, F_E_INT, F_FORCE, F_Q, F_TIME, F_LINV, F_VISC
+    F_D, F_E_INT, F_FORCE, F_Q, F_TIME, F_LINV, F_VISC, F_H
 };
 
 struct FieldRef {
@@ -1674,6 +1674,9 @@ __device__ __forceinline__ FieldRef field_ref(const DevState& s, int field, int 
         case F_DEFGRAD:
             return s.GH ? FieldRef{reinterpret_cast<const double*>(s.GH), nullptr, 9, 1, 1, 10}
                         : FieldRef{nullptr, reinterpret_cast<const float*>(s.GH32), 9, 1, 1, 10};
+        case F_H:   // F - I as stored, without the round trip through F
+            return s.GH ? FieldRef{reinterpret_cast<const double*>(s.GH), nullptr, 9, 0, 1, 10}
+                        : FieldRef{nullptr, reinterpret_cast<const float*>(s.GH32), 9, 0, 1, 10};
         case F_Q:
             return s.GQ ? FieldRef{reinterpret_cast<const double*>(s.GQ), nullptr, 9, 0, 1, 10}
                         : FieldRef{nullptr, reinterpret_cast<const float*>(s.GQ32), 9, 0, 1, 10};

@@ -25,7 +25,7 @@ STORE_FORCE, USE_GRAPHS, CHECK_FINITE, NO_STAGING = 1, 2, 4, 8
 FIELDS = {"X": (0, 3), "u": (1, 3), "v": (2, 3), "F": (3, 9), "sig": (4, 6), "eps_p": (5, 1),
           "eps_p_rate": (6, 1), "d_init": (7, 1), "w_p": (8, 1), "f_void": (9, 1), "D": (10, 1),
           "e": (11, 1), "force": (12, 3), "Q": (13, 9), "t": (14, 0), "Linv": (15, 9),
-          "fvisc": (16, 3)}
+          "fvisc": (16, 3), "H": (17, 9)}
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "bad call order", 3: "HIP runtime error",
           4: "singular correction matrix", 5: "non-finite state",

@@ -330,6 +330,34 @@ def test_bitwise_determinism_graphs_and_autotune(tl):
             assert np.array_equal(o[k], outs[0][k]), k
 
 
+STATE_KEYS = ("u", "v", "H", "sig", "eps_p", "eps_p_rate", "d_init", "w_p", "f_void", "D", "e",
+              "Q", "t", "fvisc")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_resume_from_exported_state_is_bitwise(tl, precision):
+    """A run exported after 240 steps (every state field, F as the stored
+    F - I) and resumed in a fresh context continues bit for bit as the
+    uninterrupted run: the exported fields are the whole state of a step."""
+    p = I.notched_bar(dx=0.8e-3, v_max=40.0, tau=2e-6)
+    prec = tl.FP64 if precision == "fp64" else tl.MIXED
+    say("resume", precision, p.n)
+    a = tl.Sim(p, precision=prec, flags=tl.STORE_FORCE)
+    a.step(480)
+    ref = {k: a.get(k) for k in STATE_KEYS + ("force", "F")}
+    assert ref["eps_p"].max() > 0.01 and ref["d_init"].max() > 0.0
+    del a
+    b = tl.Sim(p, precision=prec, flags=tl.STORE_FORCE)
+    b.step(240)
+    ck = {k: b.get(k) for k in STATE_KEYS}
+    del b
+    c = tl.Sim(p, precision=prec, flags=tl.STORE_FORCE)
+    c.set_state(ck)
+    c.step(240)
+    for k in ref:
+        assert np.array_equal(c.get(k), ref[k]), k
+
+
 def test_contact_runs_are_bitwise_reproducible(tl):
     """Contact candidate lists are sorted and summed in list order: runs
     repeat bit for bit, also when the context was created for graph replay
