@@ -50,13 +50,19 @@ TIMING_STRIDE = 10
 ACC_BYTES = {0: 0, 1: 32, 2: 16, 3: 16}   # CL: D_init, W_p r/w; JC: D_init; GTN: f
 
 
-def algorithmic_bytes(kernel: str, mixed: bool, damage: int, n: int, nnz: int) -> int:
+def algorithmic_bytes(kernel: str, mixed: bool, damage: int, n: int, nnz: int,
+                      av: bool = False, var_h: bool = False) -> int:
+    """Bytes one launch must move: each per-particle field once, 4 bytes of
+    neighbour index per pair.  The damping's force is written by the
+    deformation pass and read by the force pass (24 bytes each); graded
+    spacing reads each particle's support in both passes (8 bytes)."""
     if kernel == "force_pass":
         per = 32 + 24 + (76 if mixed else 152) + 8 + 24 + 12 + 32 + 24
     else:
         per = (32 + 24 + (36 if mixed else 72) * 2 + (24 if mixed else 48) + 32 + 8
                + (76 if mixed else 152) + (24 if mixed else 48) + 32)
         per += ACC_BYTES[damage]
+    per += (24 if av else 0) + (8 if var_h else 0)
     return per * n + 4 * nnz
 
 
@@ -196,18 +202,19 @@ def run_form(prob, precision, steps, warmup, torch, T, flags=0, autotune=True, s
                 sd=sd[:rec].cpu().numpy(), bd=bd[:rec].cpu().numpy())
 
 
-def kernel_table(kt, mixed, damage, n, nnz):
+def kernel_table(kt, mixed, damage, n, nnz, av=False, var_h=False):
     kts = {k: v[0] / max(v[1], 1) for k, v in kt.items()}
     return kts, {k: {"avg_launch_us": round(v * 1e3, 2),
-                     "algorithmic_GBs": round(algorithmic_bytes(k, mixed, damage, n, nnz)
+                     "algorithmic_GBs": round(algorithmic_bytes(k, mixed, damage, n, nnz, av, var_h)
                                               / (v * 1e-3) / 1e9, 1)} for k, v in kts.items()}
 
 
-def roofline_of(run, damage, n, workload, mixed=False, flow_general=False, var_h=False):
+def roofline_of(run, damage, n, workload, mixed=False, flow_general=False, var_h=False,
+                av=False):
     nnz = run["info"]["nnz"]
-    kts, _ = kernel_table(run["kernel_times"], mixed, damage, n, nnz)
+    kts, _ = kernel_table(run["kernel_times"], mixed, damage, n, nnz, av, var_h)
     dom = max(kts, key=kts.get)
-    bytes_launch = algorithmic_bytes(dom, mixed, damage, n, nnz)
+    bytes_launch = algorithmic_bytes(dom, mixed, damage, n, nnz, av, var_h)
     achieved = bytes_launch / (kts[dom] * 1e-3) / 1e9
     symbol = kernel_symbol(dom, run["info"], mixed, damage, flow_general, var_h)
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -383,27 +390,28 @@ def bench_single(args, torch, I, T, workload, prob, label, damage_name, result, 
     fp = run_form(prob, T.FP64, args.steps, args.warmup, torch, T, 0, tune, k_cap=k_cap,
                   setup=setup)
     nnz = fp["info"]["nnz"]
-    _, ktab = kernel_table(fp["kernel_times"], False, damage, prob.n, nnz)
+    m0 = prob.materials[0]
+    av, var_h = bool(m0["av_q1"] or m0["av_q2"]), bool(m0["h_per_spacing"])
+    _, ktab = kernel_table(fp["kernel_times"], False, damage, prob.n, nnz, av, var_h)
     out = base_line(args, workload, prob.n * args.steps / fp["seconds"],
                     fp["seconds"] / args.steps * 1e3, "f64",
                     dict({"particles": prob.n, "neighbour_pairs": nnz, "damage": damage_name,
                           "precision": "fp64", "steps_total": args.warmup + args.steps,
                           "dt_s": prob.materials[0]["dt"]}, **shape_of(fp["info"])))
-    m0 = prob.materials[0]
-    if m0["av_q1"] or m0["av_q2"]:
+    if av:
         out["config"]["artificial_viscosity"] = {"q1": m0["av_q1"], "q2": m0["av_q2"]}
     out["kernels"] = ktab
     out["roofline"] = roofline_of(fp, damage, prob.n, workload,
                                   flow_general=bool(m0["flow"] != I.FLOW_JC or m0["implicit_return"]
-                                                    or m0["av_q1"] or m0["av_q2"]),
-                                  var_h=bool(m0["h_per_spacing"]))
+                                                    or av),
+                                  var_h=var_h, av=av)
     res64 = result(fp)
     out["fp64_result"] = res64
     del fp["sim"]
     if not args.no_mixed:
         mx = run_form(prob, T.MIXED, args.steps, args.warmup, torch, T, 0, tune, k_cap=k_cap,
                       setup=setup)
-        _, mtab = kernel_table(mx["kernel_times"], True, damage, prob.n, nnz)
+        _, mtab = kernel_table(mx["kernel_times"], True, damage, prob.n, nnz, av, var_h)
         resm = result(mx)
         out["mixed"] = {
             "value": round(prob.n * args.steps / mx["seconds"], 1), "unit": "particle-steps/s",
