@@ -16,6 +16,14 @@
  *
  * Where the paper is silent or ambiguous, the reading taken is stated at the
  * point of use ("Reading: ...").
+ *
+ * Parity unpinned: the hourglass control term (the paper cites a scheme
+ * without printing its formula) is pinned only by invariants -- zero for
+ * affine motion and rigid rotation, antisymmetric, restoring -- not by a
+ * value from the paper.  The same holds for the follow-on pieces the paper
+ * names without formulas (the velocity damping, the penalty contact): their
+ * pins are invariants and closed forms of the forms read, not the paper's
+ * numbers.
  */
 #include "tlsph_oracle.h"
 
