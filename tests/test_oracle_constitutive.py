@@ -441,3 +441,107 @@ def test_gtn_yield_onset_at_high_triaxiality(orc, J0, f):
         sd = shape * (scale * seq0 / 1.5)
         pt = _inject_trial(orc, m, J0, sd, eps_n, f, D)
         assert (pt.eps_p > eps_n) == plastic, (scale, pt.eps_p - eps_n)
+
+
+# --------------------------------------------------------------------------
+# GTN void growth (Sec. 5.4, eq. GTN_damage_growth), derived here from the
+# yield function by normality rather than from Algorithm 2's closed form
+# --------------------------------------------------------------------------
+def _gtn_phi(s33, sM, fs, q1, q2, q3):
+    """eq. yield_GTN as a function of the full stress tensor."""
+    sm = np.trace(s33) / 3.0
+    sd = s33 - sm * np.eye(3)
+    seq = math.sqrt(1.5 * np.sum(sd * sd))
+    return (seq / sM) ** 2 + 2 * q1 * fs * math.cosh(1.5 * q2 * sm / sM) - (1 + q3 * fs * fs)
+
+
+def _normal_fd(s33, phi, h):
+    """d phi / d sigma (symmetric) by central differences, one independent
+    component at a time (an off-diagonal pair moves together: half the
+    difference is each entry's derivative)."""
+    N = np.zeros((3, 3))
+    for a in range(3):
+        for b in range(a, 3):
+            E = np.zeros((3, 3))
+            E[a, b] = E[b, a] = h
+            d = (phi(s33 + E) - phi(s33 - E)) / (2 * h)
+            N[a, b] = N[b, a] = d if a == b else 0.5 * d
+    return N
+
+
+def _gtn_growth_case(orc, J0, f, k_omega, fN=0.0, seed=11):
+    """Inject a plastic trial state at high tensile mean stress, return the
+    oracle's step and what the flow rule predicts for the void growth.
+
+    The prediction uses only: the flow rule (plastic strain along d Phi /
+    d sigma at the returned stress, eq. flow_rule, evaluated here by finite
+    differences of eq. yield_GTN), the equivalent plastic strain increment
+    from the stress drop (eq. delta_epsilon_p_eq) and the growth law
+    f_dot = (1 - f) tr(eps_p_dot) + k_w f omega sigma_d : eps_p_dot / sigma_eq
+    (eq. GTN_damage_growth), plus Chu-Needleman nucleation A_N d eps_M when
+    F_N > 0.  Algorithm 2's last line (alpha, the factor 1 / (alpha sigma* + 1),
+    sigma_M / sigma_y) is not used."""
+    m = gtn_mat(n=0.26, k_omega=k_omega, fN=fN)
+    q1, q2, q3 = m["q1"], m["q2"], m["q3"]
+    fs = orc.fstar(m, f)
+    assert fs == f                          # below f_c: f* = f in the flow rule too
+    D = q1 * fs
+    eps_n = 0.08
+    sM0 = orc.flow_stress(m, eps_n)
+    sm_tr = orc.mean_stress_eos(m, J0, D, 0.0, False)
+    c = (1 + q3 * fs * fs) - 2 * q1 * fs * math.cosh(1.5 * q2 * sm_tr / sM0)
+    assert c > 0.1
+    rng = np.random.default_rng(seed)
+    sd = rng.normal(size=(3, 3))
+    sd = sd + sd.T
+    sd -= np.trace(sd) / 3 * np.eye(3)
+    seq_tr = 1.08 * sM0 * math.sqrt(c)       # 8 % outside the surface
+    sd *= seq_tr / math.sqrt(1.5 * np.sum(sd * sd))
+    pt = _inject_trial(orc, m, J0, sd, eps_n, f, D)
+    dem = pt.eps_p - eps_n
+    assert dem > 0
+    s_out = full(pt.sig)
+    sm_out = np.trace(s_out) / 3
+    sd_out = s_out - sm_out * np.eye(3)
+    seq_out = math.sqrt(1.5 * np.sum(sd_out * sd_out))
+    sstar = sm_out / seq_out
+    assert 0.8 < sstar < 2.5                # high triaxiality
+    sM = orc.flow_stress(m, pt.eps_p)
+    N = _normal_fd(s_out, lambda s: _gtn_phi(s, sM, fs, q1, q2, q3), 1e-6 * seq_out)
+    Nd = N - np.trace(N) / 3 * np.eye(3)
+    neq = math.sqrt(2.0 / 3.0 * np.sum(Nd * Nd))
+    tr_ratio = np.trace(N) / neq             # tr(d eps_p) / d eps_p_eq
+    shear_ratio = np.sum(sd_out * N) / (seq_out * neq)   # sigma_d : d eps_p / (sigma_eq d eps_p_eq)
+    G = G_of(m)
+    dep_eq = (seq_tr - seq_out) / (3 * G * (1 - D))
+    detd = np.linalg.det(sd_out)
+    om = 1.0 - (27.0 * detd / (2.0 * seq_out ** 3)) ** 2
+    growth = ((1 - f) * tr_ratio + k_omega * f * om * shear_ratio) * dep_eq
+    nucl = 0.0
+    if fN > 0:
+        z = (pt.eps_p - m["eN"]) / m["sN"]
+        nucl = fN / (m["sN"] * math.sqrt(2 * math.pi)) * math.exp(-0.5 * z * z) * dem
+    return pt.f_void - f, growth + nucl, tr_ratio, sstar
+
+
+@pytest.mark.parametrize("J0,f", [(1.006, 0.02), (1.009, 0.05), (1.005, 0.1)])
+def test_gtn_dilatational_void_growth_from_normality(orc, J0, f):
+    """F_N = 0, k_w = 0: the void fraction grows by (1 - f) tr(d eps_p), with
+    the trace from the normal to the yield surface and d eps_p_eq from the
+    stress drop.  At these triaxialities the trace is a sizeable fraction of
+    the equivalent increment, so a wrong factor in the ratio or in the
+    work-equivalence conversion shows at once."""
+    df, expect, tr_ratio, sstar = _gtn_growth_case(orc, J0, f, 0.0)
+    assert tr_ratio * sstar > 0.05
+    assert df > 0
+    assert df == pytest.approx(expect, rel=1e-7)
+
+
+@pytest.mark.parametrize("J0,f,fN", [(1.007, 0.04, 0.0), (1.006, 0.08, 0.0), (1.008, 0.06, 0.04)])
+def test_gtn_void_growth_with_shear_and_nucleation(orc, J0, f, fN):
+    """k_w = 3.5 on a non-axisymmetric deviator (omega > 0): the shear term
+    k_w f omega sigma_d : d eps_p / sigma_eq adds to the dilatational one
+    (eq. GTN_damage_growth, omega of eq. omega), and with F_N > 0 the
+    nucleation A_N d eps_M at the step's end strain."""
+    df, expect, _, _ = _gtn_growth_case(orc, J0, f, 3.5, fN=fN, seed=23)
+    assert df == pytest.approx(expect, rel=1e-7)

@@ -85,6 +85,14 @@ MUTANTS = [
      "return m->T_star > 0.0 ? 1.0 - pow(m->T_star, m->m) : 1.0;",
      "return m->T_star > 0.0 ? 1.0 - m->T_star : 1.0;"),
     ("failure strain temperature factor sign", "(1.0 + m->D5 * Tstar);", "(1.0 - m->D5 * Tstar);"),
+    ("GTN void growth ratio without its 3/2",
+     "double alpha = 1.5 * (sM / sy) * m->q1 * m->q2 * f * sinh(arg);",
+     "double alpha = 1.0 * (sM / sy) * m->q1 * m->q2 * f * sinh(arg);"),
+    ("GTN void growth without 1 / (alpha sigma* + 1)",
+     "+ (1.0 - f) / (alpha * sstar + 1.0) * (sM / sy)",
+     "+ (1.0 - f) * (sM / sy)"),
+    ("GTN shear growth without f", "* (alpha * (1.0 - f) + f * m->k_omega * omega) * dem;",
+     "* (alpha * (1.0 - f) + m->k_omega * omega) * dem;"),
 ]
 
 
@@ -138,6 +146,9 @@ HOME = {
     'energy from P^{n+1} only': 'system',
     'thermal factor without its exponent': 'flow',
     'failure strain temperature factor sign': 'flow',
+    'GTN void growth ratio without its 3/2': 'constitutive',
+    'GTN void growth without 1 / (alpha sigma* + 1)': 'constitutive',
+    'GTN shear growth without f': 'constitutive',
 }
 
 
