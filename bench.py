@@ -1,19 +1,21 @@
 """Benchmark: damaged TLSPH steps on one MI355X.
 
-Default workload (the headline): the notched round bar in tension (radius
-5 mm, length 40 mm, 90-degree V-notch 1 mm deep, 0.25 mm lattice, 200 216
-particles, seeded 3 % jitter), Johnson-Cook plasticity and Johnson-Cook
-damage, grips driven at +-10 m/s (1 - exp(-t / 1 ms)), from rest to past
-failure.  A step is one pass of the whole path: nodal forces with hourglass
-control, leapfrog update, damaged dF/dt, EOS, radial return, damage, PK1.
-The headline value is the FP64 form; the mixed FP32/FP64 form runs the same
-steps and is reported beside it with its deviation from FP64 (reaction-force
-curve and failure displacement).
+Default workload (the headline): the GTN holed plate in plane-strain-like
+tension (100 x 40 x 2 mm, central hole of 5 mm diameter, 0.125 mm lattice,
+4 075 776 particles, seeded 3 % jitter), Johnson-Cook matrix flow and
+Gurson-Tvergaard-Needleman damage (Algorithm 2 in double in both forms),
+grips driven at +-10 m/s (1 - exp(-t / 1 ms)), v_z = 0 everywhere.  The plate
+is first driven along the ramp, untimed, until at least 2 % of its particles
+yield in a step; the timed steps follow from there, so the GTN return
+mapping's Newton loops run in them.  A step is one pass of the whole path:
+nodal forces with hourglass control, leapfrog update, damaged dF/dt, EOS,
+return mapping, damage, PK1.  The headline value is the FP64 form; the mixed
+FP32/FP64 form takes over the same state and is timed over the same steps.
 
-Other workloads (--workload): the Taylor bar (996 314 particles, CL, rigid
-wall, 5000 steps), the GTN holed plate (4.08 M particles), and a batch of 256
-notched bars of 2k-60k particles (8.55 M in all) stepped in one captured launch
-per pass in the mixed form, against 256 separate FP64 contexts.
+Other workloads (--workload): the notched round bar (200 216 particles, JC
+damage, from rest to past failure, with its failure displacement), the
+Taylor bar (996 314 particles, CL, rigid wall, 5000 steps), and a batch of
+256 notched bars of 2k-60k particles (8.55 M in all), among others.
 
 Inputs and state are resident in HBM before the timed region starts.
 Prints one JSON line.
@@ -150,11 +152,13 @@ def log(*a):
 
 
 def run_form(prob, precision, steps, warmup, torch, T, flags=0, autotune=True, stream=None,
-             diag=True, shape=None, k_cap=32, setup=None):
+             diag=True, shape=None, k_cap=32, setup=None, sim=None):
     """Warm up, autotune (or apply a given launch shape), then time `steps`
-    steps; diagnostics every DIAG_EVERY steps (inside the timed region)."""
+    steps; diagnostics every DIAG_EVERY steps (inside the timed region).  A
+    given context continues from its state."""
     log(f"{prob.name}: {prob.n} particles, precision {precision}, flags {flags}")
-    sim = T.Sim(prob, precision=precision, flags=flags, stream=stream, k_cap=k_cap)
+    if sim is None:
+        sim = T.Sim(prob, precision=precision, flags=flags, stream=stream, k_cap=k_cap)
     if setup is not None:
         setup(sim)
     if shape is not None:
@@ -190,7 +194,8 @@ def run_form(prob, precision, steps, warmup, torch, T, flags=0, autotune=True, s
     use_timing = not (flags & T.USE_GRAPHS)
     torch.cuda.synchronize()
     if use_timing:
-        sim.enable_kernel_timing(TIMING_STRIDE)
+        # every step's kernels timed on short runs, a sample of them on long ones
+        sim.enable_kernel_timing(max(1, min(TIMING_STRIDE, steps // 100)))
     t0 = time.perf_counter()
     advance(steps)
     torch.cuda.synchronize()
@@ -481,17 +486,96 @@ def bench_collision(args, torch, I, T):
     return out
 
 
+PLASTIC_TARGET = 0.02     # share of particles yielding in a step before the plate is timed
+PRELOAD_CAP = 60000       # most steps spent reaching it
+PRELOAD_CHUNK = 1000
+
+
+def plastic_share(sim, torch):
+    """Share of particles whose plastic strain grew in the last step."""
+    r = sim.get_tensor("eps_p_rate")
+    torch.cuda.synchronize()
+    return float((r > 0).sum().item()) / sim.n
+
+
+def plate_state(sim, torch):
+    f = sim.get_tensor("f_void")
+    torch.cuda.synchronize()
+    return {"plastic_share": plastic_share(sim, torch), "max_void_fraction": float(f.max().item())}
+
+
 def bench_plate(args, torch, I, T):
+    """The GTN holed plate (4.08 M particles) in its yielding regime: the
+    FP64 context is driven along the grip ramp (untimed) until at least 2 %
+    of the particles yield in a step, so that Algorithm 2's Newton loops run
+    in the timed steps; the mixed context takes over that same state and is
+    timed over the same steps."""
     prob = I.holed_plate()
+    workload = "gtn_plate_4m"
+    damage = I.DMG_GTN
+    tune = not args.no_autotune
+    fp_sim = T.Sim(prob, precision=T.FP64)
+    pre = 0
+    target = args.preload if args.preload is not None else -1
+    t0 = time.perf_counter()
+    while (target < 0 and pre < PRELOAD_CAP) or (target >= 0 and pre < target):
+        k = PRELOAD_CHUNK if target < 0 else min(PRELOAD_CHUNK, target - pre)
+        fp_sim.step(k)
+        pre += k
+        if target < 0 and plastic_share(fp_sim, torch) >= PLASTIC_TARGET:
+            break
+    torch.cuda.synchronize()
+    start = plate_state(fp_sim, torch)
+    log(f"preload: {pre} steps in {time.perf_counter() - t0:.1f} s, {start}")
+    mx_sim = None
+    if not args.no_mixed:
+        mx_sim = T.Sim(prob, precision=T.MIXED)
+        mx_sim.copy_state_from(fp_sim)
 
     def result(r):
         bd, sd = r["bd"], r["sd"]
-        f = r["sim"].get("f_void")
+        st = plate_state(r["sim"], torch)
         return {"reaction_kN": float(-bd[-1, 1, 0]) / 1e3,
                 "grip_separation_mm": float(bd[-1, 1, 3] - bd[-1, 0, 3]) * 1e3,
-                "max_void_fraction": float(f.max()), "max_D": float(sd[-1, 0, 3])}
-    return bench_single(args, torch, I, T, "gtn_plate_4m", prob,
-                        "GTN holed plate in tension", "gtn", result)
+                "max_void_fraction": st["max_void_fraction"], "max_D": float(sd[-1, 0, 3]),
+                "plastic_share_last_step": st["plastic_share"]}
+
+    fp = run_form(prob, T.FP64, args.steps, args.warmup, torch, T, 0, tune, sim=fp_sim)
+    nnz = fp["info"]["nnz"]
+    _, ktab = kernel_table(fp["kernel_times"], False, damage, prob.n, nnz)
+    out = base_line(args, workload, prob.n * args.steps / fp["seconds"],
+                    fp["seconds"] / args.steps * 1e3, "f64",
+                    dict({"particles": prob.n, "neighbour_pairs": nnz, "damage": "gtn",
+                          "precision": "fp64", "preload_steps": pre,
+                          "steps_total": pre + args.warmup + args.steps,
+                          "dt_s": prob.materials[0]["dt"],
+                          "timed_from": {"plastic_share": round(start["plastic_share"], 5),
+                                         "max_void_fraction": round(start["max_void_fraction"],
+                                                                    6)}},
+                         **shape_of(fp["info"])))
+    step_bytes = sum(algorithmic_bytes(k, False, damage, prob.n, nnz) for k in ktab)
+    out["step_algorithmic_GBs"] = round(step_bytes * args.steps / fp["seconds"] / 1e9, 1)
+    out["kernels"] = ktab
+    out["roofline"] = roofline_of(fp, damage, prob.n, workload)
+    res64 = result(fp)
+    out["fp64_result"] = res64
+    del fp["sim"], fp_sim
+    if mx_sim is not None:
+        mx = run_form(prob, T.MIXED, args.steps, args.warmup, torch, T, 0, tune, sim=mx_sim)
+        _, mtab = kernel_table(mx["kernel_times"], True, damage, prob.n, nnz)
+        resm = result(mx)
+        out["mixed"] = {
+            "value": round(prob.n * args.steps / mx["seconds"], 1), "unit": "particle-steps/s",
+            "ms_per_step": round(mx["seconds"] / args.steps * 1e3, 5), "dtype": "f32/f64",
+            "from": "the FP64 state after the preload (float fields rounded)",
+            "launch": shape_of(mx["info"]), "kernels": mtab, "result": resm,
+            "rel_diff_vs_fp64": {k: (round(abs(resm[k] - res64[k]) / abs(res64[k]), 6)
+                                     if res64[k] else None) for k in res64}}
+        del mx["sim"], mx_sim
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prob, "GTN holed plate from rest (elastic steps)",
+                                           max_steps=60)
+    return out
 
 
 def bench_batch(args, torch, I, T):
@@ -555,14 +639,14 @@ WORKLOADS = {"notched_bar_200k": (bench_notched_bar, 42000, 1000),
              "taylor_bar_1m_av": (bench_taylor_av, 4900, 100),
              "graded_bar_93k": (bench_graded, 4900, 100),
              "bar_collision_395k": (bench_collision, 1900, 100),
-             "gtn_plate_4m": (bench_plate, 1900, 100),
+             "gtn_plate_4m": (bench_plate, 2000, 20),
              "batch_256_bars": (bench_batch, 400, 50)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="notched_bar_200k", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="gtn_plate_4m", choices=sorted(WORKLOADS))
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
@@ -572,6 +656,9 @@ def main():
                     help="extra untimed FP64 runs from perturbed starts (notched bar)")
     ap.add_argument("--unstaged", action="store_true",
                     help="force pass gathers from global memory instead of LDS tiles")
+    ap.add_argument("--preload", type=int, default=None,
+                    help="GTN plate: untimed steps before the timed region (default: until "
+                         "2%% of the particles yield)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()

@@ -26,9 +26,11 @@
  *  - Every call returns a status; nothing throws or aborts across the ABI.
  *    Argument errors are detected before any HIP call.  Detail text of the
  *    last failure is available from tlsph_last_error().
- *  - All device work is ordered on the stream passed in.  Only
- *    tlsph_build_neighbors and tlsph_autotune synchronise with the host.  A
- *    context is used by one host thread at a time.
+ *  - All device work is ordered on the stream passed in, host copies
+ *    included.  Only tlsph_build_neighbors, tlsph_autotune,
+ *    tlsph_set_launch_shape (a new tile size) and tlsph_info synchronise with
+ *    the host, on that stream.  A context is used by one host thread at a
+ *    time.
  *  - Summation order is fixed per particle (no floating-point atomics): the
  *    same inputs give bitwise identical results run to run and for every
  *    launch shape the autotuner may pick.
@@ -142,6 +144,12 @@ typedef struct {
                                                  JC_viscoplastic_model), the JC failure
                                                  strain 1 + D5 T* (Sec. 5.2); T* = 0:
                                                  isothermal                           */
+    int32_t newton_max_iter;                  /* iteration cap of the Newton loops of
+                                                 Algorithm 2 and of the implicit return
+                                                 (0: 50 and 100); a loop that reaches it
+                                                 keeps its last iterate and raises info
+                                                 flag bit 1.  Tests force that path with
+                                                 a cap of 1                           */
 } tlsph_specimen;
 
 /* Prescribed-velocity group.  At mid-step time t the velocity component c of
@@ -286,8 +294,9 @@ tlsph_status tlsph_kernel_times(tlsph_ctx *ctx, double ms[2], int64_t launches[2
  * more than 32 contact candidates, left the list's skin, or the contact grid
  * outgrew 2^14 cells per axis), [6] lanes per particle of the force pass, [7] LDS
  * bytes per workgroup of the staged force pass (0 when unstaged), [8]
- * particles per tile of the staged force pass (0 when unstaged). */
-tlsph_status tlsph_info(tlsph_ctx *ctx, int64_t out[9]);
+ * particles per tile of the staged force pass (0 when unstaged).  The flags
+ * are read after the work already queued on the stream: synchronises it. */
+tlsph_status tlsph_info(tlsph_ctx *ctx, int64_t out[9], hipStream_t stream);
 
 /* Pin the launch shape (host int32[5]): [0] 1 = LDS-staged force pass, 0 =
  * gathers from global memory; [1] lanes per particle of the force pass (1,

@@ -105,6 +105,7 @@ def lib():
         L.orc_shape_matrices.restype = C.c_int64
         L.orc_init_state.argtypes = [C.POINTER(ProblemC), _dp, C.POINTER(StateC)]
         L.orc_step.argtypes = [C.POINTER(ProblemC), C.POINTER(StateC)]
+        L.orc_diagnostics.argtypes = [C.POINTER(ProblemC), C.POINTER(StateC), _dp, _dp]
         L.orc_point_update.argtypes = [C.POINTER(Material), C.c_double, _dp, C.POINTER(PointC),
                                        _dp, C.POINTER(PointInfo)]
         L.orc_mean_stress_eos.argtypes = [C.POINTER(Material), C.c_double, C.c_double,
@@ -311,6 +312,15 @@ class Sim:
     def step(self, k: int = 1):
         for _ in range(k):
             lib().orc_step(C.byref(self.pc), C.byref(self.sc))
+
+    def diagnostics(self):
+        """(spec_diag (n_spec, 8), bc_diag (n_bc, 8)) of the current state:
+        kinetic and internal energy, failed count, max D, time per specimen;
+        summed nodal force, mean displacement and count per group."""
+        sd = np.zeros((self.prob.n_spec, 8))
+        bd = np.zeros((max(len(self.prob.bc_groups), 1), 8))
+        lib().orc_diagnostics(C.byref(self.pc), C.byref(self.sc), _p(sd), _p(bd))
+        return sd, bd[: len(self.prob.bc_groups)]
 
     def get(self, name: str) -> np.ndarray:
         return self.state[name].copy()

@@ -1063,6 +1063,50 @@ void orc_step(const orc_problem *p, orc_state *s) {
     for (int32_t k = 0; k < p->n_spec; ++k) s->t[k] += p->mat[k].dt;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Diagnostics of a state: the quantities the runs of Sec. 6 are read by     */
+/* (the force on each gripped end, i.e. minus its reaction, and the grips'   */
+/* displacement) and the two energies of eq. conservation3's balance.        */
+/* Per specimen: sum 1/2 m |v|^2 with m = rho0 V0 and v the stored           */
+/* half-step velocity, sum m e, the number of failed particles (D >= 1),     */
+/* max D, and the specimen's time.  Per prescribed-velocity group: the sum   */
+/* of the members' nodal forces, their mean displacement, their count.      */
+/* Plain sums in ascending particle order.                                   */
+/* ------------------------------------------------------------------------ */
+void orc_diagnostics(const orc_problem *p, const orc_state *s, double *spec_diag,
+                     double *bc_diag) {
+    for (int32_t q = 0; q < p->n_spec; ++q) {
+        for (int k = 0; k < 8; ++k) spec_diag[8 * q + k] = 0.0;
+        spec_diag[8 * q + 4] = s->t[q];
+    }
+    for (int32_t g = 0; g < p->n_bc; ++g)
+        for (int k = 0; k < 8; ++k) bc_diag[8 * g + k] = 0.0;
+    for (int64_t i = 0; i < p->n; ++i) {
+        int32_t q = p->spec[i];
+        double m = p->mat[q].rho0 * p->V0[i];
+        const double *v = s->v + 3 * i;
+        double *o = spec_diag + 8 * q;
+        o[0] += 0.5 * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        o[1] += m * s->e[i];
+        if (s->D[i] >= 1.0) o[2] += 1.0;
+        if (s->D[i] > o[3]) o[3] = s->D[i];
+        int32_t g = p->bc[i];
+        if (g >= 0 && g < p->n_bc) {
+            double *b = bc_diag + 8 * g;
+            for (int a = 0; a < 3; ++a) {
+                b[a] += s->force[3 * i + a];
+                b[3 + a] += s->u[3 * i + a];
+            }
+            b[6] += 1.0;
+        }
+    }
+    for (int32_t g = 0; g < p->n_bc; ++g) {
+        double *b = bc_diag + 8 * g;
+        if (b[6] > 0.0)
+            for (int a = 0; a < 3; ++a) b[3 + a] /= b[6];
+    }
+}
+
 /* Thread count of the OpenMP loops (results do not depend on it). */
 void orc_set_threads(int32_t nthreads) {
 #ifdef _OPENMP

@@ -129,6 +129,13 @@ void orc_init_state(const orc_problem *p, const double *v_init, orc_state *s);
 /* One leapfrog step of every specimen. */
 void orc_step(const orc_problem *p, orc_state *s);
 
+/* Diagnostics of the state: spec_diag double[n_spec][8] = sum 1/2 m |v|^2,
+ * sum m e, failed count (D >= 1), max D, time, 0, 0, 0; bc_diag
+ * double[n_bc][8] = summed nodal force (3), mean displacement (3), count, 0.
+ * Plain sums in ascending particle order. */
+void orc_diagnostics(const orc_problem *p, const orc_state *s, double *spec_diag,
+                     double *bc_diag);
+
 /* Constitutive update of one material point over one step, given dF/dt. */
 void orc_point_update(const orc_material *m, double dt, const double Fdot[9],
                       orc_point *pt, double P[9], orc_point_info *info);

@@ -133,6 +133,7 @@ struct tlsph_ctx {
     uint32_t flags = 0;
     DevState st{};
     std::vector<int64_t> spec_off;
+    std::vector<int64_t> diag_seg_host;   // diagnostics segment table (source of an async copy)
     std::vector<DevSpec> specs;
     std::vector<DevBC> bcs;
     int32_t n_bc_cap = 0;
@@ -439,7 +440,8 @@ tlsph_status tlsph_create(int64_t n, int32_t n_spec, const int64_t* spec_offsets
             !(p.av_q1 >= 0.0 && p.av_q1 <= 1e300) || !(p.av_q2 >= 0.0 && p.av_q2 <= 1e300) ||
             !(p.h_per_spacing >= 0.0 && p.h_per_spacing <= 1e300) ||
             !(p.contact_k >= 0.0 && p.contact_k <= 1e300) ||
-            !(p.T_star >= 0.0 && p.T_star < 1.0) || (p.T_star > 0.0 && !finite_pos(p.m)))
+            !(p.T_star >= 0.0 && p.T_star < 1.0) || (p.T_star > 0.0 && !finite_pos(p.m)) ||
+            p.newton_max_iter < 0 || p.newton_max_iter > 1000)
             return TLSPH_E_INVALID_ARG;
         if (p.damage == TLSPH_DMG_GTN &&
             (!finite_pos(p.q1) || !finite_pos(p.sN) || !(p.fF > p.fc) || !(p.fc > 0.0)))
@@ -499,6 +501,8 @@ tlsph_status tlsph_create(int64_t n, int32_t n_spec, const int64_t* spec_offsets
         d.h_per_spacing = p.h_per_spacing;
         d.contact_k = p.contact_k;
         d.contact_comp = (1.0 - p.nu * p.nu) / p.E;
+        d.newton_gtn = p.newton_max_iter > 0 ? p.newton_max_iter : 50;
+        d.newton_impl = p.newton_max_iter > 0 ? p.newton_max_iter : 100;
         d.first = spec_offsets[s];
         d.last = spec_offsets[s + 1];
     }
@@ -599,7 +603,9 @@ tlsph_status tlsph_build_neighbors(tlsph_ctx* c, const double* X, const double* 
     HIPCHK(c, hipStreamSynchronize(stream));
     if (err[0] != 0x7fffffff) {
         int32_t orig = -1;
-        HIPCHK(c, hipMemcpy(&orig, c->ws + L.perm + (size_t)err[0] * 4, 4, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpyAsync(&orig, c->ws + L.perm + (size_t)err[0] * 4, 4,
+                                 hipMemcpyDeviceToHost, stream));
+        HIPCHK(c, hipStreamSynchronize(stream));
         return fail(c, TLSPH_E_SINGULAR_L,
                     "singular correction matrix at particle " + std::to_string(orig));
     }
@@ -612,13 +618,18 @@ tlsph_status tlsph_build_neighbors(tlsph_ctx* c, const double* X, const double* 
             c->block_b = c->st.tile * c->sub_b;
         }
     }
+    // group sizes and neighbour counts to the host (one synchronisation)
+    std::vector<int64_t> bptr((size_t)L.n_bc + 1, 0);
+    std::vector<int32_t> cnt(L.np);
+    if (L.n_bc > 0)
+        HIPCHK(c, hipMemcpyAsync(bptr.data(), c->ws + L.bc_ptr, bptr.size() * 8,
+                                 hipMemcpyDeviceToHost, stream));
+    HIPCHK(c, hipMemcpyAsync(cnt.data(), c->ws + L.nnb, L.np * 4, hipMemcpyDeviceToHost, stream));
+    HIPCHK(c, hipStreamSynchronize(stream));
     // diagnostics segments: chunks of each specimen, then of each group
     {
-        std::vector<int64_t> bptr((size_t)L.n_bc + 1, 0);
-        if (L.n_bc > 0)
-            HIPCHK(c, hipMemcpy(bptr.data(), c->ws + L.bc_ptr, bptr.size() * 8,
-                                hipMemcpyDeviceToHost));
-        std::vector<int64_t> seg((size_t)L.n_spec + L.n_bc + 1, 0);
+        std::vector<int64_t>& seg = c->diag_seg_host;
+        seg.assign((size_t)L.n_spec + L.n_bc + 1, 0);
         auto chunks = [](int64_t m) { return m > 0 ? (m + kDiagChunk - 1) / kDiagChunk : 1; };
         for (int32_t q = 0; q < L.n_spec; ++q)
             seg[q + 1] = seg[q] + chunks(c->spec_off[q + 1] - c->spec_off[q]);
@@ -626,13 +637,13 @@ tlsph_status tlsph_build_neighbors(tlsph_ctx* c, const double* X, const double* 
             seg[L.n_spec + g + 1] = seg[L.n_spec + g] + chunks(bptr[g + 1] - bptr[g]);
         if (seg.back() > L.diag_chunk_cap)
             return fail(c, TLSPH_E_HIP, "diagnostics chunk table exceeds its capacity");
-        HIPCHK(c, hipMemcpy(c->ws + L.diag_seg, seg.data(), seg.size() * 8, hipMemcpyHostToDevice));
+        // (the host table lives in the context, so the copy may complete later)
+        HIPCHK(c, hipMemcpyAsync(c->ws + L.diag_seg, seg.data(), seg.size() * 8,
+                                 hipMemcpyHostToDevice, stream));
         c->diag_chunks_spec = seg[L.n_spec];
         c->diag_chunks_all = seg.back();
     }
     // neighbour pairs: sum of counts
-    std::vector<int32_t> cnt(L.np);
-    HIPCHK(c, hipMemcpy(cnt.data(), c->ws + L.nnb, L.np * 4, hipMemcpyDeviceToHost));
     int64_t nnz = 0;
     for (int64_t p = 0; p < L.n; ++p) nnz += cnt[p];
     c->nnz = nnz;
@@ -925,7 +936,7 @@ tlsph_status tlsph_autotune(tlsph_ctx* c, hipStream_t stream) {
     return TLSPH_OK;
 }
 
-tlsph_status tlsph_info(tlsph_ctx* c, int64_t out[9]) {
+tlsph_status tlsph_info(tlsph_ctx* c, int64_t out[9], hipStream_t stream) {
     if (!c || !out) return TLSPH_E_INVALID_ARG;
     out[0] = c->st.staged ? -c->block_b : c->block_b;
     out[1] = c->block_a;
@@ -938,7 +949,8 @@ tlsph_status tlsph_info(tlsph_ctx* c, int64_t out[9]) {
     out[8] = c->st.staged ? c->st.tile : 0;
     if (c->built) {
         int32_t fl = 0;
-        HIPCHK(c, hipMemcpy(&fl, c->ws + c->L.err + 8, 4, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpyAsync(&fl, c->ws + c->L.err + 8, 4, hipMemcpyDeviceToHost, stream));
+        HIPCHK(c, hipStreamSynchronize(stream));
         out[5] = fl;
     }
     return TLSPH_OK;

@@ -44,6 +44,8 @@ struct DevSpec {
     double h_per_spacing;      // > 0: per-particle support h_i = this V_i^(1/3)
     double contact_k;          // penalty contact factor (0: off)
     double contact_comp;       // (1 - nu^2) / E: the specimen's share of 1 / E*
+    int32_t newton_gtn;        // iteration caps: Algorithm 2's loops, the implicit return
+    int32_t newton_impl;
     int64_t first, last;   // sorted-order particle range [first, last)
 };
 

@@ -258,7 +258,7 @@ __host__ __device__ __forceinline__ void hardening_and_slope(const DevSpec& P, d
 // omD = 1 - D).  The left side falls and the right side rises with d, so the
 // root in [0, d_max] (d_max: the increment at the step's-start flow stress) is
 // unique; Newton steps are kept inside the shrinking bracket (bisection when
-// a step leaves it), at most 100 iterations.  The iteration ends on a Newton
+// a step leaves it), at most P.newton_impl (100 by default) iterations.  The iteration ends on a Newton
 // step below 1e-8 of d (Newton converges quadratically here, g being smooth
 // with |g''| d of the order of |g'|, so the next correction would be below
 // about 1e-16 d), on any step below 1e-14 of d, or on a bracket that narrow.
@@ -266,7 +266,7 @@ __host__ __device__ inline double implicit_increment(const DevSpec& P, double k3
                                                      double seq, double eps, double d_max,
                                                      int32_t& flags) {
     double lo = 0.0, hi = d_max, d = d_max;
-    for (int it = 0; it < 100; ++it) {
+    for (int it = 0; it < P.newton_impl; ++it) {
         const double rs = d * P.inv_dt * P.inv_eps_dot0;
         const bool fast = rs > 1.0 && P.C != 0.0;
         const double rf = fast ? 1.0 + P.C * log(rs) : 1.0;
@@ -348,19 +348,20 @@ __host__ __device__ inline void gtn_return(const DevSpec& P, double D, double dt
     double x = seq / sM0 < 1.0 ? seq / sM0 : 1.0;
     const double kx = 1.5 * q2 * ss;
     const double cst = 1.0 + q3 * fs * fs;
+    const int cap = P.newton_gtn;
     int it = 0;
-    for (; it < 50; ++it) {
+    for (; it < cap; ++it) {
         const double ch = cosh(kx * x), sh = sinh(kx * x);
         const double dx = -(x * x + 2.0 * q1 * fs * ch - cst) / (2.0 * x + 3.0 * q1 * q2 * fs * ss * sh);
         x += dx;
         if (fabs(dx) <= 1e-14) break;
     }
-    if (it == 50) flags |= kErrNewton;
+    if (it == cap) flags |= kErrNewton;
     // matrix plastic strain increment: d = c (seq - x sigma_f(eps_M + d))
     const double shx = sinh(kx * x);
     const double c = (x + 1.5 * q1 * q2 * f * ss * shx) / (3.0 * P.G * (1.0 - D) * (1.0 - f));
     double dem = c * (seq - x * sM0);
-    for (it = 0; it < 50; ++it) {
+    for (it = 0; it < cap; ++it) {
         const double e1 = epsM + dem;
         const double hard = hardening_slope<kFlow>(P, e1) * rf;
         const double sf = hardening<kFlow>(P, e1) * rf;
@@ -371,7 +372,7 @@ __host__ __device__ inline void gtn_return(const DevSpec& P, double D, double dt
         dem = nx;
         if (fabs(stp) <= 1e-14 * (dem > 1e-12 ? dem : 1e-12)) break;
     }
-    if (it == 50) flags |= kErrNewton;
+    if (it == cap) flags |= kErrNewton;
     epsM += dem;
     const double sM = hardening<kFlow>(P, epsM) * rf;
     const double sy = x * sM;
@@ -511,51 +512,55 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
         Dn = gtn_D(P, fv);
     } else {
         sm = mean_stress<R>(P, Jm1, R(D), R(e), true);
+        // The trial deviator is formed in the working precision; the radial
+        // return from it (the overstress sigma_eq - sigma_f, whose
+        // cancellation sets the plastic increment, and the scale factor) and
+        // the damage inputs (triaxiality, largest principal stress) are
+        // double in both forms: per particle, and what they feed accumulates
+        // in double.
         R st[6];
 #pragma unroll
         for (int k = 0; k < 6; ++k) st[k] = sdr[k] + R(2) * G * omD * de[k];
         // elastic if sigma_eq < sigma_f, decided on the squares (no root)
-        const R q2 = R(1.5) * (st[0] * st[0] + st[1] * st[1] + st[2] * st[2] +
-                               R(2) * (st[3] * st[3] + st[4] * st[4] + st[5] * st[5]));
+        const double t0 = st[0], t1 = st[1], t2 = st[2], t3 = st[3], t4 = st[4], t5 = st[5];
+        const double q2 = 1.5 * (t0 * t0 + t1 * t1 + t2 * t2 + 2.0 * (t3 * t3 + t4 * t4 + t5 * t5));
         const bool impl = kFlow && P.implicit_return;
         const double h0 = hardening<kFlow>(P, eps);
-        const R sf = R(h0 * (impl ? 1.0 : jc_rate_factor(P, rate))) * omD;
-        R dep = R(0);
+        const double omDd = 1.0 - D;
+        const double sf = h0 * (impl ? 1.0 : jc_rate_factor(P, rate)) * omDd;
         double depd = 0.0;
-        R sret = sf;   // equivalent stress after the return
-        if (q2 < sf * sf) {
-#pragma unroll
-            for (int k = 0; k < 6; ++k) sd[k] = st[k];
-        } else {
-            const R seq = sqrt(q2);
+        double sret = sf;   // equivalent stress after the return
+        double sc = 1.0;    // its ratio to the trial value
+        if (q2 >= sf * sf) {
+            const double seq = sqrt(q2);
             if (impl) {
-                const double omDd = 1.0 - D, k3 = 3.0 * P.G * omDd;
-                depd = implicit_increment(P, k3, omDd, double(seq), eps,
-                                          (double(seq) - omDd * h0) / k3, flags);
-                dep = R(depd);
-                sret = R(double(seq) - k3 * depd);
+                const double k3 = 3.0 * P.G * omDd;
+                depd = implicit_increment(P, k3, omDd, seq, eps, (seq - omDd * h0) / k3, flags);
+                sret = seq - k3 * depd;
             } else {
-                dep = (seq - sf) * rcp_nr(R(3) * G * omD);
-                depd = double(dep);
+                depd = (seq - sf) * rcp_nr(3.0 * P.G * omDd);
             }
-            const R sc = sret * rcp_nr(seq);
-#pragma unroll
-            for (int k = 0; k < 6; ++k) sd[k] = sc * st[k];
+            sc = sret * rcp_nr(seq);
         }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) sd[k] = R(sc * double(st[k]));
         eps += depd;
         rate = depd * P.inv_dt;
         if (depd > 0.0 && (model == 1 || model == 2)) {
             if (model == 2) {
                 // the returned deviator lies on the yield surface: its
                 // equivalent stress is sret
-                const R sstar = sm * rcp_nr(sret);
-                const double ef = (P.D1 + P.D2 * exp(P.D3 * double(sstar))) *
+                const double sstar = double(sm) * rcp_nr(sret);
+                const double ef = (P.D1 + P.D2 * exp(P.D3 * sstar)) *
                                   pow_el(1.0 + rate * P.inv_eps_dot0, P.D4);
                 dinit += depd * rcp_nr(ef);
             } else {
-                R full6[6] = {sd[0] + sm, sd[1] + sm, sd[2] + sm, sd[3], sd[4], sd[5]};
-                const R s1 = max_principal(full6);
-                wp += double(s1 > R(0) ? s1 : R(0)) * depd;
+                const double smd = double(sm);
+                double full6[6] = {sc * double(st[0]) + smd, sc * double(st[1]) + smd,
+                                   sc * double(st[2]) + smd, sc * double(st[3]),
+                                   sc * double(st[4]), sc * double(st[5])};
+                const double s1 = max_principal(full6);
+                wp += (s1 > 0.0 ? s1 : 0.0) * depd;
                 dinit = wp / P.Wcr;
             }
             double dn = 10.0 * (dinit - 1.0);

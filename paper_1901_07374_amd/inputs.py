@@ -36,7 +36,7 @@ MATERIAL_KEYS = (
     "q1", "q2", "q3", "f0", "fN", "eN", "sN", "fc", "fF", "k_omega",
     "h", "dt", "hg_alpha", "has_wall", "wall_n", "wall_d",
     "flow", "implicit_return", "flow_e0", "flow_beta", "av_q1", "av_q2", "h_per_spacing",
-    "contact_k", "T_star", "m",
+    "contact_k", "T_star", "m", "newton_max_iter",
 )
 
 # Steel used by every synthetic workload (rho, E, nu and the Johnson-Cook
@@ -63,7 +63,7 @@ def material(dx: float, damage: int = DMG_NONE, **over) -> Dict:
                   fc=1.0, fF=1.0, k_omega=0.0, hg_alpha=1.0, has_wall=0,
                   wall_n=(0.0, 0.0, 1.0), wall_d=0.0, flow=FLOW_JC, implicit_return=0,
                   flow_e0=0.0, flow_beta=0.0, av_q1=0.0, av_q2=0.0, h_per_spacing=0.0,
-                  contact_k=0.0, T_star=0.0, m=1.0))
+                  contact_k=0.0, T_star=0.0, m=1.0, newton_max_iter=0))
     if damage == DMG_JC:
         m.update(JC_DAMAGE)
     if damage == DMG_GTN:

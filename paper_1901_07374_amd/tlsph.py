@@ -49,7 +49,7 @@ class Specimen(C.Structure):
                 ("flow", C.c_int32), ("implicit_return", C.c_int32), ("flow_e0", C.c_double),
                 ("flow_beta", C.c_double), ("av_q1", C.c_double), ("av_q2", C.c_double),
                 ("h_per_spacing", C.c_double), ("contact_k", C.c_double),
-                ("T_star", C.c_double), ("m", C.c_double)]
+                ("T_star", C.c_double), ("m", C.c_double), ("newton_max_iter", C.c_int32)]
 
 
 class BCGroup(C.Structure):
@@ -89,7 +89,7 @@ def lib():
         L.tlsph_autotune.argtypes = [_vp, _vp]
         L.tlsph_enable_kernel_timing.argtypes = [_vp, C.c_int32]
         L.tlsph_kernel_times.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
-        L.tlsph_info.argtypes = [_vp, C.POINTER(C.c_int64)]
+        L.tlsph_info.argtypes = [_vp, C.POINTER(C.c_int64), _vp]
         L.tlsph_set_launch_shape.argtypes = [_vp, C.POINTER(C.c_int32), _vp]
         L.tlsph_destroy.argtypes = [_vp]
         L.tlsph_destroy.restype = None
@@ -113,7 +113,7 @@ def specimen_struct(m: Dict) -> Specimen:
         if name == "wall_n":
             s.wall_n = (C.c_double * 3)(*m["wall_n"])
         elif typ is C.c_int32:
-            setattr(s, name, int(m[name]))
+            setattr(s, name, int(m.get(name, 0)))
         else:
             setattr(s, name, float(m[name]))
     return s
@@ -240,6 +240,32 @@ class Sim:
         for k, v in st.items():
             self.set(k, v)
 
+    def set_tensor(self, name: str, x):
+        """Overwrite a field from a device tensor shaped as get_tensor returns
+        it (stream-ordered, no host copy)."""
+        fid, comps = FIELDS[name]
+        if name == "t" or comps == 1:
+            src = x.contiguous()
+        else:
+            src = x.t().contiguous()
+        self._check(lib().tlsph_set_state(self.ctx, fid, src.data_ptr(), src.numel() * 8,
+                                          self._sp()), f"tlsph_set_state({name})")
+        self.stream.synchronize()
+
+    # every field that makes up the evolving state (F through H = F - I, so a
+    # context of the same precision continues bit for bit)
+    STATE = ("u", "v", "H", "sig", "eps_p", "eps_p_rate", "d_init", "w_p", "f_void", "D", "e",
+             "Q", "fvisc", "t")
+
+    def copy_state_from(self, other: "Sim"):
+        """Take over the state of another context over the same problem
+        (device to device); across precisions the stored float fields are
+        rounded or widened."""
+        for k in self.STATE:
+            x = other.get_tensor(k)
+            other.stream.synchronize()
+            self.set_tensor(k, x)
+
     def neighbors(self):
         t = self.torch
         nnz = C.c_int64()
@@ -282,7 +308,7 @@ class Sim:
 
     def info(self) -> Dict[str, int]:
         out = (C.c_int64 * 9)()
-        self._check(lib().tlsph_info(self.ctx, out), "tlsph_info")
+        self._check(lib().tlsph_info(self.ctx, out, self._sp()), "tlsph_info")
         return dict(block_force=abs(out[0]), staged=out[0] < 0, block_deformation=out[1],
                     nnz=out[2], slots=out[3], n=out[4], flags=out[5],
                     lanes_per_particle=out[6], lds_bytes=out[7], tile=out[8])

@@ -108,7 +108,7 @@ def test_null_context_calls(L):
     assert L.tlsph_set_state(None, 1, None, 0, None) == 1
     assert L.tlsph_build_neighbors(None, None, None, None, None) == 1
     assert L.tlsph_autotune(None, None) == 1
-    assert L.tlsph_info(None, None) == 1
+    assert L.tlsph_info(None, None, None) == 1
     assert L.tlsph_set_launch_shape(None, None, None) == 1
     L.tlsph_set_contact.argtypes = [C.c_void_p, C.c_int32, C.c_double]
     assert L.tlsph_set_contact(None, 1, 0.0) == 1

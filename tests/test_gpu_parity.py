@@ -454,6 +454,36 @@ def test_diagnostics_match_fields(tl, case):
     assert np.array_equal(sd, sd2) and np.array_equal(bd, bd2)
 
 
+@pytest.mark.parametrize("case", ["bar", "batch3"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_diagnostics_match_oracle(tl, orc, case, precision):
+    """The GPU's diagnostics against the oracle's plain sums over its own
+    state, after steps from an injected state with failed particles: the
+    energies, the failed count (exact), max D, time, and the force and mean
+    displacement of each gripped end (the reaction-displacement record the
+    runs of Sec. 6 are read by)."""
+    p = {"bar": lambda: I.notched_bar(dx=0.7e-3), "batch3": CASES["batch3"]}[case]()
+    st = I.random_state(p, seed=61)
+    o = orc.Sim(p)
+    o.set_state(st)
+    g = tl.Sim(p, precision=tl.FP64 if precision == "fp64" else tl.MIXED, flags=tl.STORE_FORCE)
+    g.set_state(st)
+    tol = 1e-11 if precision == "fp64" else 1e-5
+    for k in (1, 2):
+        o.step(k)
+        g.step(k)
+        sd, bd = g.diagnostics()
+        sdo, bdo = o.diagnostics()
+        say(case, precision, "diag", np.abs(sd - sdo).max(axis=0))
+        assert np.array_equal(sd[:, 2], sdo[:, 2]) and sdo[:, 2].sum() > 0
+        for c in (0, 1, 3, 4):
+            assert np.abs(sd[:, c] - sdo[:, c]).max() <= tol * np.abs(sdo[:, c]).max(), c
+        fscale = np.abs(o.get("force")).sum()
+        assert np.abs(bd[:, :3] - bdo[:, :3]).max() <= tol * fscale
+        assert np.abs(bd[:, 3:6] - bdo[:, 3:6]).max() <= tol * np.abs(bdo[:, 3:6]).max()
+        assert np.array_equal(bd[:, 6], bdo[:, 6])
+
+
 def test_error_paths(tl):
     p = I.cube(nside=5, jitter=0.0)
     X = p.X.copy()
@@ -480,3 +510,45 @@ def test_error_paths(tl):
     with pytest.raises(tl.TLSPHError) as ei:
         g2.set_launch_shape(1, 4)
     assert ei.value.status == 7
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_nonfinite_state_is_latched(tl, precision):
+    """TLSPH_CHECK_FINITE: a NaN injected into one particle's velocity
+    reaches its stress in the next step; the device latches the non-finite
+    flag (info bit 0).  Without the check nothing is flagged."""
+    p = I.notched_bar(dx=0.8e-3)
+    pr = tl.FP64 if precision == "fp64" else tl.MIXED
+    for flags, expect in ((tl.CHECK_FINITE, 1), (0, 0)):
+        g = tl.Sim(p, precision=pr, flags=flags)
+        g.step(3)
+        assert g.info()["flags"] == 0
+        v = g.get("v")
+        v[p.n // 2, 0] = np.nan
+        g.set("v", v)
+        g.step(1)
+        assert g.info()["flags"] & 1 == expect
+
+
+def test_newton_not_converged_is_flagged(tl, orc):
+    """Algorithm 2's Newton loops and the implicit return give up at their
+    iteration cap and raise info bit 1; a cap of one iteration (a specimen
+    parameter) forces that path from the host on plastic GTN and implicit
+    states, while the default cap leaves the flag clear."""
+    base = I.holed_plate(dx=0.25e-3, W=8e-3, H=4e-3, T=0.5e-3, hole_d=1.5e-3)
+    st = I.random_state(base, seed=71)
+    consistent_gtn(orc, base, st, f_hi=0.1, seed=71)
+    for cap, expect in ((0, 0), (1, 2)):
+        p = remat(base, dict(newton_max_iter=cap))
+        g = tl.Sim(p)
+        g.set_state(st)
+        g.step(1)
+        assert g.info()["flags"] & 2 == expect, cap
+    bar = I.notched_bar(dx=0.8e-3)
+    stb = I.random_state(bar, seed=72)
+    for cap, expect in ((0, 0), (1, 2)):
+        p = remat(bar, dict(VOCE, implicit_return=1, newton_max_iter=cap))
+        g = tl.Sim(p)
+        g.set_state(stb)
+        g.step(1)
+        assert g.info()["flags"] & 2 == expect, cap

@@ -253,3 +253,48 @@ def test_thread_count_does_not_change_results(orc):
     for o in out[1:]:
         for k in o:
             assert np.array_equal(o[k], out[0][k]), k
+
+
+def test_diagnostics_are_the_plain_sums(orc):
+    """The oracle's diagnostics (the grip force and displacement the runs of
+    Sec. 6 are read by, the energies of eq. conservation3, failed count and
+    max D) equal the same sums taken by numpy over its exported state, for
+    two specimens with both grips, some particles failed."""
+    p = I.bar_batch(n_spec=2, counts=(1500, 2500))
+    s = orc.Sim(p)
+    st = I.random_state(p, 31)
+    s.set_state(st)
+    s.step(2)
+    sd, bd = s.diagnostics()
+    sid = p.spec_id()
+    v, e, D, u, f = (s.get(k) for k in ("v", "e", "D", "u", "force"))
+    for q in range(p.n_spec):
+        sel = sid == q
+        m = p.materials[q]["rho0"] * p.V0[sel]
+        assert sd[q, 0] == pytest.approx(0.5 * np.sum(m[:, None] * v[sel] ** 2), rel=1e-13)
+        assert sd[q, 1] == pytest.approx(np.sum(m * e[sel]), rel=1e-13)
+        assert sd[q, 2] == np.sum(D[sel] >= 1.0) and sd[q, 2] > 0
+        assert sd[q, 3] == D[sel].max()
+        assert sd[q, 4] == s.get("t")[q]
+    for g in range(len(p.bc_groups)):
+        sel = p.bc_group == g
+        assert bd[g, 6] == sel.sum() > 0
+        assert np.allclose(bd[g, :3], f[sel].sum(0), rtol=1e-13, atol=1e-13 * np.abs(f[sel]).sum())
+        assert np.allclose(bd[g, 3:6], u[sel].mean(0), rtol=1e-13, atol=1e-20)
+
+
+def test_diagnostics_energy_in_free_vibration(orc):
+    """Read through the diagnostics, the free elastic vibration keeps kinetic
+    plus internal energy at the initial kinetic energy (eq. conservation3,
+    bounded leapfrog error)."""
+    p = no_bc(I.cube(nside=8), hg_alpha=0.0)
+    s = orc.Sim(p)
+    v0 = np.zeros((p.n, 3))
+    v0[:, 0] = 0.5 * np.sin(p.X[:, 2] / 8e-3 * np.pi)
+    s.set("v", v0)
+    E0 = 0.5 * np.sum(p.materials[0]["rho0"] * p.V0[:, None] * v0 ** 2)
+    for _ in range(5):
+        s.step(40)
+        sd, _ = s.diagnostics()
+        assert sd[0, 1] > 0.0
+        assert abs(sd[0, 0] + sd[0, 1] - E0) < 1e-2 * E0
