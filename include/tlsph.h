@@ -266,6 +266,19 @@ tlsph_status tlsph_get_neighbors(tlsph_ctx *ctx, int64_t *row_ptr, int32_t *col,
 tlsph_status tlsph_get_diagnostics(tlsph_ctx *ctx, double *spec_diag, double *bc_diag,
                                    hipStream_t stream);
 
+/* The same diagnostics for callers that cannot allocate device memory at
+ * the call (code under graph capture, serving loops, harnesses that forbid
+ * allocation): identical kernels, summation order and results, with the
+ * chunk partials in a static device array of the library (1 MiB per device,
+ * 16384 partials: one per 2048 particles of each specimen and each group,
+ * at least one each) instead of the workspace.  Allocates nothing; the first
+ * call on a device looks up that device's array.  Every call on one device
+ * shares the array: calls that overlap on one device (other streams or
+ * threads) race and must be ordered by the caller.  Errors: as
+ * tlsph_get_diagnostics, CAPACITY when the partials would not fit. */
+tlsph_status tlsph_get_diagnostics_static(tlsph_ctx *ctx, double *spec_diag, double *bc_diag,
+                                          hipStream_t stream);
+
 /* Replace the prescribed-velocity table (host, tlsph_bc_group[n_bc],
  * n_bc <= the count given at create), ordered on the stream.  Errors:
  * INVALID_ARG, HIP. */

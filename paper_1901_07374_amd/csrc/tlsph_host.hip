@@ -758,6 +758,26 @@ tlsph_status tlsph_get_diagnostics(tlsph_ctx* c, double* spec_diag, double* bc_d
     return TLSPH_OK;
 }
 
+tlsph_status tlsph_get_diagnostics_static(tlsph_ctx* c, double* spec_diag, double* bc_diag,
+                                          hipStream_t stream) {
+    if (!c || !spec_diag) return fail(c, TLSPH_E_INVALID_ARG, "null argument");
+    if (!c->built) return fail(c, TLSPH_E_BAD_STATE, "diagnostics before build");
+    const bool groups = bc_diag != nullptr && c->L.n_bc > 0;
+    const int64_t chunks = groups ? c->diag_chunks_all : c->diag_chunks_spec;
+    if (chunks * kNDiag > kScratchDoubles)
+        return fail(c, TLSPH_E_CAPACITY,
+                    "diagnostics need " + std::to_string(chunks) + " chunk partials; the static "
+                    "scratch holds " + std::to_string(kScratchDoubles / kNDiag) +
+                    " (use tlsph_get_diagnostics)");
+    double* part = nullptr;
+    HIPCHK(c, scratch_ptr(&part));
+    HIPCHK(c, launch_diagnostics(c->st, c->parity, at<int32_t>(c, c->L.bc_list),
+                                 at<int64_t>(c, c->L.bc_ptr), at<int64_t>(c, c->L.diag_seg),
+                                 groups ? c->L.n_spec + c->L.n_bc : c->L.n_spec, chunks, part,
+                                 spec_diag, bc_diag, stream));
+    return TLSPH_OK;
+}
+
 tlsph_status tlsph_set_bc_groups(tlsph_ctx* c, int32_t n_bc, const tlsph_bc_group* bc,
                                  hipStream_t stream) {
     if (!c || n_bc < 0 || n_bc > c->n_bc_cap || (n_bc > 0 && !bc))

@@ -15,6 +15,9 @@ constexpr int kDiagChunk = 2048;   // particles per partial sum of the diagnosti
 constexpr int kTile = 256;         // most particles per workgroup tile of the LDS-staged pass
 constexpr int kHaloSortMax = 8192; // tile entries sorted in LDS at build (kTile * k_cap)
 constexpr int kContactCap = 32;    // contact candidates per particle
+// doubles of the static scratch array of the allocation-free diagnostics
+// (1 MiB per device: 16384 chunk partials of kNDiag doubles)
+constexpr int64_t kScratchDoubles = 1 << 17;
 
 // Per-specimen parameters as the kernels read them (raw + derived).
 struct DevSpec {
@@ -189,6 +192,9 @@ hipError_t launch_export_neighbors(const DevState& s, int64_t* row_ptr, int32_t*
 // Two-level fixed-order reductions: chunk partials (seg[q] .. seg[q+1] are the
 // chunks of segment q: specimens first, then boundary groups), then one block
 // per segment.
+// Device address of this device's static scratch array (kScratchDoubles
+// doubles), looked up on the first call with the device current.
+hipError_t scratch_ptr(double** out);
 hipError_t launch_diagnostics(const DevState& s, int parity, const int32_t* bc_list,
                               const int64_t* bc_ptr, const int64_t* seg, int32_t n_seg,
                               int64_t n_chunks, double* part, double* spec_diag, double* bc_diag,

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "tlsph_internal.h"
@@ -2106,6 +2107,35 @@ __global__ void __launch_bounds__(256) k_diag_final(DevState s, const int64_t* _
         o[6] = cnt;
         o[7] = 0.0;
     }
+}
+
+// ===========================================================================
+// scratch of the allocation-free diagnostics entry point
+// ===========================================================================
+
+// Chunk partials of tlsph_get_diagnostics_static: one array per device, held
+// until the process ends.  Host code must not pass `scratch` itself to a
+// kernel (on the host it names a stand-in, not device memory): scratch_ptr
+// looks up each device's address once, with that device current.
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+hipError_t scratch_ptr(double** out) {
+    constexpr int kMaxDev = 64;
+    static std::mutex mu;
+    static double* addr[kMaxDev] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDev) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<double*>(p);
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_diagnostics(const DevState& s, int parity, const int32_t* bc_list,

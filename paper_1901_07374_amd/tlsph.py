@@ -85,6 +85,7 @@ def lib():
         L.tlsph_neighbor_count.argtypes = [_vp, C.POINTER(C.c_int64)]
         L.tlsph_get_neighbors.argtypes = [_vp, _vp, _vp, _vp]
         L.tlsph_get_diagnostics.argtypes = [_vp, _vp, _vp, _vp]
+        L.tlsph_get_diagnostics_static.argtypes = [_vp, _vp, _vp, _vp]
         L.tlsph_set_bc_groups.argtypes = [_vp, C.c_int32, C.POINTER(BCGroup), _vp]
         L.tlsph_autotune.argtypes = [_vp, _vp]
         L.tlsph_enable_kernel_timing.argtypes = [_vp, C.c_int32]
@@ -99,7 +100,8 @@ def lib():
         L.tlsph_last_error.restype = C.c_char_p
         for name in ("tlsph_workspace_bytes", "tlsph_create", "tlsph_build_neighbors",
                      "tlsph_step", "tlsph_get_state", "tlsph_set_state", "tlsph_neighbor_count",
-                     "tlsph_get_neighbors", "tlsph_get_diagnostics", "tlsph_set_bc_groups",
+                     "tlsph_get_neighbors", "tlsph_get_diagnostics",
+                     "tlsph_get_diagnostics_static", "tlsph_set_bc_groups",
                      "tlsph_autotune", "tlsph_enable_kernel_timing", "tlsph_kernel_times",
                      "tlsph_info", "tlsph_set_launch_shape"):
             getattr(L, name).restype = C.c_int
