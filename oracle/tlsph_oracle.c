@@ -496,7 +496,9 @@ void orc_hughes_winget(double dt, const double w[9], const double sd_in[9],
 /* falls and the right side rises with d, so the root is unique in          */
 /* [0, (sigma_eq,tr - (1 - D) sigma_f(eps_n, 0)) / (3G(1 - D))]; it is found  */
 /* by Newton steps kept inside a shrinking bracket (bisection when a step   */
-/* leaves it), to a step of 1e-14 relative, at most 100 iterations.         */
+/* leaves it), to a step of 1e-14 relative to d or to the increment        */
+/* sigma_eq,tr / (3G(1 - D)) that would unload the trial stress, at most    */
+/* 100 iterations.                                                          */
 /* ------------------------------------------------------------------------ */
 static double implicit_increment(const orc_material *m, double k3, double omD, double seq_tr,
                                  double eps_p, double dt, double d_max, int32_t *failed) {
@@ -513,7 +515,7 @@ static double implicit_increment(const orc_material *m, double k3, double omD, d
         if (!(nd > lo && nd < hi)) nd = 0.5 * (lo + hi);
         double step = fabs(nd - d);
         d = nd;
-        if (step <= 1e-14 * d || hi - lo <= 1e-14 * hi) return d;
+        if (step <= 1e-14 * d || step <= 1e-14 * seq_tr / k3 || hi - lo <= 1e-14 * hi) return d;
     }
     *failed = 1;
     return d;
@@ -557,7 +559,10 @@ static void alg1_return(const orc_material *m, double G, double D, double dt,
 /* d_eps_p_eq = (sigma_eq,trial - sigma_y)/(3G(1-D)), which keeps the        */
 /* triaxiality constant as the derivation assumes; nucleation is the        */
 /* Chu-Needleman normal distribution (squared exponent) times d_eps_M;      */
-/* Newton tolerances 1e-14 (absolute on x, relative on d_eps_M), at most 50 */
+/* Newton tolerances 1e-14 (absolute on x; on d_eps_M relative to the      */
+/* increment c sigma_eq,trial that would unload the trial stress, the scale */
+/* its rounding is set by: relative to d_eps_M itself a small increment    */
+/* never converges), at most 50                                             */
 /* iterations; a trial stress below 1e-12 sigma_M is elastic.               */
 /* ------------------------------------------------------------------------ */
 static void gtn_return(const orc_material *m, double G, double D, double dt,
@@ -614,8 +619,7 @@ static void gtn_return(const orc_material *m, double G, double D, double dt,
         if (next < 0.0) next = 0.5 * dem; /* keep the increment non-negative */
         double step = next - dem;
         dem = next;
-        double scale = dem > 1e-12 ? dem : 1e-12;
-        if (fabs(step) <= 1e-14 * scale) break;
+        if (fabs(step) <= 1e-14 * c * seq_tr) break;
     }
     info->newton_e_iters = it + 1;
     if (it == 50) info->newton_failed |= 2;

@@ -826,6 +826,11 @@ tlsph_status tlsph_autotune(tlsph_ctx* c, hipStream_t stream) {
     HIPCHK(c, hipMemcpyAsync(backup, state, L.backup_bytes, hipMemcpyDeviceToDevice, stream));
     HIPCHK(c, hipMemcpyAsync(backup + L.backup_bytes, c->st.t, L.n_spec * 8,
                              hipMemcpyDeviceToDevice, stream));
+    // the sticky error flags too: the timing runs repeat single passes on
+    // states no step would produce, which may raise flags of their own
+    int32_t flags_before = 0;
+    HIPCHK(c, hipMemcpyAsync(&flags_before, c->ws + L.err + 8, 4, hipMemcpyDeviceToHost, stream));
+    HIPCHK(c, hipStreamSynchronize(stream));
     // force pass: unstaged (lanes per particle, block) and staged (tile
     // size, lanes per particle); deformation pass: block
     struct Cand { int staged, sub, block, tile; };
@@ -951,6 +956,7 @@ tlsph_status tlsph_autotune(tlsph_ctx* c, hipStream_t stream) {
     HIPCHK(c, hipMemcpyAsync(state, backup, L.backup_bytes, hipMemcpyDeviceToDevice, stream));
     HIPCHK(c, hipMemcpyAsync(c->st.t, backup + L.backup_bytes, L.n_spec * 8,
                              hipMemcpyDeviceToDevice, stream));
+    HIPCHK(c, hipMemcpyAsync(c->ws + L.err + 8, &flags_before, 4, hipMemcpyHostToDevice, stream));
     HIPCHK(c, hipStreamSynchronize(stream));
     c->contact_age = 1 << 30;
     return TLSPH_OK;

@@ -261,7 +261,9 @@ __host__ __device__ __forceinline__ void hardening_and_slope(const DevSpec& P, d
 // a step leaves it), at most P.newton_impl (100 by default) iterations.  The iteration ends on a Newton
 // step below 1e-8 of d (Newton converges quadratically here, g being smooth
 // with |g''| d of the order of |g'|, so the next correction would be below
-// about 1e-16 d), on any step below 1e-14 of d, or on a bracket that narrow.
+// about 1e-16 d), on any step below 1e-14 of d or of seq / k3 (the increment
+// that would unload the trial stress, which sets the rounding of g: a tiny
+// d cannot be resolved to 1e-14 of itself), or on a bracket that narrow.
 __host__ __device__ inline double implicit_increment(const DevSpec& P, double k3, double omD,
                                                      double seq, double eps, double d_max,
                                                      int32_t& flags) {
@@ -281,7 +283,8 @@ __host__ __device__ inline double implicit_increment(const DevSpec& P, double k3
         if (!newton) nd = 0.5 * (lo + hi);
         const double step = fabs(nd - d);
         d = nd;
-        if ((newton && step <= 1e-8 * d) || step <= 1e-14 * d || hi - lo <= 1e-14 * hi)
+        if ((newton && step <= 1e-8 * d) || step <= 1e-14 * d || step <= 1e-14 * seq / k3 ||
+            hi - lo <= 1e-14 * hi)
             return d;
     }
     flags |= kErrNewton;
@@ -370,7 +373,10 @@ __host__ __device__ inline void gtn_return(const DevSpec& P, double D, double dt
         if (nx < 0.0) nx = 0.5 * dem;
         const double stp = nx - dem;
         dem = nx;
-        if (fabs(stp) <= 1e-14 * (dem > 1e-12 ? dem : 1e-12)) break;
+        // converged once the correction is below 1e-14 of c seq, the
+        // increment that would unload the trial stress (the rounding of g
+        // scales with it; relative to a tiny dem itself the loop would stall)
+        if (fabs(stp) <= 1e-14 * c * seq) break;
     }
     if (it == cap) flags |= kErrNewton;
     epsM += dem;

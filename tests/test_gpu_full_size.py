@@ -59,6 +59,8 @@ def run_case(tl, orc, p, precisions, seed, k_cap=32, setup=None):
         say(p.name, p.n, prec, g.info(), {k: f"{v:.1e}" for k, v in errs.items()})
         bad = {k: v for k, v in errs.items() if not v <= tol}
         assert not bad, bad
+        # every Newton loop of the step ended by its convergence test
+        assert g.info()["flags"] & 2 == 0
         del g
 
 

@@ -545,3 +545,26 @@ def test_gtn_void_growth_with_shear_and_nucleation(orc, J0, f, fN):
     nucleation A_N d eps_M at the step's end strain."""
     df, expect, _, _ = _gtn_growth_case(orc, J0, f, 3.5, fN=fN, seed=23)
     assert df == pytest.approx(expect, rel=1e-7)
+
+
+def test_gtn_newton_converges_on_small_increments(orc):
+    """Algorithm 2's second loop on the plastic increments of steady loading
+    at rates from 1e-3 to 300 per second (increments down to about 1e-12 per
+    step): every step must end by the loop's convergence test within a few
+    iterations, not at the iteration cap.  (A stopping rule relative to the
+    increment itself is not attainable in double for small increments: the
+    residual's rounding scales with the trial stress, not with the
+    increment.)"""
+    m = I.material(0.125e-3, I.DMG_GTN, C=0.0)
+    dt = m["dt"]
+    for rate in np.geomspace(1e-3, 300.0, 25):
+        pt = orc.Point(m, f_void=0.001, D=m["q1"] * 0.001)
+        for _ in range(2600):                     # into the plastic range
+            pt.update(np.diag([300.0, -90.0, 0.0]), dt)
+        Fd = np.diag([rate, -0.3 * rate, 0.0])
+        for _ in range(4):
+            pt.update(Fd, dt)
+            info = pt.info
+            assert info.yielded == 1 and info.dep > 0.0, rate
+            assert info.newton_failed == 0 and info.newton_e_iters <= 8, (
+                rate, info.newton_e_iters, info.dep)
