@@ -266,6 +266,7 @@ def launch_shape(info):
 
 def shape_of(info):
     return {"force_pass_variant": "LDS-staged tiles" if info["staged"] else "global gathers",
+            "tile": info["tile"],
             "force_pass_block": info["block_force"],
             "force_lanes_per_particle": info["lanes_per_particle"],
             "deformation_pass_block": info["block_deformation"]}
@@ -522,7 +523,10 @@ def bench_plate(args, torch, I, T):
         k = PRELOAD_CHUNK if target < 0 else min(PRELOAD_CHUNK, target - pre)
         fp_sim.step(k)
         pre += k
-        if target < 0 and plastic_share(fp_sim, torch) >= PLASTIC_TARGET:
+        share = plastic_share(fp_sim, torch)
+        if pre % (4 * PRELOAD_CHUNK) == 0:
+            log(f"preload: {pre} steps, {time.perf_counter() - t0:.1f} s, plastic share {share:.4f}")
+        if target < 0 and share >= PLASTIC_TARGET:
             break
     torch.cuda.synchronize()
     start = plate_state(fp_sim, torch)
@@ -559,6 +563,7 @@ def bench_plate(args, torch, I, T):
     out["roofline"] = roofline_of(fp, damage, prob.n, workload)
     res64 = result(fp)
     out["fp64_result"] = res64
+    out["fp64_device_flags"] = fp_sim.info()["flags"]
     del fp["sim"], fp_sim
     if mx_sim is not None:
         mx = run_form(prob, T.MIXED, args.steps, args.warmup, torch, T, 0, tune, sim=mx_sim)
@@ -568,6 +573,7 @@ def bench_plate(args, torch, I, T):
             "value": round(prob.n * args.steps / mx["seconds"], 1), "unit": "particle-steps/s",
             "ms_per_step": round(mx["seconds"] / args.steps * 1e3, 5), "dtype": "f32/f64",
             "from": "the FP64 state after the preload (float fields rounded)",
+            "device_flags": mx_sim.info()["flags"],
             "launch": shape_of(mx["info"]), "kernels": mtab, "result": resm,
             "rel_diff_vs_fp64": {k: (round(abs(resm[k] - res64[k]) / abs(res64[k]), 6)
                                      if res64[k] else None) for k in res64}}
@@ -681,6 +687,8 @@ def main():
     out = fn(args, torch, I, T)
 
     if args.copy_probe_mib > 0:
+        # counter calibration: a plain device copy of known size, and a gather
+        # of 64-byte rows in random order (each row read once)
         nb = args.copy_probe_mib * 1024 * 1024
         a = torch.empty(nb, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)
@@ -689,6 +697,16 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = nb
+        del a, b
+        rows = nb // 64
+        tab = torch.ones((rows, 8), dtype=torch.float64, device="cuda")
+        idx = torch.randperm(rows, device="cuda")
+        torch.cuda.synchronize()
+        g = tab.index_select(0, idx)
+        torch.cuda.synchronize()
+        out["gather_probe"] = {"rows": rows, "row_bytes": 64, "index_bytes": 8,
+                               "read_bytes": rows * 72, "write_bytes": rows * 64}
+        del tab, idx, g
     print(json.dumps(out), flush=True)
 
 

@@ -685,8 +685,19 @@ __device__ __forceinline__ void force_pair(const LRecB<R>& ni, const LRecB<R>& n
         kg = kw * inv_h;
     }
     const R q = r2 * ir * inv_h;
+    // cubic spline: with a = 1 - q and b = max(1/2 - q, 0), W / c = 2 a^3 -
+    // 8 b^3 and h dW/dr / c = -6 a^2 + 24 b^2 (b = 0 beyond q = 1/2, where
+    // seven pairs in eight lie).  FP64 evaluates it without a branch; the
+    // mixed form keeps the two-branch form, which fits its register budget
+    // of four waves per SIMD without spilling.
     R w, sl;
-    if (q < R(0.5)) {
+    if constexpr (sizeof(R) == 8) {
+        const R a = R(1) - q;
+        const R b = fmax(R(0.5) - q, R(0));
+        const R a2 = a * a, b2 = b * b;
+        sl = fma(R(24), b2, R(-6) * a2);
+        w = fma(R(-8) * b2, b, (a + a) * a2);
+    } else if (q < R(0.5)) {
         w = fma(q * q, fma(R(6), q, R(-6)), R(1));
         sl = q * fma(R(18), q, R(-12));
     } else {
@@ -729,12 +740,30 @@ __device__ __forceinline__ ForceAcc<R> acc_sum(const ForceAcc<R>& x, const Force
     return r;
 }
 
-template <typename R>
-__device__ __forceinline__ ForceAcc<R> acc_xor(const ForceAcc<R>& x, int m) {
+// The value of lane l ^ m (m = 1 or 2) within each group of four lanes, by a
+// DPP quad permutation (a VALU operand modifier: no LDS traffic).
+template <int M>
+__device__ __forceinline__ float quad_xor(float v) {
+    static_assert(M == 1 || M == 2, "quad permutations for xor 1 and 2");
+    constexpr int ctrl = M == 1 ? 0xB1 : 0x4E;   // quad_perm [1,0,3,2] / [2,3,0,1]
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xF, 0xF, false));
+}
+template <int M>
+__device__ __forceinline__ double quad_xor(double v) {
+    static_assert(M == 1 || M == 2, "quad permutations for xor 1 and 2");
+    constexpr int ctrl = M == 1 ? 0xB1 : 0x4E;
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), ctrl, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int M, typename R>
+__device__ __forceinline__ ForceAcc<R> acc_xor(const ForceAcc<R>& x) {
     ForceAcc<R> r;
-    r.a0 = __shfl_xor(x.a0, m); r.a1 = __shfl_xor(x.a1, m); r.a2 = __shfl_xor(x.a2, m);
-    r.b0 = __shfl_xor(x.b0, m); r.b1 = __shfl_xor(x.b1, m); r.b2 = __shfl_xor(x.b2, m);
-    r.g0 = __shfl_xor(x.g0, m); r.g1 = __shfl_xor(x.g1, m); r.g2 = __shfl_xor(x.g2, m);
+    r.a0 = quad_xor<M>(x.a0); r.a1 = quad_xor<M>(x.a1); r.a2 = quad_xor<M>(x.a2);
+    r.b0 = quad_xor<M>(x.b0); r.b1 = quad_xor<M>(x.b1); r.b2 = quad_xor<M>(x.b2);
+    r.g0 = quad_xor<M>(x.g0); r.g1 = quad_xor<M>(x.g1); r.g2 = quad_xor<M>(x.g2);
     return r;
 }
 
@@ -789,12 +818,12 @@ __device__ __forceinline__ ForceAcc<R> pair_sums(const LRecB<R>& ni, int cnt, in
     if constexpr (S == 1) {
         return acc_sum(acc_sum(A[0], A[1]), acc_sum(A[2], A[3]));
     } else if constexpr (S == 2) {
-        const ForceAcc<R> x = acc_sum(A[0], acc_xor(A[0], 1));   // p0 + p1
-        const ForceAcc<R> y = acc_sum(A[1], acc_xor(A[1], 1));   // p2 + p3
+        const ForceAcc<R> x = acc_sum(A[0], acc_xor<1>(A[0]));   // p0 + p1
+        const ForceAcc<R> y = acc_sum(A[1], acc_xor<1>(A[1]));   // p2 + p3
         return acc_sum(x, y);
     } else {
-        const ForceAcc<R> x = acc_sum(A[0], acc_xor(A[0], 1));   // p0 + p1 | p2 + p3
-        return acc_sum(x, acc_xor(x, 2));
+        const ForceAcc<R> x = acc_sum(A[0], acc_xor<1>(A[0]));   // p0 + p1 | p2 + p3
+        return acc_sum(x, acc_xor<2>(x));
     }
 }
 
@@ -1247,13 +1276,10 @@ __device__ __forceinline__ void gather_fdot(const D4& xi, const D4& vi, int cnt,
                 ih = rcp_nr(hpair);
             }
             const R q = r2 * ir * ih;
-            R sl;
-            if (q < R(0.5)) {
-                sl = q * fma(R(18), q, R(-12));
-            } else {
-                const R a = R(1) - q;
-                sl = R(-6) * (a * a);
-            }
+            // h dW/dr / c = -6 (1 - q)^2 + 24 max(1/2 - q, 0)^2, no branch
+            const R a = R(1) - q;
+            const R b = fmax(R(0.5) - q, R(0));
+            const R sl = fma(R(24), b * b, R(-6) * (a * a));
             R gw = sl * ir * R(nb[t].w);
             if constexpr (kVarH) gw *= R(8.0 / M_PI) * ih * ih * ih * ih;
             const R gx = gw * dx, gy = gw * dy, gz = gw * dz;

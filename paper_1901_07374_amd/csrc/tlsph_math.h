@@ -319,6 +319,14 @@ __host__ __device__ __forceinline__ double gtn_D(const DevSpec& P, double f) {
     return d < 1.0 ? d : 1.0;
 }
 
+// cosh y and sinh y from one exponential and its reciprocal (for the y of
+// Algorithm 2, |y| well below 700)
+__host__ __device__ __forceinline__ void cosh_sinh(double y, double& ch, double& sh) {
+    const double e = exp(y), ie = rcp_nr(e);
+    ch = 0.5 * (e + ie);
+    sh = 0.5 * (e - ie);
+}
+
 // GTN return mapping (Algorithm 2), double precision.  In: trial deviator
 // (Voigt) and trial mean stress, state (eps_M, its last rate, f), damage D.
 // Out: returned deviator and mean stress, updated eps_M, rate, f.
@@ -336,8 +344,17 @@ __host__ __device__ inline void gtn_return(const DevSpec& P, double D, double dt
     if (seq >= 1e-12 * sM0) {
         ss = smt / seq;
         const double r = seq / sM0;
-        const double phi = r * r + 2.0 * q1 * fs * cosh(1.5 * q2 * ss * r) - (1.0 + q3 * fs * fs);
-        plastic = !(phi < 0.0);
+        const double a = 1.5 * q2 * ss * r;
+        const double cst = 1.0 + q3 * fs * fs;
+        // cosh a <= 1 + 0.6 a^2 for |a| <= 1: a trial state that this bound
+        // already puts more than 1e-9 inside the yield surface is elastic
+        // without the exponential (the exact test below would agree: its
+        // rounding is far below the margin)
+        const double bound = r * r + 2.0 * q1 * fs * (1.0 + 0.6 * a * a) - cst;
+        if (!(fabs(a) <= 1.0 && bound < -1e-9)) {
+            const double phi = r * r + 2.0 * q1 * fs * cosh(a) - cst;
+            plastic = !(phi < 0.0);
+        }
     }
     if (!plastic) {
 #pragma unroll
@@ -354,20 +371,33 @@ __host__ __device__ inline void gtn_return(const DevSpec& P, double D, double dt
     const int cap = P.newton_gtn;
     int it = 0;
     for (; it < cap; ++it) {
-        const double ch = cosh(kx * x), sh = sinh(kx * x);
+        double ch, sh;
+        cosh_sinh(kx * x, ch, sh);
         const double dx = -(x * x + 2.0 * q1 * fs * ch - cst) / (2.0 * x + 3.0 * q1 * q2 * fs * ss * sh);
         x += dx;
         if (fabs(dx) <= 1e-14) break;
     }
     if (it == cap) flags |= kErrNewton;
     // matrix plastic strain increment: d = c (seq - x sigma_f(eps_M + d))
-    const double shx = sinh(kx * x);
+    double chx, shx;
+    cosh_sinh(kx * x, chx, shx);
     const double c = (x + 1.5 * q1 * q2 * f * ss * shx) / (3.0 * P.G * (1.0 - D) * (1.0 - f));
     double dem = c * (seq - x * sM0);
     for (it = 0; it < cap; ++it) {
         const double e1 = epsM + dem;
-        const double hard = hardening_slope<kFlow>(P, e1) * rf;
-        const double sf = hardening<kFlow>(P, e1) * rf;
+        double h1, hp1;   // the hardening factor and its slope, one transcendental
+        if constexpr (kFlow) {
+            hardening_and_slope(P, e1, h1, hp1);
+        } else if (e1 > 0.0) {
+            const double b = P.B * pow_el(e1, P.n);
+            h1 = P.A + b;
+            hp1 = P.n * b * rcp_nr(e1);
+        } else {
+            h1 = P.A;
+            hp1 = 0.0;
+        }
+        const double hard = hp1 * rf;
+        const double sf = h1 * rf;
         const double g = dem - c * (seq - x * sf);
         double nx = dem - g / (1.0 + c * x * hard);
         if (nx < 0.0) nx = 0.5 * dem;
