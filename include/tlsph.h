@@ -334,6 +334,61 @@ tlsph_status tlsph_set_launch_shape(tlsph_ctx *ctx, const int32_t shape[5], hipS
  * graphs.  Errors: INVALID_ARG (every < 1, skin < 0 or not finite). */
 tlsph_status tlsph_set_contact(tlsph_ctx *ctx, int32_t every, double skin);
 
+/* Run control of a batch: each specimen stops on its own, at a step cap or
+ * once failed, while the others go on; a stopped specimen keeps its state
+ * (later steps leave it alone; the LDS-staged passes launch over the list of
+ * tiles that still hold a running specimen's particle, so stopped specimens
+ * cost next to nothing).  Failure is read off the specimen's load, as the
+ * tensile tests of Sec. 6 read the strain at failure off the decay of the
+ * stress once damage sets in: the load is the reaction of one boundary group,
+ * sign * (sum over the group's particles of one component of the nodal force
+ * of Sec. 3.1 at t^n, as the force pass computes it before the prescribed
+ * velocity replaces the kick), summed in a fixed order; the specimen has
+ * failed after the first step whose reaction is below drop * (its running
+ * peak), once that peak is positive and at least min_peak.  A step's stop
+ * decision comes after the step, so a stopped specimen has taken exactly the
+ * steps counted for it. */
+typedef struct {
+    int64_t step_cap;   /* stop after this many steps from the call (0: no cap) */
+    int32_t group;      /* watched boundary group, -1: none (the cap alone) */
+    int32_t axis;       /* force component 0, 1 or 2 */
+    double sign;        /* +1 or -1 */
+    double drop;        /* in (0, 1) */
+    double min_peak;    /* >= 0 (newtons) */
+} tlsph_stop_rule;
+
+/* Set run control (rules: host tlsph_stop_rule[n_spec], read before the call
+ * returns) or switch it off (rules = NULL: every specimen steps again, from
+ * the state it kept).  Setting resets every specimen's step count, peak and
+ * stop reason.  Steps with run control add two small kernels each (the
+ * reaction and stop test, one block per specimen, and the tile list, one
+ * block that returns at once unless a specimen stopped); graphs capture them
+ * too.  Autotuning times the passes over every specimen and keeps the
+ * control.  Building the neighbour list switches it off.  Synchronises the
+ * stream.  Errors: BAD_STATE (before build), INVALID_ARG (a rule out of
+ * range: step_cap < 0, group outside [-1, n_bc), axis, sign not +-1, drop
+ * outside (0, 1), min_peak < 0 or not finite), HIP. */
+tlsph_status tlsph_set_run_control(tlsph_ctx *ctx, const tlsph_stop_rule *rules,
+                                   hipStream_t stream);
+
+/* Run-control status after the work queued on the stream (synchronises it).
+ * Host outputs, each may be NULL: why[n_spec] (0 running, 1 stopped at its
+ * cap, 2 failed), steps[n_spec] (steps taken since the control was set),
+ * peak[n_spec] (running peak of the reaction; 0 without a watched group),
+ * n_running (specimens still running).  Errors: BAD_STATE (no run control),
+ * HIP. */
+tlsph_status tlsph_get_run_status(tlsph_ctx *ctx, int32_t *why, int64_t *steps, double *peak,
+                                  int32_t *n_running, hipStream_t stream);
+
+/* Step until every specimen has stopped or max_steps steps have run, reading
+ * the running count every check_every steps (one synchronisation each; the
+ * steps in between go as tlsph_step, graphs included).  steps_run (host, may
+ * be NULL) receives the steps launched, a multiple of check_every unless
+ * max_steps cut the last chunk.  Errors: BAD_STATE (no run control),
+ * INVALID_ARG (max_steps < 0, check_every < 1), HIP. */
+tlsph_status tlsph_run(tlsph_ctx *ctx, int64_t max_steps, int32_t check_every,
+                       int64_t *steps_run, hipStream_t stream);
+
 /* Free the host-side context (not the workspace).  Null is accepted. */
 void tlsph_destroy(tlsph_ctx *ctx);
 

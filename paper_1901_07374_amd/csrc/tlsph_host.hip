@@ -9,6 +9,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -39,7 +40,8 @@ struct Layout {
     int64_t n_tiles;
     size_t GQ, GH, U0, U1, VW, sig, eps_p, eps_rate, d_init, w_p, f_void, e, D, force, fvisc, hs, err,
         arad, ccnt, ccol, ubuild, cbox,
-        spec_off, bbox, keys, vals, bc_list, bc_ptr, diag_seg, diag_part, backup;
+        spec_off, bbox, keys, vals, bc_list, bc_ptr, diag_seg, diag_part, backup,
+        run, done, tile_list, run_count;
     int64_t diag_chunk_cap;
     size_t state_begin, backup_bytes;
     size_t total;
@@ -119,6 +121,12 @@ Layout make_layout(int64_t n, int32_t n_spec, int32_t n_bc, int32_t k_cap, bool 
     L.diag_seg = take(((size_t)n_spec + n_bc + 1) * 8);
     L.diag_part = take((size_t)L.diag_chunk_cap * kNDiag * 8);
     L.backup = take(L.backup_bytes + (size_t)n_spec * 8);
+    // run control: per-specimen records and stop reasons, the tile list (room
+    // for the smallest tile size) and its counters
+    L.run = take((size_t)n_spec * sizeof(RunSpec));
+    L.done = take((size_t)n_spec * 4);
+    L.tile_list = take((size_t)L.n_tiles * 4);
+    L.run_count = take(4 * 4);
     L.total = align_up(cur);
     return L;
 }
@@ -136,6 +144,8 @@ struct tlsph_ctx {
     std::vector<int64_t> diag_seg_host;   // diagnostics segment table (source of an async copy)
     std::vector<DevSpec> specs;
     std::vector<DevBC> bcs;
+    std::vector<RunSpec> run_host;     // staging of the run-control records
+    std::vector<int32_t> done_host;
     int32_t n_bc_cap = 0;
     bool built = false;
     int parity = 0;
@@ -160,6 +170,8 @@ struct tlsph_ctx {
     hipGraphExec_t gexec = nullptr;
     int graph_parity = -1;
     int graph_block_a = 0, graph_block_b = 0, graph_sub_b = 0, graph_tile = 0;
+    bool graph_run = false;
+    bool run_ctl = false;       // run control set (its pointers in st while stepping)
 };
 
 namespace {
@@ -269,6 +281,20 @@ tlsph_status contact_rebuild(tlsph_ctx* c, hipStream_t stream) {
     return TLSPH_OK;
 }
 
+// Run control's pointers in the kernels' state (on while it is set), and a
+// fresh tile list for the current tile size.
+tlsph_status run_pointers(tlsph_ctx* c, bool on, hipStream_t stream) {
+    const Layout& L = c->L;
+    c->st.done = on ? at<int32_t>(c, L.done) : nullptr;
+    c->st.tile_list = on ? at<int32_t>(c, L.tile_list) : nullptr;
+    c->st.run_count = on ? at<int32_t>(c, L.run_count) : nullptr;
+    if (on) {
+        hipError_t e = launch_tile_list(c->st, 1, stream);
+        if (e != hipSuccess) return hip_fail(c, e, "tile list");
+    }
+    return TLSPH_OK;
+}
+
 tlsph_status run_steps_eager(tlsph_ctx* c, int32_t n_steps, hipStream_t stream) {
     const bool mixed = c->L.mixed;
     for (int32_t k = 0; k < n_steps; ++k) {
@@ -295,6 +321,13 @@ tlsph_status run_steps_eager(tlsph_ctx* c, int32_t n_steps, hipStream_t stream) 
             if (e != hipSuccess) return hip_fail(c, e, pass == 0 ? "force pass" : "deformation pass");
             if (timed) HIPCHK(c, hipEventRecord(e1, stream));
         }
+        if (c->st.done) {
+            hipError_t e = launch_run_control(c->st, c->parity, at<RunSpec>(c, c->L.run),
+                                              at<int32_t>(c, c->L.bc_list),
+                                              at<int64_t>(c, c->L.bc_ptr), stream);
+            if (e == hipSuccess) e = launch_tile_list(c->st, 0, stream);
+            if (e != hipSuccess) return hip_fail(c, e, "run control");
+        }
         c->parity ^= 1;
     }
     return TLSPH_OK;
@@ -303,7 +336,8 @@ tlsph_status run_steps_eager(tlsph_ctx* c, int32_t n_steps, hipStream_t stream) 
 tlsph_status ensure_graph(tlsph_ctx* c, hipStream_t stream) {
     if (c->gexec && c->graph_parity == c->parity && c->graph_block_a == c->block_a &&
         c->graph_block_b == (c->st.staged ? -c->block_b : c->block_b) &&
-        c->graph_sub_b == c->sub_b && c->graph_tile == c->st.tile)
+        c->graph_sub_b == c->sub_b && c->graph_tile == c->st.tile &&
+        c->graph_run == (c->st.done != nullptr))
         return TLSPH_OK;
     if (c->gexec) {
         (void)hipGraphExecDestroy(c->gexec);
@@ -328,13 +362,14 @@ tlsph_status ensure_graph(tlsph_ctx* c, hipStream_t stream) {
     c->graph_block_b = c->st.staged ? -c->block_b : c->block_b;
     c->graph_sub_b = c->sub_b;
     c->graph_tile = c->st.tile;
+    c->graph_run = c->st.done != nullptr;
     return TLSPH_OK;
 }
 
 // Per-tile halo lists and local neighbour slots for tiles of T particles,
 // and the LDS image size they need; the staged force pass is usable when the
 // largest tile plus its halo fits one workgroup's LDS.  Synchronises.
-tlsph_status set_tile(tlsph_ctx* c, int T, hipStream_t stream) {
+tlsph_status set_tile_lists(tlsph_ctx* c, int T, hipStream_t stream) {
     const Layout& L = c->L;
     c->staged_ok = false;
     c->st.staged = 0;
@@ -366,6 +401,13 @@ tlsph_status set_tile(tlsph_ctx* c, int T, hipStream_t stream) {
         c->st.staged_lds_a = (size_t)(T + largest) * staged_a_record_bytes(var_h) <= 65536 ? 1 : 0;
     }
     return TLSPH_OK;
+}
+
+// The same, and under run control the list of running tiles at that size.
+tlsph_status set_tile(tlsph_ctx* c, int T, hipStream_t stream) {
+    tlsph_status ts = set_tile_lists(c, T, stream);
+    if (ts == TLSPH_OK && c->st.done) ts = run_pointers(c, true, stream);
+    return ts;
 }
 
 int field_comps(int f, int32_t n_spec) {
@@ -525,6 +567,7 @@ tlsph_status tlsph_create(int64_t n, int32_t n_spec, const int64_t* spec_offsets
         if (spec[q].flow != TLSPH_FLOW_JC || spec[q].implicit_return != 0 || c->st.av)
             c->st.flow_general = 1;
     }
+
     const Layout& L = c->L;
     hipError_t e = hipMemcpyAsync(c->ws + L.specs, c->specs.data(), n_spec * sizeof(DevSpec),
                                   hipMemcpyHostToDevice, stream);
@@ -548,6 +591,8 @@ tlsph_status tlsph_build_neighbors(tlsph_ctx* c, const double* X, const double* 
     const Layout& L = c->L;
     c->built = false;
     c->parity = 0;
+    c->run_ctl = false;
+    c->st.done = c->st.tile_list = c->st.run_count = nullptr;
     if (c->gexec) {
         (void)hipGraphExecDestroy(c->gexec);
         c->gexec = nullptr;
@@ -731,6 +776,96 @@ tlsph_status tlsph_set_contact(tlsph_ctx* c, int32_t every, double skin) {
     return TLSPH_OK;
 }
 
+tlsph_status tlsph_set_run_control(tlsph_ctx* c, const tlsph_stop_rule* rules,
+                                   hipStream_t stream) {
+    if (!c) return TLSPH_E_INVALID_ARG;
+    if (!c->built) return fail(c, TLSPH_E_BAD_STATE, "run control before build");
+    const Layout& L = c->L;
+    if (!rules) {
+        c->run_ctl = false;
+        tlsph_status r = run_pointers(c, false, stream);
+        if (r != TLSPH_OK) return r;
+        HIPCHK(c, hipStreamSynchronize(stream));
+        return TLSPH_OK;
+    }
+    for (int32_t q = 0; q < L.n_spec; ++q) {
+        const tlsph_stop_rule& r = rules[q];
+        if (r.step_cap < 0 || r.group < -1 || r.group >= c->n_bc_cap || r.axis < 0 ||
+            r.axis > 2 || !(r.sign == 1.0 || r.sign == -1.0) || !(r.drop > 0.0 && r.drop < 1.0) ||
+            !(r.min_peak >= 0.0 && r.min_peak <= 1e300))
+            return fail(c, TLSPH_E_INVALID_ARG, "stop rule of specimen " + std::to_string(q));
+    }
+    c->run_host.assign(L.n_spec, RunSpec{});
+    c->done_host.assign(L.n_spec, kRunning);
+    for (int32_t q = 0; q < L.n_spec; ++q) {
+        RunSpec& d = c->run_host[q];
+        d.cap = rules[q].step_cap;
+        d.steps = 0;
+        d.sign = rules[q].sign;
+        d.drop = rules[q].drop;
+        d.min_peak = rules[q].min_peak;
+        d.peak = 0.0;
+        d.last = 0.0;
+        d.group = rules[q].group;
+        d.axis = rules[q].axis;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->ws + L.run, c->run_host.data(), L.n_spec * sizeof(RunSpec),
+                             hipMemcpyHostToDevice, stream));
+    HIPCHK(c, hipMemcpyAsync(c->ws + L.done, c->done_host.data(), L.n_spec * 4,
+                             hipMemcpyHostToDevice, stream));
+    c->run_ctl = true;
+    tlsph_status r = run_pointers(c, true, stream);
+    if (r != TLSPH_OK) return r;
+    HIPCHK(c, hipStreamSynchronize(stream));
+    return TLSPH_OK;
+}
+
+tlsph_status tlsph_get_run_status(tlsph_ctx* c, int32_t* why, int64_t* steps, double* peak,
+                                  int32_t* n_running, hipStream_t stream) {
+    if (!c) return TLSPH_E_INVALID_ARG;
+    if (!c->run_ctl) return fail(c, TLSPH_E_BAD_STATE, "no run control set");
+    const Layout& L = c->L;
+    int32_t cnt[4] = {0, 0, 0, 0};
+    HIPCHK(c, hipMemcpyAsync(c->run_host.data(), c->ws + L.run, L.n_spec * sizeof(RunSpec),
+                             hipMemcpyDeviceToHost, stream));
+    HIPCHK(c, hipMemcpyAsync(c->done_host.data(), c->ws + L.done, L.n_spec * 4,
+                             hipMemcpyDeviceToHost, stream));
+    HIPCHK(c, hipMemcpyAsync(cnt, c->ws + L.run_count, sizeof cnt, hipMemcpyDeviceToHost, stream));
+    HIPCHK(c, hipStreamSynchronize(stream));
+    for (int32_t q = 0; q < L.n_spec; ++q) {
+        if (why) why[q] = c->done_host[q];
+        if (steps) steps[q] = c->run_host[q].steps;
+        if (peak) peak[q] = c->run_host[q].peak;
+    }
+    if (n_running) *n_running = cnt[2];
+    return TLSPH_OK;
+}
+
+tlsph_status tlsph_run(tlsph_ctx* c, int64_t max_steps, int32_t check_every, int64_t* steps_run,
+                       hipStream_t stream) {
+    if (!c) return TLSPH_E_INVALID_ARG;
+    if (steps_run) *steps_run = 0;
+    if (!c->run_ctl) return fail(c, TLSPH_E_BAD_STATE, "no run control set");
+    if (max_steps < 0 || check_every < 1)
+        return fail(c, TLSPH_E_INVALID_ARG, "max_steps >= 0 and check_every >= 1");
+    int64_t done = 0;
+    int32_t running = 0;
+    HIPCHK(c, hipMemcpyAsync(&running, c->ws + c->L.run_count + 8, 4, hipMemcpyDeviceToHost,
+                             stream));
+    HIPCHK(c, hipStreamSynchronize(stream));
+    while (done < max_steps && running > 0) {
+        const int32_t k = (int32_t)std::min<int64_t>(check_every, max_steps - done);
+        tlsph_status r = tlsph_step(c, k, stream);
+        if (r != TLSPH_OK) return r;
+        done += k;
+        if (steps_run) *steps_run = done;
+        HIPCHK(c, hipMemcpyAsync(&running, c->ws + c->L.run_count + 8, 4, hipMemcpyDeviceToHost,
+                                 stream));
+        HIPCHK(c, hipStreamSynchronize(stream));
+    }
+    return TLSPH_OK;
+}
+
 tlsph_status tlsph_neighbor_count(const tlsph_ctx* c, int64_t* nnz) {
     if (!c || !nnz) return TLSPH_E_INVALID_ARG;
     if (!c->built) return TLSPH_E_BAD_STATE;
@@ -817,8 +952,7 @@ tlsph_status tlsph_kernel_times(tlsph_ctx* c, double ms[2], int64_t launches[2])
     return TLSPH_OK;
 }
 
-tlsph_status tlsph_autotune(tlsph_ctx* c, hipStream_t stream) {
-    if (!c) return TLSPH_E_INVALID_ARG;
+static tlsph_status autotune_all(tlsph_ctx* c, hipStream_t stream) {
     if (!c->built) return fail(c, TLSPH_E_BAD_STATE, "autotune before build");
     const Layout& L = c->L;
     uint8_t* state = c->ws + L.state_begin;
@@ -960,6 +1094,23 @@ tlsph_status tlsph_autotune(tlsph_ctx* c, hipStream_t stream) {
     HIPCHK(c, hipStreamSynchronize(stream));
     c->contact_age = 1 << 30;
     return TLSPH_OK;
+}
+
+tlsph_status tlsph_autotune(tlsph_ctx* c, hipStream_t stream) {
+    if (!c) return TLSPH_E_INVALID_ARG;
+    // the candidates are timed over every specimen, with run control
+    // suspended (the state is restored afterwards)
+    const bool rc = c->st.done != nullptr;
+    if (rc) {
+        tlsph_status r = run_pointers(c, false, stream);
+        if (r != TLSPH_OK) return r;
+    }
+    tlsph_status s = autotune_all(c, stream);
+    if (rc) {
+        tlsph_status r = run_pointers(c, true, stream);
+        if (s == TLSPH_OK) s = r;
+    }
+    return s;
 }
 
 tlsph_status tlsph_info(tlsph_ctx* c, int64_t out[9], hipStream_t stream) {

@@ -52,6 +52,26 @@ struct DevSpec {
     int64_t first, last;   // sorted-order particle range [first, last)
 };
 
+// Run control of a batch whose specimens stop on their own, per specimen:
+// at a step cap, or once failed.  Failure is read off the specimen's load, as
+// the tensile tests of Sec. 6 read the strain at failure off the decay of the
+// stress after damage sets in: the load is the reaction of one boundary group
+// (the sign-adjusted sum of one component of its particles' nodal forces),
+// and the specimen has failed once it has fallen below `drop` times its
+// running peak, after that peak reached `min_peak`.
+struct RunSpec {
+    int64_t cap;        // steps after which the specimen stops (0: no cap)
+    int64_t steps;      // steps taken since the control was set
+    double sign;        // reaction = sign * sum of the group's force component
+    double drop;
+    double min_peak;
+    double peak;        // running peak of the reaction
+    double last;        // reaction of the last step
+    int32_t group;      // watched boundary group (-1: none)
+    int32_t axis;       // its force component
+};
+enum : int32_t { kRunning = 0, kStopCap = 1, kStopFailed = 2 };
+
 struct DevBC {
     int32_t mask;
     int32_t pad_;
@@ -146,6 +166,13 @@ struct DevState {
     int32_t contact;          // 1 if a specimen has penalty contact
     int32_t tile;             // particles per tile of the staged force pass (<= kTile)
     int32_t staged_lds_a;     // 1 when the tile records of the deformation pass fit LDS
+    // run control (all null when off): why each specimen stopped (kRunning
+    // while it runs), the tiles of `tile` particles holding a running
+    // specimen's particle (ascending), and [0] their count, [1] nonzero once
+    // a specimen stopped after the list was made, [2] running specimens
+    int32_t* done;
+    int32_t* tile_list;
+    int32_t* run_count;
 };
 
 enum : uint32_t { kFlagStoreForce = 1u, kFlagGraphs = 2u, kFlagCheckFinite = 4u,
@@ -203,6 +230,12 @@ hipError_t launch_diagnostics(const DevState& s, int parity, const int32_t* bc_l
 // scratch; cbox: 8 doubles).
 hipError_t launch_contact_build(const DevState& s, int parity, uint64_t* keys, int32_t* vals,
                                 int64_t n_pow2, double* cbox, hipStream_t st);
+// Run control after a step of parity `parity`: count it, watch each running
+// specimen's reaction, stop specimens (their displacement into both buffers),
+// then remake the tile list if a specimen stopped (or always with `force`).
+hipError_t launch_run_control(const DevState& s, int parity, RunSpec* run, const int32_t* bc_list,
+                              const int64_t* bc_ptr, hipStream_t st);
+hipError_t launch_tile_list(const DevState& s, int force, hipStream_t st);
 hipError_t launch_bc_lists(const DevState& s, uint64_t* keys, int32_t* vals, int64_t n_pow2,
                            int32_t* bc_list, int64_t* bc_ptr, hipStream_t st);
 

@@ -589,6 +589,25 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nblk) {
     return x * q + (x < r ? x : r) + k;
 }
 
+// Tile of a staged pass's workgroup.  Under run control the grid still spans
+// every tile, and the first workgroups take the listed tiles of running
+// specimens (with the same XCD-contiguous mapping over the list); the others
+// get -1 and return at once.
+__device__ __forceinline__ int64_t work_tile(const DevState& s) {
+    if (s.tile_list) {
+        const int64_t nw = s.run_count[0];
+        if ((int64_t)blockIdx.x >= nw) return -1;
+        const int64_t t = s.tile_list[xcd_tile(blockIdx.x, nw)];
+        return t < (int64_t)gridDim.x ? t : -1;   // (a list of this tile size has none beyond)
+    }
+    return xcd_tile(blockIdx.x, gridDim.x);
+}
+
+// A specimen that run control has stopped keeps its state.
+__device__ __forceinline__ bool frozen(const DevState& s, int sp) {
+    return s.done != nullptr && s.done[sp] != kRunning;
+}
+
 template <typename R>
 __device__ __forceinline__ GQRec<R>* gq_of(const DevState& s);
 template <>
@@ -983,7 +1002,8 @@ k_pass_b(DevState s, int par) {
     LRecB<R> ni = make_recb<R>(XV[ii], GQ[ii], GH[ii], Uc[ii]);
     if constexpr (kVarH) ni.hs = s.hs[ii];
     const R inv_h = R(P.inv_h);
-    const int cnt = in ? s.nnb[i] : 0;
+    const bool live = in && !frozen(s, sp);
+    const int cnt = live ? s.nnb[i] : 0;
     const FinishIn fin = finish_in<kVarH>(s, ii, P);
     const int32_t* __restrict__ cp = s.col + s.slice_ptr[ii / kSlice] + (ii % kSlice);
     const auto idx = [&](int k) { return (int)cp[(int64_t)k * kSlice]; };
@@ -998,7 +1018,7 @@ k_pass_b(DevState s, int par) {
     // the particle's own Q is needed only now: reread it (the compiler barrier
     // keeps the load here) rather than keep it in registers through the loop
     asm volatile("" ::: "memory");
-    if (in && sub == 0)
+    if (live && sub == 0)
         force_finish<R>(s, i, par, P, sp, make_recb<R>(XV[i], GQ[i], GH[i], Uc[i]), A, fin);
 }
 
@@ -1134,7 +1154,8 @@ __attribute__((amdgpu_waves_per_eu(staged_waves_min<R, S, kVarH>(), 8))) k_pass_
     double* __restrict__ Lhs = reinterpret_cast<double*>(L + (size_t)M * LdsB<R>::kUnits);
     const int T = s.tile;
     const int B = T * S;
-    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t tile = work_tile(s);
+    if (tile < 0) return;
     const int64_t start = tile * T;
     const int tot = T + s.halo_cnt[tile];
     const int32_t* __restrict__ hl = s.halo + tile * (int64_t)s.halo_cap;
@@ -1203,7 +1224,7 @@ __attribute__((amdgpu_waves_per_eu(staged_waves_min<R, S, kVarH>(), 8))) k_pass_
     // barrier above, so a compiler barrier suffices: waves go on to their
     // finish as their own sums end)
     asm volatile("" ::: "memory");
-    if (in && sub == 0)
+    if (in && sub == 0 && !frozen(s, sp))
         force_finish<R>(s, i, par, P, sp, LdsB<R>::get(L, M, pl), A,
                         kEarly ? fin_early : finish_in<kVarH>(s, i, P));
 }
@@ -1446,6 +1467,7 @@ k_pass_a(DevState s, int /* displacement buffer: unused here */) {
     const int64_t i = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= s.n) return;
     const int sp_lane = s.spec[i];
+    if (frozen(s, sp_lane)) return;
     for (;;) {
         const int sp = __builtin_amdgcn_readfirstlane(sp_lane);
         if (sp == sp_lane) {
@@ -1486,7 +1508,8 @@ k_pass_a_staged(DevState s, int /* displacement buffer: unused here */) {
     double* __restrict__ Lvz = reinterpret_cast<double*>(Lvxy + M);
     double* __restrict__ Lhs = Lvz + M;
     const int T = s.tile;
-    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t tile = work_tile(s);
+    if (tile < 0) return;
     const int64_t start = tile * T;
     const int tot = T + s.halo_cnt[tile];
     const int32_t* __restrict__ hl = s.halo + tile * (int64_t)s.halo_cap;
@@ -1535,7 +1558,7 @@ k_pass_a_staged(DevState s, int /* displacement buffer: unused here */) {
         for (int u = 0; u < kU; ++u) g[u] = slot_particle(m0 + u * T, T, tot, start, s.n, hl);
     }
     __syncthreads();
-    if ((int)threadIdx.x >= T || !in) return;
+    if ((int)threadIdx.x >= T || !in || frozen(s, sp_lane)) return;
     for (;;) {
         const int sp = __builtin_amdgcn_readfirstlane(sp_lane);
         if (sp == sp_lane) {
@@ -2028,6 +2051,119 @@ hipError_t launch_bc_lists(const DevState& s, uint64_t* keys, int32_t* vals, int
             k_bitonic<<<g, T, 0, st>>>(keys, vals, n_pow2, j, k);
     const int64_t m = (s.n > s.n_bc + 1) ? s.n : s.n_bc + 1;
     k_bc_ptr<<<(unsigned)((m + T - 1) / T), T, 0, st>>>(s, keys, s.n, vals, bc_list, bc_ptr);
+    return hipGetLastError();
+}
+
+// ===========================================================================
+// run control: specimens of a batch that stop on their own
+// ===========================================================================
+
+// One block per specimen, after a step that read U[par] and wrote U[par ^ 1]:
+// count the step, sum the watched group's force component in a fixed order
+// (each thread a strided share of the group's list, then a tree), update the
+// running peak, and stop the specimen once failed or at its cap.  A specimen
+// that stops gets its new displacement copied into the other buffer too, so
+// that it stays put whichever buffer later steps read.
+__global__ void __launch_bounds__(256) k_run_control(DevState s, int par, RunSpec* __restrict__ run,
+                                                     const int32_t* __restrict__ bc_list,
+                                                     const int64_t* __restrict__ bc_ptr) {
+    __shared__ double red[256];
+    __shared__ int32_t why_s;
+    const int sp = blockIdx.x;
+    if (s.done[sp] != kRunning) return;
+    RunSpec& C = run[sp];
+    const int g = C.group;
+    double acc = 0.0;
+    if (g >= 0) {
+        const double* __restrict__ f = s.force + (int64_t)C.axis * s.np;
+        for (int64_t k = bc_ptr[g] + threadIdx.x; k < bc_ptr[g + 1]; k += blockDim.x)
+            acc += f[bc_list[k]];
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int64_t steps = C.steps + 1;
+        C.steps = steps;
+        int32_t why = kRunning;
+        if (g >= 0) {
+            const double r = C.sign * red[0];
+            C.last = r;
+            if (r > C.peak) C.peak = r;
+            if (C.peak > 0.0 && C.peak >= C.min_peak && r < C.drop * C.peak) why = kStopFailed;
+        }
+        if (why == kRunning && C.cap > 0 && steps >= C.cap) why = kStopCap;
+        why_s = why;
+        if (why != kRunning) {
+            s.done[sp] = why;
+            atomicOr(&s.run_count[1], 1);
+        }
+    }
+    __syncthreads();
+    if (why_s == kRunning) return;
+    const DevSpec& P = s.specs[sp];
+    D4* __restrict__ dst = s.U[par];
+    const D4* __restrict__ src = s.U[par ^ 1];
+    for (int64_t i = P.first + threadIdx.x; i < P.last; i += blockDim.x) dst[i] = src[i];
+}
+
+// The list of tiles (T particles each, in sorted order) that hold a running
+// specimen's particle, ascending, its length, and the number of running
+// specimens.  One block; unless `force`, it returns at once when no specimen
+// stopped since the last list.  Specimens are contiguous in sorted order, so
+// a tile holds those from its first particle's to its last's.
+__global__ void __launch_bounds__(1024) k_tile_list(DevState s, int64_t n_tiles, int T, int force) {
+    __shared__ int32_t wave_cnt[16];
+    __shared__ int32_t running;
+    int32_t* __restrict__ cnt = s.run_count;
+    if (!force && cnt[1] == 0) return;
+    if (threadIdx.x == 0) running = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int64_t base = 0;
+    for (int64_t t0 = 0; t0 < n_tiles; t0 += blockDim.x) {
+        const int64_t t = t0 + threadIdx.x;
+        bool act = false;
+        if (t < n_tiles) {
+            const int64_t a = t * T;
+            const int64_t b = (a + T < s.n ? a + T : s.n) - 1;
+            for (int sp = s.spec[a]; sp <= s.spec[b] && !act; ++sp) act = s.done[sp] == kRunning;
+        }
+        const uint64_t m = __ballot(act);
+        if (lane == 0) wave_cnt[wave] = __popcll(m);
+        __syncthreads();
+        int64_t off = base, tot = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            off += w < wave ? wave_cnt[w] : 0;
+            tot += wave_cnt[w];
+        }
+        if (act) s.tile_list[off + __popcll(m & ((1ull << lane) - 1))] = (int32_t)t;
+        base += tot;
+        __syncthreads();
+    }
+    int32_t mine = 0;
+    for (int sp = threadIdx.x; sp < s.n_spec; sp += blockDim.x) mine += s.done[sp] == kRunning;
+    if (mine) atomicAdd(&running, mine);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        cnt[0] = (int32_t)base;
+        cnt[1] = 0;
+        cnt[2] = running;
+    }
+}
+
+hipError_t launch_run_control(const DevState& s, int parity, RunSpec* run, const int32_t* bc_list,
+                              const int64_t* bc_ptr, hipStream_t st) {
+    k_run_control<<<(unsigned)s.n_spec, 256, 0, st>>>(s, parity, run, bc_list, bc_ptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_list(const DevState& s, int force, hipStream_t st) {
+    const int64_t n_tiles = (s.n + s.tile - 1) / s.tile;
+    k_tile_list<<<1, 1024, 0, st>>>(s, n_tiles, s.tile, force);
     return hipGetLastError();
 }
 

@@ -57,6 +57,14 @@ class BCGroup(C.Structure):
                 ("grad", C.c_double * 9)]
 
 
+class StopRule(C.Structure):
+    _fields_ = [("step_cap", C.c_int64), ("group", C.c_int32), ("axis", C.c_int32),
+                ("sign", C.c_double), ("drop", C.c_double), ("min_peak", C.c_double)]
+
+
+# why a specimen stopped under run control
+RUNNING, STOPPED_AT_CAP, FAILED = 0, 1, 2
+
 _vp = C.c_void_p
 _lib = None
 
@@ -92,6 +100,9 @@ def lib():
         L.tlsph_kernel_times.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.tlsph_info.argtypes = [_vp, C.POINTER(C.c_int64), _vp]
         L.tlsph_set_launch_shape.argtypes = [_vp, C.POINTER(C.c_int32), _vp]
+        L.tlsph_set_run_control.argtypes = [_vp, C.POINTER(StopRule), _vp]
+        L.tlsph_get_run_status.argtypes = [_vp, _vp, _vp, _vp, C.POINTER(C.c_int32), _vp]
+        L.tlsph_run.argtypes = [_vp, C.c_int64, C.c_int32, C.POINTER(C.c_int64), _vp]
         L.tlsph_destroy.argtypes = [_vp]
         L.tlsph_destroy.restype = None
         L.tlsph_status_string.argtypes = [C.c_int]
@@ -321,6 +332,39 @@ class Sim:
         skin / 2 between rebuilds; flagged otherwise)."""
         self._check(lib().tlsph_set_contact(self.ctx, int(every), float(skin)),
                     "tlsph_set_contact")
+
+    def set_run_control(self, rules: Optional[Sequence[Dict]]):
+        """Per-specimen stop rules (dicts with step_cap, and for failure
+        group, axis, sign, drop, min_peak), or None to switch run control
+        off."""
+        if rules is None:
+            self._check(lib().tlsph_set_run_control(self.ctx, None, self._sp()),
+                        "tlsph_set_run_control")
+            return
+        arr = (StopRule * self.n_spec)()
+        for q, r in enumerate(rules):
+            arr[q] = StopRule(int(r.get("step_cap", 0)), int(r.get("group", -1)),
+                              int(r.get("axis", 0)), float(r.get("sign", 1.0)),
+                              float(r.get("drop", 0.5)), float(r.get("min_peak", 0.0)))
+        self._check(lib().tlsph_set_run_control(self.ctx, arr, self._sp()),
+                    "tlsph_set_run_control")
+
+    def run_status(self) -> Dict[str, np.ndarray]:
+        why = np.zeros(self.n_spec, np.int32)
+        steps = np.zeros(self.n_spec, np.int64)
+        peak = np.zeros(self.n_spec, np.float64)
+        nr = C.c_int32(0)
+        self._check(lib().tlsph_get_run_status(self.ctx, why.ctypes.data, steps.ctypes.data,
+                                               peak.ctypes.data, C.byref(nr), self._sp()),
+                    "tlsph_get_run_status")
+        return {"why": why, "steps": steps, "peak": peak, "running": int(nr.value)}
+
+    def run(self, max_steps: int, check_every: int = 100) -> int:
+        """Step until every specimen has stopped (or max_steps); the steps run."""
+        done = C.c_int64(0)
+        self._check(lib().tlsph_run(self.ctx, int(max_steps), int(check_every), C.byref(done),
+                                    self._sp()), "tlsph_run")
+        return int(done.value)
 
     def set_launch_shape(self, staged: bool, lanes: int, block_force: int = 256,
                          block_deformation: int = 256, tile: int = 0):

@@ -1,0 +1,156 @@
+"""Run control of a batch: specimens stop on their own (at a step cap, or
+once their load has dropped after its peak) while the others go on.
+
+The batch of four notched bars (uneven particle counts, scattered Johnson-Cook
+parameters, each pulled at both ends) runs under run control with graphs
+until every specimen has stopped; each specimen then runs alone, in a context
+of its own (eager launches), under the same rule.  In FP64 every specimen
+must stop at the same step for the same reason, and its whole state must
+equal the batch's bit for bit: the batch adds nothing to a specimen's
+arithmetic, a stopped specimen's state is kept while the others step on, and
+the stop decision (a fixed-order sum over the watched group) is taken the
+same way in both.  A specimen stopped at its cap well before failure shows
+that stopping early keeps the state of exactly that step.
+
+The stop decision itself is checked against the diagnostics: stepping the
+lone specimen one step at a time without run control, the group's force sum
+from tlsph_get_diagnostics (another summation order) must first fall below
+drop * (running peak) at the step run control stopped at, and the peaks must
+agree to rounding."""
+import numpy as np
+import pytest
+
+from paper_1901_07374_amd import inputs as I
+from test_gpu_parity import say
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("u", "v", "H", "sig", "eps_p", "eps_p_rate", "d_init", "w_p", "D", "e", "Q", "force", "t")
+DROP = 0.5
+
+
+@pytest.fixture(scope="module")
+def tl():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1901_07374_amd import tlsph
+    return tlsph
+
+
+def batch():
+    return I.bar_batch(n_spec=4, counts=(1500, 2500, 3000, 2000))
+
+
+def rule(q, group):
+    """Stop rule of the batch's specimen q (watching `group`): specimen 1
+    stops at a cap long before failure, the others at failure (specimen 3
+    with a cap beyond it as a backstop)."""
+    return {"group": group, "axis": 2, "sign": -1.0, "drop": DROP, "min_peak": 20000.0,
+            "step_cap": {1: 5000, 3: 60000}.get(q, 0)}
+
+
+def state_of(sim, lo, hi, q):
+    out = {}
+    for k in FIELDS:
+        a = sim.get(k)
+        out[k] = a[q:q + 1] if k == "t" else a[lo:hi]
+    return out
+
+
+@pytest.fixture(scope="module")
+def batch_run(tl):
+    import torch
+    p = batch()
+    # graphs are replayed on a stream of its own (the default stream steps eagerly)
+    g = tl.Sim(p, flags=tl.USE_GRAPHS, stream=torch.cuda.Stream())
+    g.set_run_control([rule(q, 2 * q + 1) for q in range(p.n_spec)])
+    ran = g.run(100000, check_every=250)
+    st = g.run_status()
+    say("batch", p.n, "particles, steps run", ran, "stopped", st["why"], "at", st["steps"],
+        "peaks", st["peak"])
+    assert st["running"] == 0
+    return p, g, st
+
+
+def test_batch_equals_separate_runs(tl, batch_run):
+    p, g, st = batch_run
+    why = st["why"]
+    assert why[1] == tl.STOPPED_AT_CAP and st["steps"][1] == 5000
+    assert all(why[q] == tl.FAILED for q in (0, 2, 3))
+    assert st["steps"][1] < min(st["steps"][q] for q in (0, 2, 3))
+    offs = p.spec_offsets
+    for q in range(p.n_spec):
+        sub = I.subset(p, [q])
+        s1 = tl.Sim(sub)
+        s1.set_run_control([rule(q, 1)])
+        s1.run(100000, check_every=500)
+        st1 = s1.run_status()
+        say("specimen", q, sub.n, "alone: stopped", st1["why"], "at", st1["steps"])
+        assert st1["why"][0] == why[q] and st1["steps"][0] == st["steps"][q]
+        assert st1["peak"][0] == st["peak"][q]
+        a, b = state_of(g, offs[q], offs[q + 1], q), state_of(s1, 0, sub.n, 0)
+        for k in FIELDS:
+            assert np.array_equal(a[k], b[k]), (q, k)
+        del s1
+
+
+def test_stop_step_follows_the_diagnostics(tl, batch_run):
+    import torch
+    p, _, st = batch_run
+    L = tl.lib()
+    for q in (0, 2):
+        sub = I.subset(p, [q])
+        s1 = tl.Sim(sub)
+        sd = torch.empty((1, 8), dtype=torch.float64, device="cuda")
+        bd = torch.empty((2, 8), dtype=torch.float64, device="cuda")
+        stop = int(st["steps"][q])
+        # reactions after every step up to two past the stop
+        s1.step(stop - 300)
+        r = []
+        for k in range(302):
+            s1.step(1)
+            assert L.tlsph_get_diagnostics(s1.ctx, sd.data_ptr(), bd.data_ptr(), s1._sp()) == 0
+            r.append(-float(bd[1, 2].item()))
+        r = np.array(r)
+        peak = float(st["peak"][q])
+        # the peak lies before this window: the window's reactions are below it
+        assert r.max() <= peak * (1 + 1e-12)
+        below = np.nonzero(r < DROP * peak)[0]
+        first = stop - 300 + 1 + int(below[0])
+        say("specimen", q, "run control stopped at", stop, "diagnostics first below at", first,
+            "margin", f"{(r[below[0]] - DROP * peak) / peak:+.2e}")
+        assert first == stop
+        del s1
+
+
+def test_switching_off_resumes_every_specimen(tl):
+    p = batch()
+    g = tl.Sim(p)
+    g.set_run_control([{"step_cap": 20 if q == 2 else 0} for q in range(p.n_spec)])
+    g.step(50)
+    st = g.run_status()
+    assert list(st["why"]) == [0, 0, tl.STOPPED_AT_CAP, 0] and list(st["steps"]) == [50, 50, 20, 50]
+    t = g.get("t")
+    dt = np.array([m["dt"] for m in p.materials])
+    assert np.allclose(t, dt * np.array([50, 50, 20, 50]), rtol=1e-12)
+    g.set_run_control(None)
+    g.step(10)
+    assert np.allclose(g.get("t"), dt * np.array([60, 60, 30, 60]), rtol=1e-12)
+    with pytest.raises(tl.TLSPHError) as ei:
+        g.run_status()
+    assert ei.value.status == 2
+
+
+def test_run_control_errors(tl):
+    p = batch()
+    g = tl.Sim(p)
+    with pytest.raises(tl.TLSPHError) as ei:
+        g.run(10)
+    assert ei.value.status == 2
+    good = {"step_cap": 0, "group": 1, "axis": 2, "sign": -1.0, "drop": 0.5, "min_peak": 0.0}
+    for bad in ({"group": 8}, {"group": -2}, {"axis": 3}, {"sign": 2.0}, {"drop": 1.0},
+                {"drop": 0.0}, {"min_peak": -1.0}, {"step_cap": -1}):
+        with pytest.raises(tl.TLSPHError) as ei:
+            g.set_run_control([dict(good, **bad)] + [good] * (p.n_spec - 1))
+        assert ei.value.status == 1, bad
