@@ -219,6 +219,7 @@ void wire_state(tlsph_ctx* c) {
     s.halo_cnt = at<int32_t>(c, L.halo_cnt);
     s.halo_cap = 0;
     s.tile = kTile;
+    s.a_group = 1;
     s.staged = 0;
     s.lds_slots = 0;
     s.Linv = at<double>(c, L.Linv);
@@ -374,6 +375,7 @@ tlsph_status set_tile_lists(tlsph_ctx* c, int T, hipStream_t stream) {
     c->staged_ok = false;
     c->st.staged = 0;
     c->st.staged_lds_a = 0;
+    c->st.a_group = 1;
     if (c->block_a == 0) c->block_a = 256;
     c->lds_b = 0;
     if (T < 64 || T > kTile) return fail(c, TLSPH_E_INVALID_ARG, "tile size outside [64, 256]");
@@ -397,8 +399,12 @@ tlsph_status set_tile_lists(tlsph_ctx* c, int T, hipStream_t stream) {
         c->lds_b = lds;
         c->st.lds_slots = T + largest;
         // the deformation pass's records (56 bytes, 64 with graded spacing)
-        // within the default LDS limit
-        c->st.staged_lds_a = (size_t)(T + largest) * staged_a_record_bytes(var_h) <= 65536 ? 1 : 0;
+        // within the default LDS limit; two tiles per workgroup where a tile
+        // is not a whole number of waves (one thread per particle), if both
+        // images fit
+        const size_t la = (size_t)(T + largest) * staged_a_record_bytes(var_h);
+        c->st.staged_lds_a = la <= 65536 ? 1 : 0;
+        c->st.a_group = (T % 64 != 0 && 2 * T <= 256 && 2 * la <= 65536) ? 2 : 1;
     }
     return TLSPH_OK;
 }

@@ -166,6 +166,8 @@ struct DevState {
     int32_t contact;          // 1 if a specimen has penalty contact
     int32_t tile;             // particles per tile of the staged force pass (<= kTile)
     int32_t staged_lds_a;     // 1 when the tile records of the deformation pass fit LDS
+    int32_t a_group;          // tiles per workgroup of the staged deformation pass (1, 2)
+    int32_t pad3_;
     // run control (all null when off): why each specimen stopped (kRunning
     // while it runs), the tiles of `tile` particles holding a running
     // specimen's particle (ascending), and [0] their count, [1] nonzero once

@@ -589,18 +589,24 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nblk) {
     return x * q + (x < r ? x : r) + k;
 }
 
-// Tile of a staged pass's workgroup.  Under run control the grid still spans
-// every tile, and the first workgroups take the listed tiles of running
-// specimens (with the same XCD-contiguous mapping over the list); the others
-// get -1 and return at once.
-__device__ __forceinline__ int64_t work_tile(const DevState& s) {
+// Tile `part` (of G per workgroup) of a staged pass's workgroup, -1 if none.
+// Workgroups take groups of G consecutive tiles (XCD-contiguous: the groups
+// an XCD runs are one range).  Under run control the grid still spans every
+// tile, and the first workgroups take the listed tiles of running specimens,
+// G at a time with the same mapping over the list; the others get -1 and
+// return at once.
+__device__ __forceinline__ int64_t work_tile(const DevState& s, int G, int part, int64_t n_tiles) {
     if (s.tile_list) {
         const int64_t nw = s.run_count[0];
-        if ((int64_t)blockIdx.x >= nw) return -1;
-        const int64_t t = s.tile_list[xcd_tile(blockIdx.x, nw)];
-        return t < (int64_t)gridDim.x ? t : -1;   // (a list of this tile size has none beyond)
+        const int64_t ng = (nw + G - 1) / G;
+        if ((int64_t)blockIdx.x >= ng) return -1;
+        const int64_t k = xcd_tile(blockIdx.x, ng) * G + part;
+        if (k >= nw) return -1;
+        const int64_t t = s.tile_list[k];
+        return t < n_tiles ? t : -1;   // (a list of this tile size has none beyond)
     }
-    return xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t t = xcd_tile(blockIdx.x, gridDim.x) * G + part;
+    return t < n_tiles ? t : -1;
 }
 
 // A specimen that run control has stopped keeps its state.
@@ -1154,7 +1160,7 @@ __attribute__((amdgpu_waves_per_eu(staged_waves_min<R, S, kVarH>(), 8))) k_pass_
     double* __restrict__ Lhs = reinterpret_cast<double*>(L + (size_t)M * LdsB<R>::kUnits);
     const int T = s.tile;
     const int B = T * S;
-    const int64_t tile = work_tile(s);
+    const int64_t tile = work_tile(s, 1, 0, gridDim.x);
     if (tile < 0) return;
     const int64_t start = tile * T;
     const int tot = T + s.halo_cnt[tile];
@@ -1501,18 +1507,28 @@ template <typename R, int DM, bool kFlow, bool kVarH = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pass_a_waves_min<R, DM, kFlow>(), 8)))
 k_pass_a_staged(DevState s, int /* displacement buffer: unused here */) {
     extern __shared__ __align__(16) unsigned char lds_a[];
+    // G tiles per workgroup (two where a tile is not a whole number of waves),
+    // each with an image of M slots of its own; thread tx of part `part`
+    // takes particle tx of that part's tile
     const int M = s.lds_slots;
-    double2* __restrict__ Lxy = reinterpret_cast<double2*>(lds_a);
-    double2* __restrict__ Lzw = Lxy + M;
-    double2* __restrict__ Lvxy = Lzw + M;
-    double* __restrict__ Lvz = reinterpret_cast<double*>(Lvxy + M);
-    double* __restrict__ Lhs = Lvz + M;
     const int T = s.tile;
-    const int64_t tile = work_tile(s);
-    if (tile < 0) return;
-    const int64_t start = tile * T;
-    const int tot = T + s.halo_cnt[tile];
-    const int32_t* __restrict__ hl = s.halo + tile * (int64_t)s.halo_cap;
+    const int G = s.a_group;
+    const int part = G > 1 ? (int)threadIdx.x / T : 0;
+    const int tx = (int)threadIdx.x - part * T;
+    const int64_t n_tiles = (s.n + T - 1) / T;
+    if (work_tile(s, G, 0, n_tiles) < 0) return;   // (then no part has a tile)
+    const int64_t tile = work_tile(s, G, part, n_tiles);
+    const int64_t tl = tile < 0 ? 0 : tile;
+    const size_t base = (size_t)part * M;
+    const size_t GM = (size_t)G * M;
+    double2* __restrict__ Lxy = reinterpret_cast<double2*>(lds_a) + base;
+    double2* __restrict__ Lzw = reinterpret_cast<double2*>(lds_a) + GM + base;
+    double2* __restrict__ Lvxy = reinterpret_cast<double2*>(lds_a) + 2 * GM + base;
+    double* __restrict__ Lvz = reinterpret_cast<double*>(reinterpret_cast<double2*>(lds_a) + 3 * GM) + base;
+    double* __restrict__ Lhs = reinterpret_cast<double*>(reinterpret_cast<double2*>(lds_a) + 3 * GM) + GM + base;
+    const int64_t start = tl * T;
+    const int tot = tile < 0 ? 0 : T + s.halo_cnt[tl];
+    const int32_t* __restrict__ hl = s.halo + tl * (int64_t)s.halo_cap;
     const D4* __restrict__ XV = s.XV;
     const D4* __restrict__ VW = s.VW;
     // Up to four slots per thread per round: index loads, record loads, LDS
@@ -1521,12 +1537,12 @@ k_pass_a_staged(DevState s, int /* displacement buffer: unused here */) {
     // them.  Slots past the image, and past the particle count (last tile),
     // load the tile's first record and store nothing.
     constexpr int kU = 4;
-    int m0 = threadIdx.x;
+    int m0 = tx;
     int64_t g[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) g[u] = slot_particle(m0 + u * T, T, tot, start, s.n, hl);
-    const int64_t i = start + threadIdx.x;
-    const bool in = i < s.n;
+    const int64_t i = start + tx;
+    const bool in = tile >= 0 && i < s.n;
     const int64_t ii = in ? i : start;
     const int cnt = s.nnb[ii];
     const int64_t slice0 = s.slice_ptr[ii / kSlice];
@@ -1558,12 +1574,12 @@ k_pass_a_staged(DevState s, int /* displacement buffer: unused here */) {
         for (int u = 0; u < kU; ++u) g[u] = slot_particle(m0 + u * T, T, tot, start, s.n, hl);
     }
     __syncthreads();
-    if ((int)threadIdx.x >= T || !in || frozen(s, sp_lane)) return;
+    if (!in || frozen(s, sp_lane)) return;
     for (;;) {
         const int sp = __builtin_amdgcn_readfirstlane(sp_lane);
         if (sp == sp_lane) {
             const DevSpec& P = s.specs[sp];
-            const int t = threadIdx.x;
+            const int t = tx;
             const double2 a = Lxy[t], b = Lzw[t], c = Lvxy[t];
             R M9[9], AV[3];
             gather_fdot<R, kFlow, kVarH>(D4{a.x, a.y, b.x, 0.0}, D4{c.x, c.y, Lvz[t], b.y}, cnt,
@@ -1656,13 +1672,15 @@ hipError_t prepare_staged(size_t lds_bytes_b) {
 template <int DM, bool kFlow, bool kVarH = false>
 static void launch_a(const DevState& s, int parity, unsigned grid, int block, bool mixed,
                      hipStream_t st) {
-    if (block == 0) {   // staged over the force pass's tiles
-        const unsigned tiles = (unsigned)((s.n + s.tile - 1) / s.tile);
-        const size_t lds = (size_t)s.lds_slots * staged_a_record_bytes(kVarH);
+    if (block == 0) {   // staged over the force pass's tiles, a_group of them per workgroup
+        const int64_t tiles = (s.n + s.tile - 1) / s.tile;
+        const unsigned groups = (unsigned)((tiles + s.a_group - 1) / s.a_group);
+        const int threads = s.tile * s.a_group;
+        const size_t lds = (size_t)s.a_group * s.lds_slots * staged_a_record_bytes(kVarH);
         if (mixed)
-            k_pass_a_staged<float, DM, kFlow, kVarH><<<tiles, s.tile, lds, st>>>(s, parity);
+            k_pass_a_staged<float, DM, kFlow, kVarH><<<groups, threads, lds, st>>>(s, parity);
         else
-            k_pass_a_staged<double, DM, kFlow, kVarH><<<tiles, s.tile, lds, st>>>(s, parity);
+            k_pass_a_staged<double, DM, kFlow, kVarH><<<groups, threads, lds, st>>>(s, parity);
         return;
     }
     if (mixed)
@@ -1672,7 +1690,9 @@ static void launch_a(const DevState& s, int parity, unsigned grid, int block, bo
 }
 
 hipError_t launch_pass_a(const DevState& s, int parity, int block, bool mixed, hipStream_t st) {
-    if (block == 0 && (!s.staged_lds_a || s.tile > 256)) return hipErrorInvalidValue;
+    if (block == 0 && (!s.staged_lds_a || s.a_group < 1 || s.a_group > 2 ||
+                       s.tile * s.a_group > 256))
+        return hipErrorInvalidValue;
     const unsigned grid = block > 0 ? (unsigned)((s.n + block - 1) / block) : 0u;
     if (s.var_h) {   // graded spacing: the general variant with per-pair supports
         launch_a<-1, true, true>(s, parity, grid, block, mixed, st);
