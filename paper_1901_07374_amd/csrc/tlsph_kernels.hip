@@ -1407,8 +1407,8 @@ __device__ __forceinline__ void pass_a_update(const DevState& s, int64_t i, int 
 #pragma unroll
         for (int b = 0; b < 3; ++b)
             go.q[3 * a + b] = failed ? R(0)
-                                     : o.P[3 * a] * Li[3 * b] + o.P[3 * a + 1] * Li[3 * b + 1] +
-                                           o.P[3 * a + 2] * Li[3 * b + 2];
+                                     : dot3(o.P[3 * a], Li[3 * b], o.P[3 * a + 1], Li[3 * b + 1],
+                                            o.P[3 * a + 2], Li[3 * b + 2]);
 #pragma unroll
     for (int k = 0; k < 9; ++k) ho.h[k] = o.H[k];
     go.omd = R(1.0 - o.D);

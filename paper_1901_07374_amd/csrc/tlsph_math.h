@@ -47,42 +47,48 @@ __host__ __device__ __forceinline__ double pow_el(double x, double y) {
     return exp(y * log(x));
 }
 
+// The small-tensor products below spell out their fused multiply-adds (the
+// library is compiled without contraction, so every variant rounds alike):
+// ab - cd as fma(a, b, -(c d)), dot products as fma chains.
 template <typename R>
-__host__ __device__ __forceinline__ R det33(const R a[9]) {
-    return a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
-           a[2] * (a[3] * a[7] - a[4] * a[6]);
+__host__ __device__ __forceinline__ R mdiff(R a, R b, R c, R d) {
+    return fma(a, b, -(c * d));
 }
 
-// adjugate / determinant
 template <typename R>
-__host__ __device__ __forceinline__ void inv33(const R a[9], R o[9]) {
-    const R c0 = a[4] * a[8] - a[5] * a[7];
-    const R c1 = a[5] * a[6] - a[3] * a[8];
-    const R c2 = a[3] * a[7] - a[4] * a[6];
-    const R inv = rcp_nr(a[0] * c0 + a[1] * c1 + a[2] * c2);
-    o[0] = c0 * inv;
-    o[1] = (a[2] * a[7] - a[1] * a[8]) * inv;
-    o[2] = (a[1] * a[5] - a[2] * a[4]) * inv;
-    o[3] = c1 * inv;
-    o[4] = (a[0] * a[8] - a[2] * a[6]) * inv;
-    o[5] = (a[2] * a[3] - a[0] * a[5]) * inv;
-    o[6] = c2 * inv;
-    o[7] = (a[1] * a[6] - a[0] * a[7]) * inv;
-    o[8] = (a[0] * a[4] - a[1] * a[3]) * inv;
+__host__ __device__ __forceinline__ R dot3(R a0, R b0, R a1, R b1, R a2, R b2) {
+    return fma(a0, b0, fma(a1, b1, a2 * b2));
+}
+
+template <typename R>
+__host__ __device__ __forceinline__ R det33(const R a[9]) {
+    return dot3(a[0], mdiff(a[4], a[8], a[5], a[7]), a[1], mdiff(a[5], a[6], a[3], a[8]),
+                a[2], mdiff(a[3], a[7], a[4], a[6]));
 }
 
 // cofactor matrix cof(a) = det(a) a^-T (no division)
 template <typename R>
 __host__ __device__ __forceinline__ void cof33(const R a[9], R o[9]) {
-    o[0] = a[4] * a[8] - a[5] * a[7];
-    o[1] = a[5] * a[6] - a[3] * a[8];
-    o[2] = a[3] * a[7] - a[4] * a[6];
-    o[3] = a[2] * a[7] - a[1] * a[8];
-    o[4] = a[0] * a[8] - a[2] * a[6];
-    o[5] = a[1] * a[6] - a[0] * a[7];
-    o[6] = a[1] * a[5] - a[2] * a[4];
-    o[7] = a[2] * a[3] - a[0] * a[5];
-    o[8] = a[0] * a[4] - a[1] * a[3];
+    o[0] = mdiff(a[4], a[8], a[5], a[7]);
+    o[1] = mdiff(a[5], a[6], a[3], a[8]);
+    o[2] = mdiff(a[3], a[7], a[4], a[6]);
+    o[3] = mdiff(a[2], a[7], a[1], a[8]);
+    o[4] = mdiff(a[0], a[8], a[2], a[6]);
+    o[5] = mdiff(a[1], a[6], a[0], a[7]);
+    o[6] = mdiff(a[1], a[5], a[2], a[4]);
+    o[7] = mdiff(a[2], a[3], a[0], a[5]);
+    o[8] = mdiff(a[0], a[4], a[1], a[3]);
+}
+
+// adjugate / determinant
+template <typename R>
+__host__ __device__ __forceinline__ void inv33(const R a[9], R o[9]) {
+    R c[9];
+    cof33(a, c);
+    const R inv = rcp_nr(dot3(a[0], c[0], a[1], c[1], a[2], c[2]));
+    o[0] = c[0] * inv; o[1] = c[3] * inv; o[2] = c[6] * inv;
+    o[3] = c[1] * inv; o[4] = c[4] * inv; o[5] = c[7] * inv;
+    o[6] = c[2] * inv; o[7] = c[5] * inv; o[8] = c[8] * inv;
 }
 
 template <typename R>
@@ -91,7 +97,7 @@ __host__ __device__ __forceinline__ void mm33(const R a[9], const R b[9], R o[9]
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j)
-            o[3 * i + j] = a[3 * i] * b[j] + a[3 * i + 1] * b[3 + j] + a[3 * i + 2] * b[6 + j];
+            o[3 * i + j] = dot3(a[3 * i], b[j], a[3 * i + 1], b[3 + j], a[3 * i + 2], b[6 + j]);
 }
 
 // o = a b^T
@@ -101,8 +107,8 @@ __host__ __device__ __forceinline__ void mmT33(const R a[9], const R b[9], R o[9
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j)
-            o[3 * i + j] =
-                a[3 * i] * b[3 * j] + a[3 * i + 1] * b[3 * j + 1] + a[3 * i + 2] * b[3 * j + 2];
+            o[3 * i + j] = dot3(a[3 * i], b[3 * j], a[3 * i + 1], b[3 * j + 1], a[3 * i + 2],
+                                b[3 * j + 2]);
 }
 
 template <typename R>
@@ -124,8 +130,8 @@ __host__ __device__ __forceinline__ void voigt_from_sym(const R a[9], R s[6]) {
 // sqrt(3/2 s:s) of a deviator held in Voigt form
 template <typename R>
 __host__ __device__ __forceinline__ R mises_voigt(const R s[6]) {
-    return sqrt(R(1.5) * (s[0] * s[0] + s[1] * s[1] + s[2] * s[2] +
-                          R(2) * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5])));
+    return sqrt(R(1.5) * fma(R(2), dot3(s[3], s[3], s[4], s[4], s[5], s[5]),
+                             dot3(s[0], s[0], s[1], s[1], s[2], s[2])));
 }
 
 // Cubic spline with compact support h (q = r/h < 1 for every listed pair):
@@ -147,7 +153,8 @@ __host__ __device__ __forceinline__ void spline(R r, R inv_h, R wnorm, R& W, R& 
 template <typename R>
 __host__ __device__ __forceinline__ R det_ipH_m1(const R h[9]) {
     const R tr = h[0] + h[4] + h[8];
-    const R m2 = h[0] * h[4] - h[1] * h[3] + h[0] * h[8] - h[2] * h[6] + h[4] * h[8] - h[5] * h[7];
+    const R m2 = mdiff(h[0], h[4], h[1], h[3]) + mdiff(h[0], h[8], h[2], h[6]) +
+                 mdiff(h[4], h[8], h[5], h[7]);
     return tr + m2 + det33(h);
 }
 
@@ -341,9 +348,12 @@ __host__ __device__ inline void gtn_return(const DevSpec& P, double D, double dt
     const double q1 = P.q1, q2 = P.q2, q3 = P.q3;
     bool plastic = false;
     double ss = 0.0;
+    // (quotients as products with refined reciprocals, a few ulp from the
+    // divisions, as elsewhere in the update)
+    const double iseq = rcp_nr(seq), isM0 = rcp_nr(sM0);
     if (seq >= 1e-12 * sM0) {
-        ss = smt / seq;
-        const double r = seq / sM0;
+        ss = smt * iseq;
+        const double r = seq * isM0;
         const double a = 1.5 * q2 * ss * r;
         const double cst = 1.0 + q3 * fs * fs;
         // cosh a <= 1 + 0.6 a^2 for |a| <= 1: a trial state that this bound
@@ -365,7 +375,7 @@ __host__ __device__ inline void gtn_return(const DevSpec& P, double D, double dt
     }
     // yield ratio x = sigma_y / sigma_M: Newton from above on the convex,
     // increasing yield function
-    double x = seq / sM0 < 1.0 ? seq / sM0 : 1.0;
+    double x = seq * isM0 < 1.0 ? seq * isM0 : 1.0;
     const double kx = 1.5 * q2 * ss;
     const double cst = 1.0 + q3 * fs * fs;
     const int cap = P.newton_gtn;
@@ -373,7 +383,8 @@ __host__ __device__ inline void gtn_return(const DevSpec& P, double D, double dt
     for (; it < cap; ++it) {
         double ch, sh;
         cosh_sinh(kx * x, ch, sh);
-        const double dx = -(x * x + 2.0 * q1 * fs * ch - cst) / (2.0 * x + 3.0 * q1 * q2 * fs * ss * sh);
+        const double dx = -(x * x + 2.0 * q1 * fs * ch - cst) *
+                          rcp_nr(2.0 * x + 3.0 * q1 * q2 * fs * ss * sh);
         x += dx;
         if (fabs(dx) <= 1e-14) break;
     }
@@ -381,7 +392,7 @@ __host__ __device__ inline void gtn_return(const DevSpec& P, double D, double dt
     // matrix plastic strain increment: d = c (seq - x sigma_f(eps_M + d))
     double chx, shx;
     cosh_sinh(kx * x, chx, shx);
-    const double c = (x + 1.5 * q1 * q2 * f * ss * shx) / (3.0 * P.G * (1.0 - D) * (1.0 - f));
+    const double c = (x + 1.5 * q1 * q2 * f * ss * shx) * rcp_nr(3.0 * P.G * (1.0 - D) * (1.0 - f));
     double dem = c * (seq - x * sM0);
     for (it = 0; it < cap; ++it) {
         const double e1 = epsM + dem;
@@ -399,7 +410,7 @@ __host__ __device__ inline void gtn_return(const DevSpec& P, double D, double dt
         const double hard = hp1 * rf;
         const double sf = h1 * rf;
         const double g = dem - c * (seq - x * sf);
-        double nx = dem - g / (1.0 + c * x * hard);
+        double nx = dem - g * rcp_nr(1.0 + c * x * hard);
         if (nx < 0.0) nx = 0.5 * dem;
         const double stp = nx - dem;
         dem = nx;
@@ -412,27 +423,29 @@ __host__ __device__ inline void gtn_return(const DevSpec& P, double D, double dt
     epsM += dem;
     const double sM = hardening<kFlow>(P, epsM) * rf;
     const double sy = x * sM;
-    const double scale = sy / seq;
+    const double scale = sy * iseq;
 #pragma unroll
     for (int k = 0; k < 6; ++k) sd[k] = scale * sdt[k];
     // mean stress returned at constant triaxiality
     sm = smt - ss * (seq - sy);
-    const double alpha = 1.5 * (sM / sy) * q1 * q2 * f * shx;
+    const double sMy = sM * rcp_nr(sy);   // sigma_M / sigma_y
+    const double alpha = 1.5 * sMy * q1 * q2 * f * shx;
     // omega of the returned stress: 1 - (27 det(s_d) / (2 s_eq^3))^2
     const double detd = sd[0] * (sd[1] * sd[2] - sd[3] * sd[3]) -
                         sd[5] * (sd[5] * sd[2] - sd[3] * sd[4]) +
                         sd[4] * (sd[5] * sd[3] - sd[1] * sd[4]);
     double om = 0.0;
     if (sy > 0.0) {
-        const double xi = 27.0 * detd / (2.0 * sy * sy * sy);
+        const double xi = 13.5 * detd * rcp_nr(sy * sy * sy);
         om = 1.0 - xi * xi;
         om = om < 0.0 ? 0.0 : (om > 1.0 ? 1.0 : om);
     }
-    const double z = (epsM - P.eN) / P.sN;
-    const double AN = P.fN / (P.sN * 2.5066282746310002) * exp(-0.5 * z * z);
+    const double isN = rcp_nr(P.sN);
+    const double z = (epsM - P.eN) * isN;
+    const double AN = P.fN * isN * 0.3989422804014327 * exp(-0.5 * z * z);   // 1/sqrt(2 pi)
     f = f + AN * dem +
-        (1.0 - f) / (alpha * ss + 1.0) * (sM / sy) * (alpha * (1.0 - f) + f * P.k_omega * om) * dem;
-    rate = dem / dt;
+        (1.0 - f) * rcp_nr(alpha * ss + 1.0) * sMy * (alpha * (1.0 - f) + f * P.k_omega * om) * dem;
+    rate = dem * rcp_nr(dt);
 }
 
 // Result of the constitutive update of one particle.
@@ -464,7 +477,7 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
     // kFlow: the other hardening laws and the implicit return are compiled in
     const R dt = R(P.dt);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) o.H[k] = Hn[k] + dt * Fd[k];
+    for (int k = 0; k < 9; ++k) o.H[k] = fma(dt, Fd[k], Hn[k]);
     if (D >= 1.0) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) o.sig[k] = R(0);
@@ -486,7 +499,7 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
         cof33(F0, C0);
         mm33(S0, C0, P0);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) work0 += Fd[k] * P0[k];
+        for (int k = 0; k < 9; ++k) work0 = fma(Fd[k], P0[k], work0);
     }
     R Fb[9], Fbi[9], l[9];
 #pragma unroll
@@ -516,17 +529,17 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
         const R aa = a1 * a1 + a2 * a2 + a3 * a3;
         const R c = rcp_nr(R(1) + aa);
         const R d0 = (R(1) - aa) * c, t2 = R(2) * c;
-        const R Rm[9] = {d0 + t2 * a1 * a1, t2 * (a1 * a2 - a3), t2 * (a1 * a3 + a2),
-                         t2 * (a2 * a1 + a3), d0 + t2 * a2 * a2, t2 * (a2 * a3 - a1),
-                         t2 * (a3 * a1 - a2), t2 * (a3 * a2 + a1), d0 + t2 * a3 * a3};
+        const R Rm[9] = {fma(t2 * a1, a1, d0), t2 * fma(a1, a2, -a3), t2 * fma(a1, a3, a2),
+                         t2 * fma(a2, a1, a3), fma(t2 * a2, a2, d0), t2 * fma(a2, a3, -a1),
+                         t2 * fma(a3, a1, -a2), t2 * fma(a3, a2, a1), fma(t2 * a3, a3, d0)};
         // R S R^T is symmetric: its upper triangle, in Voigt order
         R T[9];
         mm33(Rm, Sd, T);
         constexpr int vi[6] = {0, 1, 2, 1, 0, 0}, vj[6] = {0, 1, 2, 2, 2, 1};
 #pragma unroll
         for (int k = 0; k < 6; ++k)
-            sdr[k] = T[3 * vi[k]] * Rm[3 * vj[k]] + T[3 * vi[k] + 1] * Rm[3 * vj[k] + 1] +
-                     T[3 * vi[k] + 2] * Rm[3 * vj[k] + 2];
+            sdr[k] = dot3(T[3 * vi[k]], Rm[3 * vj[k]], T[3 * vi[k] + 1], Rm[3 * vj[k] + 1],
+                          T[3 * vi[k] + 2], Rm[3 * vj[k] + 2]);
     }
     // deviatoric strain increment
     const R trd = (d6[0] + d6[1] + d6[2]) * third;
@@ -539,7 +552,7 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
     if (model == 3) {
         double sdt[6], sdo[6], smo;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) sdt[k] = double(sdr[k] + R(2) * G * omD * de[k]);
+        for (int k = 0; k < 6; ++k) sdt[k] = double(fma(R(2) * G * omD, de[k], sdr[k]));
         const double smt = double(mean_stress<R>(P, Jm1, R(D), R(e), false));
         gtn_return<kFlow>(P, D, P.dt, sdt, smt, eps, rate, fv, sdo, smo, flags);
 #pragma unroll
@@ -556,10 +569,10 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
         // in double.
         R st[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) st[k] = sdr[k] + R(2) * G * omD * de[k];
+        for (int k = 0; k < 6; ++k) st[k] = fma(R(2) * G * omD, de[k], sdr[k]);
         // elastic if sigma_eq < sigma_f, decided on the squares (no root)
         const double t0 = st[0], t1 = st[1], t2 = st[2], t3 = st[3], t4 = st[4], t5 = st[5];
-        const double q2 = 1.5 * (t0 * t0 + t1 * t1 + t2 * t2 + 2.0 * (t3 * t3 + t4 * t4 + t5 * t5));
+        const double q2 = 1.5 * fma(2.0, dot3(t3, t3, t4, t4, t5, t5), dot3(t0, t0, t1, t1, t2, t2));
         const bool impl = kFlow && P.implicit_return;
         const double h0 = hardening<kFlow>(P, eps);
         const double omDd = 1.0 - D;
@@ -622,7 +635,7 @@ __host__ __device__ __forceinline__ void point_update(const DevSpec& P, const R 
     // the P^{n+1} half of the energy update
     R work1 = R(0);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) work1 += Fd[k] * o.P[k];
+    for (int k = 0; k < 9; ++k) work1 = fma(Fd[k], o.P[k], work1);
     e += double(P.dt) * double(R(0.5) * (work0 + work1)) * P.inv_rho0;
 }
 
