@@ -79,7 +79,7 @@ def kernel_symbol(kernel: str, info: dict, mixed: bool, model: int, flow_general
     if kernel == "force_pass":
         name = "k_pass_b_staged" if info["staged"] else "k_pass_b"
         return f"{name}<{r}, {info['lanes_per_particle']}, {vh}>"
-    name = "k_pass_a_staged" if info["block_deformation"] == 0 else "k_pass_a"
+    name = "k_pass_a_staged" if info["block_deformation"] <= 0 else "k_pass_a"
     if var_h:
         model, flow_general = -1, True
     return f"{name}<{r}, {model}, {'true' if flow_general else 'false'}, {vh}>"
@@ -269,7 +269,9 @@ def shape_of(info):
             "tile": info["tile"],
             "force_pass_block": info["block_force"],
             "force_lanes_per_particle": info["lanes_per_particle"],
-            "deformation_pass_block": info["block_deformation"]}
+            "deformation_pass_block": max(info["block_deformation"], 0),
+            "deformation_pass_tile": (-info["block_deformation"] if info["block_deformation"] < 0
+                                      else info["tile"] if info["block_deformation"] == 0 else 0)}
 
 
 # --------------------------------------------------------------------------

@@ -301,7 +301,8 @@ tlsph_status tlsph_kernel_times(tlsph_ctx *ctx, double ms[2], int64_t launches[2
 
 /* Launch shape and layout facts: [0] threads per block of the force pass
  * (negative when the LDS-staged variant is in use), [1] of the deformation
- * pass, [2] neighbour pairs, [3] padded slots of the sliced neighbour layout,
+ * pass (0: staged over the force pass's tiles; -T: staged over tiles of T
+ * particles of its own), [2] neighbour pairs, [3] padded slots of the sliced neighbour layout,
  * [4] particles, [5] sticky device error flags (bit 0 non-finite, bit 1 GTN
  * Newton not converged, bit 2 a contact list missed a pair: a particle had
  * more than 32 contact candidates, left the list's skin, or the contact grid
@@ -315,10 +316,14 @@ tlsph_status tlsph_info(tlsph_ctx *ctx, int64_t out[9], hipStream_t stream);
  * gathers from global memory; [1] lanes per particle of the force pass (1,
  * 2 or 4); [2] threads per block of the unstaged force pass (64, 128, 192 or
  * 256; ignored when staged, which runs tile * lanes threads per block);
- * [3] threads per block of the deformation pass (64 to 256, multiple of 64);
- * [4] particles per tile of the staged pass (64 to 256; 0 = the size chosen
- * at build, which fills whole rounds of compute units).  A new tile size
- * rebuilds the per-tile halo lists on the stream and synchronises.  Every
+ * [3] threads per block of the deformation pass (64 to 256, multiple of 64),
+ * or 0 = LDS-staged over the force pass's tiles, or -T = LDS-staged over
+ * tiles of T particles of its own (64 to 256; their halo lists are built
+ * into arrays of their own); [4] particles per tile of the staged force pass
+ * (64 to 256; 0 = the size chosen at build, which fills whole rounds of
+ * compute units).  A new tile size rebuilds the per-tile halo lists on the
+ * stream and synchronises.  The staged deformation pass runs two tiles per
+ * workgroup where a tile is not a multiple of 64 particles.  Every
  * shape gives bitwise identical results: the neighbour sums keep one
  * canonical order.  Errors: INVALID_ARG, BAD_STATE (before build),
  * UNSUPPORTED (staged requested where a tile and its halo do not fit in

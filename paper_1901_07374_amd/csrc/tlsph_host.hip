@@ -41,7 +41,7 @@ struct Layout {
     size_t GQ, GH, U0, U1, VW, sig, eps_p, eps_rate, d_init, w_p, f_void, e, D, force, fvisc, hs, err,
         arad, ccnt, ccol, ubuild, cbox,
         spec_off, bbox, keys, vals, bc_list, bc_ptr, diag_seg, diag_part, backup,
-        run, done, tile_list, run_count;
+        run, done, tile_list, run_count, halo_a, halo_cnt_a, lcol_a, tile_list_a;
     int64_t diag_chunk_cap;
     size_t state_begin, backup_bytes;
     size_t total;
@@ -127,6 +127,12 @@ Layout make_layout(int64_t n, int32_t n_spec, int32_t n_bc, int32_t k_cap, bool 
     L.done = take((size_t)n_spec * 4);
     L.tile_list = take((size_t)L.n_tiles * 4);
     L.run_count = take(4 * 4);
+    // the deformation pass's own tiles (when their size differs from the
+    // force pass's): halo lists, local slots, run-control list
+    L.halo_a = take(((size_t)n + kTile) * k_cap * 4);
+    L.halo_cnt_a = take((size_t)L.n_tiles * 4);
+    L.lcol_a = take((size_t)k_cap * np * 2);
+    L.tile_list_a = take((size_t)L.n_tiles * 4);
     L.total = align_up(cur);
     return L;
 }
@@ -171,6 +177,9 @@ struct tlsph_ctx {
     int graph_parity = -1;
     int graph_block_a = 0, graph_block_b = 0, graph_sub_b = 0, graph_tile = 0;
     bool graph_run = false;
+    int graph_tile_a = 0;
+    bool a_own = false;         // the deformation pass runs over tiles of its own size
+    int largest_b = 0;          // largest halo of the force pass's tiles
     bool run_ctl = false;       // run control set (its pointers in st while stepping)
 };
 
@@ -220,6 +229,12 @@ void wire_state(tlsph_ctx* c) {
     s.halo_cap = 0;
     s.tile = kTile;
     s.a_group = 1;
+    s.tile_a = kTile;
+    s.halo_cap_a = 0;
+    s.lds_slots_a = 0;
+    s.halo_a = s.halo;
+    s.halo_cnt_a = s.halo_cnt;
+    s.lcol_a = s.lcol;
     s.staged = 0;
     s.lds_slots = 0;
     s.Linv = at<double>(c, L.Linv);
@@ -288,6 +303,7 @@ tlsph_status run_pointers(tlsph_ctx* c, bool on, hipStream_t stream) {
     const Layout& L = c->L;
     c->st.done = on ? at<int32_t>(c, L.done) : nullptr;
     c->st.tile_list = on ? at<int32_t>(c, L.tile_list) : nullptr;
+    c->st.tile_list_a = on ? at<int32_t>(c, c->a_own ? L.tile_list_a : L.tile_list) : nullptr;
     c->st.run_count = on ? at<int32_t>(c, L.run_count) : nullptr;
     if (on) {
         hipError_t e = launch_tile_list(c->st, 1, stream);
@@ -338,7 +354,7 @@ tlsph_status ensure_graph(tlsph_ctx* c, hipStream_t stream) {
     if (c->gexec && c->graph_parity == c->parity && c->graph_block_a == c->block_a &&
         c->graph_block_b == (c->st.staged ? -c->block_b : c->block_b) &&
         c->graph_sub_b == c->sub_b && c->graph_tile == c->st.tile &&
-        c->graph_run == (c->st.done != nullptr))
+        c->graph_run == (c->st.done != nullptr) && c->graph_tile_a == c->st.tile_a)
         return TLSPH_OK;
     if (c->gexec) {
         (void)hipGraphExecDestroy(c->gexec);
@@ -364,54 +380,116 @@ tlsph_status ensure_graph(tlsph_ctx* c, hipStream_t stream) {
     c->graph_sub_b = c->sub_b;
     c->graph_tile = c->st.tile;
     c->graph_run = c->st.done != nullptr;
+    c->graph_tile_a = c->st.tile_a;
     return TLSPH_OK;
 }
 
-// Per-tile halo lists and local neighbour slots for tiles of T particles,
-// and the LDS image size they need; the staged force pass is usable when the
-// largest tile plus its halo fits one workgroup's LDS.  Synchronises.
-tlsph_status set_tile_lists(tlsph_ctx* c, int T, hipStream_t stream) {
+// The staged deformation pass over tiles of T particles whose largest halo
+// is `largest` (lists already built): its records (56 bytes, 64 with graded
+// spacing) within the default LDS limit; two tiles per workgroup where a
+// tile is not a whole number of waves (one thread per particle), if both
+// images fit.
+void set_pass_a_shape(tlsph_ctx* c, int T, int largest) {
+    const size_t la = (size_t)(T + largest) * staged_a_record_bytes(c->st.var_h != 0);
+    c->st.tile_a = T;
+    c->st.halo_cap_a = T * c->L.k_cap;
+    c->st.lds_slots_a = T + largest;
+    c->st.staged_lds_a = la <= 65536 && T + largest <= 65536 ? 1 : 0;
+    c->st.a_group = (T % 64 != 0 && 2 * T <= 256 && 2 * la <= 65536) ? 2 : 1;
+}
+
+// Halo lists and local neighbour slots for tiles of T particles into the
+// given arrays; their largest halo, or -1 where the lists cannot be built
+// (the sort's LDS, or staging switched off).  Synchronises.
+tlsph_status build_tile_lists(tlsph_ctx* c, int T, size_t halo, size_t halo_cnt, size_t lcol,
+                              int* largest, hipStream_t stream) {
     const Layout& L = c->L;
-    c->staged_ok = false;
-    c->st.staged = 0;
-    c->st.staged_lds_a = 0;
-    c->st.a_group = 1;
-    if (c->block_a == 0) c->block_a = 256;
-    c->lds_b = 0;
-    if (T < 64 || T > kTile) return fail(c, TLSPH_E_INVALID_ARG, "tile size outside [64, 256]");
-    c->st.tile = T;
-    c->st.halo_cap = T * L.k_cap;
+    *largest = -1;
     int E = 256;
     while (E < T * L.k_cap) E <<= 1;
     if ((2 * (size_t)E + 257) * 4 > (size_t)c->max_lds || (c->flags & TLSPH_NO_STAGING))
         return TLSPH_OK;
     const int32_t zero = 0;
     HIPCHK(c, hipMemcpyAsync(c->ws + L.err + 16, &zero, 4, hipMemcpyHostToDevice, stream));
-    HIPCHK(c, launch_halo(c->st, L.k_cap, stream));
-    int32_t largest = 0;
-    HIPCHK(c, hipMemcpyAsync(&largest, c->ws + L.err + 16, 4, hipMemcpyDeviceToHost, stream));
+    HIPCHK(c, launch_halo(c->st, L.k_cap, T, at<int32_t>(c, halo), at<int32_t>(c, halo_cnt),
+                          at<uint16_t>(c, lcol), stream));
+    int32_t lg = 0;
+    HIPCHK(c, hipMemcpyAsync(&lg, c->ws + L.err + 16, 4, hipMemcpyDeviceToHost, stream));
     HIPCHK(c, hipStreamSynchronize(stream));
-    const bool var_h = c->st.var_h != 0;
-    const size_t lds = (size_t)(T + largest) * staged_record_bytes(L.mixed, var_h);
+    *largest = lg;
+    return TLSPH_OK;
+}
+
+// Per-tile halo lists and local neighbour slots for the force pass's tiles of
+// T particles, and the LDS image size they need; the staged force pass is
+// usable when the largest tile plus its halo fits one workgroup's LDS.  A
+// deformation pass without tiles of its own shares them.  Synchronises.
+tlsph_status set_tile_lists(tlsph_ctx* c, int T, hipStream_t stream) {
+    const Layout& L = c->L;
+    c->staged_ok = false;
+    c->st.staged = 0;
+    c->lds_b = 0;
+    if (!c->a_own) {
+        c->st.staged_lds_a = 0;
+        c->st.a_group = 1;
+        if (c->block_a == 0) c->block_a = 256;
+    }
+    if (T < 64 || T > kTile) return fail(c, TLSPH_E_INVALID_ARG, "tile size outside [64, 256]");
+    c->st.tile = T;
+    c->st.halo_cap = T * L.k_cap;
+    if (!c->a_own) c->st.tile_a = T;
+    int largest = -1;
+    tlsph_status bs = build_tile_lists(c, T, L.halo, L.halo_cnt, L.lcol, &largest, stream);
+    if (bs != TLSPH_OK || largest < 0) return bs;
+    c->largest_b = largest;
+    const size_t lds = (size_t)(T + largest) * staged_record_bytes(L.mixed, c->st.var_h != 0);
     if (lds <= (size_t)c->max_lds && T + largest <= 65536) {
         HIPCHK(c, prepare_staged(lds));
         c->staged_ok = true;
         c->lds_b = lds;
         c->st.lds_slots = T + largest;
-        // the deformation pass's records (56 bytes, 64 with graded spacing)
-        // within the default LDS limit; two tiles per workgroup where a tile
-        // is not a whole number of waves (one thread per particle), if both
-        // images fit
-        const size_t la = (size_t)(T + largest) * staged_a_record_bytes(var_h);
-        c->st.staged_lds_a = la <= 65536 ? 1 : 0;
-        c->st.a_group = (T % 64 != 0 && 2 * T <= 256 && 2 * la <= 65536) ? 2 : 1;
+        if (!c->a_own) set_pass_a_shape(c, T, largest);
     }
     return TLSPH_OK;
 }
 
-// The same, and under run control the list of running tiles at that size.
+// The deformation pass's tiles: the force pass's (T equal to its tile size:
+// the same arrays) or T particles of their own.  Synchronises.
+tlsph_status set_tile_a_lists(tlsph_ctx* c, int T, hipStream_t stream) {
+    const Layout& L = c->L;
+    if (T < 64 || T > kTile) return fail(c, TLSPH_E_INVALID_ARG, "tile size outside [64, 256]");
+    c->st.staged_lds_a = 0;
+    c->st.a_group = 1;
+    if (T == c->st.tile) {
+        c->a_own = false;
+        c->st.halo_a = c->st.halo;
+        c->st.halo_cnt_a = c->st.halo_cnt;
+        c->st.lcol_a = c->st.lcol;
+        c->st.tile_a = T;
+        if (c->staged_ok) set_pass_a_shape(c, T, c->largest_b);
+        return TLSPH_OK;
+    }
+    c->a_own = true;
+    c->st.halo_a = at<int32_t>(c, L.halo_a);
+    c->st.halo_cnt_a = at<int32_t>(c, L.halo_cnt_a);
+    c->st.lcol_a = at<uint16_t>(c, L.lcol_a);
+    c->st.tile_a = T;
+    int largest = -1;
+    tlsph_status bs = build_tile_lists(c, T, L.halo_a, L.halo_cnt_a, L.lcol_a, &largest, stream);
+    if (bs != TLSPH_OK) return bs;
+    if (largest >= 0) set_pass_a_shape(c, T, largest);
+    return TLSPH_OK;
+}
+
+// The same, and under run control the lists of running tiles at those sizes.
 tlsph_status set_tile(tlsph_ctx* c, int T, hipStream_t stream) {
     tlsph_status ts = set_tile_lists(c, T, stream);
+    if (ts == TLSPH_OK && c->st.done) ts = run_pointers(c, true, stream);
+    return ts;
+}
+
+tlsph_status set_tile_a(tlsph_ctx* c, int T, hipStream_t stream) {
+    tlsph_status ts = set_tile_a_lists(c, T, stream);
     if (ts == TLSPH_OK && c->st.done) ts = run_pointers(c, true, stream);
     return ts;
 }
@@ -630,6 +708,10 @@ tlsph_status tlsph_build_neighbors(tlsph_ctx* c, const double* X, const double* 
     HIPCHK(c, launch_build_fill(c->st, b, stream));
     c->st.staged = 0;
     c->staged_ok = false;
+    c->a_own = false;
+    c->st.halo_a = c->st.halo;
+    c->st.halo_cnt_a = c->st.halo_cnt;
+    c->st.lcol_a = c->st.lcol;
     c->lds_b = 0;
     c->block_b = 256;
     c->sub_b = 2;
@@ -976,7 +1058,7 @@ static tlsph_status autotune_all(tlsph_ctx* c, hipStream_t stream) {
     struct Cand { int staged, sub, block, tile; };
     const Cand cand_u[] = {{0, 4, 256, 0}, {0, 4, 128, 0}, {0, 2, 128, 0}, {0, 1, 64, 0},
                            {0, 1, 128, 0}, {0, 1, 256, 0}};
-    const int cand_a[] = {64, 128, 256, 0};   // 0: staged over the force pass's tiles
+    const int cand_a[] = {64, 128, 256};   // (staged: per tile size below)
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
@@ -995,9 +1077,8 @@ static tlsph_status autotune_all(tlsph_ctx* c, hipStream_t stream) {
         HIPCHK(c, hipEventElapsedTime(ms, e0, e1));
         return TLSPH_OK;
     };
-    // The two passes are timed separately and the step's shape chosen for
-    // the least sum: unstaged candidates do not depend on the tile size,
-    // staged ones (force pass and deformation pass) are timed per tile size.
+    // The two passes are timed separately: unstaged candidates do not depend
+    // on the tile size, staged ones are timed per tile size.
     auto time_b = [&](int staged, int sub, int block, float* ms) -> tlsph_status {
         c->st.staged = staged;
         const int blk = staged ? c->st.tile * sub : block;
@@ -1008,8 +1089,15 @@ static tlsph_status autotune_all(tlsph_ctx* c, hipStream_t stream) {
     auto time_a = [&](int block, float* ms) -> tlsph_status {
         return timed([&] { return launch_pass_a(c->st, c->parity, block, L.mixed, stream); }, ms);
     };
-    struct Plan { int staged, sub, block_b, tile, block_a; float ms; };
-    Plan best{0, 2, 256, c->tile_auto, 256, 1e30f};
+    // Each pass's fastest shape, chosen on its own: the force pass unstaged
+    // (lanes, block) or staged (tile size, lanes); the deformation pass
+    // unstaged (block) or staged over tiles of some size, its own or the
+    // force pass's.  Candidates for the deformation pass's tiles are timed
+    // on the force pass's lists of that size.
+    c->a_own = false;
+    c->st.halo_a = c->st.halo;
+    c->st.halo_cnt_a = c->st.halo_cnt;
+    c->st.lcol_a = c->st.lcol;
     float bu = 1e30f, au = 1e30f;
     int bu_sub = 2, bu_blk = 256, au_blk = 256;
     for (const Cand& k : cand_u) {
@@ -1019,18 +1107,18 @@ static tlsph_status autotune_all(tlsph_ctx* c, hipStream_t stream) {
         if (t < bu) { bu = t; bu_sub = k.sub; bu_blk = k.block; }
     }
     for (int blk : cand_a) {
-        if (blk == 0) continue;
         float t = 0.0f;
         tlsph_status st = time_a(blk, &t);
         if (st != TLSPH_OK) return st;
         if (t < au) { au = t; au_blk = blk; }
     }
-    best = Plan{0, bu_sub, bu_blk, c->tile_auto, au_blk, bu + au};
+    float bs_best = 1e30f, as_best = 1e30f;
+    int bs_sub = 2, bs_tile = 0, as_tile = 0;
     if (!(c->flags & TLSPH_NO_STAGING)) {
-        // Tile sizes: the build's, three fixed ones, and for each of those
+        // Tile sizes: the build's, four fixed ones, and for each of those
         // the sizes that fill whole rounds at the number of workgroups per
-        // CU its LDS image allows (the next smaller, and a few percent
-        // larger if that drops a barely started last round).
+        // CU the force pass's LDS image allows (the next smaller, and a few
+        // percent larger if that drops a barely started last round).
         int dev = 0, lds_cu = 0, n_cu = 0;
         HIPCHK(c, hipGetDevice(&dev));
         HIPCHK(c, hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
@@ -1038,7 +1126,8 @@ static tlsph_status autotune_all(tlsph_ctx* c, hipStream_t stream) {
         HIPCHK(c, hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
         if (lds_cu < c->max_lds) lds_cu = c->max_lds;
         if (n_cu < 1) n_cu = 1;
-        std::vector<int> tiles = {c->tile_auto, 128, 96, 64};
+        std::vector<int> tiles = {c->tile_auto, 128, 112, 96, 64};
+        const size_t n_fixed = tiles.size();
         for (size_t q = 0; q < tiles.size(); ++q) {
             bool seen = false;
             for (size_t r = 0; r < q; ++r) seen = seen || tiles[r] == tiles[q];
@@ -1046,26 +1135,21 @@ static tlsph_status autotune_all(tlsph_ctx* c, hipStream_t stream) {
             tlsph_status ts = set_tile(c, tiles[q], stream);
             if (ts != TLSPH_OK) return ts;
             if (!c->staged_ok) continue;
-            float bs = 1e30f, as = 1e30f;
-            int bs_sub = 2;
             for (int sub : {4, 2, 1}) {
                 if (tiles[q] > staged_tile_max(sub)) continue;
                 float t = 0.0f;
                 tlsph_status st = time_b(1, sub, 0, &t);
                 if (st != TLSPH_OK) return st;
-                if (t < bs) { bs = t; bs_sub = sub; }
+                if (t < bs_best) { bs_best = t; bs_sub = sub; bs_tile = tiles[q]; }
             }
             if (c->st.staged_lds_a) {
-                tlsph_status st = time_a(0, &as);
+                float t = 0.0f;
+                tlsph_status st = time_a(0, &t);
                 if (st != TLSPH_OK) return st;
+                if (t < as_best) { as_best = t; as_tile = tiles[q]; }
             }
-            const Plan opts[3] = {{1, bs_sub, 0, tiles[q], au_blk, bs + au},
-                                  {1, bs_sub, 0, tiles[q], 0, bs + as},
-                                  {0, bu_sub, bu_blk, tiles[q], 0, bu + as}};
-            for (const Plan& o : opts)
-                if (o.ms < best.ms) best = o;
             const int64_t w = (int64_t)lds_cu / (int64_t)c->lds_b;
-            if (w >= 1 && q < 4) {
+            if (w >= 1 && q < n_fixed) {
                 const int64_t slots = w * n_cu;
                 const int64_t rounds = (L.n + (int64_t)tiles[q] * slots - 1) /
                                        ((int64_t)tiles[q] * slots);
@@ -1080,16 +1164,24 @@ static tlsph_status autotune_all(tlsph_ctx* c, hipStream_t stream) {
             }
         }
     }
-    // leave the halo lists of the chosen tile size and apply the plan
+    // apply: the force pass's tiles (or, unstaged, the deformation pass's
+    // staged size, or the build's), then the deformation pass's
     {
-        tlsph_status ts = set_tile(c, best.tile, stream);
+        const bool b_staged = bs_best < bu;
+        const bool a_staged = as_best < au;
+        const int tb = b_staged ? bs_tile : (a_staged ? as_tile : c->tile_auto);
+        tlsph_status ts = set_tile(c, tb, stream);
         if (ts != TLSPH_OK) return ts;
-        const bool ok_b = !best.staged || c->staged_ok;
-        const bool ok_a = best.block_a != 0 || c->st.staged_lds_a;
-        c->st.staged = best.staged && ok_b;
-        c->sub_b = ok_b ? best.sub : 2;
-        c->block_b = c->st.staged ? c->st.tile * c->sub_b : (best.staged ? 256 : best.block_b);
-        c->block_a = ok_a ? best.block_a : 256;
+        const bool ok_b = !b_staged || c->staged_ok;
+        c->st.staged = b_staged && ok_b;
+        c->sub_b = b_staged && ok_b ? bs_sub : bu_sub;
+        c->block_b = c->st.staged ? c->st.tile * c->sub_b : bu_blk;
+        c->block_a = au_blk;
+        if (a_staged) {
+            ts = set_tile_a(c, as_tile, stream);
+            if (ts != TLSPH_OK) return ts;
+            if (c->st.staged_lds_a) c->block_a = 0;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1122,7 +1214,7 @@ tlsph_status tlsph_autotune(tlsph_ctx* c, hipStream_t stream) {
 tlsph_status tlsph_info(tlsph_ctx* c, int64_t out[9], hipStream_t stream) {
     if (!c || !out) return TLSPH_E_INVALID_ARG;
     out[0] = c->st.staged ? -c->block_b : c->block_b;
-    out[1] = c->block_a;
+    out[1] = c->block_a == 0 && c->a_own ? -c->st.tile_a : c->block_a;
     out[2] = c->nnz;
     out[3] = c->slots;
     out[4] = c->L.n;
@@ -1148,34 +1240,33 @@ tlsph_status tlsph_set_launch_shape(tlsph_ctx* c, const int32_t shape[5], hipStr
     if (sub != 1 && sub != 2 && sub != 4) return fail(c, TLSPH_E_INVALID_ARG, "lanes per particle");
     if (!staged && (blk_b < 64 || blk_b > 256 || blk_b % 64 != 0))
         return fail(c, TLSPH_E_INVALID_ARG, "force-pass block must be 64, 128, 192 or 256");
-    if (blk_a != 0 && (blk_a < 64 || blk_a > 256 || blk_a % 64 != 0))
+    if (blk_a > 0 && (blk_a < 64 || blk_a > 256 || blk_a % 64 != 0))
         return fail(c, TLSPH_E_INVALID_ARG,
-                    "deformation-pass block must be 0 (staged), 64, 128, 192 or 256");
-    if (staged && (tile < 64 || tile > kTile))
+                    "deformation-pass block must be 64, 128, 192 or 256, 0 (staged over the "
+                    "force pass's tiles) or -T (staged over tiles of its own, T in [64, 256])");
+    if (blk_a < 0 && (-blk_a < 64 || -blk_a > kTile))
+        return fail(c, TLSPH_E_INVALID_ARG, "the deformation pass's tiles hold 64 to 256 particles");
+    if ((staged || blk_a == 0) && (tile < 64 || tile > kTile))
         return fail(c, TLSPH_E_INVALID_ARG, "tile must hold 64 to 256 particles");
     if (staged && tile > staged_tile_max(sub))
         return fail(c, TLSPH_E_UNSUPPORTED, "four lanes per particle run tiles of at most 128");
-    if (staged) {
-        if (tile != c->st.tile || !c->staged_ok) {
-            tlsph_status ts = set_tile(c, tile, stream);
-            if (ts != TLSPH_OK) return ts;
-        }
-        if (!c->staged_ok)
-            return fail(c, TLSPH_E_UNSUPPORTED,
-                        "the LDS-staged force pass does not fit this input at this tile size");
+    if ((staged || blk_a == 0) && (tile != c->st.tile || !c->staged_ok)) {
+        tlsph_status ts = set_tile(c, tile, stream);
+        if (ts != TLSPH_OK) return ts;
     }
-    if (blk_a == 0) {
-        if (!c->staged_ok || !c->st.staged_lds_a) {
-            tlsph_status ts = set_tile(c, tile, stream);
-            if (ts != TLSPH_OK) return ts;
-        }
+    if (staged && !c->staged_ok)
+        return fail(c, TLSPH_E_UNSUPPORTED,
+                    "the LDS-staged force pass does not fit this input at this tile size");
+    if (blk_a <= 0) {
+        tlsph_status ts = set_tile_a(c, blk_a == 0 ? c->st.tile : -blk_a, stream);
+        if (ts != TLSPH_OK) return ts;
         if (!c->st.staged_lds_a)
             return fail(c, TLSPH_E_UNSUPPORTED, "the staged deformation pass does not fit LDS");
     }
     c->st.staged = staged;
     c->sub_b = sub;
     c->block_b = staged ? c->st.tile * sub : blk_b;
-    c->block_a = blk_a;
+    c->block_a = blk_a > 0 ? blk_a : 0;
     return TLSPH_OK;
 }
 

@@ -165,15 +165,26 @@ struct DevState {
     int32_t var_h;            // 1 if a specimen has graded spacing (per-particle support)
     int32_t contact;          // 1 if a specimen has penalty contact
     int32_t tile;             // particles per tile of the staged force pass (<= kTile)
+    // The staged deformation pass's tiles: the force pass's (the same
+    // arrays), or a size of their own (arrays of their own).
     int32_t staged_lds_a;     // 1 when the tile records of the deformation pass fit LDS
     int32_t a_group;          // tiles per workgroup of the staged deformation pass (1, 2)
+    int32_t tile_a;           // its particles per tile
+    int32_t halo_cap_a;
+    int32_t lds_slots_a;      // slots of one tile's image
     int32_t pad3_;
+    const int32_t* halo_a;
+    const int32_t* halo_cnt_a;
+    const uint16_t* lcol_a;
     // run control (all null when off): why each specimen stopped (kRunning
     // while it runs), the tiles of `tile` particles holding a running
-    // specimen's particle (ascending), and [0] their count, [1] nonzero once
-    // a specimen stopped after the list was made, [2] running specimens
+    // specimen's particle (ascending), the same for tiles of `tile_a` (the
+    // same list when the passes share their tiles), and [0] the force
+    // pass's count, [1] nonzero once a specimen stopped after the lists were
+    // made, [2] running specimens, [3] the deformation pass's count
     int32_t* done;
     int32_t* tile_list;
+    int32_t* tile_list_a;
     int32_t* run_count;
 };
 
@@ -203,7 +214,10 @@ struct BuildBuffers {
 
 hipError_t launch_build_count(DevState& s, const BuildBuffers& b, hipStream_t st);
 hipError_t launch_build_fill(DevState& s, const BuildBuffers& b, hipStream_t st);
-hipError_t launch_halo(const DevState& s, int k_cap, hipStream_t st);
+// Halo lists and local slots for tiles of T particles (halo_cap = T k_cap)
+// into the given arrays; the largest halo is max-reduced into s.err[4].
+hipError_t launch_halo(const DevState& s, int k_cap, int T, int32_t* halo, int32_t* halo_cnt,
+                       uint16_t* lcol, hipStream_t st);
 hipError_t prepare_staged(size_t lds_bytes_b);
 // Largest tile the staged force pass runs with `sub` lanes per particle.
 int staged_tile_max(int sub);

@@ -522,17 +522,20 @@ __global__ void __launch_bounds__(256) k_halo(DevState s, int k_cap, int E,
     }
 }
 
-hipError_t launch_halo(const DevState& s, int k_cap, hipStream_t st) {
-    if (s.tile < 1 || s.tile > kTile) return hipErrorInvalidValue;
+hipError_t launch_halo(const DevState& s, int k_cap, int T, int32_t* halo, int32_t* halo_cnt,
+                       uint16_t* lcol, hipStream_t st) {
+    if (T < 1 || T > kTile) return hipErrorInvalidValue;
     int E = 256;
-    while (E < s.tile * k_cap) E <<= 1;
+    while (E < T * k_cap) E <<= 1;
     const size_t lds = (2 * (size_t)E + 257) * sizeof(int32_t);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_halo),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    const unsigned tiles = (unsigned)((s.n + s.tile - 1) / s.tile);
-    k_halo<<<tiles, 256, lds, st>>>(s, k_cap, E, const_cast<int32_t*>(s.halo),
-                                    const_cast<int32_t*>(s.halo_cnt), const_cast<uint16_t*>(s.lcol));
+    DevState t = s;   // the kernel reads the tile size and list stride from it
+    t.tile = T;
+    t.halo_cap = T * k_cap;
+    const unsigned tiles = (unsigned)((s.n + T - 1) / T);
+    k_halo<<<tiles, 256, lds, st>>>(t, k_cap, E, halo, halo_cnt, lcol);
     return hipGetLastError();
 }
 
@@ -595,14 +598,16 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nblk) {
 // tile, and the first workgroups take the listed tiles of running specimens,
 // G at a time with the same mapping over the list; the others get -1 and
 // return at once.
-__device__ __forceinline__ int64_t work_tile(const DevState& s, int G, int part, int64_t n_tiles) {
-    if (s.tile_list) {
-        const int64_t nw = s.run_count[0];
+// (list: the pass's run-control list, null when off; count: its length)
+__device__ __forceinline__ int64_t work_tile(const int32_t* list, const int32_t* count, int G,
+                                             int part, int64_t n_tiles) {
+    if (list) {
+        const int64_t nw = *count;
         const int64_t ng = (nw + G - 1) / G;
         if ((int64_t)blockIdx.x >= ng) return -1;
         const int64_t k = xcd_tile(blockIdx.x, ng) * G + part;
         if (k >= nw) return -1;
-        const int64_t t = s.tile_list[k];
+        const int64_t t = list[k];
         return t < n_tiles ? t : -1;   // (a list of this tile size has none beyond)
     }
     const int64_t t = xcd_tile(blockIdx.x, gridDim.x) * G + part;
@@ -1160,7 +1165,7 @@ __attribute__((amdgpu_waves_per_eu(staged_waves_min<R, S, kVarH>(), 8))) k_pass_
     double* __restrict__ Lhs = reinterpret_cast<double*>(L + (size_t)M * LdsB<R>::kUnits);
     const int T = s.tile;
     const int B = T * S;
-    const int64_t tile = work_tile(s, 1, 0, gridDim.x);
+    const int64_t tile = work_tile(s.tile_list, s.run_count, 1, 0, gridDim.x);
     if (tile < 0) return;
     const int64_t start = tile * T;
     const int tot = T + s.halo_cnt[tile];
@@ -1510,14 +1515,15 @@ k_pass_a_staged(DevState s, int /* displacement buffer: unused here */) {
     // G tiles per workgroup (two where a tile is not a whole number of waves),
     // each with an image of M slots of its own; thread tx of part `part`
     // takes particle tx of that part's tile
-    const int M = s.lds_slots;
-    const int T = s.tile;
+    const int M = s.lds_slots_a;
+    const int T = s.tile_a;
     const int G = s.a_group;
     const int part = G > 1 ? (int)threadIdx.x / T : 0;
     const int tx = (int)threadIdx.x - part * T;
     const int64_t n_tiles = (s.n + T - 1) / T;
-    if (work_tile(s, G, 0, n_tiles) < 0) return;   // (then no part has a tile)
-    const int64_t tile = work_tile(s, G, part, n_tiles);
+    const int32_t* cnt_a = s.run_count ? s.run_count + 3 : nullptr;
+    if (work_tile(s.tile_list_a, cnt_a, G, 0, n_tiles) < 0) return;   // (then no part has a tile)
+    const int64_t tile = work_tile(s.tile_list_a, cnt_a, G, part, n_tiles);
     const int64_t tl = tile < 0 ? 0 : tile;
     const size_t base = (size_t)part * M;
     const size_t GM = (size_t)G * M;
@@ -1527,8 +1533,8 @@ k_pass_a_staged(DevState s, int /* displacement buffer: unused here */) {
     double* __restrict__ Lvz = reinterpret_cast<double*>(reinterpret_cast<double2*>(lds_a) + 3 * GM) + base;
     double* __restrict__ Lhs = reinterpret_cast<double*>(reinterpret_cast<double2*>(lds_a) + 3 * GM) + GM + base;
     const int64_t start = tl * T;
-    const int tot = tile < 0 ? 0 : T + s.halo_cnt[tl];
-    const int32_t* __restrict__ hl = s.halo + tl * (int64_t)s.halo_cap;
+    const int tot = tile < 0 ? 0 : T + s.halo_cnt_a[tl];
+    const int32_t* __restrict__ hl = s.halo_a + tl * (int64_t)s.halo_cap_a;
     const D4* __restrict__ XV = s.XV;
     const D4* __restrict__ VW = s.VW;
     // Up to four slots per thread per round: index loads, record loads, LDS
@@ -1547,7 +1553,7 @@ k_pass_a_staged(DevState s, int /* displacement buffer: unused here */) {
     const int cnt = s.nnb[ii];
     const int64_t slice0 = s.slice_ptr[ii / kSlice];
     const int sp_lane = s.spec[ii];
-    const uint16_t* __restrict__ lp = s.lcol + slice0 + (ii % kSlice);
+    const uint16_t* __restrict__ lp = s.lcol_a + slice0 + (ii % kSlice);
     while (m0 < tot) {
         D4 x[kU], v[kU];
         double hv[kU];
@@ -1672,11 +1678,11 @@ hipError_t prepare_staged(size_t lds_bytes_b) {
 template <int DM, bool kFlow, bool kVarH = false>
 static void launch_a(const DevState& s, int parity, unsigned grid, int block, bool mixed,
                      hipStream_t st) {
-    if (block == 0) {   // staged over the force pass's tiles, a_group of them per workgroup
-        const int64_t tiles = (s.n + s.tile - 1) / s.tile;
+    if (block == 0) {   // staged over its tiles, a_group of them per workgroup
+        const int64_t tiles = (s.n + s.tile_a - 1) / s.tile_a;
         const unsigned groups = (unsigned)((tiles + s.a_group - 1) / s.a_group);
-        const int threads = s.tile * s.a_group;
-        const size_t lds = (size_t)s.a_group * s.lds_slots * staged_a_record_bytes(kVarH);
+        const int threads = s.tile_a * s.a_group;
+        const size_t lds = (size_t)s.a_group * s.lds_slots_a * staged_a_record_bytes(kVarH);
         if (mixed)
             k_pass_a_staged<float, DM, kFlow, kVarH><<<groups, threads, lds, st>>>(s, parity);
         else
@@ -1691,7 +1697,7 @@ static void launch_a(const DevState& s, int parity, unsigned grid, int block, bo
 
 hipError_t launch_pass_a(const DevState& s, int parity, int block, bool mixed, hipStream_t st) {
     if (block == 0 && (!s.staged_lds_a || s.a_group < 1 || s.a_group > 2 ||
-                       s.tile * s.a_group > 256))
+                       s.tile_a * s.a_group > 256))
         return hipErrorInvalidValue;
     const unsigned grid = block > 0 ? (unsigned)((s.n + block - 1) / block) : 0u;
     if (s.var_h) {   // graded spacing: the general variant with per-pair supports
@@ -2130,18 +2136,12 @@ __global__ void __launch_bounds__(256) k_run_control(DevState s, int par, RunSpe
     for (int64_t i = P.first + threadIdx.x; i < P.last; i += blockDim.x) dst[i] = src[i];
 }
 
-// The list of tiles (T particles each, in sorted order) that hold a running
-// specimen's particle, ascending, its length, and the number of running
-// specimens.  One block; unless `force`, it returns at once when no specimen
-// stopped since the last list.  Specimens are contiguous in sorted order, so
-// a tile holds those from its first particle's to its last's.
-__global__ void __launch_bounds__(1024) k_tile_list(DevState s, int64_t n_tiles, int T, int force) {
-    __shared__ int32_t wave_cnt[16];
-    __shared__ int32_t running;
-    int32_t* __restrict__ cnt = s.run_count;
-    if (!force && cnt[1] == 0) return;
-    if (threadIdx.x == 0) running = 0;
-    __syncthreads();
+// Append, in ascending order, the tiles of T particles (sorted order) that
+// hold a running specimen's particle to `list`; returns their count (every
+// thread).  Specimens are contiguous in sorted order, so a tile holds those
+// from its first particle's to its last's.  One block of up to 1024 threads.
+__device__ int64_t list_running_tiles(const DevState& s, int64_t n_tiles, int T,
+                                      int32_t* __restrict__ list, int32_t* wave_cnt) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int64_t base = 0;
     for (int64_t t0 = 0; t0 < n_tiles; t0 += blockDim.x) {
@@ -2160,18 +2160,38 @@ __global__ void __launch_bounds__(1024) k_tile_list(DevState s, int64_t n_tiles,
             off += w < wave ? wave_cnt[w] : 0;
             tot += wave_cnt[w];
         }
-        if (act) s.tile_list[off + __popcll(m & ((1ull << lane) - 1))] = (int32_t)t;
+        if (act) list[off + __popcll(m & ((1ull << lane) - 1))] = (int32_t)t;
         base += tot;
         __syncthreads();
     }
+    return base;
+}
+
+// The run-control tile lists of both passes (one when they share their
+// tiles) and the number of running specimens.  One block; unless `force`, it
+// returns at once when no specimen stopped since the last lists.
+__global__ void __launch_bounds__(1024) k_tile_list(DevState s, int force) {
+    __shared__ int32_t wave_cnt[16];
+    __shared__ int32_t running;
+    int32_t* __restrict__ cnt = s.run_count;
+    if (!force && cnt[1] == 0) return;
+    if (threadIdx.x == 0) running = 0;
+    __syncthreads();
+    const int64_t nb = list_running_tiles(s, (s.n + s.tile - 1) / s.tile, s.tile, s.tile_list,
+                                          wave_cnt);
+    int64_t na = nb;
+    if (s.tile_list_a != s.tile_list)
+        na = list_running_tiles(s, (s.n + s.tile_a - 1) / s.tile_a, s.tile_a, s.tile_list_a,
+                                wave_cnt);
     int32_t mine = 0;
     for (int sp = threadIdx.x; sp < s.n_spec; sp += blockDim.x) mine += s.done[sp] == kRunning;
     if (mine) atomicAdd(&running, mine);
     __syncthreads();
     if (threadIdx.x == 0) {
-        cnt[0] = (int32_t)base;
+        cnt[0] = (int32_t)nb;
         cnt[1] = 0;
         cnt[2] = running;
+        cnt[3] = (int32_t)na;
     }
 }
 
@@ -2182,8 +2202,7 @@ hipError_t launch_run_control(const DevState& s, int parity, RunSpec* run, const
 }
 
 hipError_t launch_tile_list(const DevState& s, int force, hipStream_t st) {
-    const int64_t n_tiles = (s.n + s.tile - 1) / s.tile;
-    k_tile_list<<<1, 1024, 0, st>>>(s, n_tiles, s.tile, force);
+    k_tile_list<<<1, 1024, 0, st>>>(s, force);
     return hipGetLastError();
 }
 

@@ -23,6 +23,15 @@ def test_headline_symbols_are_in_the_profiles():
         assert force in text and deform in text, name
 
 
+def test_deformation_pass_over_its_own_tiles():
+    own = dict(STAGED, block_deformation=-128, tile=96, block_force=192)
+    assert bench.kernel_symbol("deformation_pass", own, False, 3) == \
+        "k_pass_a_staged<double, 3, false, false>"
+    sh = bench.shape_of(own)
+    assert sh["deformation_pass_block"] == 0 and sh["deformation_pass_tile"] == 128
+    assert bench.launch_shape(own) == (1, 2, 256, -128, 96)
+
+
 def test_graded_and_general_symbols():
     unstaged = {"staged": False, "lanes_per_particle": 4, "block_deformation": 128}
     assert bench.kernel_symbol("force_pass", unstaged, True, 2, var_h=True) == \

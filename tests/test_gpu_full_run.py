@@ -97,6 +97,8 @@ def gpu_run(tl, p, precision, n_samples, v_pert=0.0, seed=0, until_failed=False)
             if fd(b[:, 1, 5] - b[:, 0, 5], -b[:, 1, 2], 0.1) is not None:
                 break
     b = bd[:k].cpu().numpy()
+    # one line per run, so that a long ensemble shows progress
+    say("run", "fp64" if precision == tl.FP64 else "mixed", "seed", seed, "samples", k)
     return -b[:, 1, 2], b[:, 1, 5] - b[:, 0, 5]
 
 

@@ -388,7 +388,9 @@ SHAPES = [  # (staged, lanes per particle, force block, deformation block, tile)
     (1, 4, 256, 256, 0), (1, 2, 256, 128, 0), (1, 1, 256, 64, 0), (1, 2, 256, 64, 64),
     (1, 4, 256, 64, 96), (1, 1, 256, 128, 256), (0, 4, 256, 256, 0), (0, 4, 64, 192, 0),
     (0, 2, 128, 128, 0), (0, 1, 64, 64, 0), (0, 1, 256, 256, 0), (1, 2, 256, 0, 0),
-    (1, 4, 256, 0, 64), (0, 2, 128, 0, 96)]
+    (1, 4, 256, 0, 64), (0, 2, 128, 0, 96),
+    # the deformation pass over tiles of its own size (two per workgroup at 80)
+    (1, 2, 256, -128, 96), (0, 2, 128, -128, 0), (1, 4, 256, -80, 64), (1, 1, 256, -256, 128)]
 
 
 @pytest.mark.parametrize("case", ["batch3", "graded_bar_voce_av"])
@@ -414,6 +416,7 @@ def test_every_launch_shape_is_bitwise_identical(tl, orc, precision, case):
         inf = g.info()
         assert inf["staged"] == bool(shape[0]) and inf["lanes_per_particle"] == shape[1]
         assert inf["tile"] == (shape[4] or inf["tile"]) if shape[0] else inf["tile"] == 0
+        assert inf["block_deformation"] == shape[3]
         g.set_state(st)
         g.step(3)
         outs.append({k: g.get(k) for k in ("force", "v", "u", "F", "Q", "sig", "D")})
@@ -502,7 +505,8 @@ def test_error_paths(tl):
     assert ei.value.status == 2
     g = tl.Sim(p)
     for bad in ((2, 4, 256, 256), (0, 3, 256, 256), (0, 4, 96, 256), (0, 4, 256, 32),
-                (0, 4, 512, 256), (1, 4, 256, 256, 32), (1, 4, 256, 256, 512)):
+                (0, 4, 512, 256), (1, 4, 256, 256, 32), (1, 4, 256, 256, 512),
+                (0, 4, 256, -32), (0, 4, 256, -512)):
         with pytest.raises(tl.TLSPHError) as ei:
             g.set_launch_shape(*bad)
         assert ei.value.status == 1, bad

@@ -3,9 +3,10 @@ once their load has dropped after its peak) while the others go on.
 
 The batch of four notched bars (uneven particle counts, scattered Johnson-Cook
 parameters, each pulled at both ends) runs under run control with graphs and
-LDS-staged passes over tiles of 96 particles until every specimen has stopped;
-each specimen then runs alone, in a context of its own (eager launches,
-default tiles), under the same rule.  In FP64 every specimen
+LDS-staged passes (force pass over tiles of 96 particles, deformation pass
+over tiles of 80 of its own) until every specimen has stopped; each specimen
+then runs alone, in a context of its own (eager launches, default tiles),
+under the same rule.  In FP64 every specimen
 must stop at the same step for the same reason, and its whole state must
 equal the batch's bit for bit: the batch adds nothing to a specimen's
 arithmetic, a stopped specimen's state is kept while the others step on, and
@@ -64,10 +65,11 @@ def batch_run(tl):
     import torch
     p = batch()
     # graphs are replayed on a stream of its own (the default stream steps
-    # eagerly); tiles of 96 particles, two per deformation-pass workgroup
-    # (the lone runs keep their default tiles of 64)
+    # eagerly); the force pass on tiles of 96 particles, the deformation pass
+    # on tiles of 80 of its own, two per workgroup (the lone runs keep their
+    # default tiles of 64 for both)
     g = tl.Sim(p, flags=tl.USE_GRAPHS, stream=torch.cuda.Stream())
-    g.set_launch_shape(True, 2, 256, 0, 96)
+    g.set_launch_shape(True, 2, 256, -80, 96)
     g.set_run_control([rule(q, 2 * q + 1) for q in range(p.n_spec)])
     ran = g.run(100000, check_every=250)
     st = g.run_status()
