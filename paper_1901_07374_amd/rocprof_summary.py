@@ -176,7 +176,7 @@ def pmc(args):
     print(f"fetch_scale = {f_fac:.4f}")
     print(f"write_scale = {w_fac:.4f}")
     print("# kernels counted: " + "; ".join(sorted(k[:48] for k in fetch)))
-    gat = [k for k in fetch if "indexSelect" in k or "index_select" in k or "index" in k.lower()]
+    gat = [k for k in fetch if "gather" in k.lower() or "index" in k.lower()]
     if gat and args.gather_read_bytes:
         gf = max(max(fetch[k]) for k in gat)
         print(f"# gather calibration: {gat[0][:60]} reads {args.gather_read_bytes} bytes "
