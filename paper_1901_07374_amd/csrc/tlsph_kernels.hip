@@ -1461,13 +1461,15 @@ __device__ __forceinline__ void pass_a_update(const DevState& s, int64_t i, int 
 }
 
 // Waves per SIMD the deformation pass is compiled for: three (at most 168
-// registers) for the JC-type models with Johnson-Cook hardening and the
-// explicit return, whose update fits that, and for the mixed form with the
-// other flow laws (JC or no damage); the GTN return, the mixed-model variant
-// and the FP64 form with the other flow laws need more.
+// registers) for each single damage model with Johnson-Cook hardening and
+// the explicit return, and for the mixed form with the other flow laws (JC
+// or no damage).  The FP64 GTN variant then spills 76 bytes (outside its
+// Newton loops) and still runs faster than at two waves; the mixed-model
+// variant and the FP64 form with the other flow laws would spill more and
+// keep their registers.
 template <typename R, int DM, bool kFlow>
 __host__ __device__ constexpr int pass_a_waves_min() {
-    return DM >= 0 && DM <= 2 && (!kFlow || (sizeof(R) == 4 && DM != 1)) ? 3 : 1;
+    return DM >= 0 && DM <= 3 && (!kFlow || (sizeof(R) == 4 && DM != 1)) ? 3 : 1;
 }
 
 // Specimen parameters are read with scalar loads: the lanes of a wave take
