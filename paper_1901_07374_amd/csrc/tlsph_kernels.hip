@@ -132,6 +132,66 @@ __global__ void k_bitonic(uint64_t* __restrict__ keys, int32_t* __restrict__ val
     }
 }
 
+// The stages of the same sort whose partners lie within one block of kSortB
+// elements (j < kSortB), run in LDS: with k <= kSortB every stage of the
+// network from k = 2 (the block's own sort), else the stages j < kSortB of
+// the merge of size k.  Blocks of kSortB / 2 threads, one pair per stage each;
+// N (a power of two) below kSortB makes one block of N elements.
+constexpr int kSortB = 2048;
+__global__ void __launch_bounds__(kSortB / 2) k_bitonic_lds(uint64_t* __restrict__ keys,
+                                                            int32_t* __restrict__ vals, int64_t N,
+                                                            int64_t k_merge) {
+    __shared__ uint64_t sk[kSortB];
+    __shared__ int32_t sv[kSortB];
+    const int B = (int)(N < kSortB ? N : kSortB);
+    const int64_t base = (int64_t)blockIdx.x * B;
+    for (int e = threadIdx.x; e < B; e += blockDim.x) {
+        sk[e] = keys[base + e];
+        sv[e] = vals[base + e];
+    }
+    __syncthreads();
+    const int64_t k_lo = k_merge > 0 ? k_merge : 2;
+    const int64_t k_hi = k_merge > 0 ? k_merge : B;
+    for (int64_t k = k_lo; k <= k_hi; k <<= 1) {
+        for (int64_t j = (k >> 1 < B ? k >> 1 : B >> 1); j > 0; j >>= 1) {
+            for (int t = threadIdx.x; t < B / 2; t += blockDim.x) {
+                // the t-th pair (e, e + j) of the stage
+                const int e = (int)(((t / j) * 2 * j) + (t % j));
+                const int l = e + (int)j;
+                const uint64_t ka = sk[e], kb = sk[l];
+                const int32_t va = sv[e], vb = sv[l];
+                const bool a_gt_b = (ka > kb) || (ka == kb && va > vb);
+                const bool asc = ((base + e) & k) == 0;
+                if (a_gt_b == asc) {
+                    sk[e] = kb; sk[l] = ka;
+                    sv[e] = vb; sv[l] = va;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = threadIdx.x; e < B; e += blockDim.x) {
+        keys[base + e] = sk[e];
+        vals[base + e] = sv[e];
+    }
+}
+
+// Sort N (a power of two, >= 2) (key, val) pairs ascending by key, then val:
+// the bitonic network, its stages with partners closer than kSortB run in
+// LDS, the others one launch each.
+hipError_t launch_bitonic_sort(uint64_t* keys, int32_t* vals, int64_t N, hipStream_t st) {
+    constexpr int T = 256;
+    const int B = (int)(N < kSortB ? N : kSortB);
+    const unsigned blocks = (unsigned)(N / B);
+    k_bitonic_lds<<<blocks, B / 2, 0, st>>>(keys, vals, N, 0);
+    for (int64_t k = 2 * (int64_t)B; k <= N; k <<= 1) {
+        for (int64_t j = k >> 1; j >= B; j >>= 1)
+            k_bitonic<<<(unsigned)((N + T - 1) / T), T, 0, st>>>(keys, vals, N, j, k);
+        k_bitonic_lds<<<blocks, B / 2, 0, st>>>(keys, vals, N, k);
+    }
+    return hipGetLastError();
+}
+
 __global__ void k_apply_perm(DevState s, const double* __restrict__ X_in,
                              const double* __restrict__ V0_in, const int32_t* __restrict__ bc_in,
                              const uint64_t* __restrict__ keys, const int32_t* __restrict__ vals,
@@ -404,10 +464,8 @@ hipError_t launch_build_count(DevState& s, const BuildBuffers& b, hipStream_t st
     k_keys<<<(unsigned)((b.n_pow2 + T - 1) / T), T, 0, st>>>(b.X_in, s.n, b.n_pow2, b.spec_off,
                                                              s.n_spec, b.bbox, b.keys, b.vals,
                                                              s.err);
-    for (int64_t k = 2; k <= b.n_pow2; k <<= 1)
-        for (int64_t j = k >> 1; j > 0; j >>= 1)
-            k_bitonic<<<(unsigned)((b.n_pow2 + T - 1) / T), T, 0, st>>>(b.keys, b.vals, b.n_pow2,
-                                                                        j, k);
+    hipError_t e = launch_bitonic_sort(b.keys, b.vals, b.n_pow2, st);
+    if (e != hipSuccess) return e;
     const unsigned gp = (unsigned)((s.np + T - 1) / T);
     k_apply_perm<<<gp, T, 0, st>>>(s, b.X_in, b.V0_in, b.bc_in, b.keys, b.vals,
                                    const_cast<D4*>(s.XV), const_cast<int32_t*>(s.spec),
@@ -2062,9 +2120,8 @@ hipError_t launch_contact_build(const DevState& s, int parity, uint64_t* keys, i
     k_cbox<<<1, 1024, 0, st>>>(s, parity, cbox);
     constexpr int T = 256;
     k_ckeys<<<(unsigned)((n_pow2 + T - 1) / T), T, 0, st>>>(s, parity, cbox, n_pow2, keys, vals);
-    for (int64_t k = 2; k <= n_pow2; k <<= 1)
-        for (int64_t j = k >> 1; j > 0; j >>= 1)
-            k_bitonic<<<(unsigned)((n_pow2 + T - 1) / T), T, 0, st>>>(keys, vals, n_pow2, j, k);
+    hipError_t e = launch_bitonic_sort(keys, vals, n_pow2, st);
+    if (e != hipSuccess) return e;
     k_cfill<<<(unsigned)((s.np + T - 1) / T), T, 0, st>>>(s, parity, cbox, keys, vals);
     return hipGetLastError();
 }
@@ -2074,9 +2131,8 @@ hipError_t launch_bc_lists(const DevState& s, uint64_t* keys, int32_t* vals, int
     const int T = 256;
     const unsigned g = (unsigned)((n_pow2 + T - 1) / T);
     k_bc_keys<<<g, T, 0, st>>>(s, keys, vals, n_pow2);
-    for (int64_t k = 2; k <= n_pow2; k <<= 1)
-        for (int64_t j = k >> 1; j > 0; j >>= 1)
-            k_bitonic<<<g, T, 0, st>>>(keys, vals, n_pow2, j, k);
+    hipError_t e = launch_bitonic_sort(keys, vals, n_pow2, st);
+    if (e != hipSuccess) return e;
     const int64_t m = (s.n > s.n_bc + 1) ? s.n : s.n_bc + 1;
     k_bc_ptr<<<(unsigned)((m + T - 1) / T), T, 0, st>>>(s, keys, s.n, vals, bc_list, bc_ptr);
     return hipGetLastError();
