@@ -23,6 +23,16 @@ def test_headline_symbols_are_in_the_profiles():
         assert force in text and deform in text, name
 
 
+def test_plate_symbols_are_in_the_profiles():
+    # the FP64 GTN plate's autotuned kernels (staged force pass, two lanes;
+    # staged deformation pass with the GTN model)
+    force = bench.kernel_symbol("force_pass", STAGED, False, 3)
+    deform = bench.kernel_symbol("deformation_pass", STAGED, False, 3)
+    for name in ("pmc_gtn_plate_4m.txt", "trace_gtn_plate_4m.txt", "sq_gtn_plate_4m.txt"):
+        text = open(os.path.join(ROOT, "profiles", name)).read()
+        assert force in text and deform in text, name
+
+
 def test_deformation_pass_over_its_own_tiles():
     own = dict(STAGED, block_deformation=-128, tile=96, block_force=192)
     assert bench.kernel_symbol("deformation_pass", own, False, 3) == \
