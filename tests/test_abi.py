@@ -112,5 +112,10 @@ def test_null_context_calls(L):
     assert L.tlsph_set_launch_shape(None, None, None) == 1
     L.tlsph_set_contact.argtypes = [C.c_void_p, C.c_int32, C.c_double]
     assert L.tlsph_set_contact(None, 1, 0.0) == 1
+    assert L.tlsph_set_run_control(None, None, None) == 1
+    assert L.tlsph_get_run_status(None, None, None, None, None, None) == 1
+    assert L.tlsph_run(None, 10, 1, None, None) == 1
+    assert L.tlsph_get_diagnostics(None, None, None, None) == 1
+    assert L.tlsph_get_diagnostics_static(None, None, None, None) == 1
     L.tlsph_destroy(None)
     assert L.tlsph_last_error(None) == b""
