@@ -486,6 +486,15 @@ def bench_collision(args, torch, I, T):
                        "two bars meeting head on, CL damage, penalty contact", "cockcroft-latham",
                        result, setup=lambda sim: sim.set_contact(10, 0.2 * dx))
     out["config"]["contact"] = {"rebuild_every": 10, "skin_m": 0.2 * dx}
+    # the same FP64 run replayed from graphs (twenty steps a replay, the
+    # lists rebuilt at the first and the eleventh)
+    side = torch.cuda.Stream()
+    gr = run_form(prob, T.FP64, args.steps, args.warmup, torch, T, T.USE_GRAPHS,
+                  not args.no_autotune, stream=side, diag=False,
+                  setup=lambda sim: sim.set_contact(10, 0.2 * dx))
+    out["fp64_graphs"] = {"value": round(prob.n * args.steps / gr["seconds"], 1),
+                          "ms_per_step": round(gr["seconds"] / args.steps * 1e3, 5)}
+    del gr["sim"]
     return out
 
 

@@ -335,8 +335,10 @@ tlsph_status tlsph_set_launch_shape(tlsph_ctx *ctx, const int32_t shape[5], hipS
  * configuration, at most 32) is rebuilt on the stream every `every` steps;
  * between rebuilds it is valid while no particle moves more than skin / 2,
  * which the force pass checks (info flag bit 2 otherwise).  Default every = 1,
- * skin = 0: rebuilt every step, exact.  Steps with contact run without
- * graphs.  Errors: INVALID_ARG (every < 1, skin < 0 or not finite). */
+ * skin = 0: rebuilt every step, exact.  With graphs, steps with contact
+ * replay graphs of twice the rebuild interval, each starting at a rebuild
+ * (eager steps lead up to the first).  Errors: INVALID_ARG (every < 1, skin
+ * < 0 or not finite). */
 tlsph_status tlsph_set_contact(tlsph_ctx *ctx, int32_t every, double skin);
 
 /* Run control of a batch: each specimen stops on its own, at a step cap or

@@ -177,6 +177,7 @@ struct tlsph_ctx {
     int graph_parity = -1;
     int graph_block_a = 0, graph_block_b = 0, graph_sub_b = 0, graph_tile = 0;
     bool graph_run = false;
+    int graph_steps = 0;        // steps one replay covers (2, or twice the contact interval)
     int graph_tile_a = 0;
     bool a_own = false;         // the deformation pass runs over tiles of its own size
     int largest_b = 0;          // largest halo of the force pass's tiles
@@ -350,11 +351,15 @@ tlsph_status run_steps_eager(tlsph_ctx* c, int32_t n_steps, hipStream_t stream) 
     return TLSPH_OK;
 }
 
-tlsph_status ensure_graph(tlsph_ctx* c, hipStream_t stream) {
+// The graph of `steps` steps from the current parity (with contact: from a
+// step that rebuilds the candidate lists, `steps` twice the rebuild interval,
+// so that every replay starts where the last ended).
+tlsph_status ensure_graph(tlsph_ctx* c, int32_t steps, hipStream_t stream) {
     if (c->gexec && c->graph_parity == c->parity && c->graph_block_a == c->block_a &&
         c->graph_block_b == (c->st.staged ? -c->block_b : c->block_b) &&
         c->graph_sub_b == c->sub_b && c->graph_tile == c->st.tile &&
-        c->graph_run == (c->st.done != nullptr) && c->graph_tile_a == c->st.tile_a)
+        c->graph_run == (c->st.done != nullptr) && c->graph_tile_a == c->st.tile_a &&
+        c->graph_steps == steps)
         return TLSPH_OK;
     if (c->gexec) {
         (void)hipGraphExecDestroy(c->gexec);
@@ -362,13 +367,15 @@ tlsph_status ensure_graph(tlsph_ctx* c, hipStream_t stream) {
     }
     hipGraph_t g = nullptr;
     const int p0 = c->parity;
+    const int32_t age0 = c->contact_age;
     HIPCHK(c, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
     const bool timing = c->timing;
     c->timing = false;
-    tlsph_status s = run_steps_eager(c, 2, stream);
+    tlsph_status s = run_steps_eager(c, steps, stream);
     c->timing = timing;
     hipError_t ce = hipStreamEndCapture(stream, &g);
     c->parity = p0;  // capture only recorded the launches
+    c->contact_age = age0;
     if (s != TLSPH_OK) return s;
     if (ce != hipSuccess) return hip_fail(c, ce, "hipStreamEndCapture");
     hipError_t ie = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
@@ -381,6 +388,7 @@ tlsph_status ensure_graph(tlsph_ctx* c, hipStream_t stream) {
     c->graph_tile = c->st.tile;
     c->graph_run = c->st.done != nullptr;
     c->graph_tile_a = c->st.tile_a;
+    c->graph_steps = steps;
     return TLSPH_OK;
 }
 
@@ -794,9 +802,8 @@ tlsph_status tlsph_step(tlsph_ctx* c, int32_t n_steps, hipStream_t stream) {
     if (!c) return TLSPH_E_INVALID_ARG;
     if (!c->built) return fail(c, TLSPH_E_BAD_STATE, "step before build");
     if (n_steps < 0) return fail(c, TLSPH_E_INVALID_ARG, "negative step count");
-    // (contact lists are rebuilt on a schedule: no graphs)
     bool graphs = (c->flags & TLSPH_USE_GRAPHS) && !c->timing && n_steps >= 2 &&
-                  stream != nullptr && !c->st.contact;
+                  stream != nullptr;
     if (graphs) {
         // a caller that is capturing already records the plain launches
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -805,13 +812,43 @@ tlsph_status tlsph_step(tlsph_ctx* c, int32_t n_steps, hipStream_t stream) {
     }
     if (!graphs) return run_steps_eager(c, n_steps, stream);
     int32_t left = n_steps;
+    if (c->st.contact) {
+        // replays of twice the rebuild interval, each from a step that
+        // rebuilds the lists: eager steps up to the next such step, and on
+        // to the one after if the parity differs from the graph's
+        const int32_t every = c->contact_every;
+        const int32_t G = 2 * every;
+        auto eager_to_rebuild = [&]() -> tlsph_status {
+            while (left > 0 && c->contact_age < every) {
+                tlsph_status s = run_steps_eager(c, 1, stream);
+                if (s != TLSPH_OK) return s;
+                --left;
+            }
+            return TLSPH_OK;
+        };
+        tlsph_status s = eager_to_rebuild();
+        if (s != TLSPH_OK) return s;
+        if (c->gexec && c->graph_steps == G && c->graph_parity != c->parity && left >= every + G) {
+            s = run_steps_eager(c, every, stream);
+            if (s != TLSPH_OK) return s;
+            left -= every;
+        }
+        if (left >= G) {
+            s = ensure_graph(c, G, stream);
+            if (s != TLSPH_OK) return s;
+            for (; left >= G; left -= G) HIPCHK(c, hipGraphLaunch(c->gexec, stream));
+            c->contact_age = every;   // each replay ends where the next rebuild is due
+        }
+        if (left) return run_steps_eager(c, left, stream);
+        return TLSPH_OK;
+    }
     if (c->gexec && c->graph_parity != c->parity) {
         tlsph_status s = run_steps_eager(c, 1, stream);
         if (s != TLSPH_OK) return s;
         --left;
     }
     if (left >= 2) {
-        tlsph_status s = ensure_graph(c, stream);
+        tlsph_status s = ensure_graph(c, 2, stream);
         if (s != TLSPH_OK) return s;
         for (; left >= 2; left -= 2) HIPCHK(c, hipGraphLaunch(c->gexec, stream));
     }

@@ -360,8 +360,11 @@ def test_resume_from_exported_state_is_bitwise(tl, precision):
 
 def test_contact_runs_are_bitwise_reproducible(tl):
     """Contact candidate lists are sorted and summed in list order: runs
-    repeat bit for bit, also when the context was created for graph replay
-    (contact steps run eagerly), with autotuned shapes and unstaged."""
+    repeat bit for bit, also replayed from graphs (each replay twice the
+    rebuild interval, starting at a rebuild), with autotuned shapes and
+    unstaged; with an odd rebuild interval, steps taken in uneven chunks
+    (eager steps up to a rebuild, replays, a parity change between calls)
+    equal one eager run."""
     import torch
     dx = 0.25e-3
     p = I.bar_collision(dx=dx, R=1.0e-3, L=2e-3, gap=0.01e-3, v0=20.0)
@@ -382,6 +385,16 @@ def test_contact_runs_are_bitwise_reproducible(tl):
     for o in outs[1:]:
         for k in o:
             assert np.array_equal(o[k], outs[0][k]), k
+    odd = []
+    for chunks, stream in (((120,), None), ((5, 50, 10, 55), side)):
+        g = tl.Sim(p, flags=tl.USE_GRAPHS if stream is not None else 0, stream=stream)
+        g.set_contact(7, 0.2 * dx)
+        for k in chunks:
+            g.step(k)
+        odd.append({k: g.get(k) for k in ("u", "v", "F", "sig", "D", "eps_p", "t")})
+        assert g.info()["flags"] & 4 == 0
+    for k in odd[0]:
+        assert np.array_equal(odd[0][k], odd[1][k]), k
 
 
 SHAPES = [  # (staged, lanes per particle, force block, deformation block, tile)
