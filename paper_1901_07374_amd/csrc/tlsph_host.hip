@@ -39,7 +39,7 @@ struct Layout {
         specs, bcs, t;
     int64_t n_tiles;
     size_t GQ, GH, U0, U1, VW, sig, eps_p, eps_rate, d_init, w_p, f_void, e, D, force, fvisc, hs, err,
-        arad, ccnt, ccol, ubuild, cbox,
+        arad, ccnt, ccol, ubuild, cbox, hslot, hboff, gpos, gref,
         spec_off, bbox, keys, vals, bc_list, bc_ptr, diag_seg, diag_part, backup,
         run, done, tile_list, run_count, halo_a, halo_cnt_a, lcol_a, tile_list_a;
     int64_t diag_chunk_cap;
@@ -85,7 +85,12 @@ Layout make_layout(int64_t n, int32_t n_spec, int32_t n_bc, int32_t k_cap, bool 
     L.ccnt = take(np * 4);
     L.ccol = take((size_t)kContactCap * np * 4);
     L.ubuild = take(3 * np * 8);
-    L.cbox = take(8 * 8);
+    L.cbox = take((kCBoxHead + (size_t)kCBoxParts * 7) * 8);
+    const size_t H = 2 * (size_t)L.n_pow2;
+    L.hslot = take(H * sizeof(CSlot));
+    L.hboff = take((H / kCHashScanB + 1) * 4);
+    L.gpos = take((size_t)L.n_pow2 * sizeof(D4));
+    L.gref = take((size_t)L.n_pow2 * sizeof(D4));
     L.Linv32 = take(mixed ? 9 * np * 4 : 0);
     L.specs = take((size_t)n_spec * sizeof(DevSpec));
     L.bcs = take((size_t)(n_bc > 0 ? n_bc : 1) * sizeof(DevBC));
@@ -290,9 +295,16 @@ hipEvent_t next_event(tlsph_ctx* c) {
 // Contact candidate lists from the current state (positions at t^n).
 tlsph_status contact_rebuild(tlsph_ctx* c, hipStream_t stream) {
     const Layout& L = c->L;
+    CHash h;
+    h.slot = at<CSlot>(c, L.hslot);
+    h.boff = at<int32_t>(c, L.hboff);
+    h.gpos = at<D4>(c, L.gpos);
+    h.gref = at<D4>(c, L.gref);
+    h.H = 2 * L.n_pow2;
+    h.shift = 64;
+    for (int64_t v = h.H; v > 1; v >>= 1) --h.shift;
     hipError_t e = launch_contact_build(c->st, c->parity, at<uint64_t>(c, L.keys),
-                                        at<int32_t>(c, L.vals), L.n_pow2, at<double>(c, L.cbox),
-                                        stream);
+                                        at<int32_t>(c, L.vals), h, at<double>(c, L.cbox), stream);
     if (e != hipSuccess) return hip_fail(c, e, "contact list");
     c->contact_age = 0;
     return TLSPH_OK;

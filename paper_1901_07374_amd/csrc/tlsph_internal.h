@@ -15,6 +15,8 @@ constexpr int kDiagChunk = 2048;   // particles per partial sum of the diagnosti
 constexpr int kTile = 256;         // most particles per workgroup tile of the LDS-staged pass
 constexpr int kHaloSortMax = 8192; // tile entries sorted in LDS at build (kTile * k_cap)
 constexpr int kContactCap = 32;    // contact candidates per particle
+constexpr int kCBoxParts = 512;    // workgroups of the contact bounding-box reduction
+constexpr int kCBoxHead = 16;      // doubles of the contact grid header before the partials
 // doubles of the static scratch array of the allocation-free diagnostics
 // (1 MiB per device: 16384 chunk partials of kNDiag doubles)
 constexpr int64_t kScratchDoubles = 1 << 17;
@@ -242,10 +244,36 @@ hipError_t launch_diagnostics(const DevState& s, int parity, const int32_t* bc_l
                               const int64_t* bc_ptr, const int64_t* seg, int32_t n_seg,
                               int64_t n_chunks, double* part, double* spec_diag, double* bc_diag,
                               hipStream_t st);
+// Cell table of the contact grid: H = 2 n_pow2 slots, each the count of a
+// cell's particles and the offset of its group in the cell-grouped particle
+// list (first within its scan block of kCHashScanB slots, then, once boff
+// holds the blocks' offsets, the global offset).  A grid of at most H cells
+// is dense: slot = linear cell index, x fastest, so that the groups follow
+// the cells' order in space.  A larger grid hashes its occupied cells
+// (open addressing, linear probing; at most n_pow2 occupied, so at least
+// half the slots stay empty), the slot holding the packed cell key (~0 when
+// empty).  The grouped list holds each cell's particles in ascending
+// index order, with their current positions and contact radii, and their
+// reference positions and support radii, beside them.
+constexpr int kCHashScanB = 4096;
+struct CSlot {
+    uint64_t key;
+    int32_t cnt;
+    int32_t start;
+};
+struct CHash {
+    CSlot* slot;      // [H]
+    int32_t* boff;    // [H / kCHashScanB + 1]
+    D4* gpos;         // [n_pow2] grouped x + u and contact radius
+    D4* gref;         // [n_pow2] grouped X and support radius h
+    int64_t H;
+    int shift;        // 64 - log2 H
+};
 // Contact candidate lists from the current configuration (keys, vals: n_pow2
-// scratch; cbox: 8 doubles).
+// scratch; cbox: kCBoxHead doubles of grid header, then kCBoxParts * 7
+// doubles of partial extrema).
 hipError_t launch_contact_build(const DevState& s, int parity, uint64_t* keys, int32_t* vals,
-                                int64_t n_pow2, double* cbox, hipStream_t st);
+                                const CHash& h, double* cbox, hipStream_t st);
 // Run control after a step of parity `parity`: count it, watch each running
 // specimen's reaction, stop specimens (their displacement into both buffers),
 // then remake the tile list if a specimen stopped (or always with `force`).

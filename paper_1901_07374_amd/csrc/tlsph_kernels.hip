@@ -1983,42 +1983,77 @@ __global__ void k_bc_ptr(DevState s, const uint64_t* __restrict__ keys, int64_t 
 // ===========================================================================
 
 // Bounding box of the current positions and the largest contact radius over
-// every particle (one block): cbox = lo[3], hi[3], 1 / cell edge, cell edge,
-// with the edge 2 max a + skin (a hair larger).
-__global__ void __launch_bounds__(1024) k_cbox(DevState s, int par, double* __restrict__ cbox) {
-    __shared__ double red[7][1024];
+// every particle, in two stages: kCBoxParts workgroups each reduce a
+// contiguous share of the particles to 7 partial extrema (lo[3], hi[3],
+// max a) after the header, then one workgroup reduces those to the header:
+// cbox = lo[3], hi[3], 1 / cell edge, cell edge (the edge 2 max a + skin, a
+// hair larger), then the grid's extent in cells along x, y, z and whether
+// the grid is dense (its cells fit the slot table, see CHash).  Minima and
+// maxima do not depend on the order of reduction.
+constexpr int kCBoxThreads = 256;
+
+__device__ __forceinline__ void cbox_reduce(double (*red)[kCBoxThreads], double v[7]) {
+    for (int a = 0; a < 7; ++a) red[a][threadIdx.x] = v[a];
+    __syncthreads();
+    for (int w = kCBoxThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int a = 0; a < 7; ++a) {
+                const double o = red[a][threadIdx.x + w];
+                red[a][threadIdx.x] = a < 3 ? fmin(red[a][threadIdx.x], o)
+                                            : fmax(red[a][threadIdx.x], o);
+            }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kCBoxThreads) k_cbox_part(DevState s, int par,
+                                                             double* __restrict__ cbox) {
+    __shared__ double red[7][kCBoxThreads];
     const D4* __restrict__ Uc = s.U[par];
-    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300}, am = 0.0;
-    for (int64_t p = threadIdx.x; p < s.n; p += blockDim.x) {
+    double v[7] = {1e300, 1e300, 1e300, -1e300, -1e300, -1e300, 0.0};
+    const int64_t share = (s.n + kCBoxParts - 1) / kCBoxParts;
+    const int64_t p0 = (int64_t)blockIdx.x * share;
+    const int64_t p1 = p0 + share < s.n ? p0 + share : s.n;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += kCBoxThreads) {
         const D4 x = s.XV[p], u = Uc[p];
         const double c[3] = {x.x + u.x, x.y + u.y, x.z + u.z};
         for (int a = 0; a < 3; ++a) {
-            lo[a] = fmin(lo[a], c[a]);
-            hi[a] = fmax(hi[a], c[a]);
+            v[a] = fmin(v[a], c[a]);
+            v[3 + a] = fmax(v[3 + a], c[a]);
         }
-        am = fmax(am, s.arad[p]);
+        v[6] = fmax(v[6], s.arad[p]);
     }
-    for (int a = 0; a < 3; ++a) {
-        red[a][threadIdx.x] = lo[a];
-        red[3 + a][threadIdx.x] = hi[a];
-    }
-    red[6][threadIdx.x] = am;
-    __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            for (int a = 0; a < 3; ++a) {
-                red[a][threadIdx.x] = fmin(red[a][threadIdx.x], red[a][threadIdx.x + w]);
-                red[3 + a][threadIdx.x] = fmax(red[3 + a][threadIdx.x], red[3 + a][threadIdx.x + w]);
-            }
-            red[6][threadIdx.x] = fmax(red[6][threadIdx.x], red[6][threadIdx.x + w]);
+    cbox_reduce(red, v);
+    if (threadIdx.x < 7) cbox[kCBoxHead + (int64_t)blockIdx.x * 7 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(kCBoxThreads) k_cbox_final(DevState s, double* __restrict__ cbox,
+                                                              int64_t n_slots) {
+    __shared__ double red[7][kCBoxThreads];
+    double v[7] = {1e300, 1e300, 1e300, -1e300, -1e300, -1e300, 0.0};
+    for (int b = threadIdx.x; b < kCBoxParts; b += kCBoxThreads)
+        for (int a = 0; a < 7; ++a) {
+            const double o = cbox[kCBoxHead + (int64_t)b * 7 + a];
+            v[a] = a < 3 ? fmin(v[a], o) : fmax(v[a], o);
         }
-        __syncthreads();
-    }
+    cbox_reduce(red, v);
     if (threadIdx.x < 6) cbox[threadIdx.x] = red[threadIdx.x][0];
-    if (threadIdx.x == 6) {
+    if (threadIdx.x == 0) {
         const double edge = (2.0 * red[6][0] + s.contact_skin) * (1.0 + 1e-9);
-        cbox[6] = 1.0 / edge;
+        const double inv = 1.0 / edge;
+        cbox[6] = inv;
         cbox[7] = edge;
+        // the cell of the largest coordinate, computed as every particle's
+        // own (so no particle lies beyond it), bounds the extent
+        double cells = 1.0;
+        for (int a = 0; a < 3; ++a) {
+            const double q = floor((red[3 + a][0] - red[a][0]) * inv);
+            const double e = q >= (double)((1 << kMortonBits) - 1) ? (double)(1 << kMortonBits)
+                                                                   : q + 1.0;
+            cbox[9 + a] = e;
+            cells *= e;
+        }
+        cbox[8] = cells <= (double)n_slots ? 1.0 : 0.0;
     }
 }
 
@@ -2036,93 +2071,327 @@ __device__ __forceinline__ bool contact_cell(const double* cb, double x, double 
     return ok;
 }
 
-__global__ void k_ckeys(DevState s, int par, const double* __restrict__ cbox, int64_t n_pow2,
-                        uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_pow2) return;
-    if (i >= s.n) {
-        keys[i] = ~0ull;
-        vals[i] = 0x7fffffff;
-        return;
-    }
-    const D4 x = s.XV[i], u = s.U[par][i];
+// Packed key of a contact cell (coordinates below 2^kMortonBits each).
+__device__ __forceinline__ uint64_t ccell_key(const int32_t c[3]) {
+    return (uint64_t)c[0] | ((uint64_t)c[1] << kMortonBits) |
+           ((uint64_t)c[2] << (2 * kMortonBits));
+}
+
+// The grid as the rebuild's kernels read it from the bounding box: dense
+// (slot = linear cell index, x fastest) or hashed, and its extent.
+struct CGrid {
+    bool dense;
+    int32_t ext[3];
+};
+__device__ __forceinline__ CGrid cgrid(const double* cbox) {
+    return CGrid{cbox[8] != 0.0, {(int32_t)cbox[9], (int32_t)cbox[10], (int32_t)cbox[11]}};
+}
+__device__ __forceinline__ int64_t cgrid_slot(const CGrid& g, int32_t x, int32_t y, int32_t z) {
+    return ((int64_t)z * g.ext[1] + y) * g.ext[0] + x;
+}
+
+// First slot probed for a key (Fibonacci hashing), then linear probing.
+__device__ __forceinline__ int64_t chash_home(const CHash& h, uint64_t key) {
+    return (int64_t)((key * 0x9E3779B97F4A7C15ull) >> h.shift);
+}
+
+__global__ void k_chash_clear(CHash h) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= h.H) return;
+    h.slot[t] = CSlot{~0ull, 0, 0};
+}
+
+// Each particle claims (or finds) its cell's slot and takes a place in the
+// cell's group: rank[p] = slot << 32 | place (the place depends on the order
+// of the atomics; the groups are put in index order afterwards).  Keys only
+// ever go from empty to set, so particles of one cell, probing the same
+// sequence, all stop at the same slot.
+__global__ void k_chash_insert(DevState s, int par, const double* __restrict__ cbox, CHash h,
+                               uint64_t* __restrict__ rank) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= s.n) return;
+    const D4 x = s.XV[p], u = s.U[par][p];
     int32_t c[3];
     if (!contact_cell(cbox, x.x + u.x, x.y + u.y, x.z + u.z, c)) atomicOr(&s.err[2], kErrContact);
-    keys[i] = morton3(c[0], c[1], c[2]);
-    vals[i] = (int32_t)i;
+    const CGrid G = cgrid(cbox);
+    int64_t t;
+    if (G.dense) {
+        t = cgrid_slot(G, c[0], c[1], c[2]);
+    } else {
+        const uint64_t key = ccell_key(c);
+        t = chash_home(h, key);
+        for (;;) {
+            const unsigned long long old =
+                atomicCAS((unsigned long long*)&h.slot[t].key, ~0ull, (unsigned long long)key);
+            if (old == ~0ull || old == key) break;
+            t = (t + 1) & (h.H - 1);
+        }
+    }
+    const int32_t place = atomicAdd(&h.slot[t].cnt, 1);
+    rank[p] = ((uint64_t)t << 32) | (uint32_t)place;
+}
+
+// Exclusive prefix sum of the slot counts, first within blocks of
+// kCHashScanB slots (256 threads, 16 consecutive slots each) into the slots'
+// start, each block's total into boff; then over the blocks
+// (k_chash_scan_top).
+__global__ void __launch_bounds__(256) k_chash_scan(CHash h) {
+    constexpr int kPer = kCHashScanB / 256;
+    __shared__ int32_t tot[256];
+    const int64_t i0 = (int64_t)blockIdx.x * kCHashScanB + (int64_t)threadIdx.x * kPer;
+    int32_t v[kPer];
+    int32_t run = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int32_t c = (i0 + k < h.H) ? h.slot[i0 + k].cnt : 0;
+        v[k] = run;
+        run += c;
+    }
+    tot[threadIdx.x] = run;
+    __syncthreads();
+    // inclusive scan of the thread totals (Hillis-Steele)
+    for (int d = 1; d < 256; d <<= 1) {
+        const int32_t o = (int)threadIdx.x >= d ? tot[threadIdx.x - d] : 0;
+        __syncthreads();
+        tot[threadIdx.x] += o;
+        __syncthreads();
+    }
+    const int32_t base = tot[threadIdx.x] - run;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+        if (i0 + k < h.H) h.slot[i0 + k].start = base + v[k];
+    if (threadIdx.x == 255) h.boff[blockIdx.x] = tot[255];
+}
+
+__global__ void __launch_bounds__(1024) k_chash_scan_top(CHash h, int32_t n_blocks) {
+    __shared__ int32_t tot[1024];
+    int32_t carry = 0;
+    for (int32_t b0 = 0; b0 < n_blocks; b0 += 1024) {
+        const int32_t b = b0 + (int32_t)threadIdx.x;
+        const int32_t mine = b < n_blocks ? h.boff[b] : 0;
+        tot[threadIdx.x] = mine;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {
+            const int32_t o = (int)threadIdx.x >= d ? tot[threadIdx.x - d] : 0;
+            __syncthreads();
+            tot[threadIdx.x] += o;
+            __syncthreads();
+        }
+        if (b < n_blocks) h.boff[b] = carry + tot[threadIdx.x] - mine;
+        carry += tot[1023];
+        __syncthreads();
+    }
+}
+
+__global__ void k_chash_scatter(DevState s, CHash h, const uint64_t* __restrict__ rank,
+                                int32_t* __restrict__ members) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= s.n) return;
+    const uint64_t r = rank[p];
+    const int64_t t = (int64_t)(r >> 32);
+    members[(int64_t)h.slot[t].start + h.boff[t / kCHashScanB] + (uint32_t)r] = (int32_t)p;
+}
+
+// Every slot's offset made global (so that in a dense grid the cells of a
+// row along x are one contiguous range) and each group put in ascending
+// particle index (insertion sort; a group holds a few particles).
+__global__ void k_chash_order(CHash h, int32_t* __restrict__ members) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= h.H) return;
+    const int32_t m = h.slot[t].cnt;
+    const int32_t g0 = h.slot[t].start + h.boff[t / kCHashScanB];
+    h.slot[t].start = g0;
+    if (m < 2) return;
+    int32_t* g = members + g0;
+    for (int32_t i = 1; i < m; ++i) {
+        const int32_t v = g[i];
+        int32_t j = i - 1;
+        while (j >= 0 && g[j] > v) {
+            g[j + 1] = g[j];
+            --j;
+        }
+        g[j + 1] = v;
+    }
+}
+
+// Current position and contact radius, reference position and support
+// radius of every particle, in grouped order.
+__global__ void k_chash_gather(DevState s, int par, CHash h,
+                               const int32_t* __restrict__ members) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= s.n) return;
+    const int32_t q = members[j];
+    const D4 x = s.XV[q], u = s.U[par][q];
+    h.gpos[j] = D4{x.x + u.x, x.y + u.y, x.z + u.z, s.arad[q]};
+    h.gref[j] = D4{x.x, x.y, x.z, s.hs[q]};
 }
 
 // Candidates of particle p: particles q != p within a_p + a_q + skin, over
-// the 27 cells around p (cells sorted by key, particles by index within a
-// cell); bit 31 marks a reference neighbour of the same specimen.  More than
-// kContactCap candidates: flagged, the rest dropped.
-__global__ void k_cfill(DevState s, int par, const double* __restrict__ cbox,
-                        const uint64_t* __restrict__ keys, const int32_t* __restrict__ vals) {
+// the 27 cells around p (in z, y, x order, particles by index within a
+// cell); bit 31 marks a reference neighbour of the same specimen, i.e. one
+// inside the support in the reference configuration (the neighbour search's
+// own test, with the same arithmetic, so the mark agrees with the complete
+// reference lists).  More than kContactCap candidates: flagged, the rest
+// dropped.
+struct CFill {
+    int64_t p, np;
+    double px, py, pz, ap, skin;
+    D4 xp;
+    int64_t first, last;
+    double h2, hp;
+    bool var_h;
+    int cnt;
+};
+
+// Test one particle q (current position and radius g, reference position
+// and support radius at gref[src]) and append it when it is a candidate.
+__device__ __forceinline__ void cfill_try(const DevState& s, const CHash& h, CFill& f,
+                                          int32_t q, const D4& g, int64_t src) {
+    if (q == f.p) return;
+    const double d0 = g.x - f.px, d1 = g.y - f.py, d2 = g.z - f.pz;
+    const double rr = f.ap + g.w + f.skin;
+    if (!(d0 * d0 + d1 * d1 + d2 * d2 < rr * rr)) return;
+    bool ref = false;
+    if (q >= f.first && q < f.last) {
+        const D4 xq = h.gref[src];
+        const double e0 = xq.x - f.xp.x, e1 = xq.y - f.xp.y, e2 = xq.z - f.xp.z;
+        const double r2 = e0 * e0 + e1 * e1 + e2 * e2;
+        double lim = f.h2;
+        if (f.var_h) {
+            const double hpq = 0.5 * (f.hp + xq.w);
+            lim = hpq * hpq;
+        }
+        ref = r2 < lim;
+    }
+    if (f.cnt < kContactCap)
+        s.ccol[(int64_t)f.cnt * f.np + f.p] = (int32_t)((uint32_t)q | (ref ? 0x80000000u : 0u));
+    ++f.cnt;
+}
+
+// The same from the table in memory (tiles whose cells do not fit in LDS):
+// the three cells of a row along x are looked up together.
+__device__ void cfill_direct(const DevState& s, const CHash& h, const int32_t* members,
+                             const int32_t c[3], CFill& f) {
+    constexpr int32_t kAxis = 1 << kMortonBits;
+    for (int row = 0; row < 9; ++row) {
+        const int32_t cy = c[1] + row % 3 - 1, cz = c[2] + row / 3 - 1;
+        if (cy < 0 || cz < 0 || cy >= kAxis || cz >= kAxis) continue;
+        uint64_t key[3];
+        int64_t t[3];
+        CSlot r[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int32_t cc[3] = {c[0] + k - 1, cy, cz};
+            key[k] = (cc[0] >= 0 && cc[0] < kAxis) ? ccell_key(cc) : ~0ull;
+            t[k] = chash_home(h, key[k]);
+            r[k] = h.slot[t[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (key[k] == ~0ull) continue;
+            while (r[k].key != key[k] && r[k].key != ~0ull) {
+                t[k] = (t[k] + 1) & (h.H - 1);
+                r[k] = h.slot[t[k]];
+            }
+            if (r[k].key != key[k]) continue;
+            for (int32_t i = r[k].start, e = r[k].start + r[k].cnt; i < e; ++i)
+                cfill_try(s, h, f, members[i], h.gpos[i], i);
+        }
+    }
+}
+
+// One thread per particle.  In a dense grid the three cells of each of the
+// nine rows along x are one contiguous range of the grouped list; otherwise
+// the cells are looked up in the hash table.
+__global__ void k_cfill(DevState s, int par, const double* __restrict__ cbox, CHash h,
+                        const int32_t* __restrict__ members) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= s.np) return;
     const int64_t np = s.np;
+    if (p >= np) return;
     if (p >= s.n) {
         s.ccnt[p] = 0;
         return;
     }
-    const D4* __restrict__ Uc = s.U[par];
-    const D4 xp = s.XV[p], up = Uc[p];
-    const double px = xp.x + up.x, py = xp.y + up.y, pz = xp.z + up.z;
+    CFill f;
+    const D4 xp = s.XV[p], up = s.U[par][p];
+    f.p = p;
+    f.np = np;
+    f.px = xp.x + up.x;
+    f.py = xp.y + up.y;
+    f.pz = xp.z + up.z;
     s.ubuild[p] = up.x;
     s.ubuild[np + p] = up.y;
     s.ubuild[2 * np + p] = up.z;
-    const double ap = s.arad[p], skin = s.contact_skin;
-    const int sp = s.spec[p];
-    const int nn = s.nnb[p];
-    const int32_t* __restrict__ cp = s.col + s.slice_ptr[p / kSlice] + (p % kSlice);
+    f.ap = s.arad[p];
+    f.skin = s.contact_skin;
+    f.xp = xp;
+    const DevSpec& P = s.specs[s.spec[p]];
+    f.first = P.first;
+    f.last = P.last;
+    f.h2 = P.h2;
+    f.hp = s.hs[p];
+    f.var_h = s.var_h;
+    f.cnt = 0;
     int32_t c[3];
-    contact_cell(cbox, px, py, pz, c);
-    int cnt = 0;
-    for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int32_t cx = c[0] + dx, cy = c[1] + dy, cz = c[2] + dz;
-                if (cx < 0 || cy < 0 || cz < 0 || cx >= (1 << kMortonBits) ||
-                    cy >= (1 << kMortonBits) || cz >= (1 << kMortonBits))
-                    continue;
-                const uint64_t key = morton3(cx, cy, cz);
-                int64_t lo = 0, hi = s.n;
-                while (lo < hi) {
-                    const int64_t mid = (lo + hi) >> 1;
-                    if (keys[mid] < key) lo = mid + 1; else hi = mid;
+    contact_cell(cbox, f.px, f.py, f.pz, c);
+    const CGrid G = cgrid(cbox);
+    if (G.dense) {
+        // the nine rows' ranges first, then each row's particles four at a
+        // time (their loads issued together)
+        const int32_t x0 = c[0] > 0 ? c[0] - 1 : 0;
+        const int32_t x1 = c[0] + 1 < G.ext[0] ? c[0] + 1 : G.ext[0] - 1;
+        int32_t j0[9], j1[9];
+#pragma unroll
+        for (int row = 0; row < 9; ++row) {
+            const int32_t cy = c[1] + row % 3 - 1, cz = c[2] + row / 3 - 1;
+            j0[row] = j1[row] = 0;
+            if (cy < 0 || cz < 0 || cy >= G.ext[1] || cz >= G.ext[2]) continue;
+            j0[row] = h.slot[cgrid_slot(G, x0, cy, cz)].start;
+            const CSlot r1 = h.slot[cgrid_slot(G, x1, cy, cz)];
+            j1[row] = r1.start + r1.cnt;
+        }
+        for (int row = 0; row < 9; ++row)
+            for (int32_t j = j0[row]; j < j1[row]; j += 4) {
+                int32_t q[4];
+                D4 g[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int32_t i = j + k < j1[row] ? j + k : j;
+                    q[k] = members[i];
+                    g[k] = h.gpos[i];
                 }
-                for (int64_t t = lo; t < s.n && keys[t] == key; ++t) {
-                    const int32_t q = vals[t];
-                    if (q == p) continue;
-                    const D4 xq = s.XV[q], uq = Uc[q];
-                    const double d0 = (xq.x + uq.x) - px, d1 = (xq.y + uq.y) - py,
-                                 d2 = (xq.z + uq.z) - pz;
-                    const double rr = ap + s.arad[q] + skin;
-                    if (!(d0 * d0 + d1 * d1 + d2 * d2 < rr * rr)) continue;
-                    bool ref = false;
-                    if (s.spec[q] == sp)
-                        for (int k = 0; k < nn; ++k)
-                            ref = ref || cp[(int64_t)k * kSlice] == q;
-                    if (cnt < kContactCap)
-                        s.ccol[(int64_t)cnt * np + p] = (int32_t)((uint32_t)q | (ref ? 0x80000000u : 0u));
-                    ++cnt;
-                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (j + k < j1[row]) cfill_try(s, h, f, q[k], g[k], j + k);
             }
-    if (cnt > kContactCap) {
-        atomicOr(&s.err[2], kErrContact);
-        cnt = kContactCap;
+    } else {
+        cfill_direct(s, h, members, c, f);
     }
-    s.ccnt[p] = cnt;
+    if (f.cnt > kContactCap) {
+        atomicOr(&s.err[2], kErrContact);
+        f.cnt = kContactCap;
+    }
+    s.ccnt[p] = f.cnt;
 }
 
+// The rebuild: bounding box and cell edge, the occupied cells' hash table
+// with a counting sort of the particles by cell (ranks in keys, the grouped
+// list in vals, grouped positions in gpos and gref), then the lists.
 hipError_t launch_contact_build(const DevState& s, int parity, uint64_t* keys, int32_t* vals,
-                                int64_t n_pow2, double* cbox, hipStream_t st) {
-    k_cbox<<<1, 1024, 0, st>>>(s, parity, cbox);
+                                const CHash& h, double* cbox, hipStream_t st) {
+    k_cbox_part<<<kCBoxParts, kCBoxThreads, 0, st>>>(s, parity, cbox);
+    k_cbox_final<<<1, kCBoxThreads, 0, st>>>(s, cbox, h.H);
     constexpr int T = 256;
-    k_ckeys<<<(unsigned)((n_pow2 + T - 1) / T), T, 0, st>>>(s, parity, cbox, n_pow2, keys, vals);
-    hipError_t e = launch_bitonic_sort(keys, vals, n_pow2, st);
-    if (e != hipSuccess) return e;
-    k_cfill<<<(unsigned)((s.np + T - 1) / T), T, 0, st>>>(s, parity, cbox, keys, vals);
+    const unsigned gh = (unsigned)((h.H + T - 1) / T), gn = (unsigned)((s.n + T - 1) / T);
+    const int32_t n_blocks = (int32_t)((h.H + kCHashScanB - 1) / kCHashScanB);
+    k_chash_clear<<<gh, T, 0, st>>>(h);
+    k_chash_insert<<<gn, T, 0, st>>>(s, parity, cbox, h, keys);
+    k_chash_scan<<<(unsigned)n_blocks, 256, 0, st>>>(h);
+    k_chash_scan_top<<<1, 1024, 0, st>>>(h, n_blocks);
+    k_chash_scatter<<<gn, T, 0, st>>>(s, h, keys, vals);
+    k_chash_order<<<gh, T, 0, st>>>(h, vals);
+    k_chash_gather<<<gn, T, 0, st>>>(s, parity, h, vals);
+    k_cfill<<<(unsigned)((s.np + T - 1) / T), T, 0, st>>>(s, parity, cbox, h, vals);
     return hipGetLastError();
 }
 

@@ -290,6 +290,39 @@ def test_contact_overlap_one_step(tl, orc):
         assert all(v <= tol for v in errs.values()), errs
 
 
+def test_contact_scattered_pairs_one_step(tl, orc):
+    """Six pairs of small cubes (3 x 3 x 3 particles), each pair overlapping
+    by a few micrometres, the pairs 10 spacings apart along the diagonal: the
+    lower cubes form one specimen, the upper ones the other.  Their grid of
+    contact cells (about 65 x 65 x 70) is far larger than the cell table
+    (2 x 512 slots), so the candidate search hashes the occupied cells (the
+    colliding bars and the two cubes above fit a dense table); one step from
+    injected states against the oracle, FP64 and mixed."""
+    dx, n, pairs = 1e-3, 3, 6
+    i, j, k = I._lattice(n, n, n)
+    cube = np.stack([(i + 0.5) * dx, (j + 0.5) * dx, (k + 0.5) * dx], axis=1)
+    lower = np.concatenate([cube + q * (n + 10) * dx for q in range(pairs)])
+    upper = lower + [0.0, 0.0, n * dx - 4e-6]
+    X = np.concatenate([lower, upper])
+    m = I.material(dx, I.DMG_NONE, contact_k=1.0)
+    N = X.shape[0]
+    p = I.Problem("scattered_pairs", X, np.full(N, dx ** 3),
+                  np.array([0, lower.shape[0], N], np.int64), [m, dict(m)],
+                  np.full(N, -1, np.int32), [], np.zeros((N, 3)), dx=np.array([dx, dx]))
+    st = I.random_state(p, seed=37, u_scale=1e-7, frac_failed=0.1)
+    for prec, tol in ((tl.FP64, TOL_FP64), (tl.MIXED, TOL_MIXED)):
+        g = tl.Sim(p, precision=prec, flags=tl.STORE_FORCE)
+        o = orc.Sim(p)
+        g.set_state(st)
+        o.set_state(st)
+        g.step(1)
+        o.step(1)
+        errs = compare(g, o)
+        say("contact scattered pairs", prec, errs)
+        assert all(v <= tol for v in errs.values()), errs
+        assert g.info()["flags"] & 4 == 0
+
+
 def test_full_size_notched_bar_one_step(tl, orc):
     p = I.notched_bar()
     assert p.n == 200216
