@@ -290,6 +290,28 @@ def test_contact_overlap_one_step(tl, orc):
         assert all(v <= tol for v in errs.values()), errs
 
 
+def test_contact_graded_one_step(tl, orc):
+    """Penalty contact on the graded bar (four spacings, pair supports
+    (h_i + h_j) / 2) from an injected state with 10 % of the particles
+    failed: intact bonded pairs feel no contact, so the candidate lists'
+    reference-neighbour mark (the neighbour search's own test, here with the
+    pair support) decides the result; one step against the oracle, FP64 and
+    mixed."""
+    p = remat(small_graded(), dict(contact_k=1.0))
+    st = I.random_state(p, seed=41, u_scale=2e-6, frac_failed=0.1)
+    for prec, tol in ((tl.FP64, TOL_FP64), (tl.MIXED, TOL_MIXED)):
+        g = tl.Sim(p, precision=prec, flags=tl.STORE_FORCE, k_cap=kcap(p))
+        o = orc.Sim(p)
+        g.set_state(st)
+        o.set_state(st)
+        g.step(1)
+        o.step(1)
+        errs = compare(g, o)
+        say("contact graded", prec, p.n, errs)
+        assert all(v <= tol for v in errs.values()), errs
+        assert g.info()["flags"] & 4 == 0
+
+
 def test_contact_scattered_pairs_one_step(tl, orc):
     """Six pairs of small cubes (3 x 3 x 3 particles), each pair overlapping
     by a few micrometres, the pairs 10 spacings apart along the diagonal: the
