@@ -2268,9 +2268,9 @@ __device__ __forceinline__ void cfill_try(const DevState& s, const CHash& h, CFi
     ++f.cnt;
 }
 
-// The same from the table in memory (tiles whose cells do not fit in LDS):
-// the three cells of a row along x are looked up together.
-__device__ void cfill_direct(const DevState& s, const CHash& h, const int32_t* members,
+// The 27 cells of a hashed grid: the three cells of a row along x are
+// looked up together.
+__device__ void cfill_hashed(const DevState& s, const CHash& h, const int32_t* members,
                              const int32_t c[3], CFill& f) {
     constexpr int32_t kAxis = 1 << kMortonBits;
     for (int row = 0; row < 9; ++row) {
@@ -2365,7 +2365,7 @@ __global__ void k_cfill(DevState s, int par, const double* __restrict__ cbox, CH
                     if (j + k < j1[row]) cfill_try(s, h, f, q[k], g[k], j + k);
             }
     } else {
-        cfill_direct(s, h, members, c, f);
+        cfill_hashed(s, h, members, c, f);
     }
     if (f.cnt > kContactCap) {
         atomicOr(&s.err[2], kErrContact);
