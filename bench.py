@@ -702,7 +702,7 @@ WORKLOADS = {"notched_bar_200k": (bench_notched_bar, 42000, 1000),
              "taylor_bar_1m_av": (bench_taylor_av, 4900, 100),
              "graded_bar_93k": (bench_graded, 4900, 100),
              "bar_collision_395k": (bench_collision, 1900, 100),
-             "gtn_plate_4m": (bench_plate, 2000, 20),
+             "gtn_plate_4m": (bench_plate, 200, 20),
              "batch_256_bars": (bench_batch, 400, 50)}
 
 
