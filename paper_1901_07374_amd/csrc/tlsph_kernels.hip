@@ -2047,9 +2047,11 @@ __global__ void __launch_bounds__(kCBoxThreads) k_cbox_final(DevState s, double*
         // own (so no particle lies beyond it), bounds the extent
         double cells = 1.0;
         for (int a = 0; a < 3; ++a) {
+            // (no finite position at all: an empty box, one cell)
             const double q = floor((red[3 + a][0] - red[a][0]) * inv);
-            const double e = q >= (double)((1 << kMortonBits) - 1) ? (double)(1 << kMortonBits)
-                                                                   : q + 1.0;
+            const double e = !(q >= 0.0) ? 1.0
+                             : q >= (double)((1 << kMortonBits) - 1) ? (double)(1 << kMortonBits)
+                                                                     : q + 1.0;
             cbox[9 + a] = e;
             cells *= e;
         }
@@ -2059,14 +2061,14 @@ __global__ void __launch_bounds__(kCBoxThreads) k_cbox_final(DevState s, double*
 
 __device__ __forceinline__ bool contact_cell(const double* cb, double x, double y, double z,
                                              int32_t c[3]) {
+    constexpr double kLast = (double)((1 << kMortonBits) - 1);
     const double xs[3] = {x, y, z};
     bool ok = true;
     for (int a = 0; a < 3; ++a) {
         const double q = floor((xs[a] - cb[a]) * cb[6]);
-        int32_t k = q < 0.0 ? 0 : (q >= (double)((1 << kMortonBits) - 1) ? (1 << kMortonBits) - 1
-                                                                          : (int32_t)q);
-        if (q >= (double)((1 << kMortonBits) - 1)) ok = false;
-        c[a] = k;
+        // (a position that is not a number lands in cell 0 and is flagged)
+        c[a] = !(q >= 0.0) ? 0 : (q >= kLast ? (1 << kMortonBits) - 1 : (int32_t)q);
+        if (!(q < kLast)) ok = false;
     }
     return ok;
 }
@@ -2116,6 +2118,10 @@ __global__ void k_chash_insert(DevState s, int par, const double* __restrict__ c
     const CGrid G = cgrid(cbox);
     int64_t t;
     if (G.dense) {
+        // every cell lies inside the extent (the extent is the cell of the
+        // largest coordinate, computed the same way); the clamp only keeps
+        // the slot inside the table whatever the input
+        for (int a = 0; a < 3; ++a) c[a] = c[a] < G.ext[a] ? c[a] : G.ext[a] - 1;
         t = cgrid_slot(G, c[0], c[1], c[2]);
     } else {
         const uint64_t key = ccell_key(c);
@@ -2336,6 +2342,7 @@ __global__ void k_cfill(DevState s, int par, const double* __restrict__ cbox, CH
     contact_cell(cbox, f.px, f.py, f.pz, c);
     const CGrid G = cgrid(cbox);
     if (G.dense) {
+        for (int a = 0; a < 3; ++a) c[a] = c[a] < G.ext[a] ? c[a] : G.ext[a] - 1;
         // the nine rows' ranges first, then each row's particles four at a
         // time (their loads issued together)
         const int32_t x0 = c[0] > 0 ? c[0] - 1 : 0;

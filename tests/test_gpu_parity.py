@@ -602,6 +602,33 @@ def test_nonfinite_state_is_latched(tl, precision):
         assert g.info()["flags"] & 1 == expect
 
 
+def test_contact_nonfinite_position_is_flagged(tl):
+    """A particle whose displacement is not a number, with penalty contact:
+    the candidate search puts it in cell 0 of the grid (dense for the
+    colliding bars, hashed for bars far apart) and flags the list (info bit
+    2); it is nobody's candidate, and the other particles' lists are those of
+    the same state without it."""
+    dx = 0.25e-3
+    close = I.bar_collision(dx=dx, R=1.0e-3, L=2e-3, gap=0.01e-3, v0=5.0)
+    far = I.Problem(close.name, close.X + np.where(np.arange(close.n)[:, None] >= close.spec_offsets[1],
+                                                  [0.2, 0.2, 0.2], [0.0, 0.0, 0.0]),
+                    close.V0, close.spec_offsets, close.materials, close.bc_group,
+                    close.bc_groups, close.v_init, close.steps, close.dx)
+    for p in (close, far):
+        g = tl.Sim(p)
+        g.step(2)
+        assert g.info()["flags"] == 0
+        u = g.get("u")
+        u[p.n // 3, 1] = np.nan
+        g.set("u", u)
+        g.step(1)
+        assert g.info()["flags"] & 4 == 4
+        v = g.get("v")
+        keep = np.isfinite(v).all(axis=1)
+        say("contact nonfinite", p.n, int((~keep).sum()))
+        assert keep.sum() > p.n // 2
+
+
 def test_newton_not_converged_is_flagged(tl, orc):
     """Algorithm 2's Newton loops and the implicit return give up at their
     iteration cap and raise info bit 1; a cap of one iteration (a specimen
