@@ -861,35 +861,55 @@ __device__ __forceinline__ ForceAcc<R> acc_xor(const ForceAcc<R>& x) {
 // particle (S = 1, 2 or 4), lane `sub` holding partials sub, sub + S, ...;
 // every S rounds identically.  All lanes of the wave must call this (the
 // partials are exchanged across lanes); lanes without a particle pass cnt = 0.
-// The first group of neighbour indices of a lane (neighbours sub, sub + S,
-// ... below kSub), loaded apart so that a kernel can issue it early.
-template <int S>
+// The neighbour indices of a lane's first G groups (neighbours sub, sub + S,
+// ... below G kSub), loaded apart so that a kernel can issue them before its
+// staging: the pair loop then runs those groups without waiting on memory.
+template <int S, int G>
 struct FirstIdx {
-    int q[kSub / S];
+    int q[G][kSub / S];
 };
-template <int S, typename IdxOf>
-__device__ __forceinline__ FirstIdx<S> first_indices(int cnt, int sub, IdxOf idx) {
-    FirstIdx<S> f;
+template <int S, int G, typename IdxOf>
+__device__ __forceinline__ FirstIdx<S, G> first_indices(int cnt, int sub, IdxOf idx) {
+    FirstIdx<S, G> f;
 #pragma unroll
-    for (int t = 0; t < kSub / S; ++t) {
-        const int k = sub + S * t;
-        f.q[t] = idx(k < cnt ? k : 0);
-    }
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int t = 0; t < kSub / S; ++t) {
+            const int k = g * kSub + sub + S * t;
+            f.q[g][t] = idx(k < cnt ? k : 0);
+        }
     return f;
 }
 
-template <typename R, int S, bool kVarH = false, typename IdxOf, typename RecOf>
+template <typename R, int S, bool kVarH = false, int G, typename IdxOf, typename RecOf>
 __device__ __forceinline__ ForceAcc<R> pair_sums(const LRecB<R>& ni, int cnt, int sub, R inv_h,
-                                                 IdxOf idx, RecOf rec, const FirstIdx<S>& first) {
+                                                 IdxOf idx, RecOf rec, const FirstIdx<S, G>& first) {
     static_assert(kSub == 4 && (S == 1 || S == 2 || S == 4), "canonical order has 4 partials");
+    static_assert(G >= 1, "at least the first group is preloaded");
     constexpr int NP = kSub / S;
     ForceAcc<R> A[NP];
-    // neighbour indices run one group of kSub ahead of the arithmetic
-    // (fetching further ahead measured no faster)
+    // the group after the preloaded ones goes out first: its latency is spent
+    // behind them (longer lists then run their indices one group of kSub
+    // ahead of the arithmetic)
     int q[NP];
 #pragma unroll
-    for (int t = 0; t < NP; ++t) q[t] = first.q[t];
-    for (int k0 = 0; k0 < cnt; k0 += kSub) {
+    for (int t = 0; t < NP; ++t) {
+        const int k = G * kSub + sub + S * t;
+        q[t] = idx(k < cnt ? k : 0);
+    }
+    // the preloaded groups, unrolled (a lane past its count is masked off)
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int k0 = g * kSub;
+        if (k0 < cnt) {
+#pragma unroll
+            for (int t = 0; t < NP; ++t) {
+                const int k = k0 + sub + S * t;
+                force_pair<R, kVarH>(ni, rec(first.q[g][t]), inv_h, A[t], k < cnt);
+            }
+        }
+    }
+    for (int k0 = G * kSub; k0 < cnt; k0 += kSub) {
         int cur[NP];
 #pragma unroll
         for (int t = 0; t < NP; ++t) {
@@ -1083,7 +1103,7 @@ k_pass_b(DevState s, int par) {
             if constexpr (kVarH) r.hs = s.hs[j];
             return r;
         },
-        first_indices<S>(cnt, sub, idx));
+        first_indices<S, 1>(cnt, sub, idx));
     // the particle's own Q is needed only now: reread it (the compiler barrier
     // keeps the load here) rather than keep it in registers through the loop
     asm volatile("" ::: "memory");
@@ -1212,6 +1232,12 @@ __host__ __device__ constexpr bool staged_finish_early() {
     return !(sizeof(R) == 4 && S == 2);
 }
 
+// Neighbour-index groups the staged force pass loads before its staging.
+template <typename R, int S>
+__host__ __device__ constexpr int staged_pre_groups() {
+    return sizeof(R) == 8 && S == 2 ? 6 : 1;
+}
+
 // Graded spacing (kVarH): the slots' support radii follow the records in LDS
 // (one double per slot).
 template <typename R, int S, bool kVarH = false>
@@ -1255,7 +1281,7 @@ __attribute__((amdgpu_waves_per_eu(staged_waves_min<R, S, kVarH>(), 8))) k_pass_
     const R inv_h = R(P.inv_h);
     const uint16_t* __restrict__ lp = s.lcol + slice0 + (ii % kSlice);
     const auto idx = [&](int k) { return (int)lp[(int64_t)k * kSlice]; };
-    const FirstIdx<S> first = first_indices<S>(cnt, sub, idx);
+    const auto first = first_indices<S, staged_pre_groups<R, S>()>(cnt, sub, idx);
     constexpr bool kEarly = staged_finish_early<R, S>();
     FinishIn fin_early;
     if constexpr (kEarly) fin_early = finish_in<kVarH>(s, ii, P);
@@ -1310,10 +1336,6 @@ struct NbrA {
     double hs;   // support radius (graded spacing only)
 };
 
-// M = sum_j V_j (1 - D_j)(v_j - v_i) (x) gradW_ij over the neighbours in
-// increasing order, in groups of kGatherA whose record loads are all issued
-// before their arithmetic (indices one group ahead).  The kernel slope enters without its
-// constant factor c / h (c = 8 / (pi h^3)), applied to the sum.
 // Artificial viscosity of one specimen as the gather uses it: pair factor
 // -Q1 c0 mu + Q2 mu^2 (Pi rho0) for approaching pairs, mu = h v_ij.X_ij /
 // (|X_ij|^2 + 0.01 h^2).
@@ -1328,70 +1350,114 @@ __device__ __forceinline__ AvPar<R> av_par(const DevSpec& P) {
                     P.av_q1 != 0.0 || P.av_q2 != 0.0};
 }
 
-// Graded spacing (kVarH): each pair has its own support h_ij = (h_i + h_j)/2
-// (h_i = hi), and the kernel's constant factor enters per pair (grad_k = 1).
-template <typename R, bool kExt, bool kVarH = false, typename IdxOf, typename RecOf>
+// The first G groups of a particle's neighbour indices (neighbours below
+// kGatherA G), loaded before the staging of the staged pass.
+constexpr int kGatherA = 4;
+template <int G>
+struct PreIdxA {
+    int q[G][kGatherA];
+};
+template <int G, typename IdxOf>
+__device__ __forceinline__ PreIdxA<G> pre_indices_a(int cnt, IdxOf idx) {
+    PreIdxA<G> p;
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int t = 0; t < kGatherA; ++t) {
+            const int k = g * kGatherA + t;
+            p.q[g][t] = idx(k < cnt ? k : 0);
+        }
+    return p;
+}
+
+// One group of kGatherA neighbours of the deformation pass's sums (group
+// start k0): record loads first, then the arithmetic.
+template <typename R, bool kExt, bool kVarH, typename RecOf>
+__device__ __forceinline__ void gather_group(const D4& xi, const D4& vi, int cnt, int k0, R inv_h,
+                                             const int (&j)[kGatherA], RecOf rec, R M[9],
+                                             const AvPar<R>& av, R AV[3], double hi) {
+    NbrA nb[kGatherA];
+#pragma unroll
+    for (int t = 0; t < kGatherA; ++t) nb[t] = rec(j[t]);
+#pragma unroll
+    for (int t = 0; t < kGatherA; ++t) {
+        // past the last neighbour 1/r = 0 makes every term an exact zero
+        const bool live = k0 + t < cnt;
+        const R dx = R(nb[t].x - xi.x), dy = R(nb[t].y - xi.y), dz = R(nb[t].z - xi.z);
+        const R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        const R ir = live ? rsqrt_pos(r2) : R(0);
+        R ih = inv_h, hpair = av.h;
+        if constexpr (kVarH) {
+            hpair = R(0.5 * (hi + nb[t].hs));
+            ih = rcp_nr(hpair);
+        }
+        const R q = r2 * ir * ih;
+        // h dW/dr / c = -6 (1 - q)^2 + 24 max(1/2 - q, 0)^2, no branch
+        const R a = R(1) - q;
+        const R b = fmax(R(0.5) - q, R(0));
+        const R sl = fma(R(24), b * b, R(-6) * (a * a));
+        R gw = sl * ir * R(nb[t].w);
+        if constexpr (kVarH) gw *= R(8.0 / M_PI) * ih * ih * ih * ih;
+        const R gx = gw * dx, gy = gw * dy, gz = gw * dz;
+        const R t0 = R(nb[t].vx - vi.x), t1 = R(nb[t].vy - vi.y), t2 = R(nb[t].vz - vi.z);
+        M[0] = fma(t0, gx, M[0]); M[1] = fma(t0, gy, M[1]); M[2] = fma(t0, gz, M[2]);
+        M[3] = fma(t1, gx, M[3]); M[4] = fma(t1, gy, M[4]); M[5] = fma(t1, gz, M[5]);
+        M[6] = fma(t2, gx, M[6]); M[7] = fma(t2, gy, M[7]); M[8] = fma(t2, gz, M[8]);
+        if constexpr (kExt) {
+            // sum_j (-Q1 c0 mu + Q2 mu^2) V_j (1 - D_j) gradW_ij over approaching pairs
+            if (av.on) {
+                const R vx = fma(t0, dx, fma(t1, dy, t2 * dz));
+                if (vx < R(0)) {
+                    const R eh2 = kVarH ? R(0.01) * hpair * hpair : av.eh2;
+                    const R mu = hpair * vx * rcp_nr(r2 + eh2);
+                    const R pi = mu * fma(av.q2, mu, -av.q1c0);
+                    AV[0] = fma(pi, gx, AV[0]);
+                    AV[1] = fma(pi, gy, AV[1]);
+                    AV[2] = fma(pi, gz, AV[2]);
+                }
+            }
+        }
+    }
+}
+
+// M = sum_j V_j (1 - D_j)(v_j - v_i) (x) gradW_ij over the neighbours in
+// increasing order, in groups of kGatherA whose record loads are all issued
+// before their arithmetic: the first G groups from preloaded indices, the
+// rest with indices one group ahead.  The kernel slope enters without its
+// constant factor c / h (c = 8 / (pi h^3)), applied to the sum.  Graded
+// spacing (kVarH): each pair has its own support h_ij = (h_i + h_j)/2 (h_i =
+// hi), and the kernel's constant factor enters per pair (grad_k = 1).
+template <typename R, bool kExt, bool kVarH = false, int G = 0, typename IdxOf, typename RecOf>
 __device__ __forceinline__ void gather_fdot(const D4& xi, const D4& vi, int cnt, R inv_h, R grad_k,
                                             IdxOf idx, RecOf rec, R M[9], const AvPar<R>& av,
-                                            R AV[3], double hi = 0.0) {
+                                            R AV[3], double hi = 0.0,
+                                            const PreIdxA<(G > 0 ? G : 1)>* pre = nullptr) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) M[q] = R(0);
     AV[0] = AV[1] = AV[2] = R(0);
-    constexpr int kGatherA = 4;
-    // the next group's indices are loaded while this group is summed
+    // the first group past the preloaded ones goes out first
     int jn[kGatherA];
 #pragma unroll
-    for (int t = 0; t < kGatherA; ++t) jn[t] = idx(t < cnt ? t : 0);
-    for (int k0 = 0; k0 < cnt; k0 += kGatherA) {
+    for (int t = 0; t < kGatherA; ++t) {
+        const int k = G * kGatherA + t;
+        jn[t] = idx(k < cnt ? k : 0);
+    }
+    if constexpr (G > 0) {
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+            if (g * kGatherA < cnt)
+                gather_group<R, kExt, kVarH>(xi, vi, cnt, g * kGatherA, inv_h, pre->q[g], rec, M,
+                                             av, AV, hi);
+    }
+    for (int k0 = G * kGatherA; k0 < cnt; k0 += kGatherA) {
         int j[kGatherA];
-        NbrA nb[kGatherA];
 #pragma unroll
         for (int t = 0; t < kGatherA; ++t) {
             j[t] = jn[t];
             const int kn = k0 + kGatherA + t;
             jn[t] = idx(kn < cnt ? kn : 0);
         }
-#pragma unroll
-        for (int t = 0; t < kGatherA; ++t) nb[t] = rec(j[t]);
-#pragma unroll
-        for (int t = 0; t < kGatherA; ++t) {
-            // past the last neighbour 1/r = 0 makes every term an exact zero
-            const bool live = k0 + t < cnt;
-            const R dx = R(nb[t].x - xi.x), dy = R(nb[t].y - xi.y), dz = R(nb[t].z - xi.z);
-            const R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-            const R ir = live ? rsqrt_pos(r2) : R(0);
-            R ih = inv_h, hpair = av.h;
-            if constexpr (kVarH) {
-                hpair = R(0.5 * (hi + nb[t].hs));
-                ih = rcp_nr(hpair);
-            }
-            const R q = r2 * ir * ih;
-            // h dW/dr / c = -6 (1 - q)^2 + 24 max(1/2 - q, 0)^2, no branch
-            const R a = R(1) - q;
-            const R b = fmax(R(0.5) - q, R(0));
-            const R sl = fma(R(24), b * b, R(-6) * (a * a));
-            R gw = sl * ir * R(nb[t].w);
-            if constexpr (kVarH) gw *= R(8.0 / M_PI) * ih * ih * ih * ih;
-            const R gx = gw * dx, gy = gw * dy, gz = gw * dz;
-            const R t0 = R(nb[t].vx - vi.x), t1 = R(nb[t].vy - vi.y), t2 = R(nb[t].vz - vi.z);
-            M[0] = fma(t0, gx, M[0]); M[1] = fma(t0, gy, M[1]); M[2] = fma(t0, gz, M[2]);
-            M[3] = fma(t1, gx, M[3]); M[4] = fma(t1, gy, M[4]); M[5] = fma(t1, gz, M[5]);
-            M[6] = fma(t2, gx, M[6]); M[7] = fma(t2, gy, M[7]); M[8] = fma(t2, gz, M[8]);
-            if constexpr (kExt) {
-                // sum_j (-Q1 c0 mu + Q2 mu^2) V_j (1 - D_j) gradW_ij over approaching pairs
-                if (av.on) {
-                    const R vx = fma(t0, dx, fma(t1, dy, t2 * dz));
-                    if (vx < R(0)) {
-                        const R eh2 = kVarH ? R(0.01) * hpair * hpair : av.eh2;
-                        const R mu = hpair * vx * rcp_nr(r2 + eh2);
-                        const R pi = mu * fma(av.q2, mu, -av.q1c0);
-                        AV[0] = fma(pi, gx, AV[0]);
-                        AV[1] = fma(pi, gy, AV[1]);
-                        AV[2] = fma(pi, gz, AV[2]);
-                    }
-                }
-            }
-        }
+        gather_group<R, kExt, kVarH>(xi, vi, cnt, k0, inv_h, j, rec, M, av, AV, hi);
     }
 #pragma unroll
     for (int q = 0; q < 9; ++q) M[q] *= grad_k;
@@ -1562,6 +1628,13 @@ k_pass_a(DevState s, int /* displacement buffer: unused here */) {
     }
 }
 
+// Neighbour-index groups the staged deformation pass loads before its
+// staging.
+template <typename R, int DM, bool kFlow>
+__host__ __device__ constexpr int staged_a_pre_groups() {
+    return 6;
+}
+
 // The same pass over the force pass's tiles: the records of the tile and its
 // halo (position, velocity, V0 (1 - D): 56 bytes) are staged in LDS once and
 // the neighbour sums read them through the 16-bit local slots.  Same
@@ -1614,6 +1687,9 @@ k_pass_a_staged(DevState s, int /* displacement buffer: unused here */) {
     const int64_t slice0 = s.slice_ptr[ii / kSlice];
     const int sp_lane = s.spec[ii];
     const uint16_t* __restrict__ lp = s.lcol_a + slice0 + (ii % kSlice);
+    const auto idx = [&](int k) { return (int)lp[(int64_t)k * kSlice]; };
+    constexpr int kPre = staged_a_pre_groups<R, DM, kFlow>();
+    const PreIdxA<kPre> pre = pre_indices_a<kPre>(cnt, idx);
     while (m0 < tot) {
         D4 x[kU], v[kU];
         double hv[kU];
@@ -1648,14 +1724,13 @@ k_pass_a_staged(DevState s, int /* displacement buffer: unused here */) {
             const int t = tx;
             const double2 a = Lxy[t], b = Lzw[t], c = Lvxy[t];
             R M9[9], AV[3];
-            gather_fdot<R, kFlow, kVarH>(D4{a.x, a.y, b.x, 0.0}, D4{c.x, c.y, Lvz[t], b.y}, cnt,
-                                         R(P.inv_h), kVarH ? R(1) : R(P.grad_k),
-                                         [&](int k) { return (int)lp[(int64_t)k * kSlice]; },
+            gather_fdot<R, kFlow, kVarH, kPre>(D4{a.x, a.y, b.x, 0.0}, D4{c.x, c.y, Lvz[t], b.y}, cnt,
+                                         R(P.inv_h), kVarH ? R(1) : R(P.grad_k), idx,
                                          [&](int m) {
                                              const double2 a = Lxy[m], b = Lzw[m], c = Lvxy[m];
                                              return NbrA{a.x, a.y, b.x, c.x, c.y, Lvz[m], b.y,
                                                          kVarH ? Lhs[m] : 0.0};
-                                         }, M9, av_par<R>(P), AV, kVarH ? Lhs[t] : 0.0);
+                                         }, M9, av_par<R>(P), AV, kVarH ? Lhs[t] : 0.0, &pre);
             pass_a_update<R, DM, kFlow>(s, i, sp, M9, b.y, AV);
             break;
         }
