@@ -864,26 +864,44 @@ __device__ __forceinline__ ForceAcc<R> acc_xor(const ForceAcc<R>& x) {
 // The neighbour indices of a lane's first G groups (neighbours sub, sub + S,
 // ... below G kSub), loaded apart so that a kernel can issue them before its
 // staging: the pair loop then runs those groups without waiting on memory.
-template <int S, int G>
+// Local slots (below 2^16, kPack) go two to a register.
+template <int S, int G, bool kPack = false>
 struct FirstIdx {
-    int q[G][kSub / S];
+    static constexpr int NP = kSub / S;
+    static constexpr int W = kPack && NP >= 2 ? NP / 2 : NP;
+    uint32_t w[G][W];
+    __device__ int at(int g, int t) const {
+        if constexpr (kPack && NP >= 2)
+            return (int)((t & 1) ? w[g][t >> 1] >> 16 : w[g][t >> 1] & 0xffffu);
+        else
+            return (int)w[g][t];
+    }
 };
-template <int S, int G, typename IdxOf>
-__device__ __forceinline__ FirstIdx<S, G> first_indices(int cnt, int sub, IdxOf idx) {
-    FirstIdx<S, G> f;
+template <int S, int G, bool kPack = false, typename IdxOf>
+__device__ __forceinline__ FirstIdx<S, G, kPack> first_indices(int cnt, int sub, IdxOf idx) {
+    FirstIdx<S, G, kPack> f;
+    constexpr int NP = kSub / S;
+    const auto at = [&](int g, int t) {
+        const int k = g * kSub + sub + S * t;
+        return (uint32_t)idx(k < cnt ? k : 0);
+    };
 #pragma unroll
-    for (int g = 0; g < G; ++g)
+    for (int g = 0; g < G; ++g) {
+        if constexpr (kPack && NP >= 2) {
 #pragma unroll
-        for (int t = 0; t < kSub / S; ++t) {
-            const int k = g * kSub + sub + S * t;
-            f.q[g][t] = idx(k < cnt ? k : 0);
+            for (int t = 0; t < NP; t += 2) f.w[g][t >> 1] = at(g, t) | (at(g, t + 1) << 16);
+        } else {
+#pragma unroll
+            for (int t = 0; t < NP; ++t) f.w[g][t] = at(g, t);
         }
+    }
     return f;
 }
 
-template <typename R, int S, bool kVarH = false, int G, typename IdxOf, typename RecOf>
+template <typename R, int S, bool kVarH = false, int G, bool kPack, typename IdxOf, typename RecOf>
 __device__ __forceinline__ ForceAcc<R> pair_sums(const LRecB<R>& ni, int cnt, int sub, R inv_h,
-                                                 IdxOf idx, RecOf rec, const FirstIdx<S, G>& first) {
+                                                 IdxOf idx, RecOf rec,
+                                                 const FirstIdx<S, G, kPack>& first) {
     static_assert(kSub == 4 && (S == 1 || S == 2 || S == 4), "canonical order has 4 partials");
     static_assert(G >= 1, "at least the first group is preloaded");
     constexpr int NP = kSub / S;
@@ -905,7 +923,7 @@ __device__ __forceinline__ ForceAcc<R> pair_sums(const LRecB<R>& ni, int cnt, in
 #pragma unroll
             for (int t = 0; t < NP; ++t) {
                 const int k = k0 + sub + S * t;
-                force_pair<R, kVarH>(ni, rec(first.q[g][t]), inv_h, A[t], k < cnt);
+                force_pair<R, kVarH>(ni, rec(first.at(g, t)), inv_h, A[t], k < cnt);
             }
         }
     }
@@ -1235,7 +1253,7 @@ __host__ __device__ constexpr bool staged_finish_early() {
 // Neighbour-index groups the staged force pass loads before its staging.
 template <typename R, int S>
 __host__ __device__ constexpr int staged_pre_groups() {
-    return sizeof(R) == 8 && S == 2 ? 6 : 1;
+    return S == 2 ? (sizeof(R) == 8 ? 6 : 4) : 1;
 }
 
 // Graded spacing (kVarH): the slots' support radii follow the records in LDS
@@ -1281,10 +1299,11 @@ __attribute__((amdgpu_waves_per_eu(staged_waves_min<R, S, kVarH>(), 8))) k_pass_
     const R inv_h = R(P.inv_h);
     const uint16_t* __restrict__ lp = s.lcol + slice0 + (ii % kSlice);
     const auto idx = [&](int k) { return (int)lp[(int64_t)k * kSlice]; };
-    const auto first = first_indices<S, staged_pre_groups<R, S>()>(cnt, sub, idx);
+    const auto first = first_indices<S, staged_pre_groups<R, S>(), true>(cnt, sub, idx);
     constexpr bool kEarly = staged_finish_early<R, S>();
     FinishIn fin_early;
     if constexpr (kEarly) fin_early = finish_in<kVarH>(s, ii, P);
+    const bool fz = frozen(s, sp);
     while (m0 < tot) {
         const int64_t l0 = g0 < s.n ? g0 : start, l1 = g1 < s.n ? g1 : start;
         const LRecB<R> r0 = make_recb<R>(XV[l0], GQ[l0], GH[l0], Uc[l0]);
@@ -1319,7 +1338,7 @@ __attribute__((amdgpu_waves_per_eu(staged_waves_min<R, S, kVarH>(), 8))) k_pass_
     // barrier above, so a compiler barrier suffices: waves go on to their
     // finish as their own sums end)
     asm volatile("" ::: "memory");
-    if (in && sub == 0 && !frozen(s, sp))
+    if (in && sub == 0 && !fz)
         force_finish<R>(s, i, par, P, sp, LdsB<R>::get(L, M, pl), A,
                         kEarly ? fin_early : finish_in<kVarH>(s, i, P));
 }
@@ -1351,11 +1370,15 @@ __device__ __forceinline__ AvPar<R> av_par(const DevSpec& P) {
 }
 
 // The first G groups of a particle's neighbour indices (neighbours below
-// kGatherA G), loaded before the staging of the staged pass.
+// kGatherA G), loaded before the staging of the staged pass; its local slots
+// are below 2^16, two to a register.
 constexpr int kGatherA = 4;
 template <int G>
 struct PreIdxA {
-    int q[G][kGatherA];
+    uint32_t w[G][kGatherA / 2];
+    __device__ int at(int g, int t) const {
+        return (int)((t & 1) ? w[g][t >> 1] >> 16 : w[g][t >> 1] & 0xffffu);
+    }
 };
 template <int G, typename IdxOf>
 __device__ __forceinline__ PreIdxA<G> pre_indices_a(int cnt, IdxOf idx) {
@@ -1363,9 +1386,10 @@ __device__ __forceinline__ PreIdxA<G> pre_indices_a(int cnt, IdxOf idx) {
 #pragma unroll
     for (int g = 0; g < G; ++g)
 #pragma unroll
-        for (int t = 0; t < kGatherA; ++t) {
+        for (int t = 0; t < kGatherA; t += 2) {
             const int k = g * kGatherA + t;
-            p.q[g][t] = idx(k < cnt ? k : 0);
+            p.w[g][t >> 1] = (uint32_t)idx(k < cnt ? k : 0) |
+                             ((uint32_t)idx(k + 1 < cnt ? k + 1 : 0) << 16);
         }
     return p;
 }
@@ -1445,9 +1469,13 @@ __device__ __forceinline__ void gather_fdot(const D4& xi, const D4& vi, int cnt,
     if constexpr (G > 0) {
 #pragma unroll
         for (int g = 0; g < G; ++g)
-            if (g * kGatherA < cnt)
-                gather_group<R, kExt, kVarH>(xi, vi, cnt, g * kGatherA, inv_h, pre->q[g], rec, M,
-                                             av, AV, hi);
+            if (g * kGatherA < cnt) {
+                int j[kGatherA];
+#pragma unroll
+                for (int t = 0; t < kGatherA; ++t) j[t] = pre->at(g, t);
+                gather_group<R, kExt, kVarH>(xi, vi, cnt, g * kGatherA, inv_h, j, rec, M, av, AV,
+                                             hi);
+            }
     }
     for (int k0 = G * kGatherA; k0 < cnt; k0 += kGatherA) {
         int j[kGatherA];
@@ -1468,21 +1496,35 @@ __device__ __forceinline__ void gather_fdot(const D4& xi, const D4& vi, int cnt,
 
 // The rest of the deformation pass for particle i (specimen sp) given M:
 // dF/dt = M L_i^-1, the constitutive update, Q_i = P_i L_i^-T, stores.
+// The first input of the particle's update, L^-1: the staged pass loads it
+// before its neighbour sums, which then hide its latency (loading H^n and
+// sigma^n there too would spill registers in the neighbour sums).
+template <typename R>
+struct UpdIn {
+    R Li[9];
+};
+template <typename R>
+__device__ __forceinline__ UpdIn<R> load_upd_in(const DevState& s, int64_t i) {
+    const int64_t np = s.np;
+    UpdIn<R> u;
+    if constexpr (std::is_same<R, float>::value) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) u.Li[k] = s.Linv32[k * np + i];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) u.Li[k] = s.Linv[k * np + i];
+    }
+    return u;
+}
+
 template <typename R, int DM, bool kFlow>
 __device__ __forceinline__ void pass_a_update(const DevState& s, int64_t i, int sp, const R M[9],
-                                              double wi, const R AV[3]) {
+                                              double wi, const R AV[3], const UpdIn<R>& in) {
     const int64_t np = s.np;
     const DevSpec& P = s.specs[sp];
     R Li[9];
-    if constexpr (std::is_same<R, float>::value) {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) Li[k] = s.Linv32[k * np + i];
-    } else {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) Li[k] = s.Linv[k * np + i];
-    }
     R Fd[9];
-    mm33(M, Li, Fd);
+    mm33(M, in.Li, Fd);
     GQRec<R>* __restrict__ GQ = gq_of<R>(s);
     GHRec<R>* __restrict__ GH = gh_of<R>(s);
     R Hn[9], sn[6];
@@ -1622,7 +1664,7 @@ k_pass_a(DevState s, int /* displacement buffer: unused here */) {
                                              return NbrA{x.x, x.y, x.z, v.x, v.y, v.z, v.w,
                                                          kVarH ? s.hs[j] : 0.0};
                                          }, M, av_par<R>(P), AV, kVarH ? s.hs[i] : 0.0);
-            pass_a_update<R, DM, kFlow>(s, i, sp, M, vi.w, AV);
+            pass_a_update<R, DM, kFlow>(s, i, sp, M, vi.w, AV, load_upd_in<R>(s, i));
             break;
         }
     }
@@ -1690,6 +1732,14 @@ k_pass_a_staged(DevState s, int /* displacement buffer: unused here */) {
     const auto idx = [&](int k) { return (int)lp[(int64_t)k * kSlice]; };
     constexpr int kPre = staged_a_pre_groups<R, DM, kFlow>();
     const PreIdxA<kPre> pre = pre_indices_a<kPre>(cnt, idx);
+    // whether the specimen runs and (FP64: the mixed form has no registers to
+    // spare for them) what the neighbour sums need of it: also loaded before
+    // the staging
+    constexpr bool kEarlyP = sizeof(R) == 8;
+    const DevSpec& Pl = s.specs[sp_lane];
+    const R inv_h_l = R(Pl.inv_h), grad_k_l = kVarH ? R(1) : R(Pl.grad_k);
+    const AvPar<R> av_l = av_par<R>(Pl);
+    const bool fz = frozen(s, sp_lane);
     while (m0 < tot) {
         D4 x[kU], v[kU];
         double hv[kU];
@@ -1716,22 +1766,26 @@ k_pass_a_staged(DevState s, int /* displacement buffer: unused here */) {
         for (int u = 0; u < kU; ++u) g[u] = slot_particle(m0 + u * T, T, tot, start, s.n, hl);
     }
     __syncthreads();
-    if (!in || frozen(s, sp_lane)) return;
+    if (!in || fz) return;
+    const UpdIn<R> upd = load_upd_in<R>(s, i);
     for (;;) {
         const int sp = __builtin_amdgcn_readfirstlane(sp_lane);
         if (sp == sp_lane) {
             const DevSpec& P = s.specs[sp];
+            const R inv_h = kEarlyP ? inv_h_l : R(P.inv_h);
+            const R grad_k = kEarlyP ? grad_k_l : kVarH ? R(1) : R(P.grad_k);
+            const AvPar<R> av = kEarlyP ? av_l : av_par<R>(P);
             const int t = tx;
             const double2 a = Lxy[t], b = Lzw[t], c = Lvxy[t];
             R M9[9], AV[3];
-            gather_fdot<R, kFlow, kVarH, kPre>(D4{a.x, a.y, b.x, 0.0}, D4{c.x, c.y, Lvz[t], b.y}, cnt,
-                                         R(P.inv_h), kVarH ? R(1) : R(P.grad_k), idx,
-                                         [&](int m) {
-                                             const double2 a = Lxy[m], b = Lzw[m], c = Lvxy[m];
-                                             return NbrA{a.x, a.y, b.x, c.x, c.y, Lvz[m], b.y,
-                                                         kVarH ? Lhs[m] : 0.0};
-                                         }, M9, av_par<R>(P), AV, kVarH ? Lhs[t] : 0.0, &pre);
-            pass_a_update<R, DM, kFlow>(s, i, sp, M9, b.y, AV);
+            gather_fdot<R, kFlow, kVarH, kPre>(
+                D4{a.x, a.y, b.x, 0.0}, D4{c.x, c.y, Lvz[t], b.y}, cnt, inv_h, grad_k, idx,
+                [&](int m) {
+                    const double2 a = Lxy[m], b = Lzw[m], c = Lvxy[m];
+                    return NbrA{a.x, a.y, b.x, c.x, c.y, Lvz[m], b.y, kVarH ? Lhs[m] : 0.0};
+                },
+                M9, av, AV, kVarH ? Lhs[t] : 0.0, &pre);
+            pass_a_update<R, DM, kFlow>(s, i, sp, M9, b.y, AV, upd);
             break;
         }
     }
