@@ -13,6 +13,10 @@ constexpr int kSub = 4;            // partial sums per particle in the force pas
 constexpr int kNDiag = 8;          // doubles per diagnostics record
 constexpr int kDiagChunk = 2048;   // particles per partial sum of the diagnostics
 constexpr int kTile = 256;         // most particles per workgroup tile of the LDS-staged pass
+// Halo-row entries past a tile's halo count that hold n (no particle): a
+// staging round reads at most 1024 slots (two per thread of a 512-thread
+// force pass, four per thread of a 256-particle deformation tile).
+constexpr int kHaloPad = 1024;
 constexpr int kHaloSortMax = 8192; // tile entries sorted in LDS at build (kTile * k_cap)
 constexpr int kContactCap = 32;    // contact candidates per particle
 constexpr int kCBoxParts = 512;    // workgroups of the contact bounding-box reduction

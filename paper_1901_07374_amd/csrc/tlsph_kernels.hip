@@ -550,6 +550,9 @@ __global__ void __launch_bounds__(256) k_halo(DevState s, int k_cap, int E,
     __syncthreads();
     const int H = part[256];
     for (int h = tid; h < H; h += 256) halo[t * s.halo_cap + h] = hl[h];
+    // past the count, n (no particle) for as far as a staging round reads
+    const int pad_end = H + kHaloPad < s.halo_cap ? H + kHaloPad : s.halo_cap;
+    for (int h = H + tid; h < pad_end; h += 256) halo[t * s.halo_cap + h] = (int32_t)s.n;
     if (tid == 0) {
         halo_cnt[t] = H;
         atomicMax(&s.err[4], H);
@@ -675,6 +678,16 @@ __device__ __forceinline__ int64_t work_tile(const int32_t* list, const int32_t*
 // A specimen that run control has stopped keeps its state.
 __device__ __forceinline__ bool frozen(const DevState& s, int sp) {
     return s.done != nullptr && s.done[sp] != kRunning;
+}
+// The same test in two parts, so that a kernel can load the flag early and
+// wait for it only where it decides: the word is loaded whether run control
+// is on or not (then from the specimen index array, a valid address: a
+// specimen sp < n has a particle sp).
+__device__ __forceinline__ int32_t run_word(const DevState& s, int sp) {
+    return (s.done != nullptr ? s.done : s.spec)[sp];
+}
+__device__ __forceinline__ bool frozen_word(const DevState& s, int32_t w) {
+    return s.done != nullptr && w != kRunning;
 }
 
 template <typename R>
@@ -868,32 +881,30 @@ __device__ __forceinline__ ForceAcc<R> acc_xor(const ForceAcc<R>& x) {
 template <int S, int G, bool kPack = false>
 struct FirstIdx {
     static constexpr int NP = kSub / S;
-    static constexpr int W = kPack && NP >= 2 ? NP / 2 : NP;
-    uint32_t w[G][W];
+    static constexpr int E = G * NP;   // entries, group-major
+    uint32_t w[kPack ? (E + 1) / 2 : E];
     __device__ int at(int g, int t) const {
-        if constexpr (kPack && NP >= 2)
-            return (int)((t & 1) ? w[g][t >> 1] >> 16 : w[g][t >> 1] & 0xffffu);
+        const int e = g * NP + t;
+        if constexpr (kPack)
+            return (int)((e & 1) ? w[e >> 1] >> 16 : w[e >> 1] & 0xffffu);
         else
-            return (int)w[g][t];
+            return (int)w[e];
     }
 };
 template <int S, int G, bool kPack = false, typename IdxOf>
 __device__ __forceinline__ FirstIdx<S, G, kPack> first_indices(int cnt, int sub, IdxOf idx) {
-    FirstIdx<S, G, kPack> f;
-    constexpr int NP = kSub / S;
-    const auto at = [&](int g, int t) {
-        const int k = g * kSub + sub + S * t;
+    using FI = FirstIdx<S, G, kPack>;
+    FI f;
+    const auto at = [&](int e) {
+        const int k = (e / FI::NP) * kSub + sub + S * (e % FI::NP);
         return (uint32_t)idx(k < cnt ? k : 0);
     };
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-        if constexpr (kPack && NP >= 2) {
-#pragma unroll
-            for (int t = 0; t < NP; t += 2) f.w[g][t >> 1] = at(g, t) | (at(g, t + 1) << 16);
-        } else {
-#pragma unroll
-            for (int t = 0; t < NP; ++t) f.w[g][t] = at(g, t);
-        }
+    for (int e = 0; e < FI::E; e += kPack ? 2 : 1) {
+        if constexpr (kPack)
+            f.w[e >> 1] = at(e) | (e + 1 < FI::E ? at(e + 1) << 16 : 0u);
+        else
+            f.w[e] = at(e);
     }
     return f;
 }
@@ -1129,17 +1140,19 @@ k_pass_b(DevState s, int par) {
         force_finish<R>(s, i, par, P, sp, make_recb<R>(XV[i], GQ[i], GH[i], Uc[i]), A, fin);
 }
 
-// Particle of slot m of a tile's LDS image (the tile's T particles from
-// `start`, then its halo list hl): n for slots past the image.  The halo entry
-// is loaded unconditionally, at an index inside the tile's list, and blended
-// in with masks: a select on a loaded value may be turned into a branch, whose
-// join waits for the load, and the staging wants all its index loads in
-// flight together.
-__device__ __forceinline__ int64_t slot_particle(int m, int T, int tot, int64_t start, int64_t n,
+// Particle of slot m of a tile's LDS image: the tile's T particles from
+// `start`, then its halo row hl (capacity cap), which holds n (no particle)
+// for kHaloPad entries past the tile's halo count; n for slots past the
+// image.  The row entry is loaded unconditionally, at an index inside the
+// row, and blended in with masks, so that the staging's loads need neither
+// the halo count nor a branch on a loaded value (which may be turned into a
+// branch whose join waits for the load): the first round of a staging goes
+// out before the count has arrived.
+__device__ __forceinline__ int64_t slot_particle(int m, int T, int cap, int64_t start, int64_t n,
                                                  const int32_t* __restrict__ hl) {
     const int h = m - T;
-    const int64_t hv = hl[h >= 0 && m < tot ? h : 0];
-    const int64_t in_tile = -(int64_t)(h < 0), past = -(int64_t)(m >= tot);
+    const int64_t hv = hl[h >= 0 && h < cap ? h : 0];
+    const int64_t in_tile = -(int64_t)(h < 0), past = -(int64_t)(h >= cap);
     const int64_t g = ((start + m) & in_tile) | (hv & ~in_tile);
     return (n & past) | (g & ~past);
 }
@@ -1253,7 +1266,7 @@ __host__ __device__ constexpr bool staged_finish_early() {
 // Neighbour-index groups the staged force pass loads before its staging.
 template <typename R, int S>
 __host__ __device__ constexpr int staged_pre_groups() {
-    return S == 2 ? (sizeof(R) == 8 ? 6 : 4) : 1;
+    return S == 1 ? 1 : sizeof(R) == 8 ? (S == 2 ? 6 : 2) : S == 2 ? 4 : 1;
 }
 
 // Graded spacing (kVarH): the slots' support radii follow the records in LDS
@@ -1270,7 +1283,6 @@ __attribute__((amdgpu_waves_per_eu(staged_waves_min<R, S, kVarH>(), 8))) k_pass_
     const int64_t tile = work_tile(s.tile_list, s.run_count, 1, 0, gridDim.x);
     if (tile < 0) return;
     const int64_t start = tile * T;
-    const int tot = T + s.halo_cnt[tile];
     const int32_t* __restrict__ hl = s.halo + tile * (int64_t)s.halo_cap;
     const D4* __restrict__ XV = s.XV;
     const D4* __restrict__ Uc = s.U[par];
@@ -1281,9 +1293,11 @@ __attribute__((amdgpu_waves_per_eu(staged_waves_min<R, S, kVarH>(), 8))) k_pass_
     // indices are loaded before anything else; the particle's own scalars, its
     // first neighbour slots and what its finish needs follow, so that their
     // latencies overlap those of the staging (two memory latencies before the
-    // barrier rather than four).  Slots past the image, and past the particle
-    // count (last tile), load the tile's first record and store nothing.
-    const auto particle_of = [&](int m) { return slot_particle(m, T, tot, start, s.n, hl); };
+    // barrier).  The first round needs no halo count (slots past the image
+    // hold n), which is read after it.  Slots past the image, and past the
+    // particle count (last tile), load the tile's first record and store
+    // nothing.
+    const auto particle_of = [&](int m) { return slot_particle(m, T, s.halo_cap, start, s.n, hl); };
     int m0 = threadIdx.x;
     int64_t g0 = particle_of(m0), g1 = particle_of(m0 + B);
     const int pl = threadIdx.x / S;
@@ -1303,8 +1317,7 @@ __attribute__((amdgpu_waves_per_eu(staged_waves_min<R, S, kVarH>(), 8))) k_pass_
     constexpr bool kEarly = staged_finish_early<R, S>();
     FinishIn fin_early;
     if constexpr (kEarly) fin_early = finish_in<kVarH>(s, ii, P);
-    const bool fz = frozen(s, sp);
-    while (m0 < tot) {
+    const auto stage = [&](int m0, int64_t g0, int64_t g1) {
         const int64_t l0 = g0 < s.n ? g0 : start, l1 = g1 < s.n ? g1 : start;
         const LRecB<R> r0 = make_recb<R>(XV[l0], GQ[l0], GH[l0], Uc[l0]);
         const LRecB<R> r1 = make_recb<R>(XV[l1], GQ[l1], GH[l1], Uc[l1]);
@@ -1321,9 +1334,20 @@ __attribute__((amdgpu_waves_per_eu(staged_waves_min<R, S, kVarH>(), 8))) k_pass_
             LdsB<R>::put(L, M, m0 + B, r1);
             if constexpr (kVarH) Lhs[m0 + B] = h1;
         }
-        m0 += 2 * B;
-        g0 = particle_of(m0);
-        g1 = particle_of(m0 + B);
+    };
+    if constexpr (sizeof(R) == 8) {
+        stage(m0, g0, g1);
+        const int tot = T + s.halo_cnt[tile];
+        for (m0 += 2 * B; m0 < tot; m0 += 2 * B) stage(m0, particle_of(m0), particle_of(m0 + B));
+    } else {
+        // (the mixed form: a plain loop, whose registers fit four waves per
+        // SIMD with the preloaded slots)
+        const int tot = T + s.halo_cnt[tile];
+        for (; m0 < tot; m0 += 2 * B) {
+            stage(m0, g0, g1);
+            g0 = particle_of(m0 + 2 * B);
+            g1 = particle_of(m0 + 3 * B);
+        }
     }
     __syncthreads();
     const auto rec = [&](int m) {
@@ -1338,7 +1362,7 @@ __attribute__((amdgpu_waves_per_eu(staged_waves_min<R, S, kVarH>(), 8))) k_pass_
     // barrier above, so a compiler barrier suffices: waves go on to their
     // finish as their own sums end)
     asm volatile("" ::: "memory");
-    if (in && sub == 0 && !fz)
+    if (in && sub == 0 && !frozen(s, sp))
         force_finish<R>(s, i, par, P, sp, LdsB<R>::get(L, M, pl), A,
                         kEarly ? fin_early : finish_in<kVarH>(s, i, P));
 }
@@ -1674,7 +1698,7 @@ k_pass_a(DevState s, int /* displacement buffer: unused here */) {
 // staging.
 template <typename R, int DM, bool kFlow>
 __host__ __device__ constexpr int staged_a_pre_groups() {
-    return 6;
+    return sizeof(R) == 8 ? 6 : 3;
 }
 
 // The same pass over the force pass's tiles: the records of the tile and its
@@ -1708,20 +1732,20 @@ k_pass_a_staged(DevState s, int /* displacement buffer: unused here */) {
     double* __restrict__ Lvz = reinterpret_cast<double*>(reinterpret_cast<double2*>(lds_a) + 3 * GM) + base;
     double* __restrict__ Lhs = reinterpret_cast<double*>(reinterpret_cast<double2*>(lds_a) + 3 * GM) + GM + base;
     const int64_t start = tl * T;
-    const int tot = tile < 0 ? 0 : T + s.halo_cnt_a[tl];
     const int32_t* __restrict__ hl = s.halo_a + tl * (int64_t)s.halo_cap_a;
     const D4* __restrict__ XV = s.XV;
     const D4* __restrict__ VW = s.VW;
     // Up to four slots per thread per round: index loads, record loads, LDS
     // stores (two memory latencies a round).  The first round's index loads
     // go out before the particle's own scalars, whose latency then overlaps
-    // them.  Slots past the image, and past the particle count (last tile),
-    // load the tile's first record and store nothing.
+    // them; it needs no halo count (slots past the image hold n), which is
+    // read after it.  Slots past the image, and past the particle count (last
+    // tile), load the tile's first record and store nothing.
     constexpr int kU = 4;
     int m0 = tx;
     int64_t g[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) g[u] = slot_particle(m0 + u * T, T, tot, start, s.n, hl);
+    for (int u = 0; u < kU; ++u) g[u] = slot_particle(m0 + u * T, T, s.halo_cap_a, start, s.n, hl);
     const int64_t i = start + tx;
     const bool in = tile >= 0 && i < s.n;
     const int64_t ii = in ? i : start;
@@ -1739,8 +1763,8 @@ k_pass_a_staged(DevState s, int /* displacement buffer: unused here */) {
     const DevSpec& Pl = s.specs[sp_lane];
     const R inv_h_l = R(Pl.inv_h), grad_k_l = kVarH ? R(1) : R(Pl.grad_k);
     const AvPar<R> av_l = av_par<R>(Pl);
-    const bool fz = frozen(s, sp_lane);
-    while (m0 < tot) {
+    const int32_t run_w = run_word(s, sp_lane);
+    const auto stage = [&](int m0, const int64_t (&g)[kU]) {
         D4 x[kU], v[kU];
         double hv[kU];
 #pragma unroll
@@ -1761,12 +1785,18 @@ k_pass_a_staged(DevState s, int /* displacement buffer: unused here */) {
                 if constexpr (kVarH) Lhs[m] = hv[u];
             }
         }
-        m0 += kU * T;
+    };
+    // (a part without a tile stages the first round of tile 0 into its own
+    // image, which nothing reads: no branch holds the first round's loads back)
+    stage(m0, g);
+    const int tot = tile < 0 ? 0 : T + s.halo_cnt_a[tl];
+    for (m0 += kU * T; m0 < tot; m0 += kU * T) {
 #pragma unroll
-        for (int u = 0; u < kU; ++u) g[u] = slot_particle(m0 + u * T, T, tot, start, s.n, hl);
+        for (int u = 0; u < kU; ++u) g[u] = slot_particle(m0 + u * T, T, s.halo_cap_a, start, s.n, hl);
+        stage(m0, g);
     }
     __syncthreads();
-    if (!in || fz) return;
+    if (!in || frozen_word(s, run_w)) return;
     const UpdIn<R> upd = load_upd_in<R>(s, i);
     for (;;) {
         const int sp = __builtin_amdgcn_readfirstlane(sp_lane);
