@@ -1111,7 +1111,7 @@ static tlsph_status autotune_all(tlsph_ctx* c, hipStream_t stream) {
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
-    const int reps = 5;
+    const int reps = 10;   // launches timed per candidate (their spread is about 2 %)
     auto timed = [&](auto&& launch, float* ms) -> tlsph_status {
         // every candidate starts from the saved state
         HIPCHK(c, hipMemcpyAsync(state, backup, L.backup_bytes, hipMemcpyDeviceToDevice, stream));
