@@ -219,7 +219,7 @@ tlsph_status tlsph_create(int64_t n, int32_t n_spec, const int64_t *spec_offsets
  * X (dev, double[3][n]) reference positions, V0 (dev, double[n]) reference
  * volumes, bc_group (dev, int32[n], -1 = free, else < n_bc).  They are copied.
  * Builds S_i = { j != i in the same specimen : |X_j - X_i| < h } on the GPU
- * (particles reordered along a Morton curve internally), the correction
+ * (particles reordered along a Hilbert curve internally), the correction
  * matrices L_i (eq. correction_matrix) and their inverses in double, and the
  * initial state: u = 0, v = 0, F = I, stress and accumulators 0, f = f0,
  * D = q1 f*(f0) under GTN (else 0), Q = 0, time 0.  Synchronises the stream

@@ -7,8 +7,8 @@
 namespace tlsph {
 
 constexpr int kSlice = 64;          // particles per slice of the sliced neighbour layout
-constexpr int kMortonBits = 14;     // cells per axis < 2^14
-constexpr int kSpecShift = 3 * kMortonBits;
+constexpr int kCellBits = 14;     // cells per axis < 2^14
+constexpr int kSpecShift = 3 * kCellBits;
 constexpr int kSub = 4;            // partial sums per particle in the force pass (canonical order)
 constexpr int kNDiag = 8;          // doubles per diagnostics record
 constexpr int kDiagChunk = 2048;   // particles per partial sum of the diagnostics
@@ -107,7 +107,7 @@ struct alignas(2 * sizeof(R)) GHRec {
     R pad;
 };
 
-// Device pointers of one context.  Per-particle data is in Morton order;
+// Device pointers of one context.  Per-particle data is in Hilbert order;
 // SoA fields have stride np (a multiple of kSlice), component c of particle
 // i at [c * np + i]; AoS records are indexed by particle.
 struct DevState {

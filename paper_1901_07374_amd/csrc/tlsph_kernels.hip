@@ -1,12 +1,13 @@
 // HIP kernels of the TLSPH damage step for gfx950 (MI355X).
 //
-// Data layout (all per-particle arrays in Morton order, stride np, a multiple
-// of 64): field component c of particle i at [c * np + i].  The neighbour
-// list is "sliced": the 64 particles of slice s = i / 64 keep their k-th
-// neighbour at col[slice_ptr[s] + 64 k + (i % 64)], so the 64 lanes of a
-// wavefront read 64 consecutive indices per neighbour step.  One lane owns
-// one particle and sums its neighbours in a fixed order: no floating-point
-// atomics anywhere, results independent of the launch shape.
+// Data layout (all per-particle arrays in Hilbert order of their cells,
+// stride np, a multiple of 64): field component c of particle i at
+// [c * np + i].  The neighbour list is "sliced": the 64 particles of slice
+// s = i / 64 keep their k-th neighbour at col[slice_ptr[s] + 64 k + (i % 64)],
+// so the 64 lanes of a wavefront read 64 consecutive indices per neighbour
+// step.  One lane owns one particle and sums its neighbours in a fixed order:
+// no floating-point atomics anywhere, results independent of the launch
+// shape.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -22,13 +23,39 @@ namespace tlsph {
 // neighbour-list build (Sec. 2: S_i fixed in the reference configuration)
 // ===========================================================================
 
-__device__ __forceinline__ uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
-    uint64_t m = 0;
-    for (int b = 0; b < kMortonBits; ++b) {
-        m |= (uint64_t((x >> b) & 1u) << (3 * b)) | (uint64_t((y >> b) & 1u) << (3 * b + 1)) |
-             (uint64_t((z >> b) & 1u) << (3 * b + 2));
+// Position of cell (x, y, z) along a three-dimensional Hilbert curve over
+// 2^kCellBits cells per axis: the coordinates are turned into the curve's
+// index in transposed form (Skilling's method: undo the excess rotations and
+// reflections from the top bit down, then Gray-decode), whose bits are then
+// interleaved, highest level first.  Consecutive keys are face-adjacent
+// cells, so a run of keys (a tile) is a compact region; a run of Morton keys
+// may jump across the domain, which puts more of a tile's neighbours outside
+// it.
+__device__ __forceinline__ uint64_t cell_key(uint32_t x, uint32_t y, uint32_t z) {
+    uint32_t X[3] = {x, y, z};
+    for (uint32_t Q = 1u << (kCellBits - 1); Q > 1; Q >>= 1) {
+        const uint32_t P = Q - 1;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            if (X[i] & Q) {
+                X[0] ^= P;
+            } else {
+                const uint32_t t = (X[0] ^ X[i]) & P;
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
     }
-    return m;
+    X[1] ^= X[0];
+    X[2] ^= X[1];
+    uint32_t t = 0;
+    for (uint32_t Q = 1u << (kCellBits - 1); Q > 1; Q >>= 1)
+        if (X[2] & Q) t ^= Q - 1;
+    uint64_t key = 0;
+    for (int b = kCellBits - 1; b >= 0; --b)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) key = (key << 1) | (((X[i] ^ t) >> b) & 1u);
+    return key;
 }
 
 // Per-specimen record of 8 doubles (caller order, particles contiguous per
@@ -109,9 +136,9 @@ __global__ void k_keys(const double* __restrict__ X, int64_t n, int64_t n_pow2,
     const int s = spec_of(off, n_spec, i);
     int32_t c[3];
     cell_of(bbox + kBBox * s, X[i], X[n + i], X[2 * n + i], c);
-    if (c[0] >= (1 << kMortonBits) || c[1] >= (1 << kMortonBits) || c[2] >= (1 << kMortonBits))
+    if (c[0] >= (1 << kCellBits) || c[1] >= (1 << kCellBits) || c[2] >= (1 << kCellBits))
         atomicOr(&err[3], 1);
-    keys[i] = ((uint64_t)s << kSpecShift) | morton3(c[0], c[1], c[2]);
+    keys[i] = ((uint64_t)s << kSpecShift) | cell_key(c[0], c[1], c[2]);
     vals[i] = (int32_t)i;
 }
 
@@ -264,10 +291,10 @@ __device__ __forceinline__ int for_neighbours(const DevState& s, const uint64_t*
         for (int dy = -1; dy <= 1; ++dy)
             for (int dx = -1; dx <= 1; ++dx) {
                 const int32_t cx = c[0] + dx, cy = c[1] + dy, cz = c[2] + dz;
-                if (cx < 0 || cy < 0 || cz < 0 || cx >= (1 << kMortonBits) ||
-                    cy >= (1 << kMortonBits) || cz >= (1 << kMortonBits))
+                if (cx < 0 || cy < 0 || cz < 0 || cx >= (1 << kCellBits) ||
+                    cy >= (1 << kCellBits) || cz >= (1 << kCellBits))
                     continue;
-                const uint64_t key = ((uint64_t)sp << kSpecShift) | morton3(cx, cy, cz);
+                const uint64_t key = ((uint64_t)sp << kSpecShift) | cell_key(cx, cy, cz);
                 int64_t lo = P.first, hi = P.last;
                 while (lo < hi) {
                     const int64_t mid = (lo + hi) >> 1;
@@ -645,7 +672,7 @@ __device__ __forceinline__ float rsqrt_nr(float x) {
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2).  Give XCD x a contiguous run of tiles instead, so the neighbour halos
-// of Morton-adjacent tiles are shared through one L2.
+// of adjacent tiles are shared through one L2.
 __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nblk) {
     constexpr int64_t kXcd = 8;
     const int64_t q = nblk / kXcd, r = nblk % kXcd;
@@ -1292,11 +1319,11 @@ __attribute__((amdgpu_waves_per_eu(staged_waves_min<R, S, kVarH>(), 8))) k_pass_
     // record loads and those before the LDS stores.  The first round's halo
     // indices are loaded before anything else; the particle's own scalars, its
     // first neighbour slots and what its finish needs follow, so that their
-    // latencies overlap those of the staging (two memory latencies before the
-    // barrier).  The first round needs no halo count (slots past the image
-    // hold n), which is read after it.  Slots past the image, and past the
-    // particle count (last tile), load the tile's first record and store
-    // nothing.
+    // latencies overlap those of the staging.  The first round needs no halo
+    // count (slots past the image hold n): FP64 reads the count after it (two
+    // memory latencies before the barrier); the mixed form reads it first.
+    // Slots past the image, and past the particle count (last tile), load the
+    // tile's first record and store nothing.
     const auto particle_of = [&](int m) { return slot_particle(m, T, s.halo_cap, start, s.n, hl); };
     int m0 = threadIdx.x;
     int64_t g0 = particle_of(m0), g1 = particle_of(m0 + B);
@@ -2209,7 +2236,7 @@ __global__ void __launch_bounds__(kCBoxThreads) k_cbox_final(DevState s, double*
             // (no finite position at all: an empty box, one cell)
             const double q = floor((red[3 + a][0] - red[a][0]) * inv);
             const double e = !(q >= 0.0) ? 1.0
-                             : q >= (double)((1 << kMortonBits) - 1) ? (double)(1 << kMortonBits)
+                             : q >= (double)((1 << kCellBits) - 1) ? (double)(1 << kCellBits)
                                                                      : q + 1.0;
             cbox[9 + a] = e;
             cells *= e;
@@ -2220,22 +2247,22 @@ __global__ void __launch_bounds__(kCBoxThreads) k_cbox_final(DevState s, double*
 
 __device__ __forceinline__ bool contact_cell(const double* cb, double x, double y, double z,
                                              int32_t c[3]) {
-    constexpr double kLast = (double)((1 << kMortonBits) - 1);
+    constexpr double kLast = (double)((1 << kCellBits) - 1);
     const double xs[3] = {x, y, z};
     bool ok = true;
     for (int a = 0; a < 3; ++a) {
         const double q = floor((xs[a] - cb[a]) * cb[6]);
         // (a position that is not a number lands in cell 0 and is flagged)
-        c[a] = !(q >= 0.0) ? 0 : (q >= kLast ? (1 << kMortonBits) - 1 : (int32_t)q);
+        c[a] = !(q >= 0.0) ? 0 : (q >= kLast ? (1 << kCellBits) - 1 : (int32_t)q);
         if (!(q < kLast)) ok = false;
     }
     return ok;
 }
 
-// Packed key of a contact cell (coordinates below 2^kMortonBits each).
+// Packed key of a contact cell (coordinates below 2^kCellBits each).
 __device__ __forceinline__ uint64_t ccell_key(const int32_t c[3]) {
-    return (uint64_t)c[0] | ((uint64_t)c[1] << kMortonBits) |
-           ((uint64_t)c[2] << (2 * kMortonBits));
+    return (uint64_t)c[0] | ((uint64_t)c[1] << kCellBits) |
+           ((uint64_t)c[2] << (2 * kCellBits));
 }
 
 // The grid as the rebuild's kernels read it from the bounding box: dense
@@ -2437,7 +2464,7 @@ __device__ __forceinline__ void cfill_try(const DevState& s, const CHash& h, CFi
 // looked up together.
 __device__ void cfill_hashed(const DevState& s, const CHash& h, const int32_t* members,
                              const int32_t c[3], CFill& f) {
-    constexpr int32_t kAxis = 1 << kMortonBits;
+    constexpr int32_t kAxis = 1 << kCellBits;
     for (int row = 0; row < 9; ++row) {
         const int32_t cy = c[1] + row % 3 - 1, cz = c[2] + row / 3 - 1;
         if (cy < 0 || cz < 0 || cy >= kAxis || cz >= kAxis) continue;
