@@ -1164,7 +1164,7 @@ static tlsph_status autotune_all(tlsph_ctx* c, hipStream_t stream) {
     float bs_best = 1e30f, as_best = 1e30f;
     int bs_sub = 2, bs_tile = 0, as_tile = 0;
     if (!(c->flags & TLSPH_NO_STAGING)) {
-        // Tile sizes: the build's, four fixed ones, and for each of those
+        // Tile sizes: the build's, six fixed ones, and for each of those
         // the sizes that fill whole rounds at the number of workgroups per
         // CU the force pass's LDS image allows (the next smaller, and a few
         // percent larger if that drops a barely started last round).
@@ -1175,7 +1175,7 @@ static tlsph_status autotune_all(tlsph_ctx* c, hipStream_t stream) {
         HIPCHK(c, hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
         if (lds_cu < c->max_lds) lds_cu = c->max_lds;
         if (n_cu < 1) n_cu = 1;
-        std::vector<int> tiles = {c->tile_auto, 128, 112, 96, 64};
+        std::vector<int> tiles = {c->tile_auto, 128, 112, 96, 88, 80, 64};
         const size_t n_fixed = tiles.size();
         for (size_t q = 0; q < tiles.size(); ++q) {
             bool seen = false;
