@@ -418,6 +418,14 @@ void set_pass_a_shape(tlsph_ctx* c, int T, int largest) {
     c->st.a_group = (T % 64 != 0 && 2 * T <= 256 && 2 * la <= 65536) ? 2 : 1;
 }
 
+// The staged passes read halo-row entries up to kHaloPad past a tile's halo
+// count without knowing the count (its rows hold n there): a force-pass
+// round reads two slots per thread of at most 2 kTile threads (four lanes
+// per particle stop at 128-particle tiles), a deformation-pass round four
+// per thread of at most kTile.
+static_assert(kHaloPad >= 2 * (2 * kTile) && kHaloPad >= 4 * kTile,
+              "halo rows must be padded as far as one staging round reads");
+
 // Halo lists and local neighbour slots for tiles of T particles into the
 // given arrays; their largest halo, or -1 where the lists cannot be built
 // (the sort's LDS, or staging switched off).  Synchronises.
