@@ -71,7 +71,17 @@ def golden(name):
         return json.load(fh)
 
 
-def gpu_run(tl, p, precision, n_samples, v_pert=0.0, seed=0, until_failed=False):
+def progress(cap, *a):
+    """A line on the terminal at once, outside pytest's output capture (cap:
+    the test's capfd fixture), so that a long ensemble shows it is alive."""
+    if cap is None:
+        say(*a)
+        return
+    with cap.disabled():
+        say(*a)
+
+
+def gpu_run(tl, p, precision, n_samples, v_pert=0.0, seed=0, until_failed=False, cap=None):
     """Reaction and separation every EVERY steps for n_samples samples (or,
     with until_failed, until the reaction has dropped below 10 % of its
     peak, checked every CHUNK samples)."""
@@ -98,7 +108,7 @@ def gpu_run(tl, p, precision, n_samples, v_pert=0.0, seed=0, until_failed=False)
                 break
     b = bd[:k].cpu().numpy()
     # one line per run, so that a long ensemble shows progress
-    say("run", "fp64" if precision == tl.FP64 else "mixed", "seed", seed, "samples", k)
+    progress(cap, "run", "fp64" if precision == tl.FP64 else "mixed", "seed", seed, "samples", k)
     return -b[:, 1, 2], b[:, 1, 5] - b[:, 0, 5]
 
 
@@ -121,17 +131,18 @@ def tl():
     return tlsph
 
 
-def check_run(tl, p, golden, n_ens=8, mean_tol=None):
+def check_run(tl, p, golden, n_ens=8, mean_tol=None, cap=None):
     assert p.n == golden["particles"]
     ro = np.array(golden["reaction_N"])
     so = np.array(golden["separation_m"])
     n = len(ro)
     ipk = int(np.argmax(ro))
     peak = ro[ipk]
-    runs = {"fp64": gpu_run(tl, p, tl.FP64, n), "mixed": gpu_run(tl, p, tl.MIXED, n)}
+    runs = {"fp64": gpu_run(tl, p, tl.FP64, n, cap=cap),
+            "mixed": gpu_run(tl, p, tl.MIXED, n, cap=cap)}
     # (members run up to twice the oracle's run, then stop once failed)
-    ens = [gpu_run(tl, p, tl.FP64, 2 * n, 1e-12, s, True) for s in range(1, n_ens)]
-    ens_m = [gpu_run(tl, p, tl.MIXED, 2 * n, 1e-12, s, True) for s in range(1, n_ens)]
+    ens = [gpu_run(tl, p, tl.FP64, 2 * n, 1e-12, s, True, cap) for s in range(1, n_ens)]
+    ens_m = [gpu_run(tl, p, tl.MIXED, 2 * n, 1e-12, s, True, cap) for s in range(1, n_ens)]
     fds = {lvl: [fd(s, r, lvl) for r, s in [runs["fp64"]] + ens] for lvl in (0.1, 0.5)}
     fdm = {lvl: [fd(s, r, lvl) for r, s in [runs["mixed"]] + ens_m] for lvl in (0.1, 0.5)}
     fo = {lvl: fd(so, ro, lvl) for lvl in (0.1, 0.5)}
@@ -173,10 +184,11 @@ def check_run(tl, p, golden, n_ens=8, mean_tol=None):
         assert abs(d) <= 2 * mean_tol * m64, (fds[0.5], fdm[0.5])
 
 
-def test_small_bar_to_failure_against_oracle(tl):
-    check_run(tl, I.notched_bar(dx=0.5e-3), golden("notched_bar_small_oracle.json"))
+def test_small_bar_to_failure_against_oracle(tl, capfd):
+    check_run(tl, I.notched_bar(dx=0.5e-3), golden("notched_bar_small_oracle.json"), cap=capfd)
 
 
 @pytest.mark.timeout(900)
-def test_full_size_bar_to_failure_against_oracle(tl):
-    check_run(tl, I.notched_bar(), golden("notched_bar_oracle.json"), n_ens=32, mean_tol=0.01)
+def test_full_size_bar_to_failure_against_oracle(tl, capfd):
+    check_run(tl, I.notched_bar(), golden("notched_bar_oracle.json"), n_ens=32, mean_tol=0.01,
+              cap=capfd)
